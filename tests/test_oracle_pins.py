@@ -1,0 +1,400 @@
+"""Pins for the CPU oracle: checks against what the paper and mathematics fix,
+not against the oracle itself.  All run on the CPU.
+
+Each test names the passage it follows.  Together they are chosen so that a
+plausible slip in the oracle (a dropped term of Eq. 3, a wrong sign or index,
+transposed census bits, an off-by-one in x - d, another tie rule) fails at
+least one of them.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import numpy_oracle as npo
+from paper_1610_04121_amd import synth
+
+RNG = np.random.default_rng(20161012)
+
+
+def _popcount(v) -> int:
+    return bin(int(v)).count("1")
+
+
+# --------------------------------------------------------------------------
+# Census (Sec. 3.1, Eq. 1) - closed forms on ramps, exact bit patterns.
+# --------------------------------------------------------------------------
+def _interior(c):
+    return c[3:-3, 4:-4]
+
+
+def _ramp(kind, W=40, H=30):
+    x = np.arange(W)[None, :].repeat(H, 0)
+    y = np.arange(H)[:, None].repeat(W, 1)
+    return {"x": x, "y": y, "255-x": 255 - x}[kind].astype(np.uint8)
+
+
+def _full_mask(pred):
+    """Word with bit (j+3)*9 + (i+4) set where pred(i, j)."""
+    w = 0
+    for j in range(-3, 4):
+        for i in range(-4, 5):
+            if pred(i, j):
+                w |= 1 << ((j + 3) * 9 + (i + 4))
+    return w
+
+
+@pytest.mark.parametrize("kind,pred,count", [
+    ("x", lambda i, j: i >= 0, 35),
+    ("y", lambda i, j: j >= 0, 36),
+    ("255-x", lambda i, j: i <= 0, 35),
+])
+def test_full_census_ramps(kind, pred, count):
+    c = _interior(oracle.census(_ramp(kind)))
+    word = _full_mask(pred)
+    assert _popcount(word) == count
+    assert (c == np.uint64(word)).all()
+
+
+def _csct_word(pred_ij, pred_j):
+    """Eq. 1 enumeration: i=1..4 with j=-3..3 (j fastest), then j=1..3."""
+    w, k = 0, 0
+    for i in range(1, 5):
+        for j in range(-3, 4):
+            w |= int(pred_ij(i, j)) << k
+            k += 1
+    for j in range(1, 4):
+        w |= int(pred_j(j)) << k
+        k += 1
+    assert k == 31  # "31 pairs of pixels" (Sec. 3.1)
+    return w
+
+
+@pytest.mark.parametrize("kind,pij,pj,count", [
+    ("x", lambda i, j: True, lambda j: True, 31),
+    ("y", lambda i, j: j >= 0, lambda j: True, 19),
+    ("255-x", lambda i, j: False, lambda j: True, 3),
+])
+def test_csct_ramps(kind, pij, pj, count):
+    c = _interior(oracle.census(_ramp(kind), csct=True))
+    word = _csct_word(pij, pj)
+    assert _popcount(word) == count
+    assert (c == np.uint64(word)).all()
+
+
+def test_census_flat_image_all_ones():
+    img = np.full((9, 12), 77, dtype=np.uint8)
+    assert (oracle.census(img) == np.uint64((1 << 63) - 1)).all()
+    assert (oracle.census(img, csct=True) == np.uint64((1 << 31) - 1)).all()
+
+
+def test_census_clamp_to_edge_corner():
+    # at (0,0) every sample with negative offset reads the corner pixel itself
+    img = RNG.integers(0, 256, (12, 15), dtype=np.uint8)
+    c = int(oracle.census(img)[0, 0])
+    for j in range(-3, 4):
+        for i in range(-4, 5):
+            v = img[max(j, 0), max(i, 0)]
+            assert ((c >> ((j + 3) * 9 + (i + 4))) & 1) == int(v >= img[0, 0])
+
+
+@pytest.mark.parametrize("csct", [False, True])
+def test_census_invariant_to_strictly_increasing_map(csct):
+    img = RNG.integers(0, 128, (33, 41), dtype=np.uint8)
+    lut = np.sort(RNG.choice(256, size=128, replace=False)).astype(np.uint8)
+    assert (np.diff(lut.astype(int)) > 0).all()
+    a = oracle.census(img, csct=csct)
+    b = oracle.census(lut[img], csct=csct)
+    assert (a == b).all()
+
+
+def test_census_other_window_sizes_match_numpy():
+    img = RNG.integers(0, 256, (14, 17), dtype=np.uint8)
+    for cw, ch in [(3, 3), (5, 5), (7, 9), (9, 7), (1, 3)]:
+        assert (oracle.census(img, cw, ch) == npo.census_full(img, cw, ch)).all()
+        assert (oracle.census(img, cw, ch, csct=True) == npo.census_csct(img, cw, ch)).all()
+
+
+# --------------------------------------------------------------------------
+# Matching cost (Eq. 2)
+# --------------------------------------------------------------------------
+def test_cost_is_hamming_distance_and_cmax_before_the_border():
+    l = RNG.integers(0, 256, (8, 20), dtype=np.uint8)
+    r = RNG.integers(0, 256, (8, 20), dtype=np.uint8)
+    cl, cr = oracle.census(l), oracle.census(r)
+    mc = oracle.cost_volume(cl, cr, 12, 62)
+    for (y, x, d) in [(0, 0, 0), (3, 19, 11), (7, 5, 5), (2, 4, 7), (5, 11, 3)]:
+        want = 62 if x - d < 0 else _popcount(int(cl[y, x]) ^ int(cr[y, x - d]))
+        assert mc[y, x, d] == want
+
+
+def test_cost_zero_on_constant_shift_interior():
+    W, H, s, D = 60, 20, 7, 16
+    left, right = synth.shifted_pair(W, H, s, seed=5)
+    assert (right[:, :W - s] == left[:, s:]).all()
+    mc = oracle.cost_volume(oracle.census(left), oracle.census(right), D, 62)
+    assert (mc[3:H - 3, s + 4:W - 4, s] == 0).all()
+    assert (mc[:, :5, 5:] == 62).sum() > 0
+    for x in range(D):
+        assert (mc[:, x, x + 1:] == 62).all()
+
+
+# --------------------------------------------------------------------------
+# Aggregation (Eq. 3) - brute-force enumeration of disparity sequences.
+# --------------------------------------------------------------------------
+def _V(a, b, P1, P2):
+    if a == b:
+        return 0
+    return min(P1, P2) if abs(a - b) == 1 else P2
+
+
+def _brute_path(costs, P1, P2):
+    """costs[n+1][D] along one path.  Returns the expected L at every step via
+    L(p_n, d) = E_n(d) - min_k E_{n-1}(k), E_n(d) = min over disparity
+    sequences ending in d of sum C(p_i, d_i) + sum V(d_{i-1}, d_i)."""
+    n1, D = costs.shape
+    out = np.zeros_like(costs, dtype=np.int64)
+    prevE = None
+    for n in range(n1):
+        E = np.full(D, 1 << 60, dtype=np.int64)
+        for seq in itertools.product(range(D), repeat=n + 1):
+            e = sum(int(costs[i, seq[i]]) for i in range(n + 1))
+            e += sum(_V(seq[i - 1], seq[i], P1, P2) for i in range(1, n + 1))
+            E[seq[-1]] = min(E[seq[-1]], e)
+        out[n] = E if prevE is None else E - prevE.min()
+        prevE = E
+    return out
+
+
+@pytest.mark.parametrize("trial", range(6))
+def test_aggregation_matches_brute_force_paths(trial):
+    rng = np.random.default_rng(100 + trial)
+    D = int(rng.integers(1, 6))
+    n1 = int(rng.integers(1, 7)) if D <= 4 else int(rng.integers(1, 6))
+    P1 = int(rng.integers(0, 12))
+    P2 = int(rng.integers(0, 30))
+    costs = rng.integers(0, 20, (n1, D)).astype(np.uint8)
+    want = _brute_path(costs, P1, P2)
+    # the same path laid along each of the 8 directions of a 1-pixel-wide or
+    # diagonal image
+    # horizontal, left to right and right to left
+    mc = costs[None, :, :]
+    assert (oracle.aggregate(mc, P1, P2, 1, 0)[0] == want).all()
+    assert (oracle.aggregate(mc[:, ::-1], P1, P2, -1, 0)[0, ::-1] == want).all()
+    # vertical
+    mc = costs[:, None, :]
+    assert (oracle.aggregate(mc, P1, P2, 0, 1)[:, 0] == want).all()
+    assert (oracle.aggregate(mc[::-1], P1, P2, 0, -1)[::-1, 0] == want).all()
+    # diagonal: put the path on the main diagonal of an n1 x n1 image; every
+    # other pixel gets its own independent path and does not matter
+    big = rng.integers(0, 20, (n1, n1, D)).astype(np.uint8)
+    for k in range(n1):
+        big[k, k] = costs[k]
+    L = oracle.aggregate(big, P1, P2, 1, 1)
+    assert (np.array([L[k, k] for k in range(n1)]) == want).all()
+    flipped = big[::-1, ::-1].copy()
+    L = oracle.aggregate(flipped, P1, P2, -1, -1)[::-1, ::-1]
+    assert (np.array([L[k, k] for k in range(n1)]) == want).all()
+
+
+def test_aggregation_anti_diagonals_follow_their_own_paths():
+    rng = np.random.default_rng(7)
+    D, n1, P1, P2 = 3, 5, 4, 9
+    costs = rng.integers(0, 15, (n1, D)).astype(np.uint8)
+    want = _brute_path(costs, P1, P2)
+    big = rng.integers(0, 15, (n1, n1, D)).astype(np.uint8)
+    for k in range(n1):  # pixels (n1-1-k, k): a top-right to bottom-left path
+        big[k, n1 - 1 - k] = costs[k]
+    L = oracle.aggregate(big, P1, P2, -1, 1)
+    assert (np.array([L[k, n1 - 1 - k] for k in range(n1)]) == want).all()
+
+
+@pytest.mark.parametrize("P1,P2", [(7, 86), (0, 0), (20, 5), (3, 200)])
+def test_aggregation_bound_and_min_range(P1, P2):
+    mc = RNG.integers(0, 63, (12, 17, 10)).astype(np.uint8)
+    for rx, ry in npo.DIRS8:
+        L = oracle.aggregate(mc, P1, P2, rx, ry)  # raises if C <= L <= C+P2 fails
+        assert (L >= mc).all() and (L <= mc.astype(int) + P2).all()
+        rng_ = L - L.min(axis=2, keepdims=True)
+        assert (rng_ >= 0).all() and (rng_ <= P2 + 62).all()
+
+
+def test_aggregation_p2_zero_is_the_raw_cost():
+    mc = RNG.integers(0, 63, (9, 11, 6)).astype(np.uint8)
+    for rx, ry in npo.DIRS8:
+        assert (oracle.aggregate(mc, 5, 0, rx, ry) == mc).all()
+
+
+def test_aggregation_huge_penalties_give_running_sums():
+    # with P1 = P2 larger than any possible saving, the cheapest sequence
+    # keeps d fixed, so L(p_n, d) = sum_i C(p_i, d) - min_k E_{n-1}(k)
+    n1, D = 6, 5
+    costs = RNG.integers(0, 10, (n1, D)).astype(np.uint8)
+    P = 10 * n1 * 10
+    L = oracle.aggregate(costs[None], P, P, 1, 0)[0]
+    E = np.cumsum(costs.astype(np.int64), axis=0)
+    want = E.copy()
+    want[1:] = E[1:] - E[:-1].min(axis=1, keepdims=True)
+    assert (L == want).all()
+
+
+# --------------------------------------------------------------------------
+# WTA (Eq. 4), right view, median, LR check
+# --------------------------------------------------------------------------
+def test_wta_left_is_first_argmin():
+    S = RNG.integers(0, 6, (7, 9, 11)).astype(np.uint32)  # many ties
+    assert (oracle.wta_left(S) == np.argmin(S, axis=2)).all()
+
+
+def test_wta_right_definition():
+    S = RNG.integers(0, 6, (5, 13, 6)).astype(np.uint32)
+    H, W, D = S.shape
+    got = oracle.wta_right(S)
+    for y in range(H):
+        for x in range(W):
+            n = min(D, W - x)
+            vals = [S[y, x + d, d] for d in range(n)]
+            assert got[y, x] == int(np.argmin(vals))
+
+
+def test_median_is_fifth_of_nine_edge_replicated():
+    a = RNG.integers(0, 300, (11, 14)).astype(np.uint16)
+    p = np.pad(a, 1, mode="edge")
+    want = np.zeros_like(a)
+    for y in range(a.shape[0]):
+        for x in range(a.shape[1]):
+            want[y, x] = int(np.median(p[y:y + 3, x:x + 3]))
+    assert (oracle.median3(a) == want).all()
+
+
+def test_lr_check_hand_example():
+    dl = np.array([[0, 1, 1, 3, 2, 0]], dtype=np.uint16)
+    dr = np.array([[0, 1, 3, 0, 1, 5]], dtype=np.uint16)
+    # x=0: d=0 -> dr[0]=0 ok; x=1: d=1 -> dr[0]=0, |1-0|<=1 ok;
+    # x=2: d=1 -> dr[1]=1 ok; x=3: d=3 -> dr[0]=0 -> bad;
+    # x=4: d=2 -> dr[2]=3 ok; x=5: d=0 -> dr[5]=5 bad
+    want = np.array([[0, 1, 1, 0xFFFF, 2, 0xFFFF]], dtype=np.uint16)
+    assert (oracle.lr_check(dl, dr, 1) == want).all()
+    dl2 = np.array([[2, 0]], dtype=np.uint16)  # x - d < 0 is invalid
+    assert oracle.lr_check(dl2, np.zeros_like(dl2), 1)[0, 0] == 0xFFFF
+
+
+# --------------------------------------------------------------------------
+# Whole pipeline
+# --------------------------------------------------------------------------
+def test_constant_image_gives_zero_disparity():
+    img = np.full((20, 30), 100, dtype=np.uint8)
+    r = oracle.sgm(img, img, 8, n_paths=8, median=True, lr=True)
+    assert (r.dl_raw == 0).all() and (r.dr_raw == 0).all() and (r.out == 0).all()
+
+
+@pytest.mark.parametrize("n_paths", [4, 8])
+def test_vertical_flip_equivariance(n_paths):
+    l = RNG.integers(0, 256, (21, 33), dtype=np.uint8)
+    r = RNG.integers(0, 256, (21, 33), dtype=np.uint8)
+    a = oracle.sgm(l, r, 10, n_paths=n_paths, median=True, lr=True, keep_sums=True)
+    b = oracle.sgm(l[::-1], r[::-1], 10, n_paths=n_paths, median=True, lr=True, keep_sums=True)
+    assert (a.S == b.S[::-1]).all()
+    assert (a.out == b.out[::-1]).all()
+
+
+def test_p2_zero_pipeline_is_block_matching():
+    l = RNG.integers(0, 256, (9, 24), dtype=np.uint8)
+    r = RNG.integers(0, 256, (9, 24), dtype=np.uint8)
+    D = 8
+    cl, cr = oracle.census(l), oracle.census(r)
+    H, W = l.shape
+    want = np.zeros((H, W), dtype=np.uint16)
+    for y in range(H):
+        for x in range(W):
+            cs = [62 if x - d < 0 else _popcount(int(cl[y, x]) ^ int(cr[y, x - d])) for d in range(D)]
+            want[y, x] = int(np.argmin(cs))
+    got = oracle.sgm(l, r, D, P1=3, P2=0, n_paths=8).out
+    assert (got == want).all()
+
+
+def _clean_runs(clean, rx, ry):
+    """Length of the run of consecutive clean pixels that ends at each pixel,
+    walking backwards along path direction (rx, ry)."""
+    H, W = clean.shape
+    run = np.zeros((H, W), dtype=np.int64)
+    ys = range(H) if ry >= 0 else range(H - 1, -1, -1)
+    xs = list(range(W)) if rx >= 0 else list(range(W - 1, -1, -1))
+    for y in ys:
+        for x in xs:
+            if not clean[y, x]:
+                continue
+            px, py = x - rx, y - ry
+            prev = run[py, px] if 0 <= px < W and 0 <= py < H else 0
+            run[y, x] = prev + 1
+    return run
+
+
+@pytest.mark.parametrize("n_paths,D,P1,P2", [(4, 12, 7, 86), (8, 24, 2, 10), (4, 24, 7, 20)])
+def test_exact_recovery_of_constant_shift(n_paths, D, P1, P2):
+    """Theorem (from Eq. 3): on a constant-shift pair call a pixel clean when
+    C(q, s) = 0 and C(q, d) >= 1 for d != s.  If the last P2 + 1 pixels of
+    every path into q are clean, then L_r(q, s) = 0 and L_r(q, d) >= 1, so
+    D_L(q) = s.  (Along a clean run L_r(., s) starts <= P2 and drops by at
+    least 1 per step until it is 0.)  D_R(x) = s likewise where q = x + s
+    qualifies and C(x + d, d) >= 1 for the other d."""
+    W, H, s = 240, 200, 9
+    left, right = synth.shifted_pair(W, H, s, seed=11)
+    r = oracle.sgm(left, right, D, P1, P2, n_paths=n_paths, median=True, lr=True, keep_sums=True)
+    mc = oracle.cost_volume(r.census_l, r.census_r, D, 62)
+    clean = (mc[..., s] == 0) & (np.delete(mc, s, axis=2) >= 1).all(axis=2)
+    good_l = np.ones((H, W), dtype=bool)
+    for rx, ry in oracle.directions(n_paths):
+        good_l &= _clean_runs(clean, rx, ry) >= P2 + 1
+    assert good_l.sum() > 500
+    assert (r.S[good_l][:, s] == 0).all()
+    assert (r.dl_raw[good_l] == s).all()
+    good_r = np.zeros((H, W), dtype=bool)
+    for y in range(H):
+        for x in range(W - s):
+            if not good_l[y, x + s]:
+                continue
+            n = min(D, W - x)
+            good_r[y, x] = all(mc[y, x + d, d] >= 1 for d in range(n) if d != s)
+    assert good_r.sum() > 500
+    assert (r.dr_raw[good_r] == s).all()
+    # median then LR: every 3x3 neighbour qualifies on both sides
+    def all9(m):
+        p = np.pad(m, 1, mode="edge")
+        return np.logical_and.reduce([p[j:j + H, i:i + W] for j in range(3) for i in range(3)])
+    gl, gr = all9(good_l), all9(good_r)
+    good_out = np.zeros((H, W), dtype=bool)
+    good_out[:, s:] = gl[:, s:] & gr[:, :W - s]
+    assert good_out.sum() > 50
+    assert (r.out[good_out] == s).all()
+
+
+# --------------------------------------------------------------------------
+# Two independent oracles agree (N-version)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("trial", range(8))
+def test_c_and_numpy_oracles_agree(trial):
+    rng = np.random.default_rng(trial)
+    W, H = int(rng.integers(1, 40)), int(rng.integers(1, 30))
+    D = int(rng.integers(1, 40))
+    P = int(rng.choice([2, 4, 8]))
+    csct = bool(rng.integers(0, 2))
+    P1 = int(rng.integers(0, 15))
+    P2 = int(rng.integers(P1, 120))
+    med, lr = bool(rng.integers(0, 2)), bool(rng.integers(0, 2))
+    l = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    r = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    a = oracle.sgm(l, r, D, P1, P2, P, median=med, lr=lr, csct=csct, keep_sums=True)
+    b = npo.sgm(l, r, D, P1, P2, P, median=med, lr=lr, csct=csct)
+    assert (a.S == b["S"]).all()
+    assert (a.out == b["out"]).all()
+
+
+def test_synthetic_scene_is_mostly_recovered():
+    # a sanity check of generator + oracle (not a parity pin): most
+    # non-occluded textured pixels come out within 1 px of the ground truth
+    p = synth.workload_pair("small_320x240_d64_p4")
+    r = oracle.sgm(p.left, p.right, 64, 7, 86, 4)
+    v = p.gt != 0xFFFF
+    assert (np.abs(r.out[v].astype(int) - p.gt[v]) <= 1).mean() > 0.95
