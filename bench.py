@@ -1,0 +1,166 @@
+"""Throughput of the SGM disparity pipeline on one MI355X.
+
+A step is one pass of the whole pipeline (census + cost, aggregation along
+all paths, sum + winner-take-all with the right view, median, left-right
+check) over one 640x480 pair with 128 disparity levels and 4 paths, inputs
+already resident in HBM.  Prints one JSON line:
+
+  value         frames/s over the timed steps (whole job = one GPU);
+  gcells_per_s  W*H*D*paths * frames/s / 1e9;
+  roofline      the aggregation kernel (the dominant one) against HBM:
+                algorithmic bytes per launch / its mean duration measured
+                with HIP events recorded on the pipeline's stream;
+  cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
+                same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "vga_640x480_d128_p4"
+METRIC = "frames/s and Gcells/s (W·H·D·paths) at 640x480 D=128; p50/p99 latency served"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "aggregate_vga_640x480_d128_p4_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1610_04121_amd", "csrc", "sgm_kernels.hip")
+
+
+def _kernel_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def _traffic(launch_bytes_alg: float):
+    """HBM bytes per aggregation launch from committed rocprofv3 counters,
+    or None if the counters were taken on another version of the kernels."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != _kernel_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(pair, cfg, budget_s: float = 12.0):
+    import oracle
+    oracle.build()
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        oracle.sgm(pair.left, pair.right, cfg["max_disp"], 7, 86, cfg["n_paths"],
+                   median=cfg["median"], lr=cfg["lr"])
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt, 4), "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} full {cfg['w']}x{cfg['h']} D={cfg['max_disp']} {cfg['n_paths']}-path "
+                      f"frames (median + LR), single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-samples", type=int, default=300)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(independent frames shard across GPUs with no exchange).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1610_04121_amd import SGM, synth
+
+    cfg = synth.WORKLOADS[WORKLOAD]
+    W, H, D, P = cfg["w"], cfg["h"], cfg["max_disp"], cfg["n_paths"]
+    pair = synth.workload_pair(WORKLOAD)
+    dev = torch.device("cuda:0")
+    left = torch.from_numpy(pair.left).to(dev)
+    right = torch.from_numpy(pair.right).to(dev)
+    out = torch.empty((H, W), dtype=torch.uint16, device=dev)
+    s = SGM(W, H, D, synth.P1_DEFAULT, synth.P2_DEFAULT, P, median=cfg["median"], lrcheck=cfg["lr"])
+    print(f"bench: {WORKLOAD} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        s.compute(left, right, out)
+    torch.cuda.synchronize()
+
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.compute(left, right, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ncalls, stage_ms = s.profile_read()
+    s.profile(False)
+    elapsed = t1 - t0
+    fps = args.steps / elapsed
+
+    # per-frame latency (separate, event-bracketed frames)
+    lat = []
+    st = torch.cuda.current_stream()
+    for _ in range(args.latency_samples):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        s.compute(left, right, out)
+        e1.record(st)
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    lat = np.array(lat)
+
+    # the aggregation kernel reads the cost volume and writes one L_r plane
+    # per direction: u8 costs, u8 L_r (Cmax + P2 = 148 < 256)
+    Dp = 64 * (1 if D <= 64 else (2 if D <= 128 else 4))
+    agg_bytes = P * W * H * Dp * (1 + 1)
+    agg_ms = stage_ms["aggregate"] / max(ncalls, 1)
+    achieved = agg_bytes / (agg_ms * 1e-3) / 1e9
+    traffic = _traffic(agg_bytes)
+
+    line = {
+        "metric": METRIC,
+        "value": round(fps, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "width": W, "height": H, "max_disp": D, "n_paths": P,
+                   "census": "9x7 full", "P1": synth.P1_DEFAULT, "P2": synth.P2_DEFAULT,
+                   "median": cfg["median"], "lr_check": cfg["lr"], "scene": cfg["scene"],
+                   "seed": cfg["seed"]},
+        "gcells_per_s": round(W * H * D * P * fps / 1e9, 2),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                       "p99": round(float(np.percentile(lat, 99)), 4)},
+        "stage_ms": {k: round(v / max(ncalls, 1), 5) for k, v in stage_ms.items()},
+        "roofline": {"kernel": "aggregate_kernel", "bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "alg_bytes_per_launch": agg_bytes,
+                     "mean_launch_ms": round(agg_ms, 5)},
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(pair, cfg)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,138 @@
+/*
+ * sgm.h - C ABI of an MI355X (gfx950) implementation of the Semi-Global
+ * Matching disparity pipeline of Hernandez-Juarez et al., "Embedded
+ * real-time stereo estimation via Semi-Global Matching on the GPU"
+ * (arXiv 1610.04121).
+ *
+ * Pipeline (Sec. 2): census-transform features of both images (Sec. 3.1,
+ * Eq. 1), Hamming matching cost (Eq. 2), cost aggregation along 2, 4 or 8
+ * path directions with the recurrence of Eq. 3, summation over directions and
+ * winner-take-all (Eq. 4), a 3x3 median (Sec. 2, stage 4) and, optionally, a
+ * left-right consistency check (named as a post-filter in Sec. 5).
+ *
+ * Conventions shared by every call:
+ *  - Image and disparity pointers are DEVICE pointers (e.g. from a torch
+ *    tensor's data_ptr()).  Buffers are contiguous and row-major with a pitch
+ *    equal to the width: image u8 [height][width], disparity u16
+ *    [height][width].  The caller owns them.  `left` and `right` may alias;
+ *    the output must not alias either input.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Compute
+ *    calls only enqueue work and return; the result is ready when the stream
+ *    reaches that point.
+ *  - Disparities are integers in [0, max_disp); 0xFFFF marks a pixel that
+ *    fails the left-right check.
+ *  - Ties in the winner-take-all go to the smallest disparity.
+ *  - Errors are reported as negative return codes (or NULL) before anything
+ *    is enqueued; sgm_last_error() returns a message for the calling thread.
+ *  - A context is not thread-safe; use one per host thread or serialize.
+ */
+#ifndef SGM_H
+#define SGM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sgm_ctx sgm_ctx;
+typedef void *sgm_stream_t; /* a hipStream_t */
+
+enum {
+    SGM_OK = 0,
+    SGM_EINVAL = -1,    /* invalid argument or parameter combination */
+    SGM_ENOMEM = -2,    /* device allocation failed or budget exceeded */
+    SGM_EHIP = -3,      /* a HIP runtime call failed (no GPU, launch error) */
+    SGM_EBUSY = -4,     /* server: request not admitted (no slot / memory) */
+    SGM_ECANCELED = -5  /* server: request cancelled or failed */
+};
+
+enum {
+    SGM_MEDIAN3 = 1u,     /* 3x3 median of the left (and right) disparity */
+    SGM_LRCHECK = 2u,     /* left-right consistency check */
+    SGM_CENSUS_CSCT = 4u  /* center-symmetric census (Eq. 1) instead of the
+                             full-window census */
+};
+
+/* Checks a parameter set without touching the GPU.  Returns SGM_OK or
+ * SGM_EINVAL (message in sgm_last_error).  Rules:
+ *   width, height >= 1; 1 <= max_disp <= 256; n_paths in {2, 4, 8};
+ *   census_w, census_h odd and >= 1; the census fits 64 bits (full:
+ *   w*h <= 64; CSCT: (w*h - 1)/2 <= 64); P1, P2 >= 0;
+ *   n_paths * (Cmax + P2) <= 65535, where Cmax = w*h - 1 (full) or
+ *   (w*h - 1)/2 (CSCT), so that summed costs fit in 16 bits (the bound
+ *   L_r <= C + P2 follows from the last term of Eq. 3). */
+int sgm_validate(int width, int height, int max_disp, int P1, int P2, int n_paths,
+                 int census_w, int census_h, unsigned flags);
+
+/* Creates a context for one image size and parameter set on the current HIP
+ * device and allocates its device workspace (sgm_footprint_bytes).
+ * P1, P2 are the penalties of Eq. 3 for disparity changes of one and of more
+ * than one level.  The path set is: 2 = left-to-right and top-to-bottom
+ * (Sec. 4); 4 = the four axial directions; 8 = axial plus diagonal.
+ * Returns NULL on error (SGM_EINVAL / SGM_ENOMEM / SGM_EHIP). */
+sgm_ctx *sgm_create(int width, int height, int max_disp, int P1, int P2, int n_paths,
+                    int census_w, int census_h);
+
+/* Options: SGM_MEDIAN3, SGM_LRCHECK, SGM_CENSUS_CSCT; lr_threshold is the
+ * largest accepted |D_L(x) - D_R(x - D_L(x))| (default: flags 0, threshold 1).
+ * Switching the census kind re-validates the overflow bound. */
+int sgm_set_options(sgm_ctx *ctx, unsigned flags, int lr_threshold);
+
+/* Enqueues the whole pipeline on `stream`: left u8 [H][W] is the base image,
+ * right u8 [H][W] the match image (a left pixel x matches right pixel x - d,
+ * Eq. 2); disp_out u16 [H][W] receives the disparity.  Asynchronous. */
+int sgm_compute(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right, uint16_t *disp_out,
+                sgm_stream_t stream);
+
+/* Releases the context and its workspace (synchronizes the device first).
+ * NULL is accepted. */
+void sgm_destroy(sgm_ctx *ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *sgm_last_error(void);
+
+/* Device bytes a context of this shape needs (workspace only; the caller's
+ * images and output are not counted).  0 if the shape is invalid. */
+size_t sgm_footprint_bytes(int width, int height, int max_disp, int n_paths, unsigned flags);
+
+/* ---- stage timing ----
+ * When enabled, every sgm_compute records HIP events on its stream before the
+ * first stage and after each of the four stages (0 census + cost, 1
+ * aggregation, 2 sum + winner-take-all, 3 median + LR).  sgm_profile_read
+ * waits for the recorded calls, writes the summed milliseconds of each stage
+ * into stage_ms[4] and the number of calls into *ncalls, and clears them. */
+int sgm_profile_enable(sgm_ctx *ctx, int enable);
+int sgm_profile_read(sgm_ctx *ctx, double *stage_ms, int *ncalls);
+
+/* ---- debug taps: intermediates for stage-by-stage parity tests ---- */
+
+/* Census words of one image: u64 [H][W] (CSCT words use the low bits). */
+int sgm_debug_census(sgm_ctx *ctx, const uint8_t *img, uint64_t *census_out,
+                     sgm_stream_t stream);
+
+/* Runs the pipeline up to the summed costs and writes S u16 [H][W][max_disp]
+ * (d fastest), S(p, d) = sum over directions of L_r(p, d). */
+int sgm_debug_sums(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right, uint16_t *s_out,
+                   sgm_stream_t stream);
+
+/* Raw (before median / LR) left and right disparity maps, u16 [H][W] each. */
+int sgm_debug_raw_disparity(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right,
+                            uint16_t *dl_out, uint16_t *dr_out, sgm_stream_t stream);
+
+/* Host-only: the pixels a GPU aggregation slice visits.  Direction
+ * (rx, ry) in {-1,0,1}^2 \ {(0,0)}; slice in [0, number of slices) where
+ * horizontal directions have H slices of W steps and the others W slices of H
+ * steps.  Diagonal slices wrap from one side border to the other and restart
+ * the path there (Sec. 3.2).  Writes up to max_steps (x, y, restart) triples;
+ * restart = 1 where the step begins a new path.  Returns the step count or
+ * SGM_EINVAL. */
+int sgm_path_walk(int width, int height, int rx, int ry, int slice, int max_steps, int *xs,
+                  int *ys, uint8_t *restart);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGM_H */

@@ -1,0 +1,259 @@
+// C ABI of the SGM library (declared in include/sgm.h).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <array>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sgm.h"
+#include "sgm_plan.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_err(hipError_t e, const char* what) {
+    return set_err(SGM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool make_plan(sgm::Plan& p, int w, int h, int d, int P1, int P2, int n_paths, int cw, int ch,
+               unsigned flags, int thr) {
+    p.W = w;
+    p.H = h;
+    p.D = d;
+    p.P1 = P1;
+    p.P2 = P2;
+    p.n_paths = n_paths;
+    p.cw = cw;
+    p.ch = ch;
+    p.csct = (flags & SGM_CENSUS_CSCT) != 0;
+    p.median = (flags & SGM_MEDIAN3) != 0;
+    p.lrcheck = (flags & SGM_LRCHECK) != 0;
+    p.lr_thr = thr;
+    const char* why = "invalid parameters";
+    if (flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK | SGM_CENSUS_CSCT)) {
+        set_err(SGM_EINVAL, "unknown flag bits");
+        return false;
+    }
+    if (!sgm::plan_finish(p, &why)) {
+        set_err(SGM_EINVAL, why);
+        return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+struct sgm_ctx {
+    sgm::Plan plan;
+    sgm::Workspace ws;
+    void* mem = nullptr;
+    size_t mem_bytes = 0;
+    int device = 0;
+    // stage timing: one set of kNumStages + 1 events per profiled call
+    bool profiling = false;
+    using EventSet = std::array<hipEvent_t, sgm::kNumStages + 1>;
+    std::vector<EventSet> pending, pool;
+};
+
+extern "C" {
+
+const char* sgm_last_error(void) { return g_err.c_str(); }
+
+int sgm_validate(int width, int height, int max_disp, int P1, int P2, int n_paths, int census_w,
+                 int census_h, unsigned flags) {
+    sgm::Plan p;
+    if (!make_plan(p, width, height, max_disp, P1, P2, n_paths, census_w, census_h, flags, 1))
+        return SGM_EINVAL;
+    return SGM_OK;
+}
+
+size_t sgm_footprint_bytes(int width, int height, int max_disp, int n_paths, unsigned flags) {
+    // the u8/u16 choice of L_r depends on P2; count the larger case
+    sgm::Plan p;
+    if (!make_plan(p, width, height, max_disp, 0, 0, n_paths, 9, 7, flags, 1)) return 0;
+    p.l16 = true;
+    return sgm::workspace_bytes(p);
+}
+
+sgm_ctx* sgm_create(int width, int height, int max_disp, int P1, int P2, int n_paths, int census_w,
+                    int census_h) {
+    sgm::Plan p;
+    if (!make_plan(p, width, height, max_disp, P1, P2, n_paths, census_w, census_h, 0, 1)) return nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        hip_err(e, "hipGetDevice");
+        return nullptr;
+    }
+    sgm_ctx* c = new (std::nothrow) sgm_ctx;
+    if (!c) {
+        set_err(SGM_ENOMEM, "host allocation failed");
+        return nullptr;
+    }
+    c->plan = p;
+    c->device = dev;
+    // the workspace is sized for u16 L_r so that options can change later
+    sgm::Plan big = p;
+    big.l16 = true;
+    c->mem_bytes = sgm::workspace_bytes(big);
+    e = hipMalloc(&c->mem, c->mem_bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(SGM_ENOMEM, std::string("hipMalloc of workspace failed: ") + hipGetErrorString(e));
+        delete c;
+        return nullptr;
+    }
+    c->ws = sgm::workspace_carve(p, c->mem);
+    return c;
+}
+
+int sgm_set_options(sgm_ctx* c, unsigned flags, int lr_threshold) {
+    if (!c) return set_err(SGM_EINVAL, "null context");
+    sgm::Plan p = c->plan;
+    if (!make_plan(p, p.W, p.H, p.D, p.P1, p.P2, p.n_paths, p.cw, p.ch, flags, lr_threshold))
+        return SGM_EINVAL;
+    c->plan = p;
+    c->ws = sgm::workspace_carve(p, c->mem);
+    return SGM_OK;
+}
+
+static void release_events(sgm_ctx* c) {
+    for (auto* v : {&c->pending, &c->pool})
+        for (auto& set : *v)
+            for (hipEvent_t e : set) (void)hipEventDestroy(e);
+    c->pending.clear();
+    c->pool.clear();
+}
+
+void sgm_destroy(sgm_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    release_events(c);
+    if (c->mem) (void)hipFree(c->mem);
+    delete c;
+}
+
+int sgm_profile_enable(sgm_ctx* c, int enable) {
+    if (!c) return set_err(SGM_EINVAL, "null context");
+    c->profiling = enable != 0;
+    return SGM_OK;
+}
+
+int sgm_profile_read(sgm_ctx* c, double* stage_ms, int* ncalls) {
+    if (!c || !stage_ms) return set_err(SGM_EINVAL, "null argument");
+    for (int i = 0; i < sgm::kNumStages; ++i) stage_ms[i] = 0.0;
+    int n = 0;
+    for (auto& set : c->pending) {
+        hipError_t e = hipEventSynchronize(set[sgm::kNumStages]);
+        if (e != hipSuccess) return hip_err(e, "hipEventSynchronize");
+        for (int i = 0; i < sgm::kNumStages; ++i) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, set[i], set[i + 1]);
+            if (e != hipSuccess) return hip_err(e, "hipEventElapsedTime");
+            stage_ms[i] += ms;
+        }
+        c->pool.push_back(set);
+        ++n;
+    }
+    c->pending.clear();
+    if (ncalls) *ncalls = n;
+    return SGM_OK;
+}
+
+static int check_ptrs(const void* a, const void* b, const void* out) {
+    if (!a || !b || !out) return set_err(SGM_EINVAL, "null buffer pointer");
+    return SGM_OK;
+}
+
+int sgm_compute(sgm_ctx* c, const uint8_t* left, const uint8_t* right, uint16_t* disp_out,
+                sgm_stream_t stream) {
+    if (!c) return set_err(SGM_EINVAL, "null context");
+    if (int rc = check_ptrs(left, right, disp_out)) return rc;
+    if ((const void*)disp_out == (const void*)left || (const void*)disp_out == (const void*)right)
+        return set_err(SGM_EINVAL, "output aliases an input");
+    hipEvent_t* events = nullptr;
+    if (c->profiling) {
+        if (c->pool.empty()) {
+            sgm_ctx::EventSet set;
+            for (auto& ev : set) {
+                hipError_t e = hipEventCreate(&ev);
+                if (e != hipSuccess) return hip_err(e, "hipEventCreate");
+            }
+            c->pool.push_back(set);
+        }
+        c->pending.push_back(c->pool.back());
+        c->pool.pop_back();
+        events = c->pending.back().data();
+    }
+    hipError_t e = sgm::launch_pipeline(c->plan, c->ws, left, right, disp_out, (hipStream_t)stream, events);
+    if (e != hipSuccess) return hip_err(e, "kernel launch");
+    return SGM_OK;
+}
+
+int sgm_debug_census(sgm_ctx* c, const uint8_t* img, uint64_t* census_out, sgm_stream_t stream) {
+    if (!c || !img || !census_out) return set_err(SGM_EINVAL, "null argument");
+    hipError_t e = sgm::launch_census_only(c->plan, img, census_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_err(e, "census launch");
+    return SGM_OK;
+}
+
+int sgm_debug_sums(sgm_ctx* c, const uint8_t* left, const uint8_t* right, uint16_t* s_out,
+                   sgm_stream_t stream) {
+    if (!c) return set_err(SGM_EINVAL, "null context");
+    if (int rc = check_ptrs(left, right, s_out)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = sgm::launch_census_cost(c->plan, c->ws, left, right, s);
+    if (e == hipSuccess) e = sgm::launch_aggregate(c->plan, c->ws, s);
+    if (e == hipSuccess) e = sgm::launch_sum_planes(c->plan, c->ws, s_out, s);
+    if (e != hipSuccess) return hip_err(e, "kernel launch");
+    return SGM_OK;
+}
+
+int sgm_debug_raw_disparity(sgm_ctx* c, const uint8_t* left, const uint8_t* right, uint16_t* dl_out,
+                            uint16_t* dr_out, sgm_stream_t stream) {
+    if (!c) return set_err(SGM_EINVAL, "null context");
+    if (int rc = check_ptrs(left, right, dl_out)) return rc;
+    if (!dr_out) return set_err(SGM_EINVAL, "null buffer pointer");
+    sgm::Plan p = c->plan;
+    p.lrcheck = true;   // produce the right view too
+    p.median = false;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = sgm::launch_census_cost(p, c->ws, left, right, s);
+    if (e == hipSuccess) e = sgm::launch_aggregate(p, c->ws, s);
+    if (e == hipSuccess) e = sgm::launch_wta(p, c->ws, nullptr, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dl_out, c->ws.dl, (size_t)p.W * p.H * 2, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dr_out, c->ws.dr, (size_t)p.W * p.H * 2, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_err(e, "kernel launch");
+    return SGM_OK;
+}
+
+int sgm_path_walk(int width, int height, int rx, int ry, int slice, int max_steps, int* xs, int* ys,
+                  uint8_t* restart) {
+    if (width < 1 || height < 1 || rx < -1 || rx > 1 || ry < -1 || ry > 1 || (rx == 0 && ry == 0))
+        return set_err(SGM_EINVAL, "bad walk arguments");
+    const sgm::Dir d{rx, ry};
+    if (slice < 0 || slice >= sgm::slice_count(width, height, d)) return set_err(SGM_EINVAL, "slice out of range");
+    const int steps = sgm::slice_steps(width, height, d);
+    sgm::Walk w = sgm::walk_start(width, height, d, slice);
+    int n = 0;
+    for (int k = 0; k < steps && n < max_steps; ++k) {
+        if (k) sgm::walk_next(width, w, d);
+        if (xs) xs[n] = w.x;
+        if (ys) ys[n] = w.y;
+        if (restart) restart[n] = w.restart ? 1 : 0;
+        ++n;
+    }
+    return n;
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// Shapes, workspace layout and launch entry points of one SGM pipeline.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "sgm_common.h"
+
+namespace sgm {
+
+// Everything a launch needs to know about one stereo pair's pipeline.
+struct Plan {
+    int W = 0, H = 0, D = 0;   // image size, disparity levels
+    int Dp = 0, cpl = 0;       // padded levels (64 * cells per lane)
+    int P1 = 0, P2 = 0;
+    int n_paths = 0;
+    int cw = 9, ch = 7;        // census window
+    bool csct = false;         // center-symmetric census (Eq. 1)
+    bool median = false, lrcheck = false;
+    int lr_thr = 1;
+    int cmax = 0;              // largest matching cost
+    bool l16 = false;          // L_r stored as u16 (else u8: Cmax + P2 <= 255)
+};
+
+// Device workspace of one pair.  All buffers are row-major, d fastest.
+struct Workspace {
+    uint8_t* cost = nullptr;   // C   u8 [H][W][Dp]
+    void* lbuf = nullptr;      // L_r u8|u16 [n_paths][H][W][Dp]
+    uint16_t* dl = nullptr;    // raw left disparity  u16 [H][W]
+    uint16_t* dr = nullptr;    // raw right disparity u16 [H][W]
+};
+
+// Fills the derived fields of a plan; returns false if invalid (message set).
+bool plan_finish(Plan& p, const char** why);
+size_t workspace_bytes(const Plan& p);
+// Carves a workspace out of one device allocation of workspace_bytes(p).
+Workspace workspace_carve(const Plan& p, void* base);
+
+// Enqueue the stages (all asynchronous on `stream`).
+hipError_t launch_census_cost(const Plan& p, const Workspace& ws, const uint8_t* left,
+                              const uint8_t* right, hipStream_t stream);
+hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stream);
+hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream);
+hipError_t launch_post(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream);
+// Stages of one pipeline pass, in launch order.
+enum Stage { kStageCensusCost = 0, kStageAggregate = 1, kStageWta = 2, kStagePost = 3, kNumStages = 4 };
+
+// `events` (optional, kNumStages + 1 entries) are recorded on `stream` before
+// the first stage and after each stage.
+hipError_t launch_pipeline(const Plan& p, const Workspace& ws, const uint8_t* left,
+                           const uint8_t* right, uint16_t* out, hipStream_t stream,
+                           hipEvent_t* events = nullptr);
+
+// Debug taps.
+hipError_t launch_census_only(const Plan& p, const uint8_t* img, uint64_t* out,
+                              hipStream_t stream);
+hipError_t launch_sum_planes(const Plan& p, const Workspace& ws, uint16_t* s_out,
+                             hipStream_t stream);
+
+}  // namespace sgm

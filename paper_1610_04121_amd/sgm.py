@@ -1,0 +1,209 @@
+"""Thin ctypes binding of the SGM C ABI (include/sgm.h).
+
+Only argument marshalling lives here: tensors are passed as device pointers
+and every step of the pipeline runs in the HIP library.  There is no CPU
+fallback; if ``libsgm.so`` is missing or cannot be loaded the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsgm.so")
+
+SGM_OK, SGM_EINVAL, SGM_ENOMEM, SGM_EHIP, SGM_EBUSY, SGM_ECANCELED = 0, -1, -2, -3, -4, -5
+MEDIAN3, LRCHECK, CENSUS_CSCT = 1, 2, 4
+INVALID = 0xFFFF
+
+EXPORTS = [
+    "sgm_validate", "sgm_create", "sgm_set_options", "sgm_compute", "sgm_destroy",
+    "sgm_last_error", "sgm_footprint_bytes", "sgm_debug_census", "sgm_debug_sums",
+    "sgm_debug_raw_disparity", "sgm_path_walk", "sgm_profile_enable", "sgm_profile_read",
+]
+STAGES = ("census_cost", "aggregate", "wta", "post")
+
+
+class SGMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sgm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libsgm.so (torch is imported first so that the process has one
+    HIP runtime: the one torch ships)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_1610_04121_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i, u = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint
+    L.sgm_validate.argtypes = [i, i, i, i, i, i, i, i, u]
+    L.sgm_validate.restype = i
+    L.sgm_create.argtypes = [i, i, i, i, i, i, i, i]
+    L.sgm_create.restype = P
+    L.sgm_set_options.argtypes = [P, u, i]
+    L.sgm_set_options.restype = i
+    L.sgm_compute.argtypes = [P, P, P, P, P]
+    L.sgm_compute.restype = i
+    L.sgm_destroy.argtypes = [P]
+    L.sgm_destroy.restype = None
+    L.sgm_last_error.argtypes = []
+    L.sgm_last_error.restype = ctypes.c_char_p
+    L.sgm_footprint_bytes.argtypes = [i, i, i, i, u]
+    L.sgm_footprint_bytes.restype = ctypes.c_size_t
+    L.sgm_debug_census.argtypes = [P, P, P, P]
+    L.sgm_debug_census.restype = i
+    L.sgm_debug_sums.argtypes = [P, P, P, P, P]
+    L.sgm_debug_sums.restype = i
+    L.sgm_debug_raw_disparity.argtypes = [P, P, P, P, P, P]
+    L.sgm_debug_raw_disparity.restype = i
+    L.sgm_path_walk.argtypes = [i, i, i, i, i, i, P, P, P]
+    L.sgm_path_walk.restype = i
+    L.sgm_profile_enable.argtypes = [P, i]
+    L.sgm_profile_enable.restype = i
+    L.sgm_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+    L.sgm_profile_read.restype = i
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().sgm_last_error().decode()
+
+
+def _check(rc: int):
+    if rc < 0:
+        raise SGMError(rc, last_error())
+    return rc
+
+
+def validate(width, height, max_disp, P1=7, P2=86, n_paths=4, census_w=9, census_h=7, flags=0) -> int:
+    return lib().sgm_validate(width, height, max_disp, P1, P2, n_paths, census_w, census_h, flags)
+
+
+def footprint_bytes(width, height, max_disp, n_paths=4, flags=0) -> int:
+    return lib().sgm_footprint_bytes(width, height, max_disp, n_paths, flags)
+
+
+def path_walk(width, height, rx, ry, slice_index):
+    """(xs, ys, restart) of the pixels one aggregation slice visits."""
+    import numpy as np
+    n = max(width, height)
+    xs = np.zeros(n, dtype=np.int32)
+    ys = np.zeros(n, dtype=np.int32)
+    rs = np.zeros(n, dtype=np.uint8)
+    k = _check(lib().sgm_path_walk(width, height, rx, ry, slice_index, n,
+                                   xs.ctypes.data, ys.ctypes.data, rs.ctypes.data))
+    return xs[:k], ys[:k], rs[:k].astype(bool)
+
+
+def _ptr(t, dtype_name: str, shape=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if str(t.dtype) != dtype_name:
+        raise TypeError(f"expected {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class SGM:
+    """One context: a fixed image size and parameter set.
+
+    ``compute(left, right, out)`` enqueues the pipeline on the current torch
+    stream (or ``stream``) and returns ``out`` (u16 [H][W])."""
+
+    def __init__(self, width, height, max_disp, P1=7, P2=86, n_paths=4, census_w=9, census_h=7,
+                 median=False, lrcheck=False, csct=False, lr_threshold=1):
+        self.width, self.height, self.max_disp = width, height, max_disp
+        self.n_paths = n_paths
+        self._ctx = lib().sgm_create(width, height, max_disp, P1, P2, n_paths, census_w, census_h)
+        if not self._ctx:
+            raise SGMError(SGM_EINVAL, last_error())
+        self.set_options(median=median, lrcheck=lrcheck, csct=csct, lr_threshold=lr_threshold)
+
+    def set_options(self, median=False, lrcheck=False, csct=False, lr_threshold=1):
+        flags = (MEDIAN3 if median else 0) | (LRCHECK if lrcheck else 0) | (CENSUS_CSCT if csct else 0)
+        _check(lib().sgm_set_options(self._ctx, flags, lr_threshold))
+
+    @property
+    def shape(self):
+        return (self.height, self.width)
+
+    def compute(self, left, right, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.uint16, device=left.device)
+        _check(lib().sgm_compute(self._ctx, _ptr(left, "torch.uint8", self.shape),
+                                 _ptr(right, "torch.uint8", self.shape),
+                                 _ptr(out, "torch.uint16", self.shape), _stream(stream)))
+        return out
+
+    def debug_census(self, img, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.uint64, device=img.device)
+        _check(lib().sgm_debug_census(self._ctx, _ptr(img, "torch.uint8", self.shape),
+                                      _ptr(out, "torch.uint64", self.shape), _stream(stream)))
+        return out
+
+    def debug_sums(self, left, right, out=None, stream=None):
+        import torch
+        shape = (self.height, self.width, self.max_disp)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.uint16, device=left.device)
+        _check(lib().sgm_debug_sums(self._ctx, _ptr(left, "torch.uint8", self.shape),
+                                    _ptr(right, "torch.uint8", self.shape),
+                                    _ptr(out, "torch.uint16", shape), _stream(stream)))
+        return out
+
+    def debug_raw_disparity(self, left, right, stream=None):
+        import torch
+        dl = torch.empty(self.shape, dtype=torch.uint16, device=left.device)
+        dr = torch.empty(self.shape, dtype=torch.uint16, device=left.device)
+        _check(lib().sgm_debug_raw_disparity(self._ctx, _ptr(left, "torch.uint8", self.shape),
+                                             _ptr(right, "torch.uint8", self.shape),
+                                             _ptr(dl, "torch.uint16", self.shape),
+                                             _ptr(dr, "torch.uint16", self.shape), _stream(stream)))
+        return dl, dr
+
+    def profile(self, enable: bool = True):
+        """Record per-stage HIP events in every compute() call."""
+        _check(lib().sgm_profile_enable(self._ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        """(calls, {stage: total ms}) over the calls recorded since the last read."""
+        ms = (ctypes.c_double * len(STAGES))()
+        n = ctypes.c_int(0)
+        _check(lib().sgm_profile_read(self._ctx, ms, ctypes.byref(n)))
+        return n.value, dict(zip(STAGES, list(ms)))
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().sgm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

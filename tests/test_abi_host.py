@@ -1,0 +1,137 @@
+"""Host-side checks of the C ABI library: it loads, exports what the header
+declares, validates parameters, and its slice scheduler follows the paper's
+worked example.  No compute call is made here (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT, gpu_available
+from paper_1610_04121_amd import sgm
+
+HEADER = os.path.join(ROOT, "include", "sgm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(sgm_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(sgm.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return sgm.lib()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    declared = _declared_functions()
+    assert len(declared) >= 10
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(sgm.EXPORTS) | (set(declared) - set(sgm.EXPORTS))
+    for name in sgm.EXPORTS:
+        assert name in declared, f"{name} exported by the binding but not declared"
+
+
+def test_validate_accepts_the_workload_shapes(lib):
+    assert sgm.validate(320, 240, 64, 7, 86, 4) == 0
+    assert sgm.validate(640, 480, 128, 7, 86, 4, flags=sgm.MEDIAN3 | sgm.LRCHECK) == 0
+    assert sgm.validate(1242, 375, 128, 7, 86, 8) == 0
+    assert sgm.validate(1920, 1080, 256, 7, 86, 8) == 0
+    assert sgm.validate(1, 1, 1, 0, 0, 2) == 0
+
+
+@pytest.mark.parametrize("args,frag", [
+    ((0, 10, 8, 7, 86, 4, 9, 7, 0), "width"),
+    ((10, 0, 8, 7, 86, 4, 9, 7, 0), "height"),
+    ((10, 10, 0, 7, 86, 4, 9, 7, 0), "max_disp"),
+    ((10, 10, 257, 7, 86, 4, 9, 7, 0), "max_disp"),
+    ((10, 10, 8, 7, 86, 3, 9, 7, 0), "n_paths"),
+    ((10, 10, 8, 7, 86, 4, 8, 7, 0), "odd"),
+    ((10, 10, 8, 7, 86, 4, 9, 9, 0), "64 pixels"),
+    ((10, 10, 8, -1, 86, 4, 9, 7, 0), "P1"),
+    ((10, 10, 8, 7, -2, 4, 9, 7, 0), "P1 and P2"),
+    ((10, 10, 8, 7, 8200, 8, 9, 7, 0), "65535"),
+    ((10, 10, 8, 7, 86, 4, 9, 7, 64), "flag"),
+    ((20000, 10, 8, 7, 86, 4, 9, 7, 0), "width"),
+])
+def test_validate_rejects(lib, args, frag):
+    assert sgm.validate(*args) == sgm.SGM_EINVAL
+    assert frag in sgm.last_error()
+
+
+def test_overflow_bound_is_exact(lib):
+    # n_paths * (Cmax + P2) <= 65535 with Cmax = 62 (9x7 full census)
+    p2_max = 65535 // 8 - 62
+    assert sgm.validate(64, 64, 64, 7, p2_max, 8) == 0
+    assert sgm.validate(64, 64, 64, 7, p2_max + 1, 8) == sgm.SGM_EINVAL
+    # CSCT: Cmax = 31
+    assert sgm.validate(64, 64, 64, 7, 65535 // 8 - 31, 8, flags=sgm.CENSUS_CSCT) == 0
+
+
+def test_footprint_counts_cost_and_paths(lib):
+    f4 = sgm.footprint_bytes(640, 480, 128, 4)
+    f8 = sgm.footprint_bytes(640, 480, 128, 8)
+    cells = 640 * 480 * 128
+    assert f4 >= cells * (1 + 4)
+    assert f8 - f4 >= 4 * cells
+    assert sgm.footprint_bytes(0, 480, 128, 4) == 0
+
+
+def _golden_walk():
+    rows = []
+    for line in open(os.path.join(ROOT, "tests", "golden", "diag_wrap_example.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        x, y, r = line.split()
+        rows.append((x, int(y), int(r)))
+    return rows
+
+
+@pytest.mark.parametrize("W,H", [(640, 480), (320, 240), (1242, 375)])
+def test_diagonal_wrap_matches_the_papers_example(lib, W, H):
+    xs, ys, rs = sgm.path_walk(W, H, -1, 1, 100)
+    assert len(xs) == H
+    for xstr, y, r in _golden_walk():
+        x = eval(xstr, {"W": W})
+        assert ys[y] == y and xs[y] == x and int(rs[y]) == r, (xstr, y)
+    # no other restart before row 101
+    assert not rs[1:101].any()
+
+
+@pytest.mark.parametrize("W,H", [(7, 5), (5, 7), (1, 4), (6, 1), (33, 17)])
+def test_slices_cover_every_pixel_once_and_restart_at_path_starts(lib, W, H):
+    for rx, ry in [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, 1), (1, -1), (-1, -1)]:
+        n_slices = H if ry == 0 else W
+        seen = np.zeros((H, W), dtype=int)
+        for s in range(n_slices):
+            xs, ys, rs = sgm.path_walk(W, H, rx, ry, s)
+            for k in range(len(xs)):
+                x, y = xs[k], ys[k]
+                seen[y, x] += 1
+                # a restart happens exactly where the predecessor p - r is
+                # outside the image, i.e. where a textbook path starts
+                px, py = x - rx, y - ry
+                outside = not (0 <= px < W and 0 <= py < H)
+                assert bool(rs[k]) == outside, (rx, ry, s, k)
+                if not outside:
+                    assert (xs[k - 1], ys[k - 1]) == (px, py)
+        assert (seen == 1).all()
+
+
+def test_create_without_gpu_fails_cleanly(lib):
+    if gpu_available():
+        pytest.skip("a GPU is present")
+    lib.sgm_create.restype = ctypes.c_void_p
+    ctx = lib.sgm_create(64, 48, 16, 7, 86, 4, 9, 7)
+    assert not ctx
+    assert sgm.last_error()
+    # invalid parameters are rejected before any HIP call
+    assert not lib.sgm_create(0, 48, 16, 7, 86, 4, 9, 7)
+    assert "width" in sgm.last_error()

@@ -1,0 +1,150 @@
+"""Parity of the HIP pipeline (through the C ABI) with the CPU oracle.
+
+All arithmetic is integer, so every comparison is exact equality.  Stage
+taps (census words, summed costs S, raw left/right disparities) localise a
+mismatch; the whole-pipeline cases cover the benchmark workloads at full size
+and a seeded fuzz over shapes, disparity ranges, path counts, census kinds,
+penalties and post-filters, including the degenerate cases (1-pixel-wide or
+-tall images, more disparities than columns, D = 1, D = 256).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1610_04121_amd import SGM, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rand_pair(rng, W, H):
+    return (rng.integers(0, 256, (H, W), dtype=np.uint8),
+            rng.integers(0, 256, (H, W), dtype=np.uint8))
+
+
+@pytest.mark.parametrize("W,H,cw,ch,csct", [
+    (40, 30, 9, 7, False), (40, 30, 9, 7, True), (5, 3, 9, 7, False), (1, 1, 9, 7, True),
+    (300, 17, 9, 7, False), (33, 21, 5, 5, True), (33, 21, 7, 9, False), (70, 3, 3, 3, False),
+])
+def test_census_parity(gpu, W, H, cw, ch, csct):
+    rng = np.random.default_rng(W * 1000 + H + cw)
+    img = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    img[: H // 2, : W // 2] = 77  # ties
+    _say(f"census {W}x{H} {cw}x{ch} csct={csct}")
+    s = SGM(W, H, 8, 7, 86, 4, cw, ch, csct=csct)
+    got = _np(s.debug_census(_t(img, gpu)))
+    s.close()
+    want = oracle.census(img, cw, ch, csct)
+    assert (got == want).all()
+
+
+@pytest.mark.parametrize("W,H,D,P,csct,P1,P2", [
+    (37, 23, 16, 4, False, 7, 86), (29, 31, 20, 8, True, 3, 40), (64, 40, 64, 4, False, 7, 86),
+    (50, 45, 130, 8, False, 7, 86), (21, 70, 9, 2, False, 0, 0), (70, 9, 256, 8, False, 10, 300),
+    (1, 9, 5, 8, False, 7, 86), (9, 1, 12, 8, True, 7, 86), (3, 3, 1, 4, False, 7, 86),
+])
+def test_summed_costs_parity(gpu, W, H, D, P, csct, P1, P2):
+    rng = np.random.default_rng(W * 7 + H * 13 + D)
+    l, r = _rand_pair(rng, W, H)
+    _say(f"sums {W}x{H} D={D} P={P} csct={csct} P1={P1} P2={P2}")
+    s = SGM(W, H, D, P1, P2, P, csct=csct)
+    got = _np(s.debug_sums(_t(l, gpu), _t(r, gpu)))
+    s.close()
+    want = oracle.sgm(l, r, D, P1, P2, P, csct=csct, keep_sums=True).S
+    assert got.shape == want.shape
+    bad = np.argwhere(got != want)
+    assert len(bad) == 0, f"{len(bad)} cells differ, first {bad[:5].tolist()}"
+
+
+@pytest.mark.parametrize("W,H,D,P", [(41, 27, 24, 4), (66, 19, 70, 8), (8, 12, 30, 4)])
+def test_raw_disparity_parity(gpu, W, H, D, P):
+    rng = np.random.default_rng(W + H + D)
+    l, r = _rand_pair(rng, W, H)
+    _say(f"raw disparity {W}x{H} D={D} P={P}")
+    s = SGM(W, H, D, 7, 86, P)
+    dl, dr = s.debug_raw_disparity(_t(l, gpu), _t(r, gpu))
+    dl, dr = _np(dl), _np(dr)
+    s.close()
+    want = oracle.sgm(l, r, D, 7, 86, P, lr=True)
+    assert (dl == want.dl_raw).all()
+    assert (dr == want.dr_raw).all()
+
+
+@pytest.mark.parametrize("name", list(synth.WORKLOADS))
+def test_workload_full_size_bit_exact(gpu, name):
+    cfg = synth.WORKLOADS[name]
+    pair = synth.workload_pair(name)
+    _say(f"workload {name}")
+    s = SGM(cfg["w"], cfg["h"], cfg["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, cfg["n_paths"],
+            median=cfg["median"], lrcheck=cfg["lr"])
+    got = _np(s.compute(_t(pair.left, gpu), _t(pair.right, gpu)))
+    s.close()
+    want = oracle.sgm(pair.left, pair.right, cfg["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT,
+                      cfg["n_paths"], median=cfg["median"], lr=cfg["lr"]).out
+    bad = np.argwhere(got != want)
+    assert len(bad) == 0, f"{len(bad)} pixels differ, first {bad[:5].tolist()}"
+
+
+@pytest.mark.parametrize("trial", range(24))
+def test_fuzz_pipeline(gpu, trial):
+    rng = np.random.default_rng(9000 + trial)
+    W, H = int(rng.integers(1, 71)), int(rng.integers(1, 71))
+    D = int(rng.integers(1, 131)) if trial % 6 else int(rng.choice([1, 64, 128, 256]))
+    P = int(rng.choice([2, 4, 8]))
+    csct = bool(rng.integers(0, 2))
+    cmax = 31 if csct else 62
+    P1 = int(rng.integers(0, 20))
+    P2 = int(rng.integers(0, 65535 // P - cmax + 1)) if trial % 4 == 3 else int(rng.integers(P1, 200))
+    med, lr = bool(rng.integers(0, 2)), bool(rng.integers(0, 2))
+    thr = int(rng.integers(0, 3))
+    l, r = _rand_pair(rng, W, H)
+    if trial % 5 == 0:
+        l = (l // 64 * 64).astype(np.uint8)  # many ties
+    _say(f"fuzz {trial}: {W}x{H} D={D} P={P} csct={csct} P1={P1} P2={P2} med={med} lr={lr} thr={thr}")
+    s = SGM(W, H, D, P1, P2, P, median=med, lrcheck=lr, csct=csct, lr_threshold=thr)
+    got = _np(s.compute(_t(l, gpu), _t(r, gpu)))
+    s.close()
+    want = oracle.sgm(l, r, D, P1, P2, P, median=med, lr=lr, csct=csct, lr_thr=thr).out
+    assert (got == want).all()
+
+
+def test_repeat_and_two_contexts_identical(gpu):
+    pair = synth.make_pair(200, 120, 48, "RS", seed=77)
+    _say("repeatability 200x120 D=48")
+    a = SGM(200, 120, 48, 7, 86, 8, median=True, lrcheck=True)
+    b = SGM(200, 120, 48, 7, 86, 8, median=True, lrcheck=True)
+    l, r = _t(pair.left, gpu), _t(pair.right, gpu)
+    o1 = _np(a.compute(l, r))
+    o2 = _np(a.compute(l, r))
+    o3 = _np(b.compute(l, r))
+    a.close()
+    b.close()
+    assert (o1 == o2).all() and (o1 == o3).all()
+
+
+def test_invalid_calls_raise_before_enqueue(gpu):
+    import torch
+    from paper_1610_04121_amd import SGMError
+    with pytest.raises(SGMError):
+        SGM(0, 10, 8)
+    s = SGM(32, 16, 8)
+    l = torch.zeros((16, 32), dtype=torch.uint8, device=gpu)
+    with pytest.raises(ValueError):
+        s.compute(l, torch.zeros((16, 31), dtype=torch.uint8, device=gpu))
+    with pytest.raises(SGMError):
+        s.set_options(lr_threshold=-1)
+    s.close()
