@@ -117,6 +117,13 @@ int sgm_debug_census(sgm_ctx *ctx, const uint8_t *img, uint64_t *census_out,
 int sgm_debug_sums(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right, uint16_t *s_out,
                    sgm_stream_t stream);
 
+/* One intermediate as u16 [H][W][max_disp] (d fastest): which = -1 gives the
+ * matching cost C (Eq. 2); which = r in [0, n_paths) gives L_r of path
+ * direction r (Eq. 3), directions numbered as for sgm_create: (1,0), (-1,0),
+ * (0,1), (0,-1), (1,1), (-1,1), (1,-1), (-1,-1); with 2 paths (1,0), (0,1). */
+int sgm_debug_stage(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right, int which,
+                    uint16_t *out, sgm_stream_t stream);
+
 /* Raw (before median / LR) left and right disparity maps, u16 [H][W] each. */
 int sgm_debug_raw_disparity(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right,
                             uint16_t *dl_out, uint16_t *dr_out, sgm_stream_t stream);

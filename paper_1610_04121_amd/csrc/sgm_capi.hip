@@ -219,6 +219,19 @@ int sgm_debug_sums(sgm_ctx* c, const uint8_t* left, const uint8_t* right, uint16
     return SGM_OK;
 }
 
+int sgm_debug_stage(sgm_ctx* c, const uint8_t* left, const uint8_t* right, int which, uint16_t* out,
+                    sgm_stream_t stream) {
+    if (!c) return set_err(SGM_EINVAL, "null context");
+    if (int rc = check_ptrs(left, right, out)) return rc;
+    if (which < -1 || which >= c->plan.n_paths) return set_err(SGM_EINVAL, "stage index out of range");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = sgm::launch_census_cost(c->plan, c->ws, left, right, s);
+    if (e == hipSuccess && which >= 0) e = sgm::launch_aggregate(c->plan, c->ws, s);
+    if (e == hipSuccess) e = sgm::launch_extract_plane(c->plan, c->ws, which, out, s);
+    if (e != hipSuccess) return hip_err(e, "kernel launch");
+    return SGM_OK;
+}
+
 int sgm_debug_raw_disparity(sgm_ctx* c, const uint8_t* left, const uint8_t* right, uint16_t* dl_out,
                             uint16_t* dr_out, sgm_stream_t stream) {
     if (!c) return set_err(SGM_EINVAL, "null context");

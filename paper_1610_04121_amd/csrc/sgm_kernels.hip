@@ -181,6 +181,8 @@ constexpr int kDppWaveShl1 = 0x130;  // lane i reads lane i+1
 constexpr int kDppWaveShr1 = 0x138;  // lane i reads lane i-1
 constexpr int kDppRowMirror = 0x140;
 constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
 
 // Lane i receives lane i-1's (from_lower) or lane i+1's (from_upper) value;
 // the lane without a source receives 0, which the caller ORs with kBig.
@@ -191,25 +193,20 @@ __device__ inline uint32_t from_upper_lane(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppWaveShl1, 0xF, 0xF, true);
 }
 
-__device__ inline uint32_t smin(uint32_t a, uint32_t b) {
-    uint32_t r;
-    asm("s_min_u32 %0, %1, %2" : "=s"(r) : "s"(a), "s"(b));
-    return r;
-}
-
 // Minimum over the 64 lanes as a wave-uniform (scalar) value: a butterfly
 // inside each row of 16 lanes (DPP quad permutes and mirrors, folded into
-// v_min_u32_dpp), then the four row minima are combined on the scalar unit.
+// v_min_u32_dpp), then row broadcasts carry row 0's minimum into row 1 and
+// row 2's into row 3, and rows 0-1's into rows 2-3; lane 63 ends with the
+// minimum of all 64 lanes.  Lanes outside a broadcast's row mask keep their
+// value (min(v, v) = v).
 __device__ inline uint32_t wave_min(uint32_t v) {
     v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppQuadPerm1032, 0xF, 0xF, true));
     v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppQuadPerm2301, 0xF, 0xF, true));
     v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowHalfMirror, 0xF, 0xF, true));
     v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowMirror, 0xF, 0xF, true));
-    const uint32_t a = __builtin_amdgcn_readlane((int)v, 15);
-    const uint32_t b = __builtin_amdgcn_readlane((int)v, 31);
-    const uint32_t c = __builtin_amdgcn_readlane((int)v, 47);
-    const uint32_t d = __builtin_amdgcn_readlane((int)v, 63);
-    return smin(smin(a, b), smin(c, d));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kDppRowBcast15, 0xA, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kDppRowBcast31, 0xC, 0xF, false));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 template <int CPL> struct RawCost;
@@ -296,6 +293,8 @@ __device__ inline void aggregate_slice(const uint8_t* __restrict__ cost, LT* __r
     for (int c = 0; c < CPL; ++c) pad[c] = (PAD && lofs + c >= D) ? kBig : 0u;
 
     uint32_t L[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) L[c] = 0;
     uint32_t m = 0;
     // one step of Eq. 3 at the walker's pixel, then advance the walker
     auto step = [&](uint32_t raw) {
@@ -327,26 +326,31 @@ __device__ inline void aggregate_slice(const uint8_t* __restrict__ cost, LT* __r
         w.next();
     };
 
-    // ring[j] holds the raw costs of the step that is congruent to j
-    // modulo kPrefetch; the walker `ahead` runs kPrefetch - 1 steps ahead.
+    // ring[j] holds the raw costs of the step congruent to j modulo
+    // kPrefetch.  The walker `ahead` leads by kPrefetch - 1 steps and stops at
+    // the slice's last pixel, so every load is unconditional and in bounds
+    // (loads past the end re-read the last pixel and are never consumed).
     uint32_t ring[kPrefetch];
     Walker<KIND> ahead = w;
+    int ahead_k = 0;  // step index of `ahead`
+    auto advance_ahead = [&]() {
+        if (ahead_k + 1 < steps) {
+            ahead.next();
+            ++ahead_k;
+        }
+    };
 #pragma unroll
     for (int j = 0; j < kPrefetch; ++j) {
-        if (j < steps) {
-            if (j) ahead.next();
-            ring[j] = load(ahead.po);
-        }
+        if (j) advance_ahead();
+        ring[j] = load(ahead.po);
     }
     int k = 0;
     for (; k + kPrefetch <= steps; k += kPrefetch) {
 #pragma unroll
         for (int j = 0; j < kPrefetch; ++j) {
             const uint32_t raw = ring[j];
-            if (k + j + kPrefetch < steps) {
-                ahead.next();
-                ring[j] = load(ahead.po);
-            }
+            advance_ahead();
+            ring[j] = load(ahead.po);
             step(raw);
         }
     }
@@ -526,6 +530,16 @@ __global__ void sum_planes_kernel(const void* lbuf, size_t plane, uint16_t* s, i
     }
 }
 
+// Debug tap: one L_r plane (or the cost volume) as u16 [H][W][D].
+template <typename LT>
+__global__ void extract_plane_kernel(const LT* src, uint16_t* out, int W, int H, int D, int Dp) {
+    const size_t n = (size_t)W * H * D;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t p = i / D, d = i - p * D;
+        out[i] = (uint16_t)src[p * Dp + d];
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -698,6 +712,21 @@ hipError_t launch_sum_planes(const Plan& p, const Workspace& ws, uint16_t* s_out
     else
         hipLaunchKernelGGL(sum_planes_kernel<uint8_t>, dim3(1024), dim3(256), 0, stream, ws.lbuf, plane, s_out,
                            p.W, p.H, p.D, p.Dp, p.n_paths);
+    return hipGetLastError();
+}
+
+hipError_t launch_extract_plane(const Plan& p, const Workspace& ws, int plane, uint16_t* out,
+                                hipStream_t stream) {
+    const size_t cells = (size_t)p.W * p.H * p.Dp;
+    if (plane < 0)
+        hipLaunchKernelGGL(extract_plane_kernel<uint8_t>, dim3(1024), dim3(256), 0, stream, ws.cost, out, p.W, p.H,
+                           p.D, p.Dp);
+    else if (p.l16)
+        hipLaunchKernelGGL(extract_plane_kernel<uint16_t>, dim3(1024), dim3(256), 0, stream,
+                           reinterpret_cast<const uint16_t*>(ws.lbuf) + cells * plane, out, p.W, p.H, p.D, p.Dp);
+    else
+        hipLaunchKernelGGL(extract_plane_kernel<uint8_t>, dim3(1024), dim3(256), 0, stream,
+                           reinterpret_cast<const uint8_t*>(ws.lbuf) + cells * plane, out, p.W, p.H, p.D, p.Dp);
     return hipGetLastError();
 }
 

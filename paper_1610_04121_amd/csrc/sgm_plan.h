@@ -56,5 +56,9 @@ hipError_t launch_census_only(const Plan& p, const uint8_t* img, uint64_t* out,
                               hipStream_t stream);
 hipError_t launch_sum_planes(const Plan& p, const Workspace& ws, uint16_t* s_out,
                              hipStream_t stream);
+// Copies plane `plane` of L_r (or the cost volume when plane < 0) out as u16
+// [H][W][D].
+hipError_t launch_extract_plane(const Plan& p, const Workspace& ws, int plane, uint16_t* out,
+                                hipStream_t stream);
 
 }  // namespace sgm

@@ -20,6 +20,7 @@ EXPORTS = [
     "sgm_validate", "sgm_create", "sgm_set_options", "sgm_compute", "sgm_destroy",
     "sgm_last_error", "sgm_footprint_bytes", "sgm_debug_census", "sgm_debug_sums",
     "sgm_debug_raw_disparity", "sgm_path_walk", "sgm_profile_enable", "sgm_profile_read",
+    "sgm_debug_stage",
 ]
 STAGES = ("census_cost", "aggregate", "wta", "post")
 
@@ -69,6 +70,8 @@ def lib() -> ctypes.CDLL:
     L.sgm_debug_raw_disparity.restype = i
     L.sgm_path_walk.argtypes = [i, i, i, i, i, i, P, P, P]
     L.sgm_path_walk.restype = i
+    L.sgm_debug_stage.argtypes = [P, P, P, i, P, P]
+    L.sgm_debug_stage.restype = i
     L.sgm_profile_enable.argtypes = [P, i]
     L.sgm_profile_enable.restype = i
     L.sgm_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
@@ -174,6 +177,16 @@ class SGM:
         _check(lib().sgm_debug_sums(self._ctx, _ptr(left, "torch.uint8", self.shape),
                                     _ptr(right, "torch.uint8", self.shape),
                                     _ptr(out, "torch.uint16", shape), _stream(stream)))
+        return out
+
+    def debug_stage(self, left, right, which, stream=None):
+        """which = -1: cost volume C; which = r: L_r of direction r (u16 [H][W][D])."""
+        import torch
+        shape = (self.height, self.width, self.max_disp)
+        out = torch.empty(shape, dtype=torch.uint16, device=left.device)
+        _check(lib().sgm_debug_stage(self._ctx, _ptr(left, "torch.uint8", self.shape),
+                                     _ptr(right, "torch.uint8", self.shape), which,
+                                     _ptr(out, "torch.uint16", shape), _stream(stream)))
         return out
 
     def debug_raw_disparity(self, left, right, stream=None):

@@ -52,6 +52,29 @@ def test_census_parity(gpu, W, H, cw, ch, csct):
     assert (got == want).all()
 
 
+@pytest.mark.parametrize("W,H,D,P,csct", [
+    (37, 23, 16, 4, False), (29, 31, 20, 8, True), (70, 9, 130, 8, False), (5, 1, 256, 2, False),
+])
+def test_cost_and_per_direction_parity(gpu, W, H, D, P, csct):
+    rng = np.random.default_rng(W * 3 + H + D)
+    l, r = _rand_pair(rng, W, H)
+    _say(f"stages {W}x{H} D={D} P={P} csct={csct}")
+    s = SGM(W, H, D, 7, 86, P, csct=csct)
+    tl, tr = _t(l, gpu), _t(r, gpu)
+    cost = _np(s.debug_stage(tl, tr, -1))
+    cl, cr = oracle.census(l, csct=csct), oracle.census(r, csct=csct)
+    mc = oracle.cost_volume(cl, cr, D, oracle.cmax_of(csct=csct))
+    bad = np.argwhere(cost != mc)
+    assert len(bad) == 0, f"cost: {len(bad)} cells differ, first {bad[:5].tolist()}"
+    for k, (rx, ry) in enumerate(oracle.directions(P)):
+        got = _np(s.debug_stage(tl, tr, k))
+        want = oracle.aggregate(mc, 7, 86, rx, ry)
+        bad = np.argwhere(got != want)
+        assert len(bad) == 0, (f"L_r ({rx},{ry}): {len(bad)} cells differ, first {bad[:5].tolist()} "
+                               f"got {got[tuple(bad[0])] if len(bad) else None} want {want[tuple(bad[0])] if len(bad) else None}")
+    s.close()
+
+
 @pytest.mark.parametrize("W,H,D,P,csct,P1,P2", [
     (37, 23, 16, 4, False, 7, 86), (29, 31, 20, 8, True, 3, 40), (64, 40, 64, 4, False, 7, 86),
     (50, 45, 130, 8, False, 7, 86), (21, 70, 9, 2, False, 0, 0), (70, 9, 256, 8, False, 10, 300),
