@@ -59,9 +59,8 @@ __host__ __device__ inline void walk_next(int W, Walk& w, Dir r) {
     }
 }
 
-// Disparity levels are padded to a whole number of cells per lane of a
-// 64-wide wavefront: Dp = 64 * cells_per_lane, cells_per_lane in {1, 2, 4}.
-inline int cells_per_lane(int D) { return D <= 64 ? 1 : (D <= 128 ? 2 : 4); }
-inline int padded_disp(int D) { return 64 * cells_per_lane(D); }
+// Disparity levels are padded to Dp in {64, 128, 256}, so that a group of
+// 16, 32 or 64 lanes holds an even number of levels per lane.
+inline int padded_disp(int D) { return D <= 64 ? 64 : (D <= 128 ? 128 : 256); }
 
 }  // namespace sgm

@@ -10,14 +10,15 @@
 //   post_kernel         3x3 median and left-right consistency check.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "sgm_plan.h"
 
 namespace sgm {
 
 namespace {
 
-constexpr int kCostTX = 256;           // base pixels per census/cost block
-constexpr uint32_t kBig = 1u << 30;    // "no such neighbour" in Eq. 3's minimum
+constexpr int kCostTX = 128;           // base pixels per census/cost block
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -65,58 +66,84 @@ struct CostArgs {
     int W, H, D, Dp, rx, ry, cmax, csct;
 };
 
-// One block per (row y, run of kCostTX base pixels).  The right census is
-// needed from x0 - (D-1) on, because C(x, d) reads the match image at x - d.
+// Census of the centre (cx, ry) of an LDS tile, for compile-time window
+// radii (fully unrolled) or, with RX = RY = 0, for runtime radii.
+template <int RX, int RY>
+__device__ inline uint64_t tile_census(const uint8_t* t, int pitch, int cx, int rx, int ry, int csct) {
+    if constexpr (RX > 0) {
+        if (csct) return census_csct(t, pitch, cx, RX, RY);
+        return census_full(t, pitch, cx, RX, RY);
+    } else {
+        if (csct) return census_csct(t, pitch, cx, rx, ry);
+        return census_full(t, pitch, cx, rx, ry);
+    }
+}
+
+// One block per (row y, run of kCostTX base pixels).  Both images' rows
+// y-ry..y+ry are staged in LDS, census words go to LDS (the right image's
+// from x0 - (D-1) on, because C(x, d) reads the match image at x - d), and
+// each thread then writes 16 consecutive disparities of one pixel as one
+// 16-byte store; consecutive threads cover consecutive 16-byte runs.
+template <int RX, int RY>
 __global__ __launch_bounds__(256) void census_cost_kernel(CostArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     const int y = blockIdx.y;
     const int x0 = blockIdx.x * kCostTX;
+    const int rx = RX > 0 ? RX : a.rx, ry = RX > 0 ? RY : a.ry;
     const int nright = kCostTX + a.D - 1;
-    const int xs = x0 - (a.D - 1) - a.rx;
-    const int ncol = nright + 2 * a.rx;
-    const int nrow = 2 * a.ry + 1;
+    const int xs = x0 - (a.D - 1) - rx;
+    const int ncol = nright + 2 * rx;
+    const int nrow = 2 * ry + 1;
     uint64_t* cl = reinterpret_cast<uint64_t*>(smem);
     uint64_t* cr = cl + kCostTX;
     uint8_t* tl = reinterpret_cast<uint8_t*>(cr + nright);
     uint8_t* tr = tl + nrow * ncol;
 
-    for (int i = threadIdx.x; i < nrow * ncol; i += blockDim.x) {
-        const int j = i / ncol, c = i - j * ncol;
-        const size_t src = (size_t)clampi(y + j - a.ry, 0, a.H - 1) * a.W + clampi(xs + c, 0, a.W - 1);
-        tl[i] = a.left[src];
-        tr[i] = a.right[src];
+    for (int j = 0; j < nrow; ++j) {
+        const size_t row = (size_t)clampi(y + j - ry, 0, a.H - 1) * a.W;
+        for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+            const size_t src = row + clampi(xs + c, 0, a.W - 1);
+            tl[j * ncol + c] = a.left[src];
+            tr[j * ncol + c] = a.right[src];
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kCostTX + nright; i += blockDim.x) {
-        const bool is_left = i < kCostTX;
-        const int k = is_left ? i : i - kCostTX;
-        // tile column of the census centre
-        const int cx = is_left ? (x0 + k) - xs : (x0 - (a.D - 1) + k) - xs;
-        const uint8_t* t = is_left ? tl : tr;
-        const uint64_t w = a.csct ? census_csct(t, ncol, cx, a.rx, a.ry) : census_full(t, ncol, cx, a.rx, a.ry);
-        (is_left ? cl : cr)[k] = w;
-    }
+    for (int k = threadIdx.x; k < kCostTX; k += blockDim.x)
+        cl[k] = tile_census<RX, RY>(tl, ncol, k + (a.D - 1) + rx, rx, ry, a.csct);
+    for (int k = threadIdx.x; k < nright; k += blockDim.x)
+        cr[k] = tile_census<RX, RY>(tr, ncol, k + rx, rx, ry, a.csct);
     __syncthreads();
-    const int nq = a.Dp >> 2;  // 4 disparities per thread and store
-    for (int i = threadIdx.x; i < kCostTX * nq; i += blockDim.x) {
-        const int px = i / nq, q = i - px * nq;
+
+    const int gshift = a.Dp == 64 ? 2 : (a.Dp == 128 ? 3 : 4);  // log2(Dp / 16)
+    const int ngroups = a.Dp >> 4;
+    const int items = kCostTX << gshift;
+    for (int i = threadIdx.x; i < items; i += blockDim.x) {
+        const int px = i >> gshift, g = i & (ngroups - 1);
         const int x = x0 + px;
         if (x >= a.W) break;
         const uint64_t base = cl[px];
-        uint32_t word = 0;
+        const int d0 = 16 * g;
+        // cr index of disparity d is px - d + D - 1
+        const uint64_t* m = cr + (px - d0 + a.D - 1);
+        uint32_t w[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int d = 4 * q + j;
-            uint32_t c;
-            if (d >= a.D)
-                c = 0;
-            else if (x - d < 0)
-                c = a.cmax;  // no candidate in the match image
-            else
-                c = __popcll(base ^ cr[px - d + a.D - 1]);
-            word |= c << (8 * j);
+        for (int q = 0; q < 4; ++q) {
+            uint32_t word = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int d = d0 + 4 * q + j;
+                uint32_t c;
+                if (d >= a.D)
+                    c = 0;
+                else if (x - d < 0)
+                    c = a.cmax;  // no candidate in the match image
+                else
+                    c = __popcll(base ^ m[-(4 * q + j)]);
+                word |= c << (8 * j);
+            }
+            w[q] = word;
         }
-        *reinterpret_cast<uint32_t*>(a.cost + ((size_t)y * a.W + x) * a.Dp + 4 * q) = word;
+        *reinterpret_cast<uint4*>(a.cost + ((size_t)y * a.W + x) * a.Dp + d0) = make_uint4(w[0], w[1], w[2], w[3]);
     }
 }
 
@@ -150,19 +177,25 @@ __global__ __launch_bounds__(256) void census_only_kernel(const uint8_t* img, ui
 // ---------------------------------------------------------------------------
 // Aggregation (Eq. 3).
 //
-// A wavefront owns one slice (a scanline of one direction) and walks it
-// step by step; the recurrence forbids parallelism along the path (Sec. 3.2)
-// so the parallelism is slices x disparities x directions.  Lane l holds
-// disparities l*CPL .. l*CPL+CPL-1 of L_r(p - r, .) in registers.  Per step:
-//   lp      = L + P1                     (the d+-1 candidates of Eq. 3)
-//   R(d)    = min(L(d), lp(d-1), lp(d+1), m + P2)
-//   L'(d)   = C(p, d) + R(d) - m         (m = min_k L(p - r, k))
-//   m'      = min_d L'(d)                (wavefront min-reduction)
-// The d-1 / d+1 values of a lane's first / last cell come from the
-// neighbouring lanes through DPP row-crossing shifts; lanes without a
-// neighbour read kBig, which never wins the minimum.  A restart (path start)
-// sets L = 0 and m = 0, which makes L' = C exactly.  Padded levels d >= D add
-// kBig to their cost, so they stay >= kBig and never win or leak.
+// The recurrence forbids parallelism along a path (Sec. 3.2), so the work is
+// spread over slices x disparities x directions.  A group of G lanes (G in
+// {16, 32, 64}) owns one slice and walks it step by step; a wavefront holds
+// S = 64 / G slices of the same direction.  Lane q of a group holds the
+// disparities q*CPL .. q*CPL + CPL - 1 (CPL = Dp / G) of L_r(p - r, .) as
+// CPL/2 packed u16 pairs in a "split" layout: pair k holds disparities
+// q*CPL + k (low half) and q*CPL + k + CPL/2 (high half), so the d-1 / d+1
+// neighbours of pair k are pairs k-1 / k+1 of the same lane, except at the
+// lane's two ends, which take one DPP lane shift and one v_alignbit each.
+// Per step, in saturating u16 arithmetic:
+//   lp    = L + P1                          (the d+-1 candidates of Eq. 3)
+//   R(d)  = min(L(d), lp(d-1), lp(d+1), m + P2)
+//   L'(d) = R(d) - m + C(p, d)              (m = min_k L(p - r, k))
+//   m'    = min_d L'(d)                     (group min-reduction)
+// 0xFFFF stands for "no such disparity": the d-1 of d = 0, the d+1 of
+// d = D-1 and padded levels d >= D (their cost is 0xFFFF, so they stay
+// 0xFFFF).  Real values are at most Cmax + 2*P2 < 0xFFFF (validated), so
+// saturation never changes a result.  A path start sets L = 0 and m = 0,
+// which makes L' = C exactly.
 // ---------------------------------------------------------------------------
 struct AggArgs {
     const uint8_t* cost;
@@ -174,213 +207,322 @@ struct AggArgs {
     int rx[kMaxDirs], ry[kMaxDirs], plane_index[kMaxDirs];
 };
 
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ inline u16x2 as2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ inline uint32_t as1(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ inline u16x2 vmin(u16x2 a, u16x2 b) { return __builtin_elementwise_min(a, b); }
+__device__ inline u16x2 vadds(u16x2 a, u16x2 b) { return __builtin_elementwise_add_sat(a, b); }
+
 // DPP controls (GFX9 encoding).
 constexpr int kDppQuadPerm1032 = 0xB1;
 constexpr int kDppQuadPerm2301 = 0x4E;
+constexpr int kDppRowShl1 = 0x101;   // lane i reads lane i+1 within a row of 16
+constexpr int kDppRowShr1 = 0x111;   // lane i reads lane i-1 within a row of 16
 constexpr int kDppWaveShl1 = 0x130;  // lane i reads lane i+1
 constexpr int kDppWaveShr1 = 0x138;  // lane i reads lane i-1
 constexpr int kDppRowMirror = 0x140;
 constexpr int kDppRowHalfMirror = 0x141;
-constexpr int kDppRowBcast15 = 0x142;
-constexpr int kDppRowBcast31 = 0x143;
 
-// Lane i receives lane i-1's (from_lower) or lane i+1's (from_upper) value;
-// the lane without a source receives 0, which the caller ORs with kBig.
-__device__ inline uint32_t from_lower_lane(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppWaveShr1, 0xF, 0xF, true);
+// Lane q of a group receives lane q-1's (from_lower) or q+1's (from_upper)
+// value; a lane without a source receives 0 (bound_ctrl), and group edges are
+// overwritten by the caller's OR mask.
+template <int G>
+__device__ inline uint32_t from_lower(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, G == 16 ? kDppRowShr1 : kDppWaveShr1, 0xF, 0xF, true);
 }
-__device__ inline uint32_t from_upper_lane(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppWaveShl1, 0xF, 0xF, true);
+template <int G>
+__device__ inline uint32_t from_upper(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, G == 16 ? kDppRowShl1 : kDppWaveShl1, 0xF, 0xF, true);
 }
 
-// Minimum over the 64 lanes as a wave-uniform (scalar) value: a butterfly
-// inside each row of 16 lanes (DPP quad permutes and mirrors, folded into
-// v_min_u32_dpp), then row broadcasts carry row 0's minimum into row 1 and
-// row 2's into row 3, and rows 0-1's into rows 2-3; lane 63 ends with the
-// minimum of all 64 lanes.  Lanes outside a broadcast's row mask keep their
-// value (min(v, v) = v).
-__device__ inline uint32_t wave_min(uint32_t v) {
+// Minimum over each group of G lanes; every lane of the group receives it.
+// The butterfly inside a row of 16 uses DPP (folded into v_min_u32_dpp);
+// groups spanning 2 or 4 rows combine rows with the gfx950 permlane swaps.
+template <int G>
+__device__ inline uint32_t group_min(uint32_t v) {
     v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppQuadPerm1032, 0xF, 0xF, true));
     v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppQuadPerm2301, 0xF, 0xF, true));
     v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowHalfMirror, 0xF, 0xF, true));
     v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowMirror, 0xF, 0xF, true));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kDppRowBcast15, 0xA, 0xF, false));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kDppRowBcast31, 0xC, 0xF, false));
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+    if constexpr (G >= 32) {
+        const auto sw = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        v = min((uint32_t)sw[0], (uint32_t)sw[1]);
+    }
+    if constexpr (G == 64) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        v = min((uint32_t)sw[0], (uint32_t)sw[1]);
+    }
+    return v;
 }
 
-template <int CPL> struct RawCost;
-template <> struct RawCost<1> { using T = uint8_t; };
-template <> struct RawCost<2> { using T = uint16_t; };
-template <> struct RawCost<4> { using T = uint32_t; };
+// Raw cost bytes of one lane for one step: CPL bytes.
+template <int CPL> struct Raw;
+template <> struct Raw<2> { using T = uint16_t; };
+template <> struct Raw<4> { using T = uint32_t; };
+template <> struct Raw<8> { using T = uint2; };
+template <> struct Raw<16> { using T = uint4; };
 
+// Unpacks a lane's cost bytes b_0..b_{CPL-1} into pairs (b_k, b_{k+CPL/2})
+// with one v_perm per pair.  sel[k] is the per-lane byte selector; it selects
+// 0xFF bytes for padded levels, which makes their cost 0xFFFF.
 template <int CPL>
-__device__ inline void unpack_costs(uint32_t v, uint32_t (&c)[CPL]) {
+__device__ inline void unpack_costs(const typename Raw<CPL>::T& r, const uint32_t (&sel)[CPL / 2],
+                                    u16x2 (&c)[CPL / 2]) {
+    if constexpr (CPL == 2) {
+        c[0] = as2(__builtin_amdgcn_perm(0u, (uint32_t)r, sel[0]));
+    } else if constexpr (CPL == 4) {
+        c[0] = as2(__builtin_amdgcn_perm(r, r, sel[0]));
+        c[1] = as2(__builtin_amdgcn_perm(r, r, sel[1]));
+    } else if constexpr (CPL == 8) {
 #pragma unroll
-    for (int i = 0; i < CPL; ++i) c[i] = (v >> (8 * i)) & 0xFF;
+        for (int k = 0; k < 4; ++k) c[k] = as2(__builtin_amdgcn_perm(r.y, r.x, sel[k]));
+    } else {
+        const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[k] = as2(__builtin_amdgcn_perm(w[2 + k / 4], w[k / 4], sel[k]));
+    }
 }
 
+// Selector of pair k for a lane whose first disparity is d0: low half b_k,
+// high half b_{k+CPL/2} (bytes of the v_perm source pair), 0xFFFF for d >= D.
+template <int CPL>
+__device__ inline uint32_t unpack_selector(int k, int d0, int D) {
+    constexpr int NP = CPL / 2;
+    uint32_t lo, hi;
+    if constexpr (CPL == 2) {
+        lo = 0;
+        hi = 1;
+    } else if constexpr (CPL == 4) {
+        lo = k;
+        hi = k + 2;
+    } else {
+        lo = k % 4;
+        hi = 4 + k % 4;
+    }
+    const uint32_t slo = (d0 + k < D) ? (lo | 0x0C00u) : 0x0D0Du;
+    const uint32_t shi = (d0 + k + NP < D) ? (hi | 0x0C00u) : 0x0D0Du;
+    return slo | (shi << 16);
+}
+
+// Stores a lane's L values in natural disparity order (u8 or u16).
 template <int CPL, typename LT>
-__device__ inline void store_l(LT* p, const uint32_t (&l)[CPL]) {
+__device__ inline void store_l(LT* p, const u16x2 (&l)[CPL / 2]) {
+    constexpr uint32_t kLoBytes = 0x06020400u;  // (a.b0, b.b0, a.b2, b.b2) of perm(b, a)
+    constexpr uint32_t kPairLo = 0x05040100u;   // (a.lo16, b.lo16)
+    constexpr uint32_t kPairHi = 0x07060302u;   // (a.hi16, b.hi16)
     if constexpr (sizeof(LT) == 1) {
-        if constexpr (CPL == 1) {
-            *p = (uint8_t)l[0];
-        } else if constexpr (CPL == 2) {
-            *reinterpret_cast<uint16_t*>(p) = (uint16_t)((l[0] & 0xFF) | (l[1] << 8));
+        if constexpr (CPL == 2) {
+            *reinterpret_cast<uint16_t*>(p) = (uint16_t)__builtin_amdgcn_perm(0u, as1(l[0]), 0x0C0C0200u);
+        } else if constexpr (CPL == 4) {
+            *reinterpret_cast<uint32_t*>(p) = __builtin_amdgcn_perm(as1(l[1]), as1(l[0]), kLoBytes);
+        } else if constexpr (CPL == 8) {
+            const uint32_t t01 = __builtin_amdgcn_perm(as1(l[1]), as1(l[0]), kLoBytes);
+            const uint32_t t23 = __builtin_amdgcn_perm(as1(l[3]), as1(l[2]), kLoBytes);
+            uint2 v;
+            v.x = __builtin_amdgcn_perm(t23, t01, kPairLo);
+            v.y = __builtin_amdgcn_perm(t23, t01, kPairHi);
+            *reinterpret_cast<uint2*>(p) = v;
         } else {
-            *reinterpret_cast<uint32_t*>(p) =
-                (l[0] & 0xFF) | ((l[1] & 0xFF) << 8) | ((l[2] & 0xFF) << 16) | (l[3] << 24);
+            uint32_t t[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) t[i] = __builtin_amdgcn_perm(as1(l[2 * i + 1]), as1(l[2 * i]), kLoBytes);
+            uint4 v;
+            v.x = __builtin_amdgcn_perm(t[1], t[0], kPairLo);
+            v.y = __builtin_amdgcn_perm(t[3], t[2], kPairLo);
+            v.z = __builtin_amdgcn_perm(t[1], t[0], kPairHi);
+            v.w = __builtin_amdgcn_perm(t[3], t[2], kPairHi);
+            *reinterpret_cast<uint4*>(p) = v;
         }
     } else {
-        if constexpr (CPL == 1) {
-            *p = (uint16_t)l[0];
-        } else if constexpr (CPL == 2) {
-            *reinterpret_cast<uint32_t*>(p) = (l[0] & 0xFFFF) | (l[1] << 16);
+        constexpr int NP = CPL / 2;
+        if constexpr (CPL == 2) {
+            *reinterpret_cast<uint32_t*>(p) = as1(l[0]);
         } else {
-            uint2 v;
-            v.x = (l[0] & 0xFFFF) | (l[1] << 16);
-            v.y = (l[2] & 0xFFFF) | (l[3] << 16);
-            *reinterpret_cast<uint2*>(p) = v;
+            // dword i = (d_2i, d_2i+1): from pairs (2i mod NP, 2i+1 mod NP)
+            uint32_t w[NP];
+#pragma unroll
+            for (int i = 0; i < NP / 2; ++i) {
+                w[i] = __builtin_amdgcn_perm(as1(l[2 * i + 1]), as1(l[2 * i]), kPairLo);
+                w[NP / 2 + i] = __builtin_amdgcn_perm(as1(l[2 * i + 1]), as1(l[2 * i]), kPairHi);
+            }
+            if constexpr (NP == 2) {
+                *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[1]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < NP / 4; ++i)
+                    reinterpret_cast<uint4*>(p)[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
+            }
         }
     }
 }
 
-// Walks one slice by pixel offset (y * W + x).  Horizontal and vertical
-// slices never restart after their first pixel; diagonal ones restart where
-// they wrap around a side border (see walk_next).
 enum { kHoriz = 0, kVert = 1, kDiag = 2 };
-
-template <int KIND>
-struct Walker {
-    int x, po, rx, step, W;  // step = ry * W + rx
-    bool restart;
-    __device__ inline void next() {
-        po += step;
-        restart = false;
-        if constexpr (KIND == kDiag) {
-            // branch-free wrap: x < 0 -> +W, x >= W -> -W
-            x += rx;
-            const int under = x >> 31;
-            const int over = (W - 1 - x) >> 31;
-            const int wrap = (under & W) - (over & W);
-            x += wrap;
-            po += wrap;
-            restart = (under | over) != 0;
-        }
-    }
-};
 
 // Cost loads run kPrefetch steps ahead of the recurrence so that their
 // latency overlaps the dependent min-plus chain of the steps in between.
-constexpr int kPrefetch = 16;
+template <int CPL> struct Prefetch { static constexpr int N = CPL >= 16 ? 8 : 16; };
 
-template <int CPL, typename LT, bool PAD, int KIND>
-__device__ inline void aggregate_slice(const uint8_t* __restrict__ cost, LT* __restrict__ out, int lane, int D,
-                                       uint32_t P1, uint32_t P2, Walker<KIND> w, int steps) {
-    constexpr int kLog2Dp = CPL == 1 ? 6 : (CPL == 2 ? 7 : 8);
-    using Raw = typename RawCost<CPL>::T;
-    const unsigned lofs = lane * CPL;
-    auto load = [&](int po) -> uint32_t {
+template <int G, int CPL, typename LT, int KIND>
+__device__ inline void aggregate_wave(const AggArgs& a, int r, int first_slice, int lane) {
+    constexpr int NP = CPL / 2;
+    constexpr int S = 64 / G;
+    constexpr int kLog2Dp = G * CPL == 64 ? 6 : (G * CPL == 128 ? 7 : 8);
+    constexpr int PF = Prefetch<CPL>::N;
+    using RawT = typename Raw<CPL>::T;
+
+    const int rx = a.rx[r], ry = a.ry[r];
+    const int W = a.W, H = a.H;
+    const int grp = lane / G, q = lane % G;
+    const int nslices = KIND == kHoriz ? H : W;
+    const int steps = KIND == kHoriz ? W : H;
+    // groups past the last slice repeat the last slice (identical stores)
+    const int slice0 = first_slice;
+    const int jg = min(grp, nslices - 1 - slice0);
+
+    uint32_t sel[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) sel[k] = unpack_selector<CPL>(k, q * CPL, a.D);
+    const uint32_t edge_lo = q == 0 ? 0xFFFF0000u : 0u;      // no d-1 below d = 0
+    const uint32_t edge_hi = q == G - 1 ? 0x0000FFFFu : 0u;  // no d+1 above Dp-1
+    const u16x2 P1v = as2((uint32_t)a.P1 * 0x10001u), P2v = as2((uint32_t)a.P2 * 0x10001u);
+
+    const uint8_t* cost = a.cost;
+    LT* out = reinterpret_cast<LT*>(a.lbuf) + a.plane * a.plane_index[r];
+    const int qofs = q * CPL;  // element offset of the lane inside a pixel
+
+    // Uniform walker state: pixel offset of group 0 (po) and, for diagonal
+    // slices, group 0's column xb (kept in [0, W)).
+    int y0, xb;
+    if constexpr (KIND == kHoriz) {
+        y0 = slice0;
+        xb = rx > 0 ? 0 : W - 1;
+    } else {
+        y0 = ry > 0 ? 0 : H - 1;
+        xb = slice0;
+    }
+    const int pstep = KIND == kHoriz ? rx : (KIND == kVert ? ry * W : ry * W + rx);
+    // per-lane pixel offset of the lane's group relative to group 0
+    const int gofs = KIND == kHoriz ? jg * W : jg;
+
+    // signed element offset of the lane relative to group 0's pixel; a
+    // diagonal group whose column wrapped sits W pixels back
+    auto lane_ofs = [&](int xcol) -> int {
+        if constexpr (KIND == kDiag) {
+            const int xl = xcol + jg >= W ? jg - W : jg;
+            return xl * (G * CPL) + qofs;
+        } else {
+            return gofs * (G * CPL) + qofs;
+        }
+    };
+    auto load = [&](int po, int xcol) -> RawT {
         const uint8_t* p = cost + ((size_t)(unsigned)po << kLog2Dp);
-        return *reinterpret_cast<const Raw*>(p + lofs);
-    };
-    // lanes without a d-1 / d+1 neighbour see kBig
-    const uint32_t edge_lo = lane == 0 ? kBig : 0u;
-    const uint32_t edge_hi = lane == 63 ? kBig : 0u;
-
-    uint32_t pad[CPL];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) pad[c] = (PAD && lofs + c >= D) ? kBig : 0u;
-
-    uint32_t L[CPL];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) L[c] = 0;
-    uint32_t m = 0;
-    // one step of Eq. 3 at the walker's pixel, then advance the walker
-    auto step = [&](uint32_t raw) {
-        if (w.restart) {
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) L[c] = 0;
-            m = 0;
-        }
-        uint32_t cst[CPL];
-        unpack_costs<CPL>(raw, cst);
-        uint32_t lp[CPL];
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) lp[c] = L[c] + P1;
-        const uint32_t in_lo = from_lower_lane(lp[CPL - 1]) | edge_lo;
-        const uint32_t in_hi = from_upper_lane(lp[0]) | edge_hi;
-        const uint32_t mp2 = m + P2;
-        uint32_t lmin = ~0u;
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const uint32_t lo = c == 0 ? in_lo : lp[c - 1];
-            const uint32_t hi = c == CPL - 1 ? in_hi : lp[c + 1];
-            const uint32_t R = min(min(L[c], lo), min(hi, mp2));
-            L[c] = R + (cst[c] | pad[c]) - m;
-            lmin = min(lmin, L[c]);
-        }
-        m = wave_min(lmin);
-        LT* o = out + ((size_t)(unsigned)w.po << kLog2Dp);
-        store_l<CPL, LT>(o + lofs, L);
-        w.next();
+        return *reinterpret_cast<const RawT*>(p + lane_ofs(xcol));
     };
 
-    // ring[j] holds the raw costs of the step congruent to j modulo
-    // kPrefetch.  The walker `ahead` leads by kPrefetch - 1 steps and stops at
-    // the slice's last pixel, so every load is unconditional and in bounds
-    // (loads past the end re-read the last pixel and are never consumed).
-    uint32_t ring[kPrefetch];
-    Walker<KIND> ahead = w;
-    int ahead_k = 0;  // step index of `ahead`
+    u16x2 L[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) L[k] = as2(0u);
+    u16x2 mm = as2(0u);
+
+    int po = y0 * W + xb;
+    int xcur = xb;
+    // advance group 0's position by one step along the slice
+    auto advance = [&](int& p, int& x) {
+        p += pstep;
+        if constexpr (KIND == kDiag) {
+            x += rx;
+            if (x < 0) {
+                x += W;
+                p += W;
+            } else if (x >= W) {
+                x -= W;
+                p -= W;
+            }
+        }
+    };
+
+    auto step = [&](const RawT& raw) {
+        if constexpr (KIND == kDiag) {
+            // a group restarts where its column crosses the side border
+            const int xl = xcur + jg >= W ? xcur + jg - W : xcur + jg;
+            if (xl == (rx > 0 ? 0 : W - 1)) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) L[k] = as2(0u);
+                mm = as2(0u);
+            }
+        }
+        u16x2 c[NP];
+        unpack_costs<CPL>(raw, sel, c);
+        u16x2 lp[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) lp[k] = vadds(L[k], P1v);
+        const uint32_t prev = from_lower<G>(as1(lp[NP - 1])) | edge_lo;
+        const uint32_t next = from_upper<G>(as1(lp[0])) | edge_hi;
+        const u16x2 lo0 = as2(__builtin_amdgcn_alignbit(as1(lp[NP - 1]), prev, 16));
+        const u16x2 hiN = as2(__builtin_amdgcn_alignbit(next, as1(lp[0]), 16));
+        const u16x2 mp2 = vadds(mm, P2v);
+        u16x2 t = as2(0xFFFFFFFFu);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const u16x2 lo = k == 0 ? lo0 : lp[k - 1];
+            const u16x2 hi = k == NP - 1 ? hiN : lp[k + 1];
+            const u16x2 R = vmin(vmin(lo, hi), vmin(L[k], mp2));
+            L[k] = vadds(R - mm, c[k]);
+            t = vmin(t, L[k]);
+        }
+        t = vmin(t, t.yx);
+        mm = as2(group_min<G>(as1(t)));
+        LT* o = out + ((size_t)(unsigned)po << kLog2Dp);
+        store_l<CPL, LT>(o + lane_ofs(xcur), L);
+        advance(po, xcur);
+    };
+
+    // ring[j] holds the raw costs of the step congruent to j modulo PF.  The
+    // lookahead position leads by PF - 1 steps and stops at the slice's last
+    // pixel, so every load is unconditional and in bounds.
+    RawT ring[PF];
+    int pa = po, xa = xcur, ka = 0;
     auto advance_ahead = [&]() {
-        if (ahead_k + 1 < steps) {
-            ahead.next();
-            ++ahead_k;
+        if (ka + 1 < steps) {
+            advance(pa, xa);
+            ++ka;
         }
     };
 #pragma unroll
-    for (int j = 0; j < kPrefetch; ++j) {
+    for (int j = 0; j < PF; ++j) {
         if (j) advance_ahead();
-        ring[j] = load(ahead.po);
+        ring[j] = load(pa, xa);
     }
     int k = 0;
-    for (; k + kPrefetch <= steps; k += kPrefetch) {
+    for (; k + PF <= steps; k += PF) {
 #pragma unroll
-        for (int j = 0; j < kPrefetch; ++j) {
-            const uint32_t raw = ring[j];
+        for (int j = 0; j < PF; ++j) {
+            const RawT raw = ring[j];
             advance_ahead();
-            ring[j] = load(ahead.po);
+            ring[j] = load(pa, xa);
             step(raw);
         }
     }
 #pragma unroll
-    for (int j = 0; j < kPrefetch; ++j)
+    for (int j = 0; j < PF; ++j)
         if (k + j < steps) step(ring[j]);
 }
 
-template <int CPL, typename LT, bool PAD>
+template <int G, int CPL, typename LT>
 __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (wave >= a.total) return;
     int r = 0;
     while (r + 1 < a.ndirs && wave >= a.start[r + 1]) ++r;
-    const Dir dir{a.rx[r], a.ry[r]};
-    const int steps = slice_steps(a.W, a.H, dir);
-    const Walk w0 = walk_start(a.W, a.H, dir, wave - a.start[r]);
-    LT* out = reinterpret_cast<LT*>(a.lbuf) + a.plane * a.plane_index[r];
-    const int po = w0.y * a.W + w0.x;
-    const int step = dir.ry * a.W + dir.rx;
-    if (dir.ry == 0)
-        aggregate_slice<CPL, LT, PAD, kHoriz>(a.cost, out, lane, a.D, a.P1, a.P2,
-                                               Walker<kHoriz>{w0.x, po, dir.rx, step, a.W, true}, steps);
-    else if (dir.rx == 0)
-        aggregate_slice<CPL, LT, PAD, kVert>(a.cost, out, lane, a.D, a.P1, a.P2,
-                                              Walker<kVert>{w0.x, po, dir.rx, step, a.W, true}, steps);
+    constexpr int S = 64 / G;
+    const int first = (wave - a.start[r]) * S;
+    if (a.ry[r] == 0)
+        aggregate_wave<G, CPL, LT, kHoriz>(a, r, first, lane);
+    else if (a.rx[r] == 0)
+        aggregate_wave<G, CPL, LT, kVert>(a, r, first, lane);
     else
-        aggregate_slice<CPL, LT, PAD, kDiag>(a.cost, out, lane, a.D, a.P1, a.P2,
-                                              Walker<kDiag>{w0.x, po, dir.rx, step, a.W, true}, steps);
+        aggregate_wave<G, CPL, LT, kDiag>(a, r, first, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -564,7 +706,6 @@ bool plan_finish(Plan& p, const char** why) {
     if ((long long)p.n_paths * (p.cmax + (long long)p.P2) > 65535)
         return fail("n_paths * (Cmax + P2) must be <= 65535 (16-bit summed costs)");
     if (p.lr_thr < 0) return fail("lr threshold must be >= 0");
-    p.cpl = cells_per_lane(p.D);
     p.Dp = padded_disp(p.D);
     p.l16 = p.cmax + p.P2 > 255;
     return true;
@@ -600,11 +741,14 @@ hipError_t launch_census_cost(const Plan& p, const Workspace& ws, const uint8_t*
     const int ncol = nright + 2 * a.rx;
     const size_t smem = 8 * (size_t)(kCostTX + nright) + 2 * (size_t)(2 * a.ry + 1) * ncol;
     dim3 grid((p.W + kCostTX - 1) / kCostTX, p.H);
-    hipLaunchKernelGGL(census_cost_kernel, grid, dim3(256), smem, stream, a);
+    if (p.cw == 9 && p.ch == 7)
+        hipLaunchKernelGGL((census_cost_kernel<4, 3>), grid, dim3(256), smem, stream, a);
+    else
+        hipLaunchKernelGGL((census_cost_kernel<0, 0>), grid, dim3(256), smem, stream, a);
     return hipGetLastError();
 }
 
-static void fill_agg_args(const Plan& p, const Workspace& ws, AggArgs& a) {
+static void fill_agg_args(const Plan& p, const Workspace& ws, int S, AggArgs& a) {
     a.cost = ws.cost;
     a.lbuf = ws.lbuf;
     a.plane = (size_t)p.W * p.H * p.Dp;
@@ -630,34 +774,42 @@ static void fill_agg_args(const Plan& p, const Workspace& ws, AggArgs& a) {
         a.ry[k] = d.ry;
         a.plane_index[k] = order[k];
         a.start[k] = acc;
-        acc += slice_count(p.W, p.H, d);
+        acc += (slice_count(p.W, p.H, d) + S - 1) / S;
     }
     a.start[p.n_paths] = acc;
     a.total = acc;
 }
 
-template <int CPL, typename LT>
-static void launch_agg_t(const AggArgs& a, bool pad, hipStream_t stream) {
-    dim3 grid((a.total + 3) / 4);
-    if (pad)
-        hipLaunchKernelGGL((aggregate_kernel<CPL, LT, true>), grid, dim3(256), 0, stream, a);
-    else
-        hipLaunchKernelGGL((aggregate_kernel<CPL, LT, false>), grid, dim3(256), 0, stream, a);
+template <int G, int CPL, typename LT>
+static hipError_t launch_agg_t(const Plan& p, const Workspace& ws, hipStream_t stream) {
+    AggArgs a;
+    fill_agg_args(p, ws, 64 / G, a);
+    hipLaunchKernelGGL((aggregate_kernel<G, CPL, LT>), dim3((a.total + 3) / 4), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <typename LT>
+static hipError_t launch_agg_lt(const Plan& p, const Workspace& ws, int G, hipStream_t stream) {
+    switch (p.Dp * 100 + G) {
+        case 6416: return launch_agg_t<16, 4, LT>(p, ws, stream);
+        case 6432: return launch_agg_t<32, 2, LT>(p, ws, stream);
+        case 12816: return launch_agg_t<16, 8, LT>(p, ws, stream);
+        case 12832: return launch_agg_t<32, 4, LT>(p, ws, stream);
+        case 12864: return launch_agg_t<64, 2, LT>(p, ws, stream);
+        case 25616: return launch_agg_t<16, 16, LT>(p, ws, stream);
+        case 25632: return launch_agg_t<32, 8, LT>(p, ws, stream);
+        case 25664: return launch_agg_t<64, 4, LT>(p, ws, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stream) {
-    AggArgs a;
-    fill_agg_args(p, ws, a);
-    const bool pad = p.D != p.Dp;
-    switch (p.cpl * 2 + (p.l16 ? 1 : 0)) {
-        case 2: launch_agg_t<1, uint8_t>(a, pad, stream); break;
-        case 3: launch_agg_t<1, uint16_t>(a, pad, stream); break;
-        case 4: launch_agg_t<2, uint8_t>(a, pad, stream); break;
-        case 5: launch_agg_t<2, uint16_t>(a, pad, stream); break;
-        case 8: launch_agg_t<4, uint8_t>(a, pad, stream); break;
-        default: launch_agg_t<4, uint16_t>(a, pad, stream); break;
+    int G = p.lanes > 0 ? p.lanes : 16;
+    if (const char* env = getenv("SGM_LANES")) {
+        const int g = atoi(env);
+        if (g == 16 || g == 32 || g == 64) G = g;
     }
-    return hipGetLastError();
+    return p.l16 ? launch_agg_lt<uint16_t>(p, ws, G, stream) : launch_agg_lt<uint8_t>(p, ws, G, stream);
 }
 
 hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream) {

@@ -11,7 +11,7 @@ namespace sgm {
 // Everything a launch needs to know about one stereo pair's pipeline.
 struct Plan {
     int W = 0, H = 0, D = 0;   // image size, disparity levels
-    int Dp = 0, cpl = 0;       // padded levels (64 * cells per lane)
+    int Dp = 0;                // padded levels: 64, 128 or 256
     int P1 = 0, P2 = 0;
     int n_paths = 0;
     int cw = 9, ch = 7;        // census window
@@ -20,6 +20,7 @@ struct Plan {
     int lr_thr = 1;
     int cmax = 0;              // largest matching cost
     bool l16 = false;          // L_r stored as u16 (else u8: Cmax + P2 <= 255)
+    int lanes = 0;             // lanes per aggregation slice (16, 32, 64; 0 = default)
 };
 
 // Device workspace of one pair.  All buffers are row-major, d fastest.
