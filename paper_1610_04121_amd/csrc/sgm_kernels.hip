@@ -10,6 +10,7 @@
 //   post_kernel         3x3 median and left-right consistency check.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
 #include <cstdlib>
 
 #include "sgm_plan.h"
@@ -304,41 +305,78 @@ __device__ inline uint32_t unpack_selector(int k, int d0, int D) {
     return slo | (shi << 16);
 }
 
-// Stores a lane's L values in natural disparity order (u8 or u16).
+enum { kHoriz = 0, kVert = 1, kDiag = 2 };
+
+// Raw-buffer resource for a byte range (gfx9-family descriptor word 3).  Every
+// access below passes its whole byte offset in the VGPR operand, so the
+// hardware range check covers it: loads past `bytes` return 0 and stores past
+// it are dropped.
+__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+
+template <int CPL>
+__device__ inline typename Raw<CPL>::T buffer_load_raw(__amdgpu_buffer_rsrc_t r, uint32_t ofs) {
+    if constexpr (CPL == 2) {
+        return (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, ofs, 0, 0);
+    } else if constexpr (CPL == 4) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, ofs, 0, 0);
+    } else if constexpr (CPL == 8) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, ofs, 0, 0);
+        return make_uint2(v[0], v[1]);
+    } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, ofs, 0, 0);
+        return make_uint4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+__device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint16_t v) {
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, ofs, 0, 0);
+}
+__device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint32_t v) {
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, ofs, 0, 0);
+}
+__device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint2 v) {
+    __builtin_amdgcn_raw_buffer_store_b64((unsigned __attribute__((ext_vector_type(2)))){v.x, v.y}, r, ofs, 0, 0);
+}
+__device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128((unsigned __attribute__((ext_vector_type(4)))){v.x, v.y, v.z, v.w}, r, ofs,
+                                           0, 0);
+}
+
+// Packs a lane's L values in natural disparity order (u8 or u16) and stores
+// them at byte offset `ofs` of the L_r plane.
 template <int CPL, typename LT>
-__device__ inline void store_l(LT* p, const u16x2 (&l)[CPL / 2]) {
+__device__ inline void store_l(__amdgpu_buffer_rsrc_t r, uint32_t ofs, const u16x2 (&l)[CPL / 2]) {
     constexpr uint32_t kLoBytes = 0x06020400u;  // (a.b0, b.b0, a.b2, b.b2) of perm(b, a)
     constexpr uint32_t kPairLo = 0x05040100u;   // (a.lo16, b.lo16)
     constexpr uint32_t kPairHi = 0x07060302u;   // (a.hi16, b.hi16)
     if constexpr (sizeof(LT) == 1) {
         if constexpr (CPL == 2) {
-            *reinterpret_cast<uint16_t*>(p) = (uint16_t)__builtin_amdgcn_perm(0u, as1(l[0]), 0x0C0C0200u);
+            buffer_store(r, ofs, (uint16_t)__builtin_amdgcn_perm(0u, as1(l[0]), 0x0C0C0200u));
         } else if constexpr (CPL == 4) {
-            *reinterpret_cast<uint32_t*>(p) = __builtin_amdgcn_perm(as1(l[1]), as1(l[0]), kLoBytes);
+            buffer_store(r, ofs, (uint32_t)__builtin_amdgcn_perm(as1(l[1]), as1(l[0]), kLoBytes));
         } else if constexpr (CPL == 8) {
             const uint32_t t01 = __builtin_amdgcn_perm(as1(l[1]), as1(l[0]), kLoBytes);
             const uint32_t t23 = __builtin_amdgcn_perm(as1(l[3]), as1(l[2]), kLoBytes);
-            uint2 v;
-            v.x = __builtin_amdgcn_perm(t23, t01, kPairLo);
-            v.y = __builtin_amdgcn_perm(t23, t01, kPairHi);
-            *reinterpret_cast<uint2*>(p) = v;
+            buffer_store(r, ofs, make_uint2(__builtin_amdgcn_perm(t23, t01, kPairLo),
+                                            __builtin_amdgcn_perm(t23, t01, kPairHi)));
         } else {
             uint32_t t[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) t[i] = __builtin_amdgcn_perm(as1(l[2 * i + 1]), as1(l[2 * i]), kLoBytes);
-            uint4 v;
-            v.x = __builtin_amdgcn_perm(t[1], t[0], kPairLo);
-            v.y = __builtin_amdgcn_perm(t[3], t[2], kPairLo);
-            v.z = __builtin_amdgcn_perm(t[1], t[0], kPairHi);
-            v.w = __builtin_amdgcn_perm(t[3], t[2], kPairHi);
-            *reinterpret_cast<uint4*>(p) = v;
+            buffer_store(r, ofs, make_uint4(__builtin_amdgcn_perm(t[1], t[0], kPairLo),
+                                            __builtin_amdgcn_perm(t[3], t[2], kPairLo),
+                                            __builtin_amdgcn_perm(t[1], t[0], kPairHi),
+                                            __builtin_amdgcn_perm(t[3], t[2], kPairHi)));
         }
     } else {
         constexpr int NP = CPL / 2;
         if constexpr (CPL == 2) {
-            *reinterpret_cast<uint32_t*>(p) = as1(l[0]);
+            buffer_store(r, ofs, as1(l[0]));
         } else {
-            // dword i = (d_2i, d_2i+1): from pairs (2i mod NP, 2i+1 mod NP)
+            // dword i = (d_2i, d_2i+1) from pairs 2i and 2i+1 (low halves,
+            // then high halves)
             uint32_t w[NP];
 #pragma unroll
             for (int i = 0; i < NP / 2; ++i) {
@@ -346,27 +384,24 @@ __device__ inline void store_l(LT* p, const u16x2 (&l)[CPL / 2]) {
                 w[NP / 2 + i] = __builtin_amdgcn_perm(as1(l[2 * i + 1]), as1(l[2 * i]), kPairHi);
             }
             if constexpr (NP == 2) {
-                *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[1]);
+                buffer_store(r, ofs, make_uint2(w[0], w[1]));
             } else {
 #pragma unroll
                 for (int i = 0; i < NP / 4; ++i)
-                    reinterpret_cast<uint4*>(p)[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
+                    buffer_store(r, ofs + 16 * i, make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]));
             }
         }
     }
 }
 
-enum { kHoriz = 0, kVert = 1, kDiag = 2 };
-
-// Cost loads run kPrefetch steps ahead of the recurrence so that their
-// latency overlaps the dependent min-plus chain of the steps in between.
+// Cost loads run PF steps ahead of the recurrence so that their latency
+// overlaps the dependent min-plus chain of the steps in between.
 template <int CPL> struct Prefetch { static constexpr int N = CPL >= 16 ? 8 : 16; };
 
 template <int G, int CPL, typename LT, int KIND>
 __device__ inline void aggregate_wave(const AggArgs& a, int r, int first_slice, int lane) {
     constexpr int NP = CPL / 2;
-    constexpr int S = 64 / G;
-    constexpr int kLog2Dp = G * CPL == 64 ? 6 : (G * CPL == 128 ? 7 : 8);
+    constexpr int Dp = G * CPL;
     constexpr int PF = Prefetch<CPL>::N;
     using RawT = typename Raw<CPL>::T;
 
@@ -376,8 +411,7 @@ __device__ inline void aggregate_wave(const AggArgs& a, int r, int first_slice, 
     const int nslices = KIND == kHoriz ? H : W;
     const int steps = KIND == kHoriz ? W : H;
     // groups past the last slice repeat the last slice (identical stores)
-    const int slice0 = first_slice;
-    const int jg = min(grp, nslices - 1 - slice0);
+    const int jg = min(grp, nslices - 1 - first_slice);
 
     uint32_t sel[NP];
 #pragma unroll
@@ -386,66 +420,55 @@ __device__ inline void aggregate_wave(const AggArgs& a, int r, int first_slice, 
     const uint32_t edge_hi = q == G - 1 ? 0x0000FFFFu : 0u;  // no d+1 above Dp-1
     const u16x2 P1v = as2((uint32_t)a.P1 * 0x10001u), P2v = as2((uint32_t)a.P2 * 0x10001u);
 
-    const uint8_t* cost = a.cost;
-    LT* out = reinterpret_cast<LT*>(a.lbuf) + a.plane * a.plane_index[r];
-    const int qofs = q * CPL;  // element offset of the lane inside a pixel
+    const uint32_t plane_bytes = (uint32_t)a.plane;  // cost plane, u8
+    const __amdgpu_buffer_rsrc_t rc = buffer_rsrc(a.cost, plane_bytes);
+    const __amdgpu_buffer_rsrc_t rl = buffer_rsrc(
+        reinterpret_cast<const LT*>(a.lbuf) + a.plane * a.plane_index[r], plane_bytes * (uint32_t)sizeof(LT));
 
-    // Uniform walker state: pixel offset of group 0 (po) and, for diagonal
-    // slices, group 0's column xb (kept in [0, W)).
-    int y0, xb;
+    // Group 0's position: byte offset `bo` of its pixel in a u8 [H][W][Dp]
+    // plane and, for diagonal slices, its column xc (kept in [0, W)).
+    int bo, xc;
     if constexpr (KIND == kHoriz) {
-        y0 = slice0;
-        xb = rx > 0 ? 0 : W - 1;
+        xc = rx > 0 ? 0 : W - 1;
+        bo = (first_slice * W + xc) * Dp;
     } else {
-        y0 = ry > 0 ? 0 : H - 1;
-        xb = slice0;
+        xc = first_slice;
+        bo = ((ry > 0 ? 0 : H - 1) * W + xc) * Dp;
     }
-    const int pstep = KIND == kHoriz ? rx : (KIND == kVert ? ry * W : ry * W + rx);
-    // per-lane pixel offset of the lane's group relative to group 0
-    const int gofs = KIND == kHoriz ? jg * W : jg;
-
-    // signed element offset of the lane relative to group 0's pixel; a
-    // diagonal group whose column wrapped sits W pixels back
-    auto lane_ofs = [&](int xcol) -> int {
-        if constexpr (KIND == kDiag) {
-            const int xl = xcol + jg >= W ? jg - W : jg;
-            return xl * (G * CPL) + qofs;
-        } else {
-            return gofs * (G * CPL) + qofs;
-        }
+    const int bstep = (KIND == kHoriz ? rx : ry * W + (KIND == kDiag ? rx : 0)) * Dp;
+    const int qofs = q * CPL;
+    // byte offset of the lane relative to group 0 (horizontal: rows below;
+    // vertical: columns to the right; diagonal: columns to the right, or
+    // W - jg columns to the left once the group's column has wrapped)
+    const int lofs = (KIND == kHoriz ? jg * W : jg) * Dp + qofs;
+    const int lofs_wrapped = (jg - W) * Dp + qofs;
+    auto lane_ofs = [&](int b, int x) -> uint32_t {
+        if constexpr (KIND == kDiag) return (uint32_t)(b + (x + jg >= W ? lofs_wrapped : lofs));
+        return (uint32_t)(b + lofs);
     };
-    auto load = [&](int po, int xcol) -> RawT {
-        const uint8_t* p = cost + ((size_t)(unsigned)po << kLog2Dp);
-        return *reinterpret_cast<const RawT*>(p + lane_ofs(xcol));
+    auto advance = [&](int& b, int& x) {
+        b += bstep;
+        if constexpr (KIND == kDiag) {
+            x += rx;
+            const int under = x >> 31;             // -1 if x < 0
+            const int over = (W - 1 - x) >> 31;    // -1 if x >= W
+            const int wrap = (under & W) - (over & W);
+            x += wrap;
+            b += wrap * Dp;
+        }
     };
 
     u16x2 L[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) L[k] = as2(0u);
     u16x2 mm = as2(0u);
-
-    int po = y0 * W + xb;
-    int xcur = xb;
-    // advance group 0's position by one step along the slice
-    auto advance = [&](int& p, int& x) {
-        p += pstep;
-        if constexpr (KIND == kDiag) {
-            x += rx;
-            if (x < 0) {
-                x += W;
-                p += W;
-            } else if (x >= W) {
-                x -= W;
-                p -= W;
-            }
-        }
-    };
+    // restart column of a diagonal group: where it crosses the side border
+    const int border = rx > 0 ? 0 : W - 1;
 
     auto step = [&](const RawT& raw) {
         if constexpr (KIND == kDiag) {
-            // a group restarts where its column crosses the side border
-            const int xl = xcur + jg >= W ? xcur + jg - W : xcur + jg;
-            if (xl == (rx > 0 ? 0 : W - 1)) {
+            const int xl = xc + jg >= W ? xc + jg - W : xc + jg;
+            if (xl == border) {
 #pragma unroll
                 for (int k = 0; k < NP; ++k) L[k] = as2(0u);
                 mm = as2(0u);
@@ -461,45 +484,45 @@ __device__ inline void aggregate_wave(const AggArgs& a, int r, int first_slice, 
         const u16x2 lo0 = as2(__builtin_amdgcn_alignbit(as1(lp[NP - 1]), prev, 16));
         const u16x2 hiN = as2(__builtin_amdgcn_alignbit(next, as1(lp[0]), 16));
         const u16x2 mp2 = vadds(mm, P2v);
-        u16x2 t = as2(0xFFFFFFFFu);
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             const u16x2 lo = k == 0 ? lo0 : lp[k - 1];
             const u16x2 hi = k == NP - 1 ? hiN : lp[k + 1];
             const u16x2 R = vmin(vmin(lo, hi), vmin(L[k], mp2));
             L[k] = vadds(R - mm, c[k]);
-            t = vmin(t, L[k]);
         }
-        t = vmin(t, t.yx);
-        mm = as2(group_min<G>(as1(t)));
-        LT* o = out + ((size_t)(unsigned)po << kLog2Dp);
-        store_l<CPL, LT>(o + lane_ofs(xcur), L);
-        advance(po, xcur);
+        // minimum over the lane's cells as a tree, replicated in both halves
+        u16x2 t[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) t[k] = L[k];
+#pragma unroll
+        for (int w = 1; w < NP; w *= 2)
+#pragma unroll
+            for (int k = 0; k + w < NP; k += 2 * w) t[k] = vmin(t[k], t[k + w]);
+        const u16x2 tm = vmin(t[0], t[0].yx);
+        mm = as2(group_min<G>(as1(tm)));
+        store_l<CPL, LT>(rl, lane_ofs(bo, xc) * (uint32_t)sizeof(LT), L);
+        advance(bo, xc);
     };
 
     // ring[j] holds the raw costs of the step congruent to j modulo PF.  The
-    // lookahead position leads by PF - 1 steps and stops at the slice's last
-    // pixel, so every load is unconditional and in bounds.
+    // lookahead position leads by PF - 1 steps and runs past the slice's end
+    // near the finish; those loads are never consumed (and past the plane
+    // they return 0).
     RawT ring[PF];
-    int pa = po, xa = xcur, ka = 0;
-    auto advance_ahead = [&]() {
-        if (ka + 1 < steps) {
-            advance(pa, xa);
-            ++ka;
-        }
-    };
+    int ba = bo, xa = xc;
 #pragma unroll
     for (int j = 0; j < PF; ++j) {
-        if (j) advance_ahead();
-        ring[j] = load(pa, xa);
+        if (j) advance(ba, xa);
+        ring[j] = buffer_load_raw<CPL>(rc, lane_ofs(ba, xa));
     }
     int k = 0;
     for (; k + PF <= steps; k += PF) {
 #pragma unroll
         for (int j = 0; j < PF; ++j) {
             const RawT raw = ring[j];
-            advance_ahead();
-            ring[j] = load(pa, xa);
+            advance(ba, xa);
+            ring[j] = buffer_load_raw<CPL>(rc, lane_ofs(ba, xa));
             step(raw);
         }
     }
@@ -508,21 +531,23 @@ __device__ inline void aggregate_wave(const AggArgs& a, int r, int first_slice, 
         if (k + j < steps) step(ring[j]);
 }
 
-template <int G, int CPL, typename LT>
+// One launch covers every direction.  Horizontal slices (the longest when
+// W > H) may use a different group width GH than the others (GV), so that
+// the longest dependency chains get the fewest instructions per step.
+template <int GH, int GV, int Dp, typename LT>
 __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (wave >= a.total) return;
     int r = 0;
     while (r + 1 < a.ndirs && wave >= a.start[r + 1]) ++r;
-    constexpr int S = 64 / G;
-    const int first = (wave - a.start[r]) * S;
-    if (a.ry[r] == 0)
-        aggregate_wave<G, CPL, LT, kHoriz>(a, r, first, lane);
-    else if (a.rx[r] == 0)
-        aggregate_wave<G, CPL, LT, kVert>(a, r, first, lane);
-    else
-        aggregate_wave<G, CPL, LT, kDiag>(a, r, first, lane);
+    if (a.ry[r] == 0) {
+        aggregate_wave<GH, Dp / GH, LT, kHoriz>(a, r, (wave - a.start[r]) * (64 / GH), lane);
+    } else if (a.rx[r] == 0) {
+        aggregate_wave<GV, Dp / GV, LT, kVert>(a, r, (wave - a.start[r]) * (64 / GV), lane);
+    } else {
+        aggregate_wave<GV, Dp / GV, LT, kDiag>(a, r, (wave - a.start[r]) * (64 / GV), lane);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -708,6 +733,9 @@ bool plan_finish(Plan& p, const char** why) {
     if (p.lr_thr < 0) return fail("lr threshold must be >= 0");
     p.Dp = padded_disp(p.D);
     p.l16 = p.cmax + p.P2 > 255;
+    // one L_r plane (u16) must stay below 2 GiB: kernels address planes with
+    // 32-bit byte offsets
+    if ((long long)p.W * p.H * p.Dp > (1LL << 30)) return fail("width * height * padded disparities must be <= 2^30");
     return true;
 }
 
@@ -748,7 +776,7 @@ hipError_t launch_census_cost(const Plan& p, const Workspace& ws, const uint8_t*
     return hipGetLastError();
 }
 
-static void fill_agg_args(const Plan& p, const Workspace& ws, int S, AggArgs& a) {
+static void fill_agg_args(const Plan& p, const Workspace& ws, int SH, int SV, AggArgs& a) {
     a.cost = ws.cost;
     a.lbuf = ws.lbuf;
     a.plane = (size_t)p.W * p.H * p.Dp;
@@ -770,6 +798,7 @@ static void fill_agg_args(const Plan& p, const Workspace& ws, int S, AggArgs& a)
     int acc = 0;
     for (int k = 0; k < p.n_paths; ++k) {
         const Dir d = direction(p.n_paths, order[k]);
+        const int S = d.ry == 0 ? SH : SV;
         a.rx[k] = d.rx;
         a.ry[k] = d.ry;
         a.plane_index[k] = order[k];
@@ -780,36 +809,57 @@ static void fill_agg_args(const Plan& p, const Workspace& ws, int S, AggArgs& a)
     a.total = acc;
 }
 
-template <int G, int CPL, typename LT>
+template <int GH, int GV, int Dp, typename LT>
 static hipError_t launch_agg_t(const Plan& p, const Workspace& ws, hipStream_t stream) {
     AggArgs a;
-    fill_agg_args(p, ws, 64 / G, a);
-    hipLaunchKernelGGL((aggregate_kernel<G, CPL, LT>), dim3((a.total + 3) / 4), dim3(256), 0, stream, a);
+    fill_agg_args(p, ws, 64 / GH, 64 / GV, a);
+    hipLaunchKernelGGL((aggregate_kernel<GH, GV, Dp, LT>), dim3((a.total + 3) / 4), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 
-template <typename LT>
-static hipError_t launch_agg_lt(const Plan& p, const Workspace& ws, int G, hipStream_t stream) {
-    switch (p.Dp * 100 + G) {
-        case 6416: return launch_agg_t<16, 4, LT>(p, ws, stream);
-        case 6432: return launch_agg_t<32, 2, LT>(p, ws, stream);
-        case 12816: return launch_agg_t<16, 8, LT>(p, ws, stream);
-        case 12832: return launch_agg_t<32, 4, LT>(p, ws, stream);
-        case 12864: return launch_agg_t<64, 2, LT>(p, ws, stream);
-        case 25616: return launch_agg_t<16, 16, LT>(p, ws, stream);
-        case 25632: return launch_agg_t<32, 8, LT>(p, ws, stream);
-        case 25664: return launch_agg_t<64, 4, LT>(p, ws, stream);
-        default: return hipErrorInvalidValue;
+template <int Dp, typename LT>
+static hipError_t launch_agg_dp(const Plan& p, const Workspace& ws, int gh, int gv, hipStream_t stream) {
+    switch (gh * 100 + gv) {
+        case 1616: return launch_agg_t<16, 16, Dp, LT>(p, ws, stream);
+        case 3216: return launch_agg_t<32, 16, Dp, LT>(p, ws, stream);
+        case 3232: return launch_agg_t<32, 32, Dp, LT>(p, ws, stream);
+        default: break;
     }
+    if constexpr (Dp >= 128) {  // 64 lanes need at least 2 levels per lane
+        if (gh == 64 && gv == 16) return launch_agg_t<64, 16, Dp, LT>(p, ws, stream);
+        if (gh == 64 && gv == 32) return launch_agg_t<64, 32, Dp, LT>(p, ws, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename LT>
+static hipError_t launch_agg_lt(const Plan& p, const Workspace& ws, int gh, int gv, hipStream_t stream) {
+    if (p.Dp == 64) {
+        // Dp = 64 has only 4 levels per lane at G = 16 and 2 at G = 32
+        return launch_agg_dp<64, LT>(p, ws, gh == 64 ? 32 : gh, gv, stream);
+    }
+    if (p.Dp == 128) return launch_agg_dp<128, LT>(p, ws, gh, gv, stream);
+    return launch_agg_dp<256, LT>(p, ws, gh, gv, stream);
+}
+
+// Group widths: horizontal slices are the longest chains on wide images,
+// so they get more lanes (fewer instructions per step); the rest use 16.
+void default_lanes(const Plan& p, int* gh, int* gv) {
+    *gh = p.W > p.H ? 32 : 16;
+    *gv = 16;
 }
 
 hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stream) {
-    int G = p.lanes > 0 ? p.lanes : 16;
-    if (const char* env = getenv("SGM_LANES")) {
-        const int g = atoi(env);
-        if (g == 16 || g == 32 || g == 64) G = g;
+    int gh = p.lanes_h, gv = p.lanes_v;
+    if (gh <= 0 || gv <= 0) default_lanes(p, &gh, &gv);
+    if (const char* env = getenv("SGM_LANES")) {  // "GH,GV" override for tuning sweeps
+        int a = 0, b = 0;
+        if (sscanf(env, "%d,%d", &a, &b) == 2) {
+            gh = a;
+            gv = b;
+        }
     }
-    return p.l16 ? launch_agg_lt<uint16_t>(p, ws, G, stream) : launch_agg_lt<uint8_t>(p, ws, G, stream);
+    return p.l16 ? launch_agg_lt<uint16_t>(p, ws, gh, gv, stream) : launch_agg_lt<uint8_t>(p, ws, gh, gv, stream);
 }
 
 hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream) {
