@@ -19,160 +19,207 @@ namespace sgm {
 
 namespace {
 
-constexpr int kCostTX = 128;           // base pixels per census/cost block
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // ---------------------------------------------------------------------------
-// Census (Sec. 3.1).  `tile` holds image rows y-ry..y+ry (clamped to the
-// image) with pitch `pitch`; column c of the tile is image column xs + c,
-// clamped.  (cx, ry) is the centre pixel in tile coordinates.
+// Census kernel: 9x7 windows (full or center-symmetric), register blocked.
+// A block covers 64 x 16 pixels of one image (blockIdx.z); each thread makes
+// 4 consecutive census words of one row.  The block stages a (16 + 6) x 72
+// tile (clamp-to-edge), and each thread reads its 12 x 7 window patch as
+// 3 aligned dwords per row.  A comparison bit s(u, v) = [u >= v] is the
+// sign of v - 1 - u, shifted into the word with one v_alignbit, most
+// significant bit first.
 // ---------------------------------------------------------------------------
-__device__ inline uint64_t census_full(const uint8_t* tile, int pitch, int cx, int rx, int ry) {
-    const int cw = 2 * rx + 1;
-    const int centre = tile[ry * pitch + cx];
-    uint64_t word = 0;
-    for (int j = -ry; j <= ry; ++j) {
-        const uint8_t* row = tile + (ry + j) * pitch + cx;
-        for (int i = -rx; i <= rx; ++i) {
-            const uint64_t bit = row[i] >= centre ? 1u : 0u;
-            word |= bit << ((j + ry) * cw + (i + rx));
-        }
-    }
-    return word;
-}
+constexpr int kCenTX = 64, kCenTY = 16;
 
-// Center-symmetric census, Eq. 1: pairs (x+i, y+j) vs (x-i, y-j) for
-// i = 1..rx, j = -ry..ry, then (x, y+j) vs (x, y-j) for j = 1..ry.
-__device__ inline uint64_t census_csct(const uint8_t* tile, int pitch, int cx, int rx, int ry) {
-    uint64_t word = 0;
-    int k = 0;
-    for (int i = 1; i <= rx; ++i)
-        for (int j = -ry; j <= ry; ++j, ++k) {
-            const uint64_t bit =
-                tile[(ry + j) * pitch + cx + i] >= tile[(ry - j) * pitch + cx - i] ? 1u : 0u;
-            word |= bit << k;
-        }
-    for (int j = 1; j <= ry; ++j, ++k) {
-        const uint64_t bit = tile[(ry + j) * pitch + cx] >= tile[(ry - j) * pitch + cx] ? 1u : 0u;
-        word |= bit << k;
-    }
-    return word;
-}
-
-struct CostArgs {
-    const uint8_t* left;
-    const uint8_t* right;
-    uint8_t* cost;
-    int W, H, D, Dp, rx, ry, cmax, csct;
+struct CensusArgs {
+    const uint8_t* img[2];
+    uint64_t* out[2];
+    int W, H, csct;
 };
 
-// Census of the centre (cx, ry) of an LDS tile, for compile-time window
-// radii (fully unrolled) or, with RX = RY = 0, for runtime radii.
-template <int RX, int RY>
-__device__ inline uint64_t tile_census(const uint8_t* t, int pitch, int cx, int rx, int ry, int csct) {
-    if constexpr (RX > 0) {
-        if (csct) return census_csct(t, pitch, cx, RX, RY);
-        return census_full(t, pitch, cx, RX, RY);
-    } else {
-        if (csct) return census_csct(t, pitch, cx, rx, ry);
-        return census_full(t, pitch, cx, rx, ry);
-    }
+__device__ inline uint32_t shift_in(uint32_t acc, int u, int v) {
+    // (acc << 1) | [u >= v]
+    return __builtin_amdgcn_alignbit(acc, (uint32_t)(v - 1 - u), 31);
 }
 
-// One block per (row y, run of kCostTX base pixels).  Both images' rows
-// y-ry..y+ry are staged in LDS, census words go to LDS (the right image's
-// from x0 - (D-1) on, because C(x, d) reads the match image at x - d), and
-// each thread then writes 16 consecutive disparities of one pixel as one
-// 16-byte store; consecutive threads cover consecutive 16-byte runs.
-template <int RX, int RY>
-__global__ __launch_bounds__(256) void census_cost_kernel(CostArgs a) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    const int y = blockIdx.y;
-    const int x0 = blockIdx.x * kCostTX;
-    const int rx = RX > 0 ? RX : a.rx, ry = RX > 0 ? RY : a.ry;
-    const int nright = kCostTX + a.D - 1;
-    const int xs = x0 - (a.D - 1) - rx;
-    const int ncol = nright + 2 * rx;
-    const int nrow = 2 * ry + 1;
-    uint64_t* cl = reinterpret_cast<uint64_t*>(smem);
-    uint64_t* cr = cl + kCostTX;
-    uint8_t* tl = reinterpret_cast<uint8_t*>(cr + nright);
-    uint8_t* tr = tl + nrow * ncol;
-
-    for (int j = 0; j < nrow; ++j) {
-        const size_t row = (size_t)clampi(y + j - ry, 0, a.H - 1) * a.W;
-        for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
-            const size_t src = row + clampi(xs + c, 0, a.W - 1);
-            tl[j * ncol + c] = a.left[src];
-            tr[j * ncol + c] = a.right[src];
-        }
+__global__ __launch_bounds__(256) void census97_kernel(CensusArgs a) {
+    constexpr int RY = 3, CW = 9;
+    constexpr int TW = kCenTX + 8, TH = kCenTY + 2 * RY;
+    __shared__ __align__(16) uint8_t tile[TH * TW];
+    const int z = blockIdx.z;
+    const uint8_t* img = a.img[z];
+    const int x0 = blockIdx.x * kCenTX, y0 = blockIdx.y * kCenTY;
+    for (int i = threadIdx.x; i < TH * TW; i += blockDim.x) {
+        const int r = i / TW, c = i - r * TW;
+        const int yy = clampi(y0 - RY + r, 0, a.H - 1), xx = clampi(x0 - 4 + c, 0, a.W - 1);
+        tile[i] = img[(size_t)yy * a.W + xx];
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < kCostTX; k += blockDim.x)
-        cl[k] = tile_census<RX, RY>(tl, ncol, k + (a.D - 1) + rx, rx, ry, a.csct);
-    for (int k = threadIdx.x; k < nright; k += blockDim.x)
-        cr[k] = tile_census<RX, RY>(tr, ncol, k + rx, rx, ry, a.csct);
-    __syncthreads();
-
-    const int gshift = a.Dp == 64 ? 2 : (a.Dp == 128 ? 3 : 4);  // log2(Dp / 16)
-    const int ngroups = a.Dp >> 4;
-    const int items = kCostTX << gshift;
-    for (int i = threadIdx.x; i < items; i += blockDim.x) {
-        const int px = i >> gshift, g = i & (ngroups - 1);
-        const int x = x0 + px;
-        if (x >= a.W) break;
-        const uint64_t base = cl[px];
-        const int d0 = 16 * g;
-        // cr index of disparity d is px - d + D - 1
-        const uint64_t* m = cr + (px - d0 + a.D - 1);
-        uint32_t w[4];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int y = y0 + ty;
+    // window patch: rows ty .. ty+6, tile columns 4tx .. 4tx+11
+    uint32_t dw[2 * RY + 1][3];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            uint32_t word = 0;
+    for (int j = 0; j < 2 * RY + 1; ++j)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int d = d0 + 4 * q + j;
-                uint32_t c;
-                if (d >= a.D)
-                    c = 0;
-                else if (x - d < 0)
-                    c = a.cmax;  // no candidate in the match image
+        for (int k = 0; k < 3; ++k) dw[j][k] = *reinterpret_cast<const uint32_t*>(&tile[(ty + j) * TW + 4 * tx + 4 * k]);
+    auto px = [&](int j, int b) -> int { return (int)((dw[j][b >> 2] >> (8 * (b & 3))) & 0xFF); };
+    uint64_t words[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        // byte b of a patch row is image column x0 + 4tx + b - 4; pixel p's
+        // centre is byte p + 4
+        uint32_t hi = 0, lo = 0;
+        if (!a.csct) {
+            const int c = px(RY, p + 4);
+#pragma unroll
+            for (int k = (2 * RY + 1) * CW - 1; k >= 0; --k) {
+                const int j = k / CW, i = k % CW;  // bit k = (j, i) of the window
+                const int u = px(j, p + i);
+                if (k >= 32)
+                    hi = shift_in(hi, u, c);
                 else
-                    c = __popcll(base ^ m[-(4 * q + j)]);
-                word |= c << (8 * j);
+                    lo = shift_in(lo, u, c);
             }
-            w[q] = word;
+        } else {
+            // pairs in order k = 0..30: i = 1..4 with j = -3..3, then (0, j), j = 1..3
+#pragma unroll
+            for (int k = 30; k >= 0; --k) {
+                int i, j;
+                if (k < 28) {
+                    i = 1 + k / 7;
+                    j = k % 7 - 3;
+                } else {
+                    i = 0;
+                    j = k - 27;
+                }
+                lo = shift_in(lo, px(RY + j, p + 4 + i), px(RY - j, p + 4 - i));
+            }
         }
-        *reinterpret_cast<uint4*>(a.cost + ((size_t)y * a.W + x) * a.Dp + d0) = make_uint4(w[0], w[1], w[2], w[3]);
+        words[p] = ((uint64_t)hi << 32) | lo;
+    }
+    const int x = x0 + 4 * tx;
+    if (y < a.H) {
+        uint64_t* o = a.out[z] + (size_t)y * a.W + x;
+        if (x + 3 < a.W && ((a.W & 1) == 0)) {
+            reinterpret_cast<ulonglong2*>(o)[0] = make_ulonglong2(words[0], words[1]);
+            reinterpret_cast<ulonglong2*>(o)[1] = make_ulonglong2(words[2], words[3]);
+        } else {
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+                if (x + p < a.W) o[p] = words[p];
+        }
     }
 }
 
-// Census only (debug tap): one thread per pixel straight from global memory.
-__global__ __launch_bounds__(256) void census_only_kernel(const uint8_t* img, uint64_t* out, int W,
-                                                          int H, int rx, int ry, int csct) {
+// Any other window: one thread per pixel, straight from global memory.
+__global__ __launch_bounds__(256) void census_generic_kernel(CensusArgs a, int rx, int ry) {
     const int x = blockIdx.x * 16 + (threadIdx.x & 15);
     const int y = blockIdx.y * 16 + (threadIdx.x >> 4);
-    if (x >= W || y >= H) return;
+    const int z = blockIdx.z;
+    if (x >= a.W || y >= a.H) return;
+    const uint8_t* img = a.img[z];
+    auto at = [&](int i, int j) {
+        return (int)img[(size_t)clampi(y + j, 0, a.H - 1) * a.W + clampi(x + i, 0, a.W - 1)];
+    };
     const int cw = 2 * rx + 1;
-    const int centre = img[(size_t)y * W + x];
     uint64_t word = 0;
-    if (!csct) {
+    if (!a.csct) {
+        const int c = at(0, 0);
         for (int j = -ry; j <= ry; ++j)
-            for (int i = -rx; i <= rx; ++i) {
-                const int v = img[(size_t)clampi(y + j, 0, H - 1) * W + clampi(x + i, 0, W - 1)];
-                word |= (uint64_t)(v >= centre ? 1u : 0u) << ((j + ry) * cw + (i + rx));
-            }
+            for (int i = -rx; i <= rx; ++i)
+                word |= (uint64_t)(at(i, j) >= c ? 1u : 0u) << ((j + ry) * cw + (i + rx));
     } else {
         int k = 0;
-        auto at = [&](int i, int j) {
-            return (int)img[(size_t)clampi(y + j, 0, H - 1) * W + clampi(x + i, 0, W - 1)];
-        };
         for (int i = 1; i <= rx; ++i)
             for (int j = -ry; j <= ry; ++j, ++k) word |= (uint64_t)(at(i, j) >= at(-i, -j) ? 1u : 0u) << k;
         for (int j = 1; j <= ry; ++j, ++k) word |= (uint64_t)(at(0, j) >= at(0, -j) ? 1u : 0u) << k;
     }
-    out[(size_t)y * W + x] = word;
+    a.out[z][(size_t)y * a.W + x] = word;
+}
+
+// ---------------------------------------------------------------------------
+// Matching cost (Eq. 2).  One block per (row y, run of 64 base pixels).  The
+// census words of the run and of the match run from x0 - (D-1) on are staged
+// in LDS.  Lane l of every wavefront is pixel x0 + l, so the match words a
+// wavefront reads for one disparity are consecutive (no bank conflicts) and
+// their addresses differ by constants (immediate offsets).  Each wavefront
+// computes runs of 16 disparities, writes them to an LDS tile [64][Dp + 16]
+// (the padding spreads rows over banks), and the block then copies the tile
+// to the cost volume with contiguous 16-byte stores.
+// ---------------------------------------------------------------------------
+constexpr int kCostTX = 64;
+
+struct CostArgs {
+    const uint64_t* cl;
+    const uint64_t* cr;
+    uint8_t* cost;
+    int W, H, D, Dp, cmax;
+};
+
+__global__ __launch_bounds__(256) void cost_kernel(CostArgs a) {
+    extern __shared__ __align__(16) uint64_t cw_smem[];
+    const int y = blockIdx.y;
+    const int x0 = blockIdx.x * kCostTX;
+    const int D = a.D, Dp = a.Dp;
+    const int nright = kCostTX + D - 1;
+    const int tpitch = Dp + 16;  // bytes per tile row
+    uint64_t* cl = cw_smem;
+    uint64_t* cr = cl + kCostTX;  // cr[i] = match word of column x0 - (D-1) + i
+    // the tile starts on a 16-byte boundary (an even number of words)
+    uint8_t* tile = reinterpret_cast<uint8_t*>(cl + ((kCostTX + nright + 1) & ~1));
+    const uint64_t* gl = a.cl + (size_t)y * a.W;
+    const uint64_t* gr = a.cr + (size_t)y * a.W;
+    for (int i = threadIdx.x; i < kCostTX; i += blockDim.x)
+        if (x0 + i < a.W) cl[i] = gl[x0 + i];
+    for (int i = threadIdx.x; i < nright; i += blockDim.x) {
+        const int xr = x0 - (D - 1) + i;
+        if (xr >= 0 && xr < a.W) cr[i] = gr[xr];
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int x = x0 + lane;
+    const uint64_t base = cl[lane];
+    const int nchunks = Dp >> 4;
+    for (int ch = wave; ch < nchunks; ch += 4) {
+        const int d0 = 16 * ch;
+        // match word of disparity d0 + j is cr[lane + D - 1 - d0 - j]
+        const uint64_t* m = cr + (lane + D - 1 - d0 - 15);
+        uint32_t w[4];
+        if (x0 >= d0 + 15 && d0 + 16 <= D) {  // all 16 disparities valid for every lane
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t word = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) word |= (uint32_t)__popcll(base ^ m[15 - (4 * q + j)]) << (8 * j);
+                w[q] = word;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t word = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int d = d0 + 4 * q + j;
+                    uint32_t c = 0;  // padded levels d >= D
+                    if (d < D) c = x - d < 0 ? (uint32_t)a.cmax : (uint32_t)__popcll(base ^ m[15 - (4 * q + j)]);
+                    word |= c << (8 * j);
+                }
+                w[q] = word;
+            }
+        }
+        *reinterpret_cast<uint4*>(tile + lane * tpitch + d0) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    __syncthreads();
+    const int npx = min(kCostTX, a.W - x0);
+    uint8_t* dst = a.cost + ((size_t)y * a.W + x0) * Dp;
+    for (int c = threadIdx.x; c < npx * nchunks; c += blockDim.x) {
+        const int px = c / nchunks, k = c - px * nchunks;
+        *reinterpret_cast<uint4*>(dst + 16 * c) = *reinterpret_cast<const uint4*>(tile + px * tpitch + 16 * k);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -552,11 +599,14 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
 
 // ---------------------------------------------------------------------------
 // Sum over directions and winner-take-all (Eq. 4), one block per row.
-// Thread (x, g) sums 16 disparities 16g..16g+15 over all planes.  The left
-// disparity is the smallest key (S << 9 | d) over the pixel's threads.  The
-// right view: pixel x at disparity d is right pixel x - d, so every (x, d)
-// offers its key to column x - d through an LDS atomic minimum; the column's
-// winner is argmin_d S(x + d, d) with ties to the smallest d.
+// Lane = pixel: each lane walks its pixel's disparities in runs of 16, sums
+// the planes as packed u16 pairs and forms keys (S << 8) | d with one v_perm
+// per cell (padded levels get a 0xFF top byte, so they never win).  The left
+// disparity is the smallest key of the pixel.  The right view: pixel x at
+// disparity d is right pixel x - d, so every (x, d) offers its key to column
+// x - d with an LDS atomic minimum; the lanes of a wavefront hit consecutive
+// words, and targets x - d < 0 land in a guard region in front of the row.
+// The column's winner is argmin_d S(x + d, d), ties to the smallest d.
 // ---------------------------------------------------------------------------
 struct WtaArgs {
     const void* lbuf;
@@ -566,61 +616,105 @@ struct WtaArgs {
     int W, H, D, Dp, nplanes;
 };
 
+constexpr int kWtaGuard = 256;  // >= max disparity
+
+// Sums of 16 disparities d0..d0+15 of one pixel as 8 packed pairs; pair k
+// holds disparities dpair(k) (see below).
 template <typename LT>
-__device__ inline void load16(const LT* p, uint32_t (&v)[16]) {
+__device__ inline void sum16(const LT* base, size_t plane, int nplanes, uint32_t (&S)[8]) {
     if constexpr (sizeof(LT) == 1) {
-        const uint4 q = *reinterpret_cast<const uint4*>(p);
-        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+        // bytes b0..b3 of dword i -> pairs (b0, b2) and (b1, b3)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = (w[i >> 2] >> (8 * (i & 3))) & 0xFF;
+        for (int k = 0; k < 8; ++k) S[k] = 0;
+        for (int p = 0; p < nplanes; ++p) {
+            const uint4 q = *reinterpret_cast<const uint4*>(base + plane * p);
+            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                S[2 * i] = as1(as2(S[2 * i]) + as2(__builtin_amdgcn_perm(0u, w[i], 0x0C020C00u)));
+                S[2 * i + 1] = as1(as2(S[2 * i + 1]) + as2(__builtin_amdgcn_perm(0u, w[i], 0x0C030C01u)));
+            }
+        }
     } else {
-        const uint4 q0 = reinterpret_cast<const uint4*>(p)[0];
-        const uint4 q1 = reinterpret_cast<const uint4*>(p)[1];
-        const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+        // u16 pairs are already (d, d + 1)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = (w[i >> 1] >> (16 * (i & 1))) & 0xFFFF;
+        for (int k = 0; k < 8; ++k) S[k] = 0;
+        for (int p = 0; p < nplanes; ++p) {
+            const uint4 q0 = reinterpret_cast<const uint4*>(base + plane * p)[0];
+            const uint4 q1 = reinterpret_cast<const uint4*>(base + plane * p)[1];
+            const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) S[k] = as1(as2(S[k]) + as2(w[k]));
+        }
     }
+}
+
+// Disparities (relative to the run) held by pair k: u8 planes pair 2i =
+// (4i, 4i + 2), pair 2i + 1 = (4i + 1, 4i + 3); u16 planes pair k = (2k, 2k+1).
+template <typename LT>
+__device__ inline void pair_disps(int k, int& lo, int& hi) {
+    if constexpr (sizeof(LT) == 1) {
+        lo = 4 * (k >> 1) + (k & 1);
+        hi = lo + 2;
+    } else {
+        lo = 2 * k;
+        hi = lo + 1;
+    }
+}
+
+// Minimum over aligned groups of G consecutive lanes (G = 4, 8 or 16);
+// every lane of the group receives it.
+__device__ inline uint32_t lanes_min(uint32_t v, int G) {
+    v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppQuadPerm1032, 0xF, 0xF, true));
+    v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppQuadPerm2301, 0xF, 0xF, true));
+    if (G >= 8) v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowHalfMirror, 0xF, 0xF, true));
+    if (G >= 16) v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowMirror, 0xF, 0xF, true));
+    return v;
 }
 
 template <typename LT>
 __global__ __launch_bounds__(1024) void wta_kernel(WtaArgs a) {
-    extern __shared__ uint32_t keyR[];
+    extern __shared__ uint32_t keyR_smem[];
+    uint32_t* keyR = keyR_smem + kWtaGuard;  // keyR[t], t in [-kWtaGuard, W)
     const int y = blockIdx.x;
     const bool right = a.dr != nullptr;
     if (right)
-        for (int i = threadIdx.x; i < a.W; i += blockDim.x) keyR[i] = ~0u;
+        for (int i = threadIdx.x; i < a.W + kWtaGuard; i += blockDim.x) keyR_smem[i] = ~0u;
     __syncthreads();
-    const int G = a.Dp >> 4;  // threads per pixel: 4, 8 or 16 (divides 64)
-    const LT* base = reinterpret_cast<const LT*>(a.lbuf);
+    const LT* planes = reinterpret_cast<const LT*>(a.lbuf);
+    // thread (x, g) takes disparities 16g .. 16g + 15 of pixel x; the G runs
+    // of a pixel sit on consecutive lanes, so its loads are contiguous
+    const int G = a.Dp >> 4;
+    const int gshift = G == 4 ? 2 : (G == 8 ? 3 : 4);
     for (int i = threadIdx.x; i < a.W * G; i += blockDim.x) {
-        const int x = i / G, g = i - x * G;
-        const size_t off = ((size_t)y * a.W + x) * a.Dp + 16 * g;
-        uint32_t s[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) s[j] = 0;
-        for (int p = 0; p < a.nplanes; ++p) {
-            uint32_t v[16];
-            load16<LT>(base + a.plane * p + off, v);
-#pragma unroll
-            for (int j = 0; j < 16; ++j) s[j] += v[j];
-        }
+        const int x = i >> gshift, g = i & (G - 1);
+        const int d0 = 16 * g;
+        uint32_t S[8];
+        sum16<LT>(planes + ((size_t)y * a.W + x) * a.Dp + d0, a.plane, a.nplanes, S);
         uint32_t best = ~0u;
+        // right-view targets x - d0 - 15 .. x - d0 from one base address
+        uint32_t* tgt = keyR + (x - d0 - 15);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int d = 16 * g + j;
-            if (d < a.D) {
-                const uint32_t key = (s[j] << 9) | (uint32_t)d;
-                best = min(best, key);
-                if (right && x - d >= 0) atomicMin(&keyR[x - d], key);
+        for (int k = 0; k < 8; ++k) {
+            int dlo, dhi;
+            pair_disps<LT>(k, dlo, dhi);
+            const uint32_t dpair = (uint32_t)(d0 + dlo) | ((uint32_t)(d0 + dhi) << 8);
+            // key = [d, S.lo16, 0] with a 0xFF top byte for padded levels
+            const uint32_t klo = __builtin_amdgcn_perm(S[k], dpair, d0 + dlo < a.D ? 0x0C050400u : 0x0D050400u);
+            const uint32_t khi = __builtin_amdgcn_perm(S[k], dpair, d0 + dhi < a.D ? 0x0C070601u : 0x0D070601u);
+            best = min(best, min(klo, khi));
+            if (right) {
+                if (d0 + dlo < a.D) atomicMin(tgt + (15 - dlo), klo);
+                if (d0 + dhi < a.D) atomicMin(tgt + (15 - dhi), khi);
             }
         }
-        for (int o = 1; o < G; o <<= 1) best = min(best, (uint32_t)__shfl_xor((int)best, o));
-        if (g == 0) a.dl[(size_t)y * a.W + x] = (uint16_t)(best & 0x1FF);
+        best = lanes_min(best, G);
+        if (g == 0) a.dl[(size_t)y * a.W + x] = (uint16_t)(best & 0xFF);
     }
     if (right) {
         __syncthreads();
         for (int i = threadIdx.x; i < a.W; i += blockDim.x)
-            a.dr[(size_t)y * a.W + i] = (uint16_t)(keyR[i] & 0x1FF);
+            a.dr[(size_t)y * a.W + i] = (uint16_t)(keyR[i] & 0xFF);
     }
 }
 
@@ -744,7 +838,8 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 size_t workspace_bytes(const Plan& p) {
     const size_t npx = (size_t)p.W * p.H;
     const size_t cells = npx * p.Dp;
-    return align256(cells) + align256(cells * p.n_paths * (p.l16 ? 2 : 1)) + 2 * align256(npx * 2);
+    return align256(cells) + align256(cells * p.n_paths * (p.l16 ? 2 : 1)) + 2 * align256(npx * 2) +
+           2 * align256(npx * 8);
 }
 
 Workspace workspace_carve(const Plan& p, void* base) {
@@ -759,20 +854,35 @@ Workspace workspace_carve(const Plan& p, void* base) {
     ws.dl = reinterpret_cast<uint16_t*>(b);
     b += align256(npx * 2);
     ws.dr = reinterpret_cast<uint16_t*>(b);
+    b += align256(npx * 2);
+    ws.census_l = reinterpret_cast<uint64_t*>(b);
+    b += align256(npx * 8);
+    ws.census_r = reinterpret_cast<uint64_t*>(b);
     return ws;
+}
+
+static hipError_t launch_census_pair(const Plan& p, const uint8_t* left, const uint8_t* right, uint64_t* cl,
+                                     uint64_t* cr, int nimg, hipStream_t stream) {
+    CensusArgs a{{left, right}, {cl, cr}, p.W, p.H, p.csct ? 1 : 0};
+    if (p.cw == 9 && p.ch == 7) {
+        dim3 grid((p.W + kCenTX - 1) / kCenTX, (p.H + kCenTY - 1) / kCenTY, nimg);
+        hipLaunchKernelGGL(census97_kernel, grid, dim3(256), 0, stream, a);
+    } else {
+        dim3 grid((p.W + 15) / 16, (p.H + 15) / 16, nimg);
+        hipLaunchKernelGGL(census_generic_kernel, grid, dim3(256), 0, stream, a, (p.cw - 1) / 2, (p.ch - 1) / 2);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_census_cost(const Plan& p, const Workspace& ws, const uint8_t* left,
                               const uint8_t* right, hipStream_t stream) {
-    CostArgs a{left, right, ws.cost, p.W, p.H, p.D, p.Dp, (p.cw - 1) / 2, (p.ch - 1) / 2, p.cmax, p.csct ? 1 : 0};
+    hipError_t e = launch_census_pair(p, left, right, ws.census_l, ws.census_r, 2, stream);
+    if (e != hipSuccess) return e;
+    CostArgs a{ws.census_l, ws.census_r, ws.cost, p.W, p.H, p.D, p.Dp, p.cmax};
     const int nright = kCostTX + p.D - 1;
-    const int ncol = nright + 2 * a.rx;
-    const size_t smem = 8 * (size_t)(kCostTX + nright) + 2 * (size_t)(2 * a.ry + 1) * ncol;
+    const size_t smem = 8 * (size_t)((kCostTX + nright + 1) & ~1) + (size_t)kCostTX * (p.Dp + 16);
     dim3 grid((p.W + kCostTX - 1) / kCostTX, p.H);
-    if (p.cw == 9 && p.ch == 7)
-        hipLaunchKernelGGL((census_cost_kernel<4, 3>), grid, dim3(256), smem, stream, a);
-    else
-        hipLaunchKernelGGL((census_cost_kernel<0, 0>), grid, dim3(256), smem, stream, a);
+    hipLaunchKernelGGL(cost_kernel, grid, dim3(256), smem, stream, a);
     return hipGetLastError();
 }
 
@@ -866,7 +976,7 @@ hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStre
     const bool post = p.median || p.lrcheck;
     WtaArgs a{ws.lbuf, (size_t)p.W * p.H * p.Dp, post ? ws.dl : out, p.lrcheck ? ws.dr : nullptr,
               p.W, p.H, p.D, p.Dp, p.n_paths};
-    const size_t smem = p.lrcheck ? 4 * (size_t)p.W : 0;
+    const size_t smem = p.lrcheck ? 4 * (size_t)(p.W + kWtaGuard) : 0;
     if (p.l16)
         hipLaunchKernelGGL(wta_kernel<uint16_t>, dim3(p.H), dim3(1024), smem, stream, a);
     else
@@ -900,10 +1010,7 @@ hipError_t launch_pipeline(const Plan& p, const Workspace& ws, const uint8_t* le
 }
 
 hipError_t launch_census_only(const Plan& p, const uint8_t* img, uint64_t* out, hipStream_t stream) {
-    dim3 grid((p.W + 15) / 16, (p.H + 15) / 16);
-    hipLaunchKernelGGL(census_only_kernel, grid, dim3(256), 0, stream, img, out, p.W, p.H, (p.cw - 1) / 2,
-                       (p.ch - 1) / 2, p.csct ? 1 : 0);
-    return hipGetLastError();
+    return launch_census_pair(p, img, img, out, out, 1, stream);
 }
 
 hipError_t launch_sum_planes(const Plan& p, const Workspace& ws, uint16_t* s_out, hipStream_t stream) {

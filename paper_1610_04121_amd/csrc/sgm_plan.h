@@ -30,6 +30,8 @@ struct Workspace {
     void* lbuf = nullptr;      // L_r u8|u16 [n_paths][H][W][Dp]
     uint16_t* dl = nullptr;    // raw left disparity  u16 [H][W]
     uint16_t* dr = nullptr;    // raw right disparity u16 [H][W]
+    uint64_t* census_l = nullptr;  // census words of the base image u64 [H][W]
+    uint64_t* census_r = nullptr;  // census words of the match image u64 [H][W]
 };
 
 // Fills the derived fields of a plan; returns false if invalid (message set).
