@@ -72,6 +72,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-samples", type=int, default=300)
+    ap.add_argument("--inflight", type=int, default=2,
+                    help="frames in flight for the pipelined measurement (separate contexts "
+                         "and streams); 0 skips it")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -94,6 +97,8 @@ def main():
     right = torch.from_numpy(pair.right).to(dev)
     out = torch.empty((H, W), dtype=torch.uint16, device=dev)
     s = SGM(W, H, D, synth.P1_DEFAULT, synth.P2_DEFAULT, P, median=cfg["median"], lrcheck=cfg["lr"])
+    fused = os.environ.get("SGM_FUSED", "0") == "1"
+    s.set_tuning(0, 0, fused)
     print(f"bench: {WORKLOAD} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
@@ -123,6 +128,44 @@ def main():
         e1.synchronize()
         lat.append(e0.elapsed_time(e1))
     lat = np.array(lat)
+
+    # pipelined: several frames in flight, each on its own context and stream
+    pipelined = None
+    if args.inflight > 1:
+        ctxs = [s] + [SGM(W, H, D, synth.P1_DEFAULT, synth.P2_DEFAULT, P, median=cfg["median"],
+                          lrcheck=cfg["lr"]) for _ in range(args.inflight - 1)]
+        for c in ctxs[1:]:
+            c.set_tuning(0, 0, fused)
+        streams = [torch.cuda.Stream() for _ in ctxs]
+        outs = [torch.empty((H, W), dtype=torch.uint16, device=dev) for _ in ctxs]
+        for k in range(args.warmup):
+            j = k % len(ctxs)
+            ctxs[j].compute(left, right, outs[j], stream=streams[j])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            j = k % len(ctxs)
+            ctxs[j].compute(left, right, outs[j], stream=streams[j])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pipelined = {"frames_in_flight": len(ctxs), "value": round(args.steps / (t1 - t0), 2),
+                     "unit": "frames/s", "ms_per_step": round((t1 - t0) / args.steps * 1e3, 5)}
+        for c in ctxs[1:]:
+            c.close()
+
+    # achievable HBM bandwidth: a timed device-to-device copy of 512 MiB
+    nb = 512 << 20
+    csrc = torch.empty(nb, dtype=torch.uint8, device=dev)
+    cdst = torch.empty_like(csrc)
+    cdst.copy_(csrc)
+    ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ce0.record()
+    for _ in range(10):
+        cdst.copy_(csrc)
+    ce1.record()
+    ce1.synchronize()
+    copy_gbs = 2 * nb * 10 / (ce0.elapsed_time(ce1) * 1e-3) / 1e9
+    del csrc, cdst
 
     # the aggregation kernel reads the cost volume and writes one L_r plane
     # per direction: u8 costs, u8 L_r (Cmax + P2 = 148 < 256)
@@ -156,7 +199,10 @@ def main():
         "roofline": {"kernel": "aggregate_kernel", "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "alg_bytes_per_launch": agg_bytes,
-                     "mean_launch_ms": round(agg_ms, 5)},
+                     "mean_launch_ms": round(agg_ms, 5),
+                     "measured_copy_gbs": round(copy_gbs, 1),
+                     "frac_of_measured_copy": round(achieved / copy_gbs, 4)},
+        "pipelined": pipelined,
     }
     s.close()
     if args.copy_calibration_mb:

@@ -86,6 +86,16 @@ int sgm_set_options(sgm_ctx *ctx, unsigned flags, int lr_threshold);
 int sgm_compute(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right, uint16_t *disp_out,
                 sgm_stream_t stream);
 
+/* Kernel shape of the aggregation (results never depend on it):
+ *   lanes_h - lanes per horizontal slice (16, 32 or 64), lanes_v - lanes per
+ *   vertical / diagonal slice (16 or 32); 0 and 0 select the built-in default.
+ *   fused   - 0: a separate kernel writes the u8 cost volume C[H][W][Dp] that
+ *   the aggregation reads (the default); 1: the aggregation computes the
+ *   matching costs from census words itself (no cost volume in memory).
+ * sgm_get_tuning reports the shape in effect. */
+int sgm_set_tuning(sgm_ctx *ctx, int lanes_h, int lanes_v, int fused);
+int sgm_get_tuning(sgm_ctx *ctx, int *lanes_h, int *lanes_v, int *fused);
+
 /* Releases the context and its workspace (synchronizes the device first).
  * NULL is accepted. */
 void sgm_destroy(sgm_ctx *ctx);

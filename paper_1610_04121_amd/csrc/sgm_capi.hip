@@ -121,6 +121,9 @@ int sgm_set_options(sgm_ctx* c, unsigned flags, int lr_threshold) {
     sgm::Plan p = c->plan;
     if (!make_plan(p, p.W, p.H, p.D, p.P1, p.P2, p.n_paths, p.cw, p.ch, flags, lr_threshold))
         return SGM_EINVAL;
+    p.lanes_h = c->plan.lanes_h;
+    p.lanes_v = c->plan.lanes_v;
+    p.fused = c->plan.fused;
     c->plan = p;
     c->ws = sgm::workspace_carve(p, c->mem);
     return SGM_OK;
@@ -132,6 +135,28 @@ static void release_events(sgm_ctx* c) {
             for (hipEvent_t e : set) (void)hipEventDestroy(e);
     c->pending.clear();
     c->pool.clear();
+}
+
+int sgm_set_tuning(sgm_ctx* c, int lanes_h, int lanes_v, int fused) {
+    if (!c) return set_err(SGM_EINVAL, "null context");
+    auto ok = [](int g) { return g == 0 || g == 16 || g == 32 || g == 64; };
+    if (!ok(lanes_h) || !ok(lanes_v)) return set_err(SGM_EINVAL, "lanes must be 0, 16, 32 or 64");
+    if (lanes_v == 64) return set_err(SGM_EINVAL, "lanes_v must be 0, 16 or 32");
+    if ((lanes_h == 0) != (lanes_v == 0)) return set_err(SGM_EINVAL, "set both lane counts or neither");
+    c->plan.lanes_h = lanes_h;
+    c->plan.lanes_v = lanes_v;
+    c->plan.fused = fused != 0;
+    return SGM_OK;
+}
+
+int sgm_get_tuning(sgm_ctx* c, int* lanes_h, int* lanes_v, int* fused) {
+    if (!c) return set_err(SGM_EINVAL, "null context");
+    int gh = c->plan.lanes_h, gv = c->plan.lanes_v;
+    if (gh <= 0 || gv <= 0) sgm::default_lanes(c->plan, &gh, &gv);
+    if (lanes_h) *lanes_h = gh;
+    if (lanes_v) *lanes_v = gv;
+    if (fused) *fused = c->plan.fused ? 1 : 0;
+    return SGM_OK;
 }
 
 void sgm_destroy(sgm_ctx* c) {
@@ -212,7 +237,8 @@ int sgm_debug_sums(sgm_ctx* c, const uint8_t* left, const uint8_t* right, uint16
     if (!c) return set_err(SGM_EINVAL, "null context");
     if (int rc = check_ptrs(left, right, s_out)) return rc;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = sgm::launch_census_cost(c->plan, c->ws, left, right, s);
+    hipError_t e = sgm::launch_census(c->plan, c->ws, left, right, s);
+    if (e == hipSuccess && !c->plan.fused) e = sgm::launch_cost(c->plan, c->ws, s);
     if (e == hipSuccess) e = sgm::launch_aggregate(c->plan, c->ws, s);
     if (e == hipSuccess) e = sgm::launch_sum_planes(c->plan, c->ws, s_out, s);
     if (e != hipSuccess) return hip_err(e, "kernel launch");
@@ -225,7 +251,8 @@ int sgm_debug_stage(sgm_ctx* c, const uint8_t* left, const uint8_t* right, int w
     if (int rc = check_ptrs(left, right, out)) return rc;
     if (which < -1 || which >= c->plan.n_paths) return set_err(SGM_EINVAL, "stage index out of range");
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = sgm::launch_census_cost(c->plan, c->ws, left, right, s);
+    hipError_t e = sgm::launch_census(c->plan, c->ws, left, right, s);
+    if (e == hipSuccess && (which < 0 || !c->plan.fused)) e = sgm::launch_cost(c->plan, c->ws, s);
     if (e == hipSuccess && which >= 0) e = sgm::launch_aggregate(c->plan, c->ws, s);
     if (e == hipSuccess) e = sgm::launch_extract_plane(c->plan, c->ws, which, out, s);
     if (e != hipSuccess) return hip_err(e, "kernel launch");
@@ -241,7 +268,8 @@ int sgm_debug_raw_disparity(sgm_ctx* c, const uint8_t* left, const uint8_t* righ
     p.lrcheck = true;   // produce the right view too
     p.median = false;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = sgm::launch_census_cost(p, c->ws, left, right, s);
+    hipError_t e = sgm::launch_census(p, c->ws, left, right, s);
+    if (e == hipSuccess && !p.fused) e = sgm::launch_cost(p, c->ws, s);
     if (e == hipSuccess) e = sgm::launch_aggregate(p, c->ws, s);
     if (e == hipSuccess) e = sgm::launch_wta(p, c->ws, nullptr, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dl_out, c->ws.dl, (size_t)p.W * p.H * 2, hipMemcpyDeviceToDevice, s);

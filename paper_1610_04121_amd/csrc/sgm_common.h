@@ -14,6 +14,8 @@ constexpr int kMaxDirs = 8;
 constexpr int kMaxDisp = 256;
 constexpr int kMaxWidth = 16384;  // the WTA keeps one u32 key per column in LDS
 constexpr uint32_t kInvalid = 0xFFFF;
+// words of addressable space in front of each census buffer in the workspace
+constexpr int kCensusGuard = 256;
 
 // Path directions (rx, ry): 2 paths = left-to-right and top-to-bottom
 // (Sec. 4); 4 = the axial ones; 8 = axial plus diagonal.

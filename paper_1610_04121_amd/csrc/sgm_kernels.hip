@@ -12,6 +12,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 #include "sgm_plan.h"
 
@@ -247,6 +248,9 @@ __global__ __launch_bounds__(256) void cost_kernel(CostArgs a) {
 // ---------------------------------------------------------------------------
 struct AggArgs {
     const uint8_t* cost;
+    const uint64_t* census_l;  // fused variant: census words of both images
+    const uint64_t* census_r;
+    int cmax;
     void* lbuf;
     size_t plane;  // elements per L_r plane = H * W * Dp
     int W, H, D, Dp, P1, P2;
@@ -441,16 +445,70 @@ __device__ inline void store_l(__amdgpu_buffer_rsrc_t r, uint32_t ofs, const u16
     }
 }
 
+// Census words one lane needs for one step of the fused variant: the base
+// word of its group's pixel and the CPL match words of columns x - d for its
+// disparities d = q*CPL .. q*CPL + CPL - 1 (contiguous, lowest column first).
+template <int CPL>
+struct CensusStep {
+    uint64_t base;
+    uint64_t m[CPL];
+};
+
+template <int CPL>
+__device__ inline void load_census(__amdgpu_buffer_rsrc_t rcl, __amdgpu_buffer_rsrc_t rcr, uint32_t base_ofs,
+                                   uint32_t match_ofs, CensusStep<CPL>& cs) {
+    const auto b = __builtin_amdgcn_raw_buffer_load_b64(rcl, base_ofs, 0, 0);
+    cs.base = ((uint64_t)b[1] << 32) | b[0];
+#pragma unroll
+    for (int i = 0; i < CPL / 2; ++i) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rcr, match_ofs + 16 * i, 0, 0);
+        cs.m[2 * i] = ((uint64_t)v[1] << 32) | v[0];
+        cs.m[2 * i + 1] = ((uint64_t)v[3] << 32) | v[2];
+    }
+}
+
+// Hamming costs (Eq. 2) of a lane's CPL disparities, packed as the u16 pairs
+// of the split layout.  Cell c (disparity q*CPL + c) uses match word
+// m[CPL - 1 - c]; cells with c > valid_c (x - d < 0) cost cmax.  sel[k] puts
+// the costs of cells k and k + CPL/2 into the two halves of pair k, or 0xFFFF
+// for padded levels.
+template <int CPL, bool ALL_VALID>
+__device__ inline void census_costs(const CensusStep<CPL>& cs, int valid_c, uint32_t cmax,
+                                    const uint32_t (&sel)[CPL / 2], u16x2 (&c)[CPL / 2]) {
+    constexpr int NP = CPL / 2;
+    uint32_t pc[CPL];
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+        const uint64_t x = cs.base ^ cs.m[CPL - 1 - i];
+        pc[i] = (uint32_t)__popcll(x);
+        if constexpr (!ALL_VALID) pc[i] = i > valid_c ? cmax : pc[i];
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) c[k] = as2(__builtin_amdgcn_perm(pc[k + NP], pc[k], sel[k]));
+}
+
+// Selector of pair k for the fused variant: low half = cell k (S1 byte 0),
+// high half = cell k + CPL/2 (S0 byte 0, selector 4); 0xFFFF for d >= D.
+template <int CPL>
+__device__ inline uint32_t pack_selector(int k, int d0, int D) {
+    constexpr int NP = CPL / 2;
+    const uint32_t slo = (d0 + k < D) ? 0x0C00u : 0x0D0Du;
+    const uint32_t shi = (d0 + k + NP < D) ? 0x0C04u : 0x0D0Du;
+    return slo | (shi << 16);
+}
+
 // Cost loads run PF steps ahead of the recurrence so that their latency
 // overlaps the dependent min-plus chain of the steps in between.
 template <int CPL> struct Prefetch { static constexpr int N = CPL >= 16 ? 8 : 16; };
+template <int CPL> struct FusedPrefetch { static constexpr int N = CPL >= 16 ? 2 : 4; };
 
-template <int G, int CPL, typename LT, int KIND>
+template <int G, int CPL, typename LT, int KIND, bool FUSED>
 __device__ inline void aggregate_wave(const AggArgs& a, int r, int first_slice, int lane) {
     constexpr int NP = CPL / 2;
     constexpr int Dp = G * CPL;
-    constexpr int PF = Prefetch<CPL>::N;
-    using RawT = typename Raw<CPL>::T;
+    constexpr int PF = FUSED ? FusedPrefetch<CPL>::N : Prefetch<CPL>::N;
+    // per-step input: raw cost bytes, or census words (fused variant)
+    using RawT = std::conditional_t<FUSED, CensusStep<CPL>, typename Raw<CPL>::T>;
 
     const int rx = a.rx[r], ry = a.ry[r];
     const int W = a.W, H = a.H;
@@ -462,13 +520,20 @@ __device__ inline void aggregate_wave(const AggArgs& a, int r, int first_slice, 
 
     uint32_t sel[NP];
 #pragma unroll
-    for (int k = 0; k < NP; ++k) sel[k] = unpack_selector<CPL>(k, q * CPL, a.D);
+    for (int k = 0; k < NP; ++k)
+        sel[k] = FUSED ? pack_selector<CPL>(k, q * CPL, a.D) : unpack_selector<CPL>(k, q * CPL, a.D);
     const uint32_t edge_lo = q == 0 ? 0xFFFF0000u : 0u;      // no d-1 below d = 0
     const uint32_t edge_hi = q == G - 1 ? 0x0000FFFFu : 0u;  // no d+1 above Dp-1
     const u16x2 P1v = as2((uint32_t)a.P1 * 0x10001u), P2v = as2((uint32_t)a.P2 * 0x10001u);
 
     const uint32_t plane_bytes = (uint32_t)a.plane;  // cost plane, u8
-    const __amdgpu_buffer_rsrc_t rc = buffer_rsrc(a.cost, plane_bytes);
+    const __amdgpu_buffer_rsrc_t rc = buffer_rsrc(a.cost, FUSED ? 0u : plane_bytes);
+    // the match buffer starts kCensusGuard words early: a lane's window of
+    // CPL words may begin left of column 0 (those words are never used)
+    const uint32_t census_bytes = 8u * (uint32_t)W * (uint32_t)H;
+    const __amdgpu_buffer_rsrc_t rcl = buffer_rsrc(a.census_l, FUSED ? census_bytes : 0u);
+    const __amdgpu_buffer_rsrc_t rcr =
+        buffer_rsrc(a.census_r - kCensusGuard, FUSED ? census_bytes + 8u * kCensusGuard : 0u);
     const __amdgpu_buffer_rsrc_t rl = buffer_rsrc(
         reinterpret_cast<const LT*>(a.lbuf) + a.plane * a.plane_index[r], plane_bytes * (uint32_t)sizeof(LT));
 
@@ -495,6 +560,7 @@ __device__ inline void aggregate_wave(const AggArgs& a, int r, int first_slice, 
     };
     auto advance = [&](int& b, int& x) {
         b += bstep;
+        if constexpr (KIND == kHoriz) x += rx;
         if constexpr (KIND == kDiag) {
             x += rx;
             const int under = x >> 31;             // -1 if x < 0
@@ -512,7 +578,18 @@ __device__ inline void aggregate_wave(const AggArgs& a, int r, int first_slice, 
     // restart column of a diagonal group: where it crosses the side border
     const int border = rx > 0 ? 0 : W - 1;
 
+    // smallest column any group of the wavefront is at (uniform): when it is
+    // >= Dp - 1, every lane's disparities are valid (x - d >= 0)
+    int xmin_all = 0;
     auto step = [&](const RawT& raw) {
+        if constexpr (FUSED) {
+            if constexpr (KIND == kHoriz)
+                xmin_all = xc;
+            else if constexpr (KIND == kVert)
+                xmin_all = xc;
+            else
+                xmin_all = xc + 64 / G - 1 >= W ? 0 : xc;  // a wrapped group sits at a small column
+        }
         if constexpr (KIND == kDiag) {
             const int xl = xc + jg >= W ? xc + jg - W : xc + jg;
             if (xl == border) {
@@ -522,7 +599,25 @@ __device__ inline void aggregate_wave(const AggArgs& a, int r, int first_slice, 
             }
         }
         u16x2 c[NP];
-        unpack_costs<CPL>(raw, sel, c);
+        if constexpr (FUSED) {
+            // the lane's disparities are valid (x - d >= 0) for cells
+            // c <= x - q*CPL; x of the lane's group is group 0's column + jg
+            // (horizontal: same column; diagonal: wrapped)
+            int xg;
+            if constexpr (KIND == kHoriz)
+                xg = xc;
+            else if constexpr (KIND == kVert)
+                xg = xc + jg;
+            else
+                xg = xc + jg >= W ? xc + jg - W : xc + jg;
+            const int valid_c = xg - q * CPL;
+            if (xmin_all >= Dp - 1)
+                census_costs<CPL, true>(raw, valid_c, (uint32_t)a.cmax, sel, c);
+            else
+                census_costs<CPL, false>(raw, valid_c, (uint32_t)a.cmax, sel, c);
+        } else {
+            unpack_costs<CPL>(raw, sel, c);
+        }
         u16x2 lp[NP];
 #pragma unroll
         for (int k = 0; k < NP; ++k) lp[k] = vadds(L[k], P1v);
@@ -556,12 +651,25 @@ __device__ inline void aggregate_wave(const AggArgs& a, int r, int first_slice, 
     // lookahead position leads by PF - 1 steps and runs past the slice's end
     // near the finish; those loads are never consumed (and past the plane
     // they return 0).
+    auto load = [&](int b, int x) -> RawT {
+        if constexpr (FUSED) {
+            // pixel index of the lane's group: byte offset / Dp, with the
+            // lane's disparity offset qofs removed
+            const int pix = (int)((lane_ofs(b, x) - (uint32_t)qofs) / (uint32_t)Dp);
+            RawT cs;
+            load_census<CPL>(rcl, rcr, 8u * (uint32_t)pix,
+                             8u * (uint32_t)(pix + kCensusGuard - qofs - (CPL - 1)), cs);
+            return cs;
+        } else {
+            return buffer_load_raw<CPL>(rc, lane_ofs(b, x));
+        }
+    };
     RawT ring[PF];
     int ba = bo, xa = xc;
 #pragma unroll
     for (int j = 0; j < PF; ++j) {
         if (j) advance(ba, xa);
-        ring[j] = buffer_load_raw<CPL>(rc, lane_ofs(ba, xa));
+        ring[j] = load(ba, xa);
     }
     int k = 0;
     for (; k + PF <= steps; k += PF) {
@@ -569,7 +677,7 @@ __device__ inline void aggregate_wave(const AggArgs& a, int r, int first_slice, 
         for (int j = 0; j < PF; ++j) {
             const RawT raw = ring[j];
             advance(ba, xa);
-            ring[j] = buffer_load_raw<CPL>(rc, lane_ofs(ba, xa));
+            ring[j] = load(ba, xa);
             step(raw);
         }
     }
@@ -581,7 +689,7 @@ __device__ inline void aggregate_wave(const AggArgs& a, int r, int first_slice, 
 // One launch covers every direction.  Horizontal slices (the longest when
 // W > H) may use a different group width GH than the others (GV), so that
 // the longest dependency chains get the fewest instructions per step.
-template <int GH, int GV, int Dp, typename LT>
+template <int GH, int GV, int Dp, typename LT, bool FUSED>
 __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
@@ -589,11 +697,11 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
     int r = 0;
     while (r + 1 < a.ndirs && wave >= a.start[r + 1]) ++r;
     if (a.ry[r] == 0) {
-        aggregate_wave<GH, Dp / GH, LT, kHoriz>(a, r, (wave - a.start[r]) * (64 / GH), lane);
+        aggregate_wave<GH, Dp / GH, LT, kHoriz, FUSED>(a, r, (wave - a.start[r]) * (64 / GH), lane);
     } else if (a.rx[r] == 0) {
-        aggregate_wave<GV, Dp / GV, LT, kVert>(a, r, (wave - a.start[r]) * (64 / GV), lane);
+        aggregate_wave<GV, Dp / GV, LT, kVert, FUSED>(a, r, (wave - a.start[r]) * (64 / GV), lane);
     } else {
-        aggregate_wave<GV, Dp / GV, LT, kDiag>(a, r, (wave - a.start[r]) * (64 / GV), lane);
+        aggregate_wave<GV, Dp / GV, LT, kDiag, FUSED>(a, r, (wave - a.start[r]) * (64 / GV), lane);
     }
 }
 
@@ -839,7 +947,7 @@ size_t workspace_bytes(const Plan& p) {
     const size_t npx = (size_t)p.W * p.H;
     const size_t cells = npx * p.Dp;
     return align256(cells) + align256(cells * p.n_paths * (p.l16 ? 2 : 1)) + 2 * align256(npx * 2) +
-           2 * align256(npx * 8);
+           2 * align256(8 * (npx + kCensusGuard));
 }
 
 Workspace workspace_carve(const Plan& p, void* base) {
@@ -855,9 +963,9 @@ Workspace workspace_carve(const Plan& p, void* base) {
     b += align256(npx * 2);
     ws.dr = reinterpret_cast<uint16_t*>(b);
     b += align256(npx * 2);
-    ws.census_l = reinterpret_cast<uint64_t*>(b);
-    b += align256(npx * 8);
-    ws.census_r = reinterpret_cast<uint64_t*>(b);
+    ws.census_l = reinterpret_cast<uint64_t*>(b) + kCensusGuard;
+    b += align256(8 * (npx + kCensusGuard));
+    ws.census_r = reinterpret_cast<uint64_t*>(b) + kCensusGuard;
     return ws;
 }
 
@@ -874,10 +982,12 @@ static hipError_t launch_census_pair(const Plan& p, const uint8_t* left, const u
     return hipGetLastError();
 }
 
-hipError_t launch_census_cost(const Plan& p, const Workspace& ws, const uint8_t* left,
-                              const uint8_t* right, hipStream_t stream) {
-    hipError_t e = launch_census_pair(p, left, right, ws.census_l, ws.census_r, 2, stream);
-    if (e != hipSuccess) return e;
+hipError_t launch_census(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right,
+                         hipStream_t stream) {
+    return launch_census_pair(p, left, right, ws.census_l, ws.census_r, 2, stream);
+}
+
+hipError_t launch_cost(const Plan& p, const Workspace& ws, hipStream_t stream) {
     CostArgs a{ws.census_l, ws.census_r, ws.cost, p.W, p.H, p.D, p.Dp, p.cmax};
     const int nright = kCostTX + p.D - 1;
     const size_t smem = 8 * (size_t)((kCostTX + nright + 1) & ~1) + (size_t)kCostTX * (p.Dp + 16);
@@ -888,6 +998,9 @@ hipError_t launch_census_cost(const Plan& p, const Workspace& ws, const uint8_t*
 
 static void fill_agg_args(const Plan& p, const Workspace& ws, int SH, int SV, AggArgs& a) {
     a.cost = ws.cost;
+    a.census_l = ws.census_l;
+    a.census_r = ws.census_r;
+    a.cmax = p.cmax;
     a.lbuf = ws.lbuf;
     a.plane = (size_t)p.W * p.H * p.Dp;
     a.W = p.W;
@@ -919,37 +1032,37 @@ static void fill_agg_args(const Plan& p, const Workspace& ws, int SH, int SV, Ag
     a.total = acc;
 }
 
-template <int GH, int GV, int Dp, typename LT>
+template <int GH, int GV, int Dp, typename LT, bool FUSED>
 static hipError_t launch_agg_t(const Plan& p, const Workspace& ws, hipStream_t stream) {
     AggArgs a;
     fill_agg_args(p, ws, 64 / GH, 64 / GV, a);
-    hipLaunchKernelGGL((aggregate_kernel<GH, GV, Dp, LT>), dim3((a.total + 3) / 4), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL((aggregate_kernel<GH, GV, Dp, LT, FUSED>), dim3((a.total + 3) / 4), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 
-template <int Dp, typename LT>
+template <int Dp, typename LT, bool FUSED>
 static hipError_t launch_agg_dp(const Plan& p, const Workspace& ws, int gh, int gv, hipStream_t stream) {
     switch (gh * 100 + gv) {
-        case 1616: return launch_agg_t<16, 16, Dp, LT>(p, ws, stream);
-        case 3216: return launch_agg_t<32, 16, Dp, LT>(p, ws, stream);
-        case 3232: return launch_agg_t<32, 32, Dp, LT>(p, ws, stream);
+        case 1616: return launch_agg_t<16, 16, Dp, LT, FUSED>(p, ws, stream);
+        case 3216: return launch_agg_t<32, 16, Dp, LT, FUSED>(p, ws, stream);
+        case 3232: return launch_agg_t<32, 32, Dp, LT, FUSED>(p, ws, stream);
         default: break;
     }
     if constexpr (Dp >= 128) {  // 64 lanes need at least 2 levels per lane
-        if (gh == 64 && gv == 16) return launch_agg_t<64, 16, Dp, LT>(p, ws, stream);
-        if (gh == 64 && gv == 32) return launch_agg_t<64, 32, Dp, LT>(p, ws, stream);
+        if (gh == 64 && gv == 16) return launch_agg_t<64, 16, Dp, LT, FUSED>(p, ws, stream);
+        if (gh == 64 && gv == 32) return launch_agg_t<64, 32, Dp, LT, FUSED>(p, ws, stream);
     }
     return hipErrorInvalidValue;
 }
 
-template <typename LT>
+template <typename LT, bool FUSED>
 static hipError_t launch_agg_lt(const Plan& p, const Workspace& ws, int gh, int gv, hipStream_t stream) {
     if (p.Dp == 64) {
         // Dp = 64 has only 4 levels per lane at G = 16 and 2 at G = 32
-        return launch_agg_dp<64, LT>(p, ws, gh == 64 ? 32 : gh, gv, stream);
+        return launch_agg_dp<64, LT, FUSED>(p, ws, gh == 64 ? 32 : gh, gv == 64 ? 32 : gv, stream);
     }
-    if (p.Dp == 128) return launch_agg_dp<128, LT>(p, ws, gh, gv, stream);
-    return launch_agg_dp<256, LT>(p, ws, gh, gv, stream);
+    if (p.Dp == 128) return launch_agg_dp<128, LT, FUSED>(p, ws, gh, gv, stream);
+    return launch_agg_dp<256, LT, FUSED>(p, ws, gh, gv, stream);
 }
 
 // Group widths: horizontal slices are the longest chains on wide images,
@@ -969,7 +1082,11 @@ hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stre
             gv = b;
         }
     }
-    return p.l16 ? launch_agg_lt<uint16_t>(p, ws, gh, gv, stream) : launch_agg_lt<uint8_t>(p, ws, gh, gv, stream);
+    if (p.fused)
+        return p.l16 ? launch_agg_lt<uint16_t, true>(p, ws, gh, gv, stream)
+                     : launch_agg_lt<uint8_t, true>(p, ws, gh, gv, stream);
+    return p.l16 ? launch_agg_lt<uint16_t, false>(p, ws, gh, gv, stream)
+                 : launch_agg_lt<uint8_t, false>(p, ws, gh, gv, stream);
 }
 
 hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream) {
@@ -998,7 +1115,8 @@ hipError_t launch_pipeline(const Plan& p, const Workspace& ws, const uint8_t* le
         if (events && e == hipSuccess) e = hipEventRecord(events[i], stream);
     };
     mark(0);
-    if (e == hipSuccess) e = launch_census_cost(p, ws, left, right, stream);
+    if (e == hipSuccess) e = launch_census(p, ws, left, right, stream);
+    if (e == hipSuccess && !p.fused) e = launch_cost(p, ws, stream);
     mark(1);
     if (e == hipSuccess) e = launch_aggregate(p, ws, stream);
     mark(2);

@@ -20,6 +20,8 @@ struct Plan {
     int lr_thr = 1;
     int cmax = 0;              // largest matching cost
     bool l16 = false;          // L_r stored as u16 (else u8: Cmax + P2 <= 255)
+    bool fused = false;        // aggregation computes costs from census words
+                               // instead of reading the cost volume
     int lanes_h = 0, lanes_v = 0;  // lanes per aggregation slice, horizontal / other
                                    // directions (16, 32, 64; 0 = default)
 };
@@ -41,8 +43,9 @@ size_t workspace_bytes(const Plan& p);
 Workspace workspace_carve(const Plan& p, void* base);
 
 // Enqueue the stages (all asynchronous on `stream`).
-hipError_t launch_census_cost(const Plan& p, const Workspace& ws, const uint8_t* left,
-                              const uint8_t* right, hipStream_t stream);
+hipError_t launch_census(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right,
+                         hipStream_t stream);
+hipError_t launch_cost(const Plan& p, const Workspace& ws, hipStream_t stream);
 hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stream);
 void default_lanes(const Plan& p, int* gh, int* gv);
 hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream);

@@ -20,7 +20,7 @@ EXPORTS = [
     "sgm_validate", "sgm_create", "sgm_set_options", "sgm_compute", "sgm_destroy",
     "sgm_last_error", "sgm_footprint_bytes", "sgm_debug_census", "sgm_debug_sums",
     "sgm_debug_raw_disparity", "sgm_path_walk", "sgm_profile_enable", "sgm_profile_read",
-    "sgm_debug_stage",
+    "sgm_debug_stage", "sgm_set_tuning", "sgm_get_tuning",
 ]
 STAGES = ("census_cost", "aggregate", "wta", "post")
 
@@ -70,6 +70,10 @@ def lib() -> ctypes.CDLL:
     L.sgm_debug_raw_disparity.restype = i
     L.sgm_path_walk.argtypes = [i, i, i, i, i, i, P, P, P]
     L.sgm_path_walk.restype = i
+    L.sgm_set_tuning.argtypes = [P, i, i, i]
+    L.sgm_set_tuning.restype = i
+    L.sgm_get_tuning.argtypes = [P, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
+    L.sgm_get_tuning.restype = i
     L.sgm_debug_stage.argtypes = [P, P, P, i, P, P]
     L.sgm_debug_stage.restype = i
     L.sgm_profile_enable.argtypes = [P, i]
@@ -147,6 +151,15 @@ class SGM:
     def set_options(self, median=False, lrcheck=False, csct=False, lr_threshold=1):
         flags = (MEDIAN3 if median else 0) | (LRCHECK if lrcheck else 0) | (CENSUS_CSCT if csct else 0)
         _check(lib().sgm_set_options(self._ctx, flags, lr_threshold))
+
+    def set_tuning(self, lanes_h=0, lanes_v=0, fused=True):
+        """Aggregation kernel shape (does not change results)."""
+        _check(lib().sgm_set_tuning(self._ctx, lanes_h, lanes_v, 1 if fused else 0))
+
+    def tuning(self):
+        gh, gv, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().sgm_get_tuning(self._ctx, ctypes.byref(gh), ctypes.byref(gv), ctypes.byref(f)))
+        return gh.value, gv.value, bool(f.value)
 
     @property
     def shape(self):

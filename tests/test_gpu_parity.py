@@ -52,14 +52,21 @@ def test_census_parity(gpu, W, H, cw, ch, csct):
     assert (got == want).all()
 
 
+TUNINGS = [(0, 0, True), (16, 16, True), (32, 32, True), (64, 16, True), (64, 32, True),
+           (32, 16, False), (16, 16, False), (64, 32, False)]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS)
 @pytest.mark.parametrize("W,H,D,P,csct", [
     (37, 23, 16, 4, False), (29, 31, 20, 8, True), (70, 9, 130, 8, False), (5, 1, 256, 2, False),
+    (130, 40, 64, 8, False),
 ])
-def test_cost_and_per_direction_parity(gpu, W, H, D, P, csct):
+def test_cost_and_per_direction_parity(gpu, W, H, D, P, csct, tuning):
     rng = np.random.default_rng(W * 3 + H + D)
     l, r = _rand_pair(rng, W, H)
-    _say(f"stages {W}x{H} D={D} P={P} csct={csct}")
+    _say(f"stages {W}x{H} D={D} P={P} csct={csct} tuning={tuning}")
     s = SGM(W, H, D, 7, 86, P, csct=csct)
+    s.set_tuning(*tuning)
     tl, tr = _t(l, gpu), _t(r, gpu)
     cost = _np(s.debug_stage(tl, tr, -1))
     cl, cr = oracle.census(l, csct=csct), oracle.census(r, csct=csct)
@@ -107,13 +114,15 @@ def test_raw_disparity_parity(gpu, W, H, D, P):
     assert (dr == want.dr_raw).all()
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("name", list(synth.WORKLOADS))
-def test_workload_full_size_bit_exact(gpu, name):
+def test_workload_full_size_bit_exact(gpu, name, fused):
     cfg = synth.WORKLOADS[name]
     pair = synth.workload_pair(name)
-    _say(f"workload {name}")
+    _say(f"workload {name} fused={fused}")
     s = SGM(cfg["w"], cfg["h"], cfg["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, cfg["n_paths"],
             median=cfg["median"], lrcheck=cfg["lr"])
+    s.set_tuning(0, 0, fused)
     got = _np(s.compute(_t(pair.left, gpu), _t(pair.right, gpu)))
     s.close()
     want = oracle.sgm(pair.left, pair.right, cfg["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT,
@@ -137,8 +146,11 @@ def test_fuzz_pipeline(gpu, trial):
     l, r = _rand_pair(rng, W, H)
     if trial % 5 == 0:
         l = (l // 64 * 64).astype(np.uint8)  # many ties
-    _say(f"fuzz {trial}: {W}x{H} D={D} P={P} csct={csct} P1={P1} P2={P2} med={med} lr={lr} thr={thr}")
+    tuning = TUNINGS[trial % len(TUNINGS)]
+    _say(f"fuzz {trial}: {W}x{H} D={D} P={P} csct={csct} P1={P1} P2={P2} med={med} lr={lr} thr={thr} "
+         f"tuning={tuning}")
     s = SGM(W, H, D, P1, P2, P, median=med, lrcheck=lr, csct=csct, lr_threshold=thr)
+    s.set_tuning(*tuning)
     got = _np(s.compute(_t(l, gpu), _t(r, gpu)))
     s.close()
     want = oracle.sgm(l, r, D, P1, P2, P, median=med, lr=lr, csct=csct, lr_thr=thr).out
