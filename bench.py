@@ -1,15 +1,21 @@
 """Throughput of the SGM disparity pipeline on one MI355X.
 
-A step is one pass of the whole pipeline (census + cost, aggregation along
-all paths, sum + winner-take-all with the right view, median, left-right
-check) over one 640x480 pair with 128 disparity levels and 4 paths, inputs
-already resident in HBM.  Prints one JSON line:
+A step is one pass of the whole pipeline (census, cost volume, aggregation
+along all paths, sum + winner-take-all with the right view, median,
+left-right check) over one 640x480 pair with 128 disparity levels and 4
+paths, inputs already resident in HBM.  The timed region keeps F frames in
+flight (F contexts, each with its own workspace and stream; default F = 2):
+frame k runs on context k mod F.  Prints one JSON line:
 
   value         frames/s over the timed steps (whole job = one GPU);
   gcells_per_s  W*H*D*paths * frames/s / 1e9;
   roofline      the aggregation kernel (the dominant one) against HBM:
-                algorithmic bytes per launch / its mean duration measured
-                with HIP events recorded on the pipeline's stream;
+                algorithmic bytes per launch / its mean duration, measured
+                with HIP events recorded around it on its own stream in the
+                timed region, on every 8th frame of each context (with F > 1
+                other frames share the GPU meanwhile);
+  serialized    one frame at a time on one stream (eager and graph replay);
+  latency_ms    p50/p99 of single frames, event-bracketed;
   cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
                 same workload.
 """
@@ -36,7 +42,7 @@ def _kernel_sha() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def _traffic(launch_bytes_alg: float):
+def _traffic():
     """HBM bytes per aggregation launch from committed rocprofv3 counters,
     or None if the counters were taken on another version of the kernels."""
     try:
@@ -68,13 +74,14 @@ def cpu_baseline(pair, cfg, budget_s: float = 12.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--inflight", type=int, default=2, help="frames in flight in the timed region")
+    ap.add_argument("--profile-every", type=int, default=8,
+                    help="record stage events on every n-th frame of each context")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip serialized/latency/copy measurements")
     ap.add_argument("--latency-samples", type=int, default=300)
-    ap.add_argument("--inflight", type=int, default=2,
-                    help="frames in flight for the pipelined measurement (separate contexts "
-                         "and streams); 0 skips it")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -95,85 +102,101 @@ def main():
     dev = torch.device("cuda:0")
     left = torch.from_numpy(pair.left).to(dev)
     right = torch.from_numpy(pair.right).to(dev)
-    out = torch.empty((H, W), dtype=torch.uint16, device=dev)
-    s = SGM(W, H, D, synth.P1_DEFAULT, synth.P2_DEFAULT, P, median=cfg["median"], lrcheck=cfg["lr"])
     fused = os.environ.get("SGM_FUSED", "0") == "1"
-    s.set_tuning(0, 0, fused)
-    print(f"bench: {WORKLOAD} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+    F = max(1, args.inflight)
 
-    for _ in range(args.warmup):
-        s.compute(left, right, out)
+    def make_ctx(graph=False):
+        c = SGM(W, H, D, synth.P1_DEFAULT, synth.P2_DEFAULT, P, median=cfg["median"],
+                lrcheck=cfg["lr"], graph=graph)
+        c.set_tuning(0, 0, fused)
+        return c
+
+    ctxs = [make_ctx() for _ in range(F)]
+    streams = [torch.cuda.Stream() for _ in range(F)]
+    outs = [torch.empty((H, W), dtype=torch.uint16, device=dev) for _ in range(F)]
+    print(f"bench: {WORKLOAD} inflight={F} warmup={args.warmup} steps={args.steps}",
+          file=sys.stderr, flush=True)
+
+    def run(n):
+        for k in range(n):
+            j = k % F
+            ctxs[j].compute(left, right, outs[j], stream=streams[j])
+
+    run(args.warmup)
     torch.cuda.synchronize()
-
-    s.profile(True)
+    for c in ctxs:
+        c.profile(True, every=args.profile_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s.compute(left, right, out)
+    run(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ncalls, stage_ms = s.profile_read()
-    s.profile(False)
+    ncalls, stage_ms = 0, {}
+    for c in ctxs:
+        n, st = c.profile_read()
+        c.profile(False)
+        ncalls += n
+        for k, v in st.items():
+            stage_ms[k] = stage_ms.get(k, 0.0) + v
     elapsed = t1 - t0
     fps = args.steps / elapsed
+    tuning = ctxs[0].tuning()
 
-    # per-frame latency (separate, event-bracketed frames)
-    lat = []
-    st = torch.cuda.current_stream()
-    for _ in range(args.latency_samples):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        s.compute(left, right, out)
-        e1.record(st)
-        e1.synchronize()
-        lat.append(e0.elapsed_time(e1))
-    lat = np.array(lat)
-
-    # pipelined: several frames in flight, each on its own context and stream
-    pipelined = None
-    if args.inflight > 1:
-        ctxs = [s] + [SGM(W, H, D, synth.P1_DEFAULT, synth.P2_DEFAULT, P, median=cfg["median"],
-                          lrcheck=cfg["lr"]) for _ in range(args.inflight - 1)]
-        for c in ctxs[1:]:
-            c.set_tuning(0, 0, fused)
-        streams = [torch.cuda.Stream() for _ in ctxs]
-        outs = [torch.empty((H, W), dtype=torch.uint16, device=dev) for _ in ctxs]
-        for k in range(args.warmup):
-            j = k % len(ctxs)
-            ctxs[j].compute(left, right, outs[j], stream=streams[j])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            j = k % len(ctxs)
-            ctxs[j].compute(left, right, outs[j], stream=streams[j])
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        pipelined = {"frames_in_flight": len(ctxs), "value": round(args.steps / (t1 - t0), 2),
-                     "unit": "frames/s", "ms_per_step": round((t1 - t0) / args.steps * 1e3, 5)}
-        for c in ctxs[1:]:
-            c.close()
-
-    # achievable HBM bandwidth: a timed device-to-device copy of 512 MiB
-    nb = 512 << 20
-    csrc = torch.empty(nb, dtype=torch.uint8, device=dev)
-    cdst = torch.empty_like(csrc)
-    cdst.copy_(csrc)
-    ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ce0.record()
-    for _ in range(10):
+    extras = {}
+    if not args.no_extras:
+        # one frame at a time on one stream: eager, then graph replay
+        s0 = ctxs[0]
+        st0 = torch.cuda.current_stream()
+        for mode in ("eager", "graph"):
+            c = s0 if mode == "eager" else make_ctx(graph=True)
+            for _ in range(args.warmup):
+                c.compute(left, right, outs[0], stream=st0)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            for _ in range(args.steps // 2):
+                c.compute(left, right, outs[0], stream=st0)
+            torch.cuda.synchronize()
+            extras[mode] = round((args.steps // 2) / (time.perf_counter() - ta), 2)
+            if mode == "graph":
+                lat = []
+                for _ in range(args.latency_samples):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(st0)
+                    c.compute(left, right, outs[0], stream=st0)
+                    e1.record(st0)
+                    e1.synchronize()
+                    lat.append(e0.elapsed_time(e1))
+                lat = np.array(lat)
+                extras["latency_ms"] = {"p50": round(float(np.percentile(lat, 50)), 4),
+                                        "p99": round(float(np.percentile(lat, 99)), 4),
+                                        "mode": "graph replay, one frame in flight"}
+                c.close()
+        # achievable HBM bandwidth: a timed device-to-device copy of 512 MiB
+        nb = 512 << 20
+        csrc = torch.empty(nb, dtype=torch.uint8, device=dev)
+        cdst = torch.empty_like(csrc)
         cdst.copy_(csrc)
-    ce1.record()
-    ce1.synchronize()
-    copy_gbs = 2 * nb * 10 / (ce0.elapsed_time(ce1) * 1e-3) / 1e9
-    del csrc, cdst
+        ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ce0.record()
+        for _ in range(10):
+            cdst.copy_(csrc)
+        ce1.record()
+        ce1.synchronize()
+        extras["copy_gbs"] = round(2 * nb * 10 / (ce0.elapsed_time(ce1) * 1e-3) / 1e9, 1)
+        del csrc, cdst
 
-    # the aggregation kernel reads the cost volume and writes one L_r plane
-    # per direction: u8 costs, u8 L_r (Cmax + P2 = 148 < 256)
-    Dp = 64 * (1 if D <= 64 else (2 if D <= 128 else 4))
+    # the aggregation kernel reads the cost volume (u8) and writes one L_r
+    # plane (u8: Cmax + P2 = 148 < 256) per direction
+    Dp = 64 if D <= 64 else (128 if D <= 128 else 256)
     agg_bytes = P * W * H * Dp * (1 + 1)
     agg_ms = stage_ms["aggregate"] / max(ncalls, 1)
     achieved = agg_bytes / (agg_ms * 1e-3) / 1e9
-    traffic = _traffic(agg_bytes)
+    roof = {"kernel": "aggregate_kernel", "bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": _traffic(), "alg_bytes_per_launch": agg_bytes, "mean_launch_ms": round(agg_ms, 5)}
+    if "copy_gbs" in extras:
+        roof["measured_copy_gbs"] = extras["copy_gbs"]
+        roof["frac_of_measured_copy"] = round(achieved / extras["copy_gbs"], 4)
 
     line = {
         "metric": METRIC,
@@ -191,20 +214,17 @@ def main():
         "config": {"workload": WORKLOAD, "width": W, "height": H, "max_disp": D, "n_paths": P,
                    "census": "9x7 full", "P1": synth.P1_DEFAULT, "P2": synth.P2_DEFAULT,
                    "median": cfg["median"], "lr_check": cfg["lr"], "scene": cfg["scene"],
-                   "seed": cfg["seed"]},
+                   "seed": cfg["seed"], "frames_in_flight": F,
+                   "lanes_h": tuning[0], "lanes_v": tuning[1], "fused_cost": tuning[2]},
         "gcells_per_s": round(W * H * D * P * fps / 1e9, 2),
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                       "p99": round(float(np.percentile(lat, 99)), 4)},
         "stage_ms": {k: round(v / max(ncalls, 1), 5) for k, v in stage_ms.items()},
-        "roofline": {"kernel": "aggregate_kernel", "bound": "hbm", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "alg_bytes_per_launch": agg_bytes,
-                     "mean_launch_ms": round(agg_ms, 5),
-                     "measured_copy_gbs": round(copy_gbs, 1),
-                     "frac_of_measured_copy": round(achieved / copy_gbs, 4)},
-        "pipelined": pipelined,
+        "roofline": roof,
     }
-    s.close()
+    if extras:
+        line["serialized_fps"] = {"eager": extras["eager"], "graph": extras["graph"]}
+        line["latency_ms"] = extras["latency_ms"]
+    for c in ctxs:
+        c.close()
     if args.copy_calibration_mb:
         n = args.copy_calibration_mb << 20
         src = torch.empty(n, dtype=torch.uint8, device=dev)

@@ -51,13 +51,17 @@ enum {
 enum {
     SGM_MEDIAN3 = 1u,     /* 3x3 median of the left (and right) disparity */
     SGM_LRCHECK = 2u,     /* left-right consistency check */
-    SGM_CENSUS_CSCT = 4u  /* center-symmetric census (Eq. 1) instead of the
+    SGM_CENSUS_CSCT = 4u, /* center-symmetric census (Eq. 1) instead of the
                              full-window census */
+    SGM_GRAPH = 8u        /* replay a captured HIP graph of the pipeline when
+                             sgm_compute is called again with the same
+                             buffers (not while stage timing is enabled) */
 };
 
 /* Checks a parameter set without touching the GPU.  Returns SGM_OK or
  * SGM_EINVAL (message in sgm_last_error).  Rules:
- *   width, height >= 1; 1 <= max_disp <= 256; n_paths in {2, 4, 8};
+ *   1 <= width <= 16000, height >= 1; 1 <= max_disp <= 256; n_paths in {2, 4, 8};
+ *   width * height * Dp <= 2^30 (Dp = max_disp rounded up to 64, 128 or 256);
  *   census_w, census_h odd and >= 1; the census fits 64 bits (full:
  *   w*h <= 64; CSCT: (w*h - 1)/2 <= 64); P1, P2 >= 0;
  *   n_paths * (Cmax + P2) <= 65535, where Cmax = w*h - 1 (full) or
@@ -107,13 +111,52 @@ const char *sgm_last_error(void);
  * images and output are not counted).  0 if the shape is invalid. */
 size_t sgm_footprint_bytes(int width, int height, int max_disp, int n_paths, unsigned flags);
 
+/* ---- batches: many pairs of different shapes in one set of launches ----
+ * One item is one stereo pair with its own size, disparity range, path count
+ * and options (flags: SGM_MEDIAN3, SGM_LRCHECK; the census window and P1, P2
+ * belong to the batch).  Buffers follow the conventions above. */
+typedef struct {
+    int width, height, max_disp, n_paths;
+    unsigned flags;
+    int lr_threshold;
+    const uint8_t *left;
+    const uint8_t *right;
+    uint16_t *out;
+} sgm_item;
+
+typedef struct sgm_batch sgm_batch;
+
+/* A batch runner on the current HIP device.  NULL on error. */
+sgm_batch *sgm_batch_create(int P1, int P2, int census_w, int census_h);
+
+/* Enqueues all n items on `stream`: one census, one cost, one aggregation,
+ * one sum + winner-take-all and one median + LR launch for the whole batch.
+ * The aggregation is a persistent kernel whose wavefronts take (pair,
+ * direction, slice group) work items, longest first, from a queue.  The
+ * runner keeps a device workspace that grows to the largest batch seen;
+ * growing it waits for the device to go idle first.  Items must not share
+ * output buffers.  Results are identical to n separate sgm_compute calls. */
+int sgm_batch_compute(sgm_batch *b, const sgm_item *items, int n, sgm_stream_t stream);
+
+/* Device bytes sgm_batch_compute needs for these items (0 if one is invalid). */
+size_t sgm_batch_footprint(sgm_batch *b, const sgm_item *items, int n);
+
+/* Releases the runner (synchronizes the device first).  NULL is accepted. */
+void sgm_batch_destroy(sgm_batch *b);
+
+/* One-shot convenience: create a runner, compute, wait for the stream,
+ * destroy. */
+int sgm_compute_batch(const sgm_item *items, int n, int P1, int P2, int census_w, int census_h,
+                      sgm_stream_t stream);
+
 /* ---- stage timing ----
- * When enabled, every sgm_compute records HIP events on its stream before the
- * first stage and after each of the four stages (0 census + cost, 1
- * aggregation, 2 sum + winner-take-all, 3 median + LR).  sgm_profile_read
- * waits for the recorded calls, writes the summed milliseconds of each stage
- * into stage_ms[4] and the number of calls into *ncalls, and clears them. */
-int sgm_profile_enable(sgm_ctx *ctx, int enable);
+ * sgm_profile_enable(ctx, n) with n > 0 makes every n-th sgm_compute record
+ * HIP events on its stream before the first stage and after each of the four
+ * stages (0 census + cost, 1 aggregation, 2 sum + winner-take-all, 3 median +
+ * LR); n = 0 turns timing off.  sgm_profile_read waits for the recorded
+ * calls, writes the summed milliseconds of each stage into stage_ms[4] and the
+ * number of recorded calls into *ncalls, and clears them. */
+int sgm_profile_enable(sgm_ctx *ctx, int every_n);
 int sgm_profile_read(sgm_ctx *ctx, double *stage_ms, int *ncalls);
 
 /* ---- debug taps: intermediates for stage-by-stage parity tests ---- */

@@ -1,0 +1,454 @@
+// Batched SGM: many stereo pairs of different sizes, disparity ranges and
+// path counts in one launch per stage.
+//
+// Census, cost, WTA and post launches flatten every pair's blocks into one
+// grid; a block finds its pair by binary search over the pairs' first-block
+// offsets.  The aggregation is a persistent kernel: its wavefronts take work
+// items (pair, direction, group of slices) from a queue in device memory,
+// longest slices first, through a vector atomic counter that the census
+// launch resets (no memset, so the launches can also be graph-captured).
+// Items are independent within the aggregation, so no wavefront ever waits
+// for another and every wavefront leaves the loop when the queue is empty.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sgm.h"
+#include "sgm_batch.h"
+#include "sgm_device.h"
+#include "sgm_plan.h"
+
+namespace sgm {
+
+namespace {
+
+using namespace dev;
+
+// One pair as the batched kernels see it.
+struct BatchItem {
+    const uint8_t* left;
+    const uint8_t* right;
+    uint16_t* out;
+    uint64_t* census_l;
+    uint64_t* census_r;
+    uint8_t* cost;
+    void* lbuf;
+    uint16_t* dl;
+    uint16_t* dr;
+    int W, H, D, Dp, P, cmax, l16, median, lrcheck, thr, csct, gh;
+    int census_blk0, cost_blk0, wta_blk0, post_blk0;  // first block in each launch
+};
+
+// One aggregation work item: S = 64 / G slices of one direction of one pair.
+struct WorkItem {
+    int item, plane, rx, ry, first, steps;
+};
+
+// Index of the pair whose block range [blk0, next blk0) holds block b.
+template <int BatchItem::*FIRST>
+__device__ inline int find_item(const BatchItem* items, int n, int b) {
+    int lo = 0, hi = n;  // items[lo].*FIRST <= b < items[hi].*FIRST
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (items[mid].*FIRST <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void census_batch_kernel(const BatchItem* items, int n, int generic, int rx,
+                                                           int ry, unsigned* queue_counter) {
+    const int b = blockIdx.x;
+    if (b == 0 && threadIdx.x == 0) *queue_counter = 0u;  // the aggregation launch follows
+    const int i = find_item<&BatchItem::census_blk0>(items, n, b);
+    const BatchItem& it = items[i];
+    const int local = b - it.census_blk0;
+    CensusArgs a{{it.left, it.right}, {it.census_l, it.census_r}, it.W, it.H, it.csct};
+    if (!generic) {
+        const int nx = (it.W + kCenTX - 1) / kCenTX, ny = (it.H + kCenTY - 1) / kCenTY;
+        const int z = local / (nx * ny), rem = local - z * nx * ny;
+        census97_block(a, rem % nx, rem / nx, z);
+    } else {
+        const int nx = (it.W + 15) / 16, ny = (it.H + 15) / 16;
+        const int z = local / (nx * ny), rem = local - z * nx * ny;
+        census_generic_block(a, rx, ry, rem % nx, rem / nx, z);
+    }
+}
+
+__global__ __launch_bounds__(256) void cost_batch_kernel(const BatchItem* items, int n) {
+    extern __shared__ __align__(16) uint64_t cost_smem[];
+    const int b = blockIdx.x;
+    const BatchItem& it = items[find_item<&BatchItem::cost_blk0>(items, n, b)];
+    const int local = b - it.cost_blk0;
+    const int nx = (it.W + kCostTX - 1) / kCostTX;
+    CostArgs a{it.census_l, it.census_r, it.cost, it.W, it.H, it.D, it.Dp, it.cmax};
+    cost_block(a, local % nx, local / nx, cost_smem);
+}
+
+template <typename LT, int Dp>
+__device__ inline void aggregate_item(const SliceArgs& s, int kind, int gh, int first, int lane) {
+    if (kind == kHoriz) {
+        if (gh == 32)
+            aggregate_wave<32, Dp / 32, LT, kHoriz, false>(s, first, lane);
+        else
+            aggregate_wave<16, Dp / 16, LT, kHoriz, false>(s, first, lane);
+    } else if (kind == kVert) {
+        aggregate_wave<16, Dp / 16, LT, kVert, false>(s, first, lane);
+    } else {
+        aggregate_wave<16, Dp / 16, LT, kDiag, false>(s, first, lane);
+    }
+}
+
+__global__ __launch_bounds__(256) void aggregate_batch_kernel(const BatchItem* items, const WorkItem* work,
+                                                              int nwork, unsigned* queue_counter, int P1, int P2) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned idx = 0;
+        if (lane == 0) idx = atomicAdd(queue_counter, 1u);
+        idx = __builtin_amdgcn_readfirstlane(idx);
+        if (idx >= (unsigned)nwork) break;
+        const WorkItem w = work[idx];
+        const BatchItem& it = items[w.item];
+        const uint32_t plane = (uint32_t)it.W * (uint32_t)it.H * (uint32_t)it.Dp;
+        void* lplane = it.l16 ? (void*)(reinterpret_cast<uint16_t*>(it.lbuf) + (size_t)plane * w.plane)
+                              : (void*)(reinterpret_cast<uint8_t*>(it.lbuf) + (size_t)plane * w.plane);
+        const SliceArgs s{it.cost, it.census_l, it.census_r, lplane, plane, it.W, it.H, it.D, P1, P2, it.cmax, w.rx,
+                          w.ry};
+        const int kind = w.ry == 0 ? kHoriz : (w.rx == 0 ? kVert : kDiag);
+        if (it.l16) {
+            if (it.Dp == 64) aggregate_item<uint16_t, 64>(s, kind, it.gh, w.first, lane);
+            else if (it.Dp == 128) aggregate_item<uint16_t, 128>(s, kind, it.gh, w.first, lane);
+            else aggregate_item<uint16_t, 256>(s, kind, it.gh, w.first, lane);
+        } else {
+            if (it.Dp == 64) aggregate_item<uint8_t, 64>(s, kind, it.gh, w.first, lane);
+            else if (it.Dp == 128) aggregate_item<uint8_t, 128>(s, kind, it.gh, w.first, lane);
+            else aggregate_item<uint8_t, 256>(s, kind, it.gh, w.first, lane);
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void wta_batch_kernel(const BatchItem* items, int n) {
+    extern __shared__ uint32_t wta_smem[];
+    const int b = blockIdx.x;
+    const BatchItem& it = items[find_item<&BatchItem::wta_blk0>(items, n, b)];
+    const bool post = it.median || it.lrcheck;
+    WtaArgs a{it.lbuf, (size_t)it.W * it.H * it.Dp, post ? it.dl : it.out, it.lrcheck ? it.dr : nullptr,
+              it.W, it.H, it.D, it.Dp, it.P};
+    if (it.l16)
+        wta_row<uint16_t>(a, b - it.wta_blk0, wta_smem);
+    else
+        wta_row<uint8_t>(a, b - it.wta_blk0, wta_smem);
+}
+
+__global__ __launch_bounds__(256) void post_batch_kernel(const BatchItem* items, int n) {
+    extern __shared__ uint16_t post_smem[];
+    const int b = blockIdx.x;
+    const BatchItem& it = items[find_item<&BatchItem::post_blk0>(items, n, b)];
+    PostArgs a{it.dl, it.dr, it.out, it.W, it.H, it.median, it.lrcheck, it.thr};
+    post_row(a, b - it.post_blk0, post_smem);
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+bool batch_plan(const BatchParams& bp, const sgm_item* items, int n, BatchLayout& L, const char** why) {
+    L.plans.clear();
+    L.offsets.clear();
+    L.total = 0;
+    if (n < 0 || (n > 0 && !items)) {
+        *why = "bad item array";
+        return false;
+    }
+    for (int i = 0; i < n; ++i) {
+        const sgm_item& it = items[i];
+        Plan p;
+        p.W = it.width;
+        p.H = it.height;
+        p.D = it.max_disp;
+        p.P1 = bp.P1;
+        p.P2 = bp.P2;
+        p.n_paths = it.n_paths;
+        p.cw = bp.cw;
+        p.ch = bp.ch;
+        p.csct = bp.csct;
+        p.median = (it.flags & SGM_MEDIAN3) != 0;
+        p.lrcheck = (it.flags & SGM_LRCHECK) != 0;
+        p.lr_thr = it.lr_threshold;
+        if (it.flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK)) {
+            *why = "item flags may only hold SGM_MEDIAN3 and SGM_LRCHECK";
+            return false;
+        }
+        if (!plan_finish(p, why)) return false;
+        L.offsets.push_back(L.total);
+        L.total += align256(workspace_bytes(p));
+        L.plans.push_back(p);
+    }
+    L.counter_offset = L.total;
+    L.total += 256;
+    return true;
+}
+
+}  // namespace sgm
+
+using sgm::BatchItem;
+using sgm::WorkItem;
+
+struct sgm_batch {
+    sgm::BatchParams bp;
+    int device = 0;
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    BatchItem* d_items = nullptr;
+    WorkItem* d_work = nullptr;
+    size_t items_cap = 0, work_cap = 0;
+    BatchItem* h_items = nullptr;  // pinned staging
+    WorkItem* h_work = nullptr;
+    hipEvent_t staged = nullptr;   // the last copy out of the staging buffers
+    bool staged_pending = false;
+};
+
+namespace {
+
+int berr(int code, const std::string& m) {
+    sgm::set_last_error(m);
+    return code;
+}
+
+int bhip(hipError_t e, const char* what) { return berr(SGM_EHIP, std::string(what) + ": " + hipGetErrorString(e)); }
+
+int grow_staging(sgm_batch* b, size_t nitems, size_t nwork) {
+    if (b->staged_pending) {
+        hipError_t e = hipEventSynchronize(b->staged);
+        if (e != hipSuccess) return bhip(e, "hipEventSynchronize");
+        b->staged_pending = false;
+    }
+    if (nitems > b->items_cap) {
+        size_t cap = std::max(nitems, 2 * b->items_cap);
+        if (b->h_items) (void)hipHostFree(b->h_items);
+        if (b->d_items) (void)hipFree(b->d_items);
+        b->h_items = nullptr;
+        b->d_items = nullptr;
+        b->items_cap = 0;
+        if (hipHostMalloc((void**)&b->h_items, cap * sizeof(BatchItem), hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void**)&b->d_items, cap * sizeof(BatchItem)) != hipSuccess)
+            return berr(SGM_ENOMEM, "batch descriptor allocation failed");
+        b->items_cap = cap;
+    }
+    if (nwork > b->work_cap) {
+        size_t cap = std::max(nwork, 2 * b->work_cap);
+        if (b->h_work) (void)hipHostFree(b->h_work);
+        if (b->d_work) (void)hipFree(b->d_work);
+        b->h_work = nullptr;
+        b->d_work = nullptr;
+        b->work_cap = 0;
+        if (hipHostMalloc((void**)&b->h_work, cap * sizeof(WorkItem), hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void**)&b->d_work, cap * sizeof(WorkItem)) != hipSuccess)
+            return berr(SGM_ENOMEM, "batch work-queue allocation failed");
+        b->work_cap = cap;
+    }
+    return SGM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sgm_batch* sgm_batch_create(int P1, int P2, int census_w, int census_h) {
+    sgm::Plan probe;  // validate the batch-wide parameters on a 1x1 pair
+    probe.W = probe.H = probe.D = 1;
+    probe.P1 = P1;
+    probe.P2 = P2;
+    probe.n_paths = 2;
+    probe.cw = census_w;
+    probe.ch = census_h;
+    const char* why = "invalid parameters";
+    if (!sgm::plan_finish(probe, &why)) {
+        berr(SGM_EINVAL, why);
+        return nullptr;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        bhip(e, "hipGetDevice");
+        return nullptr;
+    }
+    sgm_batch* b = new (std::nothrow) sgm_batch;
+    if (!b) {
+        berr(SGM_ENOMEM, "host allocation failed");
+        return nullptr;
+    }
+    b->bp = sgm::BatchParams{P1, P2, census_w, census_h, false};
+    b->device = dev;
+    e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        bhip(e, "hipEventCreate");
+        delete b;
+        return nullptr;
+    }
+    return b;
+}
+
+size_t sgm_batch_footprint(sgm_batch* b, const sgm_item* items, int n) {
+    if (!b) return 0;
+    sgm::BatchLayout L;
+    const char* why = "";
+    if (!sgm::batch_plan(b->bp, items, n, L, &why)) return 0;
+    return L.total;
+}
+
+int sgm_batch_compute(sgm_batch* b, const sgm_item* items, int n, sgm_stream_t stream) {
+    using namespace sgm;
+    if (!b) return berr(SGM_EINVAL, "null batch");
+    if (n == 0) return SGM_OK;
+    BatchLayout L;
+    const char* why = "invalid item";
+    if (!batch_plan(b->bp, items, n, L, &why)) return berr(SGM_EINVAL, why);
+    for (int i = 0; i < n; ++i) {
+        if (!items[i].left || !items[i].right || !items[i].out) return berr(SGM_EINVAL, "null buffer pointer");
+        if ((const void*)items[i].out == (const void*)items[i].left ||
+            (const void*)items[i].out == (const void*)items[i].right)
+            return berr(SGM_EINVAL, "output aliases an input");
+    }
+    hipStream_t s = (hipStream_t)stream;
+
+    // workspace: grows (after the device is idle) to the largest batch seen
+    if (L.total > b->arena_bytes) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return bhip(e, "hipDeviceSynchronize");
+        if (b->arena) (void)hipFree(b->arena);
+        b->arena = nullptr;
+        b->arena_bytes = 0;
+        e = hipMalloc(&b->arena, L.total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return berr(SGM_ENOMEM, std::string("batch workspace allocation failed: ") + hipGetErrorString(e));
+        }
+        b->arena_bytes = L.total;
+    }
+
+    // work items: every direction's slices of every pair, S per wavefront
+    std::vector<WorkItem> work;
+    size_t census_blocks = 0, cost_blocks = 0, wta_blocks = 0, post_blocks = 0;
+    std::vector<BatchItem> desc(n);
+    const bool generic = !(b->bp.cw == 9 && b->bp.ch == 7);
+    size_t cost_smem = 0, wta_smem = 0, post_smem = 0;
+    for (int i = 0; i < n; ++i) {
+        const Plan& p = L.plans[i];
+        const Workspace ws = workspace_carve(p, static_cast<uint8_t*>(b->arena) + L.offsets[i]);
+        int gh, gv;
+        default_lanes(p, &gh, &gv);
+        BatchItem& d = desc[i];
+        d.left = items[i].left;
+        d.right = items[i].right;
+        d.out = items[i].out;
+        d.census_l = ws.census_l;
+        d.census_r = ws.census_r;
+        d.cost = ws.cost;
+        d.lbuf = ws.lbuf;
+        d.dl = ws.dl;
+        d.dr = ws.dr;
+        d.W = p.W;
+        d.H = p.H;
+        d.D = p.D;
+        d.Dp = p.Dp;
+        d.P = p.n_paths;
+        d.cmax = p.cmax;
+        d.l16 = p.l16 ? 1 : 0;
+        d.median = p.median ? 1 : 0;
+        d.lrcheck = p.lrcheck ? 1 : 0;
+        d.thr = p.lr_thr;
+        d.csct = p.csct ? 1 : 0;
+        d.gh = gh;
+        d.census_blk0 = (int)census_blocks;
+        census_blocks += generic ? (size_t)2 * ((p.W + 15) / 16) * ((p.H + 15) / 16)
+                                 : (size_t)2 * ((p.W + kCenTX - 1) / kCenTX) * ((p.H + kCenTY - 1) / kCenTY);
+        d.cost_blk0 = (int)cost_blocks;
+        cost_blocks += (size_t)((p.W + kCostTX - 1) / kCostTX) * p.H;
+        d.wta_blk0 = (int)wta_blocks;
+        wta_blocks += p.H;
+        d.post_blk0 = (int)post_blocks;
+        if (p.median || p.lrcheck) post_blocks += p.H;
+        const int nright = kCostTX + p.D - 1;
+        cost_smem = std::max(cost_smem, 8 * (size_t)((kCostTX + nright + 1) & ~1) + (size_t)kCostTX * (p.Dp + 16));
+        if (p.lrcheck) {
+            wta_smem = std::max(wta_smem, 4 * (size_t)(p.W + kWtaGuard));
+            post_smem = std::max(post_smem, 2 * (size_t)p.W);
+        }
+        for (int r = 0; r < p.n_paths; ++r) {
+            const Dir dir = direction(p.n_paths, r);
+            const int S = 64 / (dir.ry == 0 ? gh : gv);
+            const int nsl = slice_count(p.W, p.H, dir), steps = slice_steps(p.W, p.H, dir);
+            for (int f = 0; f < nsl; f += S) work.push_back(WorkItem{i, r, dir.rx, dir.ry, f, steps});
+        }
+    }
+    // longest slices first (largest-processing-time-first order)
+    std::stable_sort(work.begin(), work.end(), [](const WorkItem& a, const WorkItem& c) { return a.steps > c.steps; });
+    if (census_blocks > 0x7FFFFFFF || cost_blocks > 0x7FFFFFFF) return berr(SGM_EINVAL, "batch too large");
+
+    if (int rc = grow_staging(b, desc.size(), work.size())) return rc;
+    memcpy(b->h_items, desc.data(), desc.size() * sizeof(BatchItem));
+    memcpy(b->h_work, work.data(), work.size() * sizeof(WorkItem));
+    hipError_t e = hipMemcpyAsync(b->d_items, b->h_items, desc.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_work, b->h_work, work.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(b->staged, s);
+    if (e != hipSuccess) return bhip(e, "descriptor copy");
+    b->staged_pending = true;
+
+    unsigned* counter = reinterpret_cast<unsigned*>(static_cast<uint8_t*>(b->arena) + L.counter_offset);
+    hipLaunchKernelGGL(census_batch_kernel, dim3((unsigned)census_blocks), dim3(256), 0, s, b->d_items, n,
+                       generic ? 1 : 0, (b->bp.cw - 1) / 2, (b->bp.ch - 1) / 2, counter);
+    hipLaunchKernelGGL(cost_batch_kernel, dim3((unsigned)cost_blocks), dim3(256), cost_smem, s, b->d_items, n);
+    // persistent grid: at most two wavefronts per SIMD (256 CUs x 4 SIMDs)
+    const int nwork = (int)work.size();
+    const int waves = std::min(nwork, 2048);
+    hipLaunchKernelGGL(aggregate_batch_kernel, dim3((waves + 3) / 4), dim3(256), 0, s, b->d_items, b->d_work, nwork,
+                       counter, b->bp.P1, b->bp.P2);
+    hipLaunchKernelGGL(wta_batch_kernel, dim3((unsigned)wta_blocks), dim3(1024), wta_smem, s, b->d_items, n);
+    if (post_blocks > 0) {
+        // pairs without a post stage own empty block ranges; the search for
+        // the last pair whose range starts at or before a block skips them
+        hipLaunchKernelGGL(post_batch_kernel, dim3((unsigned)post_blocks), dim3(256), post_smem, s, b->d_items, n);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return bhip(e, "batch kernel launch");
+    return SGM_OK;
+}
+
+void sgm_batch_destroy(sgm_batch* b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    if (b->arena) (void)hipFree(b->arena);
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_work) (void)hipFree(b->d_work);
+    if (b->h_items) (void)hipHostFree(b->h_items);
+    if (b->h_work) (void)hipHostFree(b->h_work);
+    if (b->staged) (void)hipEventDestroy(b->staged);
+    delete b;
+}
+
+int sgm_compute_batch(const sgm_item* items, int n, int P1, int P2, int census_w, int census_h,
+                      sgm_stream_t stream) {
+    sgm_batch* b = sgm_batch_create(P1, P2, census_w, census_h);
+    if (!b) return SGM_EINVAL;
+    int rc = sgm_batch_compute(b, items, n, stream);
+    if (rc == SGM_OK) {
+        hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) rc = bhip(e, "hipStreamSynchronize");
+    }
+    sgm_batch_destroy(b);
+    return rc;
+}
+
+}  // extern "C"

@@ -9,11 +9,18 @@
 #include <vector>
 
 #include "../../include/sgm.h"
+#include "sgm_batch.h"
 #include "sgm_plan.h"
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace sgm {
+void set_last_error(const std::string& msg) { g_err = msg; }
+}  // namespace sgm
+
+namespace {
 
 int set_err(int code, const std::string& msg) {
     g_err = msg;
@@ -39,7 +46,7 @@ bool make_plan(sgm::Plan& p, int w, int h, int d, int P1, int P2, int n_paths, i
     p.lrcheck = (flags & SGM_LRCHECK) != 0;
     p.lr_thr = thr;
     const char* why = "invalid parameters";
-    if (flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK | SGM_CENSUS_CSCT)) {
+    if (flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK | SGM_CENSUS_CSCT | SGM_GRAPH)) {
         set_err(SGM_EINVAL, "unknown flag bits");
         return false;
     }
@@ -60,9 +67,27 @@ struct sgm_ctx {
     int device = 0;
     // stage timing: one set of kNumStages + 1 events per profiled call
     bool profiling = false;
+    int profile_every = 1;  // record events on every n-th call
+    long long calls = 0;
     using EventSet = std::array<hipEvent_t, sgm::kNumStages + 1>;
     std::vector<EventSet> pending, pool;
+    // graph replay (SGM_GRAPH): executable graphs keyed by the caller's
+    // buffers, captured on a private stream, most recently used first
+    bool use_graph = false;
+    struct GraphEntry {
+        const void *left, *right, *out;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t capture_stream = nullptr;
 };
+
+static constexpr size_t kMaxGraphs = 8;
+
+static void drop_graphs(sgm_ctx* c) {
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
 
 extern "C" {
 
@@ -126,6 +151,8 @@ int sgm_set_options(sgm_ctx* c, unsigned flags, int lr_threshold) {
     p.fused = c->plan.fused;
     c->plan = p;
     c->ws = sgm::workspace_carve(p, c->mem);
+    c->use_graph = (flags & SGM_GRAPH) != 0;
+    drop_graphs(c);
     return SGM_OK;
 }
 
@@ -146,6 +173,7 @@ int sgm_set_tuning(sgm_ctx* c, int lanes_h, int lanes_v, int fused) {
     c->plan.lanes_h = lanes_h;
     c->plan.lanes_v = lanes_v;
     c->plan.fused = fused != 0;
+    drop_graphs(c);
     return SGM_OK;
 }
 
@@ -164,13 +192,18 @@ void sgm_destroy(sgm_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     release_events(c);
+    drop_graphs(c);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->mem) (void)hipFree(c->mem);
     delete c;
 }
 
-int sgm_profile_enable(sgm_ctx* c, int enable) {
+int sgm_profile_enable(sgm_ctx* c, int every_n) {
     if (!c) return set_err(SGM_EINVAL, "null context");
-    c->profiling = enable != 0;
+    if (every_n < 0) return set_err(SGM_EINVAL, "every_n must be >= 0");
+    c->profiling = every_n > 0;
+    c->profile_every = every_n > 0 ? every_n : 1;
+    c->calls = 0;
     return SGM_OK;
 }
 
@@ -206,8 +239,46 @@ int sgm_compute(sgm_ctx* c, const uint8_t* left, const uint8_t* right, uint16_t*
     if (int rc = check_ptrs(left, right, disp_out)) return rc;
     if ((const void*)disp_out == (const void*)left || (const void*)disp_out == (const void*)right)
         return set_err(SGM_EINVAL, "output aliases an input");
+    if (c->use_graph && !c->profiling) {  // (stage timing uses eager launches)
+        // replay a graph captured for these buffers, capturing it first if needed
+        size_t i = 0;
+        while (i < c->graphs.size() &&
+               !(c->graphs[i].left == left && c->graphs[i].right == right && c->graphs[i].out == disp_out))
+            ++i;
+        if (i == c->graphs.size()) {
+            hipError_t e = hipSuccess;
+            if (!c->capture_stream) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_err(e, "hipStreamCreate");
+            e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_err(e, "hipStreamBeginCapture");
+            hipError_t le = sgm::launch_pipeline(c->plan, c->ws, left, right, disp_out, c->capture_stream);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(c->capture_stream, &graph);
+            if (le != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return hip_err(le, "kernel launch during capture");
+            }
+            if (e != hipSuccess) return hip_err(e, "hipStreamEndCapture");
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return hip_err(e, "hipGraphInstantiate");
+            if (c->graphs.size() == kMaxGraphs) {
+                (void)hipGraphExecDestroy(c->graphs.back().exec);
+                c->graphs.pop_back();
+            }
+            c->graphs.insert(c->graphs.begin(), {left, right, disp_out, exec});
+            i = 0;
+        } else if (i > 0) {
+            std::swap(c->graphs[i], c->graphs[0]);
+            i = 0;
+        }
+        hipError_t e = hipGraphLaunch(c->graphs[i].exec, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_err(e, "hipGraphLaunch");
+        return SGM_OK;
+    }
     hipEvent_t* events = nullptr;
-    if (c->profiling) {
+    if (c->profiling && (c->calls++ % c->profile_every) == 0) {
         if (c->pool.empty()) {
             sgm_ctx::EventSet set;
             for (auto& ev : set) {

@@ -1,0 +1,863 @@
+// Device code of the SGM pipeline for gfx950 (CDNA4, 64-wide wavefronts),
+// shared by the single-pair kernels and the batched kernels.  Each stage is
+// a device function that takes its block coordinates explicitly.
+//
+// Stages (Sec. 2 of arXiv 1610.04121):
+//   census97_block / census_generic_block  census words (Eq. 1 / full window)
+//   cost_block      Hamming cost volume C (Eq. 2), u8
+//   aggregate_wave  Eq. 3 along one direction, one group of lanes per slice
+//   wta_row         S = sum_r L_r and winner-take-all (Eq. 4), right view
+//   post_row        3x3 median and left-right consistency check
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "sgm_common.h"
+
+namespace sgm {
+namespace dev {
+
+
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// ---------------------------------------------------------------------------
+// Census kernel: 9x7 windows (full or center-symmetric), register blocked.
+// A block covers 64 x 16 pixels of one image (blockIdx.z); each thread makes
+// 4 consecutive census words of one row.  The block stages a (16 + 6) x 72
+// tile (clamp-to-edge), and each thread reads its 12 x 7 window patch as
+// 3 aligned dwords per row.  A comparison bit s(u, v) = [u >= v] is the
+// sign of v - 1 - u, shifted into the word with one v_alignbit, most
+// significant bit first.
+// ---------------------------------------------------------------------------
+constexpr int kCenTX = 64, kCenTY = 16;
+
+struct CensusArgs {
+    const uint8_t* img[2];
+    uint64_t* out[2];
+    int W, H, csct;
+};
+
+__device__ inline uint32_t shift_in(uint32_t acc, int u, int v) {
+    // (acc << 1) | [u >= v]
+    return __builtin_amdgcn_alignbit(acc, (uint32_t)(v - 1 - u), 31);
+}
+
+__device__ inline void census97_block(const CensusArgs& a, int bx, int by, int z) {
+    constexpr int RY = 3, CW = 9;
+    constexpr int TW = kCenTX + 8, TH = kCenTY + 2 * RY;
+    __shared__ __align__(16) uint8_t tile[TH * TW];
+
+    const uint8_t* img = a.img[z];
+    const int x0 = bx * kCenTX, y0 = by * kCenTY;
+    for (int i = threadIdx.x; i < TH * TW; i += blockDim.x) {
+        const int r = i / TW, c = i - r * TW;
+        const int yy = clampi(y0 - RY + r, 0, a.H - 1), xx = clampi(x0 - 4 + c, 0, a.W - 1);
+        tile[i] = img[(size_t)yy * a.W + xx];
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int y = y0 + ty;
+    // window patch: rows ty .. ty+6, tile columns 4tx .. 4tx+11
+    uint32_t dw[2 * RY + 1][3];
+#pragma unroll
+    for (int j = 0; j < 2 * RY + 1; ++j)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dw[j][k] = *reinterpret_cast<const uint32_t*>(&tile[(ty + j) * TW + 4 * tx + 4 * k]);
+    auto px = [&](int j, int b) -> int { return (int)((dw[j][b >> 2] >> (8 * (b & 3))) & 0xFF); };
+    uint64_t words[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        // byte b of a patch row is image column x0 + 4tx + b - 4; pixel p's
+        // centre is byte p + 4
+        uint32_t hi = 0, lo = 0;
+        if (!a.csct) {
+            const int c = px(RY, p + 4);
+#pragma unroll
+            for (int k = (2 * RY + 1) * CW - 1; k >= 0; --k) {
+                const int j = k / CW, i = k % CW;  // bit k = (j, i) of the window
+                const int u = px(j, p + i);
+                if (k >= 32)
+                    hi = shift_in(hi, u, c);
+                else
+                    lo = shift_in(lo, u, c);
+            }
+        } else {
+            // pairs in order k = 0..30: i = 1..4 with j = -3..3, then (0, j), j = 1..3
+#pragma unroll
+            for (int k = 30; k >= 0; --k) {
+                int i, j;
+                if (k < 28) {
+                    i = 1 + k / 7;
+                    j = k % 7 - 3;
+                } else {
+                    i = 0;
+                    j = k - 27;
+                }
+                lo = shift_in(lo, px(RY + j, p + 4 + i), px(RY - j, p + 4 - i));
+            }
+        }
+        words[p] = ((uint64_t)hi << 32) | lo;
+    }
+    const int x = x0 + 4 * tx;
+    if (y < a.H) {
+        uint64_t* o = a.out[z] + (size_t)y * a.W + x;
+        if (x + 3 < a.W && ((a.W & 1) == 0)) {
+            reinterpret_cast<ulonglong2*>(o)[0] = make_ulonglong2(words[0], words[1]);
+            reinterpret_cast<ulonglong2*>(o)[1] = make_ulonglong2(words[2], words[3]);
+        } else {
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+                if (x + p < a.W) o[p] = words[p];
+        }
+    }
+}
+
+// Any other window: one thread per pixel, straight from global memory.
+__device__ inline void census_generic_block(const CensusArgs& a, int rx, int ry, int bx, int by, int z) {
+    const int x = bx * 16 + (threadIdx.x & 15);
+    const int y = by * 16 + (threadIdx.x >> 4);
+
+    if (x >= a.W || y >= a.H) return;
+    const uint8_t* img = a.img[z];
+    auto at = [&](int i, int j) {
+        return (int)img[(size_t)clampi(y + j, 0, a.H - 1) * a.W + clampi(x + i, 0, a.W - 1)];
+    };
+    const int cw = 2 * rx + 1;
+    uint64_t word = 0;
+    if (!a.csct) {
+        const int c = at(0, 0);
+        for (int j = -ry; j <= ry; ++j)
+            for (int i = -rx; i <= rx; ++i)
+                word |= (uint64_t)(at(i, j) >= c ? 1u : 0u) << ((j + ry) * cw + (i + rx));
+    } else {
+        int k = 0;
+        for (int i = 1; i <= rx; ++i)
+            for (int j = -ry; j <= ry; ++j, ++k) word |= (uint64_t)(at(i, j) >= at(-i, -j) ? 1u : 0u) << k;
+        for (int j = 1; j <= ry; ++j, ++k) word |= (uint64_t)(at(0, j) >= at(0, -j) ? 1u : 0u) << k;
+    }
+    a.out[z][(size_t)y * a.W + x] = word;
+}
+
+// ---------------------------------------------------------------------------
+// Matching cost (Eq. 2).  One block per (row y, run of 64 base pixels).  The
+// census words of the run and of the match run from x0 - (D-1) on are staged
+// in LDS.  Lane l of every wavefront is pixel x0 + l, so the match words a
+// wavefront reads for one disparity are consecutive (no bank conflicts) and
+// their addresses differ by constants (immediate offsets).  Each wavefront
+// computes runs of 16 disparities, writes them to an LDS tile [64][Dp + 16]
+// (the padding spreads rows over banks), and the block then copies the tile
+// to the cost volume with contiguous 16-byte stores.
+// ---------------------------------------------------------------------------
+constexpr int kCostTX = 64;
+
+struct CostArgs {
+    const uint64_t* cl;
+    const uint64_t* cr;
+    uint8_t* cost;
+    int W, H, D, Dp, cmax;
+};
+
+__device__ inline void cost_block(const CostArgs& a, int bx, int y, uint64_t* cw_smem) {
+    const int x0 = bx * kCostTX;
+    const int D = a.D, Dp = a.Dp;
+    const int nright = kCostTX + D - 1;
+    const int tpitch = Dp + 16;  // bytes per tile row
+    uint64_t* cl = cw_smem;
+    uint64_t* cr = cl + kCostTX;  // cr[i] = match word of column x0 - (D-1) + i
+    // the tile starts on a 16-byte boundary (an even number of words)
+    uint8_t* tile = reinterpret_cast<uint8_t*>(cl + ((kCostTX + nright + 1) & ~1));
+    const uint64_t* gl = a.cl + (size_t)y * a.W;
+    const uint64_t* gr = a.cr + (size_t)y * a.W;
+    for (int i = threadIdx.x; i < kCostTX; i += blockDim.x)
+        if (x0 + i < a.W) cl[i] = gl[x0 + i];
+    for (int i = threadIdx.x; i < nright; i += blockDim.x) {
+        const int xr = x0 - (D - 1) + i;
+        if (xr >= 0 && xr < a.W) cr[i] = gr[xr];
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int x = x0 + lane;
+    const uint64_t base = cl[lane];
+    const int nchunks = Dp >> 4;
+    for (int ch = wave; ch < nchunks; ch += 4) {
+        const int d0 = 16 * ch;
+        // match word of disparity d0 + j is cr[lane + D - 1 - d0 - j]
+        const uint64_t* m = cr + (lane + D - 1 - d0 - 15);
+        uint32_t w[4];
+        if (x0 >= d0 + 15 && d0 + 16 <= D) {  // all 16 disparities valid for every lane
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t word = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) word |= (uint32_t)__popcll(base ^ m[15 - (4 * q + j)]) << (8 * j);
+                w[q] = word;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t word = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int d = d0 + 4 * q + j;
+                    uint32_t c = 0;  // padded levels d >= D
+                    if (d < D) c = x - d < 0 ? (uint32_t)a.cmax : (uint32_t)__popcll(base ^ m[15 - (4 * q + j)]);
+                    word |= c << (8 * j);
+                }
+                w[q] = word;
+            }
+        }
+        *reinterpret_cast<uint4*>(tile + lane * tpitch + d0) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    __syncthreads();
+    const int npx = min(kCostTX, a.W - x0);
+    uint8_t* dst = a.cost + ((size_t)y * a.W + x0) * Dp;
+    for (int c = threadIdx.x; c < npx * nchunks; c += blockDim.x) {
+        const int px = c / nchunks, k = c - px * nchunks;
+        *reinterpret_cast<uint4*>(dst + 16 * c) = *reinterpret_cast<const uint4*>(tile + px * tpitch + 16 * k);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Aggregation (Eq. 3).
+//
+// The recurrence forbids parallelism along a path (Sec. 3.2), so the work is
+// spread over slices x disparities x directions.  A group of G lanes (G in
+// {16, 32, 64}) owns one slice and walks it step by step; a wavefront holds
+// S = 64 / G slices of the same direction.  Lane q of a group holds the
+// disparities q*CPL .. q*CPL + CPL - 1 (CPL = Dp / G) of L_r(p - r, .) as
+// CPL/2 packed u16 pairs in a "split" layout: pair k holds disparities
+// q*CPL + k (low half) and q*CPL + k + CPL/2 (high half), so the d-1 / d+1
+// neighbours of pair k are pairs k-1 / k+1 of the same lane, except at the
+// lane's two ends, which take one DPP lane shift and one v_alignbit each.
+// Per step, in saturating u16 arithmetic:
+//   lp    = L + P1                          (the d+-1 candidates of Eq. 3)
+//   R(d)  = min(L(d), lp(d-1), lp(d+1), m + P2)
+//   L'(d) = R(d) - m + C(p, d)              (m = min_k L(p - r, k))
+//   m'    = min_d L'(d)                     (group min-reduction)
+// 0xFFFF stands for "no such disparity": the d-1 of d = 0, the d+1 of
+// d = D-1 and padded levels d >= D (their cost is 0xFFFF, so they stay
+// 0xFFFF).  Real values are at most Cmax + 2*P2 < 0xFFFF (validated), so
+// saturation never changes a result.  A path start sets L = 0 and m = 0,
+// which makes L' = C exactly.
+// ---------------------------------------------------------------------------
+// Everything one wavefront needs to aggregate slices of one direction.
+struct SliceArgs {
+    const uint8_t* cost;       // C u8 [H][W][Dp] (cost-volume variant)
+    const uint64_t* census_l;  // census words (fused variant)
+    const uint64_t* census_r;
+    void* lplane;              // this direction's L_r plane [H][W][Dp]
+    uint32_t plane;            // elements per plane = H * W * Dp
+    int W, H, D, P1, P2, cmax, rx, ry;
+};
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ inline u16x2 as2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ inline uint32_t as1(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ inline u16x2 vmin(u16x2 a, u16x2 b) { return __builtin_elementwise_min(a, b); }
+__device__ inline u16x2 vadds(u16x2 a, u16x2 b) { return __builtin_elementwise_add_sat(a, b); }
+
+// DPP controls (GFX9 encoding).
+constexpr int kDppQuadPerm1032 = 0xB1;
+constexpr int kDppQuadPerm2301 = 0x4E;
+constexpr int kDppRowShl1 = 0x101;   // lane i reads lane i+1 within a row of 16
+constexpr int kDppRowShr1 = 0x111;   // lane i reads lane i-1 within a row of 16
+constexpr int kDppWaveShl1 = 0x130;  // lane i reads lane i+1
+constexpr int kDppWaveShr1 = 0x138;  // lane i reads lane i-1
+constexpr int kDppRowMirror = 0x140;
+constexpr int kDppRowHalfMirror = 0x141;
+
+// Lane q of a group receives lane q-1's (from_lower) or q+1's (from_upper)
+// value; a lane without a source receives 0 (bound_ctrl), and group edges are
+// overwritten by the caller's OR mask.
+template <int G>
+__device__ inline uint32_t from_lower(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, G == 16 ? kDppRowShr1 : kDppWaveShr1, 0xF, 0xF, true);
+}
+template <int G>
+__device__ inline uint32_t from_upper(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, G == 16 ? kDppRowShl1 : kDppWaveShl1, 0xF, 0xF, true);
+}
+
+// Minimum over each group of G lanes; every lane of the group receives it.
+// The butterfly inside a row of 16 uses DPP (folded into v_min_u32_dpp);
+// groups spanning 2 or 4 rows combine rows with the gfx950 permlane swaps.
+template <int G>
+__device__ inline uint32_t group_min(uint32_t v) {
+    v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppQuadPerm1032, 0xF, 0xF, true));
+    v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppQuadPerm2301, 0xF, 0xF, true));
+    v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowHalfMirror, 0xF, 0xF, true));
+    v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowMirror, 0xF, 0xF, true));
+    if constexpr (G >= 32) {
+        const auto sw = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        v = min((uint32_t)sw[0], (uint32_t)sw[1]);
+    }
+    if constexpr (G == 64) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        v = min((uint32_t)sw[0], (uint32_t)sw[1]);
+    }
+    return v;
+}
+
+// Raw cost bytes of one lane for one step: CPL bytes.
+template <int CPL> struct Raw;
+template <> struct Raw<2> { using T = uint16_t; };
+template <> struct Raw<4> { using T = uint32_t; };
+template <> struct Raw<8> { using T = uint2; };
+template <> struct Raw<16> { using T = uint4; };
+
+// Unpacks a lane's cost bytes b_0..b_{CPL-1} into pairs (b_k, b_{k+CPL/2})
+// with one v_perm per pair.  sel[k] is the per-lane byte selector; it selects
+// 0xFF bytes for padded levels, which makes their cost 0xFFFF.
+template <int CPL>
+__device__ inline void unpack_costs(const typename Raw<CPL>::T& r, const uint32_t (&sel)[CPL / 2],
+                                    u16x2 (&c)[CPL / 2]) {
+    if constexpr (CPL == 2) {
+        c[0] = as2(__builtin_amdgcn_perm(0u, (uint32_t)r, sel[0]));
+    } else if constexpr (CPL == 4) {
+        c[0] = as2(__builtin_amdgcn_perm(r, r, sel[0]));
+        c[1] = as2(__builtin_amdgcn_perm(r, r, sel[1]));
+    } else if constexpr (CPL == 8) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[k] = as2(__builtin_amdgcn_perm(r.y, r.x, sel[k]));
+    } else {
+        const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[k] = as2(__builtin_amdgcn_perm(w[2 + k / 4], w[k / 4], sel[k]));
+    }
+}
+
+// Selector of pair k for a lane whose first disparity is d0: low half b_k,
+// high half b_{k+CPL/2} (bytes of the v_perm source pair), 0xFFFF for d >= D.
+template <int CPL>
+__device__ inline uint32_t unpack_selector(int k, int d0, int D) {
+    constexpr int NP = CPL / 2;
+    uint32_t lo, hi;
+    if constexpr (CPL == 2) {
+        lo = 0;
+        hi = 1;
+    } else if constexpr (CPL == 4) {
+        lo = k;
+        hi = k + 2;
+    } else {
+        lo = k % 4;
+        hi = 4 + k % 4;
+    }
+    const uint32_t slo = (d0 + k < D) ? (lo | 0x0C00u) : 0x0D0Du;
+    const uint32_t shi = (d0 + k + NP < D) ? (hi | 0x0C00u) : 0x0D0Du;
+    return slo | (shi << 16);
+}
+
+enum { kHoriz = 0, kVert = 1, kDiag = 2 };
+
+// Raw-buffer resource for a byte range (gfx9-family descriptor word 3).  Every
+// access below passes its whole byte offset in the VGPR operand, so the
+// hardware range check covers it: loads past `bytes` return 0 and stores past
+// it are dropped.
+__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+
+template <int CPL>
+__device__ inline typename Raw<CPL>::T buffer_load_raw(__amdgpu_buffer_rsrc_t r, uint32_t ofs) {
+    if constexpr (CPL == 2) {
+        return (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, ofs, 0, 0);
+    } else if constexpr (CPL == 4) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, ofs, 0, 0);
+    } else if constexpr (CPL == 8) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, ofs, 0, 0);
+        return make_uint2(v[0], v[1]);
+    } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, ofs, 0, 0);
+        return make_uint4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+__device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint16_t v) {
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, ofs, 0, 0);
+}
+__device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint32_t v) {
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, ofs, 0, 0);
+}
+__device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint2 v) {
+    __builtin_amdgcn_raw_buffer_store_b64((unsigned __attribute__((ext_vector_type(2)))){v.x, v.y}, r, ofs, 0, 0);
+}
+__device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128((unsigned __attribute__((ext_vector_type(4)))){v.x, v.y, v.z, v.w}, r, ofs,
+                                           0, 0);
+}
+
+// Packs a lane's L values in natural disparity order (u8 or u16) and stores
+// them at byte offset `ofs` of the L_r plane.
+template <int CPL, typename LT>
+__device__ inline void store_l(__amdgpu_buffer_rsrc_t r, uint32_t ofs, const u16x2 (&l)[CPL / 2]) {
+    constexpr uint32_t kLoBytes = 0x06020400u;  // (a.b0, b.b0, a.b2, b.b2) of perm(b, a)
+    constexpr uint32_t kPairLo = 0x05040100u;   // (a.lo16, b.lo16)
+    constexpr uint32_t kPairHi = 0x07060302u;   // (a.hi16, b.hi16)
+    if constexpr (sizeof(LT) == 1) {
+        if constexpr (CPL == 2) {
+            buffer_store(r, ofs, (uint16_t)__builtin_amdgcn_perm(0u, as1(l[0]), 0x0C0C0200u));
+        } else if constexpr (CPL == 4) {
+            buffer_store(r, ofs, (uint32_t)__builtin_amdgcn_perm(as1(l[1]), as1(l[0]), kLoBytes));
+        } else if constexpr (CPL == 8) {
+            const uint32_t t01 = __builtin_amdgcn_perm(as1(l[1]), as1(l[0]), kLoBytes);
+            const uint32_t t23 = __builtin_amdgcn_perm(as1(l[3]), as1(l[2]), kLoBytes);
+            buffer_store(r, ofs, make_uint2(__builtin_amdgcn_perm(t23, t01, kPairLo),
+                                            __builtin_amdgcn_perm(t23, t01, kPairHi)));
+        } else {
+            uint32_t t[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) t[i] = __builtin_amdgcn_perm(as1(l[2 * i + 1]), as1(l[2 * i]), kLoBytes);
+            buffer_store(r, ofs, make_uint4(__builtin_amdgcn_perm(t[1], t[0], kPairLo),
+                                            __builtin_amdgcn_perm(t[3], t[2], kPairLo),
+                                            __builtin_amdgcn_perm(t[1], t[0], kPairHi),
+                                            __builtin_amdgcn_perm(t[3], t[2], kPairHi)));
+        }
+    } else {
+        constexpr int NP = CPL / 2;
+        if constexpr (CPL == 2) {
+            buffer_store(r, ofs, as1(l[0]));
+        } else {
+            // dword i = (d_2i, d_2i+1) from pairs 2i and 2i+1 (low halves,
+            // then high halves)
+            uint32_t w[NP];
+#pragma unroll
+            for (int i = 0; i < NP / 2; ++i) {
+                w[i] = __builtin_amdgcn_perm(as1(l[2 * i + 1]), as1(l[2 * i]), kPairLo);
+                w[NP / 2 + i] = __builtin_amdgcn_perm(as1(l[2 * i + 1]), as1(l[2 * i]), kPairHi);
+            }
+            if constexpr (NP == 2) {
+                buffer_store(r, ofs, make_uint2(w[0], w[1]));
+            } else {
+#pragma unroll
+                for (int i = 0; i < NP / 4; ++i)
+                    buffer_store(r, ofs + 16 * i, make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]));
+            }
+        }
+    }
+}
+
+// Census words one lane needs for one step of the fused variant: the base
+// word of its group's pixel and the CPL match words of columns x - d for its
+// disparities d = q*CPL .. q*CPL + CPL - 1 (contiguous, lowest column first).
+template <int CPL>
+struct CensusStep {
+    uint64_t base;
+    uint64_t m[CPL];
+};
+
+template <int CPL>
+__device__ inline void load_census(__amdgpu_buffer_rsrc_t rcl, __amdgpu_buffer_rsrc_t rcr, uint32_t base_ofs,
+                                   uint32_t match_ofs, CensusStep<CPL>& cs) {
+    const auto b = __builtin_amdgcn_raw_buffer_load_b64(rcl, base_ofs, 0, 0);
+    cs.base = ((uint64_t)b[1] << 32) | b[0];
+#pragma unroll
+    for (int i = 0; i < CPL / 2; ++i) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rcr, match_ofs + 16 * i, 0, 0);
+        cs.m[2 * i] = ((uint64_t)v[1] << 32) | v[0];
+        cs.m[2 * i + 1] = ((uint64_t)v[3] << 32) | v[2];
+    }
+}
+
+// Hamming costs (Eq. 2) of a lane's CPL disparities, packed as the u16 pairs
+// of the split layout.  Cell c (disparity q*CPL + c) uses match word
+// m[CPL - 1 - c]; cells with c > valid_c (x - d < 0) cost cmax.  sel[k] puts
+// the costs of cells k and k + CPL/2 into the two halves of pair k, or 0xFFFF
+// for padded levels.
+template <int CPL, bool ALL_VALID>
+__device__ inline void census_costs(const CensusStep<CPL>& cs, int valid_c, uint32_t cmax,
+                                    const uint32_t (&sel)[CPL / 2], u16x2 (&c)[CPL / 2]) {
+    constexpr int NP = CPL / 2;
+    uint32_t pc[CPL];
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+        const uint64_t x = cs.base ^ cs.m[CPL - 1 - i];
+        pc[i] = (uint32_t)__popcll(x);
+        if constexpr (!ALL_VALID) pc[i] = i > valid_c ? cmax : pc[i];
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) c[k] = as2(__builtin_amdgcn_perm(pc[k + NP], pc[k], sel[k]));
+}
+
+// Selector of pair k for the fused variant: low half = cell k (S1 byte 0),
+// high half = cell k + CPL/2 (S0 byte 0, selector 4); 0xFFFF for d >= D.
+template <int CPL>
+__device__ inline uint32_t pack_selector(int k, int d0, int D) {
+    constexpr int NP = CPL / 2;
+    const uint32_t slo = (d0 + k < D) ? 0x0C00u : 0x0D0Du;
+    const uint32_t shi = (d0 + k + NP < D) ? 0x0C04u : 0x0D0Du;
+    return slo | (shi << 16);
+}
+
+// Cost loads run PF steps ahead of the recurrence so that their latency
+// overlaps the dependent min-plus chain of the steps in between.
+template <int CPL> struct Prefetch { static constexpr int N = CPL >= 16 ? 8 : 16; };
+template <int CPL> struct FusedPrefetch { static constexpr int N = CPL >= 16 ? 2 : 4; };
+
+template <int G, int CPL, typename LT, int KIND, bool FUSED>
+__device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int lane) {
+    constexpr int NP = CPL / 2;
+    constexpr int Dp = G * CPL;
+    constexpr int PF = FUSED ? FusedPrefetch<CPL>::N : Prefetch<CPL>::N;
+    // per-step input: raw cost bytes, or census words (fused variant)
+    using RawT = std::conditional_t<FUSED, CensusStep<CPL>, typename Raw<CPL>::T>;
+
+    const int rx = a.rx, ry = a.ry;
+    const int W = a.W, H = a.H;
+    const int grp = lane / G, q = lane % G;
+    const int nslices = KIND == kHoriz ? H : W;
+    const int steps = KIND == kHoriz ? W : H;
+    // groups past the last slice repeat the last slice (identical stores)
+    const int jg = min(grp, nslices - 1 - first_slice);
+
+    uint32_t sel[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+        sel[k] = FUSED ? pack_selector<CPL>(k, q * CPL, a.D) : unpack_selector<CPL>(k, q * CPL, a.D);
+    const uint32_t edge_lo = q == 0 ? 0xFFFF0000u : 0u;      // no d-1 below d = 0
+    const uint32_t edge_hi = q == G - 1 ? 0x0000FFFFu : 0u;  // no d+1 above Dp-1
+    const u16x2 P1v = as2((uint32_t)a.P1 * 0x10001u), P2v = as2((uint32_t)a.P2 * 0x10001u);
+
+    const uint32_t plane_bytes = (uint32_t)a.plane;  // cost plane, u8
+    const __amdgpu_buffer_rsrc_t rc = buffer_rsrc(a.cost, FUSED ? 0u : plane_bytes);
+    // the match buffer starts kCensusGuard words early: a lane's window of
+    // CPL words may begin left of column 0 (those words are never used)
+    const uint32_t census_bytes = 8u * (uint32_t)W * (uint32_t)H;
+    const __amdgpu_buffer_rsrc_t rcl = buffer_rsrc(a.census_l, FUSED ? census_bytes : 0u);
+    const __amdgpu_buffer_rsrc_t rcr =
+        buffer_rsrc(a.census_r - kCensusGuard, FUSED ? census_bytes + 8u * kCensusGuard : 0u);
+    const __amdgpu_buffer_rsrc_t rl = buffer_rsrc(a.lplane, plane_bytes * (uint32_t)sizeof(LT));
+
+    // Group 0's position: byte offset `bo` of its pixel in a u8 [H][W][Dp]
+    // plane and, for diagonal slices, its column xc (kept in [0, W)).
+    int bo, xc;
+    if constexpr (KIND == kHoriz) {
+        xc = rx > 0 ? 0 : W - 1;
+        bo = (first_slice * W + xc) * Dp;
+    } else {
+        xc = first_slice;
+        bo = ((ry > 0 ? 0 : H - 1) * W + xc) * Dp;
+    }
+    const int bstep = (KIND == kHoriz ? rx : ry * W + (KIND == kDiag ? rx : 0)) * Dp;
+    const int qofs = q * CPL;
+    // byte offset of the lane relative to group 0 (horizontal: rows below;
+    // vertical: columns to the right; diagonal: columns to the right, or
+    // W - jg columns to the left once the group's column has wrapped)
+    const int lofs = (KIND == kHoriz ? jg * W : jg) * Dp + qofs;
+    const int lofs_wrapped = (jg - W) * Dp + qofs;
+    auto lane_ofs = [&](int b, int x) -> uint32_t {
+        if constexpr (KIND == kDiag) return (uint32_t)(b + (x + jg >= W ? lofs_wrapped : lofs));
+        return (uint32_t)(b + lofs);
+    };
+    auto advance = [&](int& b, int& x) {
+        b += bstep;
+        if constexpr (KIND == kHoriz) x += rx;
+        if constexpr (KIND == kDiag) {
+            x += rx;
+            const int under = x >> 31;             // -1 if x < 0
+            const int over = (W - 1 - x) >> 31;    // -1 if x >= W
+            const int wrap = (under & W) - (over & W);
+            x += wrap;
+            b += wrap * Dp;
+        }
+    };
+
+    u16x2 L[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) L[k] = as2(0u);
+    u16x2 mm = as2(0u);
+    // restart column of a diagonal group: where it crosses the side border
+    const int border = rx > 0 ? 0 : W - 1;
+
+    // smallest column any group of the wavefront is at (uniform): when it is
+    // >= Dp - 1, every lane's disparities are valid (x - d >= 0)
+    int xmin_all = 0;
+    auto step = [&](const RawT& raw) {
+        if constexpr (FUSED) {
+            if constexpr (KIND == kHoriz)
+                xmin_all = xc;
+            else if constexpr (KIND == kVert)
+                xmin_all = xc;
+            else
+                xmin_all = xc + 64 / G - 1 >= W ? 0 : xc;  // a wrapped group sits at a small column
+        }
+        if constexpr (KIND == kDiag) {
+            const int xl = xc + jg >= W ? xc + jg - W : xc + jg;
+            if (xl == border) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) L[k] = as2(0u);
+                mm = as2(0u);
+            }
+        }
+        u16x2 c[NP];
+        if constexpr (FUSED) {
+            // the lane's disparities are valid (x - d >= 0) for cells
+            // c <= x - q*CPL; x of the lane's group is group 0's column + jg
+            // (horizontal: same column; diagonal: wrapped)
+            int xg;
+            if constexpr (KIND == kHoriz)
+                xg = xc;
+            else if constexpr (KIND == kVert)
+                xg = xc + jg;
+            else
+                xg = xc + jg >= W ? xc + jg - W : xc + jg;
+            const int valid_c = xg - q * CPL;
+            if (xmin_all >= Dp - 1)
+                census_costs<CPL, true>(raw, valid_c, (uint32_t)a.cmax, sel, c);
+            else
+                census_costs<CPL, false>(raw, valid_c, (uint32_t)a.cmax, sel, c);
+        } else {
+            unpack_costs<CPL>(raw, sel, c);
+        }
+        u16x2 lp[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) lp[k] = vadds(L[k], P1v);
+        const uint32_t prev = from_lower<G>(as1(lp[NP - 1])) | edge_lo;
+        const uint32_t next = from_upper<G>(as1(lp[0])) | edge_hi;
+        const u16x2 lo0 = as2(__builtin_amdgcn_alignbit(as1(lp[NP - 1]), prev, 16));
+        const u16x2 hiN = as2(__builtin_amdgcn_alignbit(next, as1(lp[0]), 16));
+        const u16x2 mp2 = vadds(mm, P2v);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const u16x2 lo = k == 0 ? lo0 : lp[k - 1];
+            const u16x2 hi = k == NP - 1 ? hiN : lp[k + 1];
+            const u16x2 R = vmin(vmin(lo, hi), vmin(L[k], mp2));
+            L[k] = vadds(R - mm, c[k]);
+        }
+        // minimum over the lane's cells as a tree, replicated in both halves
+        u16x2 t[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) t[k] = L[k];
+#pragma unroll
+        for (int w = 1; w < NP; w *= 2)
+#pragma unroll
+            for (int k = 0; k + w < NP; k += 2 * w) t[k] = vmin(t[k], t[k + w]);
+        const u16x2 tm = vmin(t[0], t[0].yx);
+        mm = as2(group_min<G>(as1(tm)));
+        store_l<CPL, LT>(rl, lane_ofs(bo, xc) * (uint32_t)sizeof(LT), L);
+        advance(bo, xc);
+    };
+
+    // ring[j] holds the raw costs of the step congruent to j modulo PF.  The
+    // lookahead position leads by PF - 1 steps and runs past the slice's end
+    // near the finish; those loads are never consumed (and past the plane
+    // they return 0).
+    auto load = [&](int b, int x) -> RawT {
+        if constexpr (FUSED) {
+            // pixel index of the lane's group: byte offset / Dp, with the
+            // lane's disparity offset qofs removed
+            const int pix = (int)((lane_ofs(b, x) - (uint32_t)qofs) / (uint32_t)Dp);
+            RawT cs;
+            load_census<CPL>(rcl, rcr, 8u * (uint32_t)pix,
+                             8u * (uint32_t)(pix + kCensusGuard - qofs - (CPL - 1)), cs);
+            return cs;
+        } else {
+            return buffer_load_raw<CPL>(rc, lane_ofs(b, x));
+        }
+    };
+    RawT ring[PF];
+    int ba = bo, xa = xc;
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+        if (j) advance(ba, xa);
+        ring[j] = load(ba, xa);
+    }
+    int k = 0;
+    for (; k + PF <= steps; k += PF) {
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+            const RawT raw = ring[j];
+            advance(ba, xa);
+            ring[j] = load(ba, xa);
+            step(raw);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PF; ++j)
+        if (k + j < steps) step(ring[j]);
+}
+
+// ---------------------------------------------------------------------------
+// Sum over directions and winner-take-all (Eq. 4), one block per row.
+// Lane = pixel: each lane walks its pixel's disparities in runs of 16, sums
+// the planes as packed u16 pairs and forms keys (S << 8) | d with one v_perm
+// per cell (padded levels get a 0xFF top byte, so they never win).  The left
+// disparity is the smallest key of the pixel.  The right view: pixel x at
+// disparity d is right pixel x - d, so every (x, d) offers its key to column
+// x - d with an LDS atomic minimum; the lanes of a wavefront hit consecutive
+// words, and targets x - d < 0 land in a guard region in front of the row.
+// The column's winner is argmin_d S(x + d, d), ties to the smallest d.
+// ---------------------------------------------------------------------------
+struct WtaArgs {
+    const void* lbuf;
+    size_t plane;
+    uint16_t* dl;  // left disparity (raw, or the final output)
+    uint16_t* dr;  // right disparity or nullptr
+    int W, H, D, Dp, nplanes;
+};
+
+constexpr int kWtaGuard = 256;  // >= max disparity
+
+// Sums of 16 disparities d0..d0+15 of one pixel as 8 packed pairs; pair k
+// holds disparities dpair(k) (see below).
+template <typename LT>
+__device__ inline void sum16(const LT* base, size_t plane, int nplanes, uint32_t (&S)[8]) {
+    if constexpr (sizeof(LT) == 1) {
+        // bytes b0..b3 of dword i -> pairs (b0, b2) and (b1, b3)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) S[k] = 0;
+        for (int p = 0; p < nplanes; ++p) {
+            const uint4 q = *reinterpret_cast<const uint4*>(base + plane * p);
+            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                S[2 * i] = as1(as2(S[2 * i]) + as2(__builtin_amdgcn_perm(0u, w[i], 0x0C020C00u)));
+                S[2 * i + 1] = as1(as2(S[2 * i + 1]) + as2(__builtin_amdgcn_perm(0u, w[i], 0x0C030C01u)));
+            }
+        }
+    } else {
+        // u16 pairs are already (d, d + 1)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) S[k] = 0;
+        for (int p = 0; p < nplanes; ++p) {
+            const uint4 q0 = reinterpret_cast<const uint4*>(base + plane * p)[0];
+            const uint4 q1 = reinterpret_cast<const uint4*>(base + plane * p)[1];
+            const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) S[k] = as1(as2(S[k]) + as2(w[k]));
+        }
+    }
+}
+
+// Disparities (relative to the run) held by pair k: u8 planes pair 2i =
+// (4i, 4i + 2), pair 2i + 1 = (4i + 1, 4i + 3); u16 planes pair k = (2k, 2k+1).
+template <typename LT>
+__device__ inline void pair_disps(int k, int& lo, int& hi) {
+    if constexpr (sizeof(LT) == 1) {
+        lo = 4 * (k >> 1) + (k & 1);
+        hi = lo + 2;
+    } else {
+        lo = 2 * k;
+        hi = lo + 1;
+    }
+}
+
+// Minimum over aligned groups of G consecutive lanes (G = 4, 8 or 16);
+// every lane of the group receives it.
+__device__ inline uint32_t lanes_min(uint32_t v, int G) {
+    v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppQuadPerm1032, 0xF, 0xF, true));
+    v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppQuadPerm2301, 0xF, 0xF, true));
+    if (G >= 8) v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowHalfMirror, 0xF, 0xF, true));
+    if (G >= 16) v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowMirror, 0xF, 0xF, true));
+    return v;
+}
+
+template <typename LT>
+__device__ inline void wta_row(const WtaArgs& a, int y, uint32_t* keyR_smem) {
+    uint32_t* keyR = keyR_smem + kWtaGuard;  // keyR[t], t in [-kWtaGuard, W)
+    const bool right = a.dr != nullptr;
+    if (right)
+        for (int i = threadIdx.x; i < a.W + kWtaGuard; i += blockDim.x) keyR_smem[i] = ~0u;
+    __syncthreads();
+    const LT* planes = reinterpret_cast<const LT*>(a.lbuf);
+    // thread (x, g) takes disparities 16g .. 16g + 15 of pixel x; the G runs
+    // of a pixel sit on consecutive lanes, so its loads are contiguous
+    const int G = a.Dp >> 4;
+    const int gshift = G == 4 ? 2 : (G == 8 ? 3 : 4);
+    for (int i = threadIdx.x; i < a.W * G; i += blockDim.x) {
+        const int x = i >> gshift, g = i & (G - 1);
+        const int d0 = 16 * g;
+        uint32_t S[8];
+        sum16<LT>(planes + ((size_t)y * a.W + x) * a.Dp + d0, a.plane, a.nplanes, S);
+        uint32_t best = ~0u;
+        // right-view targets x - d0 - 15 .. x - d0 from one base address
+        uint32_t* tgt = keyR + (x - d0 - 15);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            int dlo, dhi;
+            pair_disps<LT>(k, dlo, dhi);
+            const uint32_t dpair = (uint32_t)(d0 + dlo) | ((uint32_t)(d0 + dhi) << 8);
+            // key = [d, S.lo16, 0] with a 0xFF top byte for padded levels
+            const uint32_t klo = __builtin_amdgcn_perm(S[k], dpair, d0 + dlo < a.D ? 0x0C050400u : 0x0D050400u);
+            const uint32_t khi = __builtin_amdgcn_perm(S[k], dpair, d0 + dhi < a.D ? 0x0C070601u : 0x0D070601u);
+            best = min(best, min(klo, khi));
+            if (right) {
+                if (d0 + dlo < a.D) atomicMin(tgt + (15 - dlo), klo);
+                if (d0 + dhi < a.D) atomicMin(tgt + (15 - dhi), khi);
+            }
+        }
+        best = lanes_min(best, G);
+        if (g == 0) a.dl[(size_t)y * a.W + x] = (uint16_t)(best & 0xFF);
+    }
+    if (right) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < a.W; i += blockDim.x)
+            a.dr[(size_t)y * a.W + i] = (uint16_t)(keyR[i] & 0xFF);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 median (clamp-to-edge) of both maps, then the left-right check.
+// The median of 9 is the median of (max of row minima, median of row
+// medians, min of row maxima) once each row of 3 is sorted.
+// ---------------------------------------------------------------------------
+__device__ inline void sort3(uint32_t& a, uint32_t& b, uint32_t& c) {
+    uint32_t t;
+    if (a > b) { t = a; a = b; b = t; }
+    if (b > c) { t = b; b = c; c = t; }
+    if (a > b) { t = a; a = b; b = t; }
+}
+
+__device__ inline uint32_t med3(uint32_t a, uint32_t b, uint32_t c) {
+    return max(min(a, b), min(max(a, b), c));
+}
+
+__device__ inline uint32_t median9(const uint16_t* img, int W, int H, int x, int y) {
+    uint32_t v[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const uint16_t* row = img + (size_t)clampi(y + j - 1, 0, H - 1) * W;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) v[j][i] = row[clampi(x + i - 1, 0, W - 1)];
+        sort3(v[j][0], v[j][1], v[j][2]);
+    }
+    const uint32_t lo = max(v[0][0], max(v[1][0], v[2][0]));
+    const uint32_t mid = med3(v[0][1], v[1][1], v[2][1]);
+    const uint32_t hi = min(v[0][2], min(v[1][2], v[2][2]));
+    return med3(lo, mid, hi);
+}
+
+struct PostArgs {
+    const uint16_t* dl;
+    const uint16_t* dr;
+    uint16_t* out;
+    int W, H, median, lrcheck, thr;
+};
+
+__device__ inline void post_row(const PostArgs& a, int y, uint16_t* rview) {
+    if (a.lrcheck) {
+        for (int x = threadIdx.x; x < a.W; x += blockDim.x)
+            rview[x] = a.median ? (uint16_t)median9(a.dr, a.W, a.H, x, y) : a.dr[(size_t)y * a.W + x];
+        __syncthreads();
+    }
+    for (int x = threadIdx.x; x < a.W; x += blockDim.x) {
+        const int d = a.median ? (int)median9(a.dl, a.W, a.H, x, y) : (int)a.dl[(size_t)y * a.W + x];
+        int o = d;
+        if (a.lrcheck) {
+            o = kInvalid;
+            if (x - d >= 0) {
+                const int e = rview[x - d];
+                if (abs(d - e) <= a.thr) o = d;
+            }
+        }
+        a.out[(size_t)y * a.W + x] = (uint16_t)o;
+    }
+}
+
+
+}  // namespace dev
+}  // namespace sgm

@@ -13,7 +13,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsgm.so")
 
 SGM_OK, SGM_EINVAL, SGM_ENOMEM, SGM_EHIP, SGM_EBUSY, SGM_ECANCELED = 0, -1, -2, -3, -4, -5
-MEDIAN3, LRCHECK, CENSUS_CSCT = 1, 2, 4
+MEDIAN3, LRCHECK, CENSUS_CSCT, GRAPH = 1, 2, 4, 8
 INVALID = 0xFFFF
 
 EXPORTS = [
@@ -21,7 +21,16 @@ EXPORTS = [
     "sgm_last_error", "sgm_footprint_bytes", "sgm_debug_census", "sgm_debug_sums",
     "sgm_debug_raw_disparity", "sgm_path_walk", "sgm_profile_enable", "sgm_profile_read",
     "sgm_debug_stage", "sgm_set_tuning", "sgm_get_tuning",
+    "sgm_batch_create", "sgm_batch_compute", "sgm_batch_footprint", "sgm_batch_destroy",
+    "sgm_compute_batch",
 ]
+
+
+class Item(ctypes.Structure):
+    """Mirror of sgm_item."""
+    _fields_ = [("width", ctypes.c_int), ("height", ctypes.c_int), ("max_disp", ctypes.c_int),
+                ("n_paths", ctypes.c_int), ("flags", ctypes.c_uint), ("lr_threshold", ctypes.c_int),
+                ("left", ctypes.c_void_p), ("right", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 STAGES = ("census_cost", "aggregate", "wta", "post")
 
 
@@ -70,6 +79,16 @@ def lib() -> ctypes.CDLL:
     L.sgm_debug_raw_disparity.restype = i
     L.sgm_path_walk.argtypes = [i, i, i, i, i, i, P, P, P]
     L.sgm_path_walk.restype = i
+    L.sgm_batch_create.argtypes = [i, i, i, i]
+    L.sgm_batch_create.restype = P
+    L.sgm_batch_compute.argtypes = [P, ctypes.POINTER(Item), i, P]
+    L.sgm_batch_compute.restype = i
+    L.sgm_batch_footprint.argtypes = [P, ctypes.POINTER(Item), i]
+    L.sgm_batch_footprint.restype = ctypes.c_size_t
+    L.sgm_batch_destroy.argtypes = [P]
+    L.sgm_batch_destroy.restype = None
+    L.sgm_compute_batch.argtypes = [ctypes.POINTER(Item), i, i, i, i, i, P]
+    L.sgm_compute_batch.restype = i
     L.sgm_set_tuning.argtypes = [P, i, i, i]
     L.sgm_set_tuning.restype = i
     L.sgm_get_tuning.argtypes = [P, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
@@ -140,16 +159,17 @@ class SGM:
     stream (or ``stream``) and returns ``out`` (u16 [H][W])."""
 
     def __init__(self, width, height, max_disp, P1=7, P2=86, n_paths=4, census_w=9, census_h=7,
-                 median=False, lrcheck=False, csct=False, lr_threshold=1):
+                 median=False, lrcheck=False, csct=False, lr_threshold=1, graph=False):
         self.width, self.height, self.max_disp = width, height, max_disp
         self.n_paths = n_paths
         self._ctx = lib().sgm_create(width, height, max_disp, P1, P2, n_paths, census_w, census_h)
         if not self._ctx:
             raise SGMError(SGM_EINVAL, last_error())
-        self.set_options(median=median, lrcheck=lrcheck, csct=csct, lr_threshold=lr_threshold)
+        self.set_options(median=median, lrcheck=lrcheck, csct=csct, lr_threshold=lr_threshold, graph=graph)
 
-    def set_options(self, median=False, lrcheck=False, csct=False, lr_threshold=1):
-        flags = (MEDIAN3 if median else 0) | (LRCHECK if lrcheck else 0) | (CENSUS_CSCT if csct else 0)
+    def set_options(self, median=False, lrcheck=False, csct=False, lr_threshold=1, graph=False):
+        flags = ((MEDIAN3 if median else 0) | (LRCHECK if lrcheck else 0) | (CENSUS_CSCT if csct else 0)
+                 | (GRAPH if graph else 0))
         _check(lib().sgm_set_options(self._ctx, flags, lr_threshold))
 
     def set_tuning(self, lanes_h=0, lanes_v=0, fused=True):
@@ -212,9 +232,9 @@ class SGM:
                                              _ptr(dr, "torch.uint16", self.shape), _stream(stream)))
         return dl, dr
 
-    def profile(self, enable: bool = True):
-        """Record per-stage HIP events in every compute() call."""
-        _check(lib().sgm_profile_enable(self._ctx, 1 if enable else 0))
+    def profile(self, enable: bool = True, every: int = 1):
+        """Record per-stage HIP events in every `every`-th compute() call."""
+        _check(lib().sgm_profile_enable(self._ctx, every if enable else 0))
 
     def profile_read(self):
         """(calls, {stage: total ms}) over the calls recorded since the last read."""
@@ -227,6 +247,48 @@ class SGM:
         if getattr(self, "_ctx", None):
             lib().sgm_destroy(self._ctx)
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _items(pairs):
+    """pairs: dicts with left, right, out (device tensors), max_disp, n_paths and
+    optional median, lrcheck, lr_threshold."""
+    arr = (Item * len(pairs))()
+    for k, p in enumerate(pairs):
+        h, w = p["left"].shape
+        flags = (MEDIAN3 if p.get("median") else 0) | (LRCHECK if p.get("lrcheck") else 0)
+        arr[k] = Item(w, h, p["max_disp"], p["n_paths"], flags, p.get("lr_threshold", 1),
+                      _ptr(p["left"], "torch.uint8", (h, w)), _ptr(p["right"], "torch.uint8", (h, w)),
+                      _ptr(p["out"], "torch.uint16", (h, w)))
+    return arr
+
+
+class Batch:
+    """Runs many pairs of different shapes with one launch per stage."""
+
+    def __init__(self, P1=7, P2=86, census_w=9, census_h=7):
+        self._b = lib().sgm_batch_create(P1, P2, census_w, census_h)
+        if not self._b:
+            raise SGMError(SGM_EINVAL, last_error())
+
+    def compute(self, pairs, stream=None):
+        arr = _items(pairs)
+        _check(lib().sgm_batch_compute(self._b, arr, len(pairs), _stream(stream)))
+        return [p["out"] for p in pairs]
+
+    def footprint(self, pairs) -> int:
+        arr = _items(pairs)
+        return lib().sgm_batch_footprint(self._b, arr, len(pairs))
+
+    def close(self):
+        if getattr(self, "_b", None):
+            lib().sgm_batch_destroy(self._b)
+            self._b = None
 
     def __del__(self):
         try:

@@ -1,0 +1,122 @@
+"""Batched pipeline (one launch per stage over pairs of different shapes)
+against the oracle and against separate single-pair calls.  Exact equality."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1610_04121_amd import SGM, synth
+from paper_1610_04121_amd.sgm import Batch
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _pairs(specs, dev, seed0):
+    import torch
+    out = []
+    for k, (w, h, d, p, med, lr) in enumerate(specs):
+        pair = synth.make_pair(w, h, d, "RS", seed=seed0 + k)
+        out.append(dict(left=_t(pair.left, dev), right=_t(pair.right, dev), max_disp=d, n_paths=p,
+                        median=med, lrcheck=lr, lr_threshold=1,
+                        out=torch.empty((h, w), dtype=torch.uint16, device=dev),
+                        np_left=pair.left, np_right=pair.right))
+    return out
+
+
+def test_heterogeneous_batch_matches_oracle(gpu):
+    import torch
+    specs = [(64, 48, 32, 4, False, False), (97, 31, 64, 8, True, True), (40, 70, 130, 2, True, False),
+             (33, 33, 200, 8, False, True), (7, 5, 16, 4, True, True), (120, 20, 16, 8, False, False),
+             (1, 9, 8, 4, False, True), (50, 1, 70, 8, True, True)]
+    pairs = _pairs(specs, gpu, 300)
+    _say(f"batch of {len(pairs)} mixed pairs")
+    b = Batch(7, 86)
+    b.compute(pairs)
+    torch.cuda.synchronize()
+    for k, p in enumerate(pairs):
+        want = oracle.sgm(p["np_left"], p["np_right"], p["max_disp"], 7, 86, p["n_paths"],
+                          median=p["median"], lr=p["lrcheck"]).out
+        got = p["out"].cpu().numpy()
+        assert (got == want).all(), (k, specs[k], int((got != want).sum()))
+    b.close()
+
+
+def test_batch_u16_planes_and_generic_census(gpu):
+    import torch
+    specs = [(45, 30, 40, 4, True, True), (30, 45, 70, 8, False, True)]
+    pairs = _pairs(specs, gpu, 700)
+    _say("batch with P2=300 (u16 L_r) and a 7x5 census")
+    b = Batch(5, 300, 7, 5)
+    b.compute(pairs)
+    torch.cuda.synchronize()
+    for p in pairs:
+        want = oracle.sgm(p["np_left"], p["np_right"], p["max_disp"], 5, 300, p["n_paths"], 7, 5,
+                          median=p["median"], lr=p["lrcheck"]).out
+        assert (p["out"].cpu().numpy() == want).all()
+    b.close()
+
+
+def test_workload_batch_matches_sequential_calls(gpu):
+    """The 64-pair mixed batch: identical to 64 single-pair calls; oracle on a sample."""
+    import torch
+    items = synth.batch_items(64)
+    specs = [(it["w"], it["h"], it["max_disp"], it["n_paths"], False, False) for it in items]
+    pairs = _pairs(specs, gpu, 1610041213)
+    _say("64-pair workload batch")
+    b = Batch(7, 86)
+    b.compute(pairs)
+    torch.cuda.synchronize()
+    seq = {}
+    for k, p in enumerate(pairs):
+        h, w = p["left"].shape
+        key = (w, h, p["max_disp"], p["n_paths"])
+        if key not in seq:
+            seq[key] = SGM(w, h, p["max_disp"], 7, 86, p["n_paths"])
+        one = seq[key].compute(p["left"], p["right"])
+        torch.cuda.synchronize()
+        assert (one.cpu().numpy() == p["out"].cpu().numpy()).all(), k
+    for c in seq.values():
+        c.close()
+    for k in (0, 17, 40):
+        p = pairs[k]
+        want = oracle.sgm(p["np_left"], p["np_right"], p["max_disp"], 7, 86, p["n_paths"]).out
+        assert (p["out"].cpu().numpy() == want).all(), k
+    b.close()
+
+
+def test_batch_reuse_with_smaller_batches(gpu):
+    import torch
+    specs = [(80, 60, 64, 8, True, True), (60, 80, 48, 4, False, True), (33, 17, 20, 2, True, False)]
+    pairs = _pairs(specs, gpu, 900)
+    b = Batch(7, 86)
+    for n in (3, 2, 1, 3):
+        _say(f"reuse round with {n} pairs")
+        for p in pairs[:n]:
+            p["out"].view(torch.int16).zero_()
+        b.compute(pairs[:n])
+        torch.cuda.synchronize()
+        for p in pairs[:n]:
+            want = oracle.sgm(p["np_left"], p["np_right"], p["max_disp"], 7, 86, p["n_paths"],
+                              median=p["median"], lr=p["lrcheck"]).out
+            assert (p["out"].cpu().numpy() == want).all()
+    b.close()
+
+
+def test_batch_rejects_invalid_items(gpu):
+    import torch
+    from paper_1610_04121_amd import SGMError
+    pairs = _pairs([(20, 10, 8, 4, False, False)], gpu, 1)
+    b = Batch(7, 86)
+    bad = dict(pairs[0])
+    bad["n_paths"] = 3
+    with pytest.raises(SGMError):
+        b.compute([pairs[0], bad])
+    b.close()

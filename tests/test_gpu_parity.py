@@ -183,3 +183,25 @@ def test_invalid_calls_raise_before_enqueue(gpu):
     with pytest.raises(SGMError):
         s.set_options(lr_threshold=-1)
     s.close()
+
+
+def test_graph_replay_matches_eager(gpu):
+    """Graph mode: several buffer sets, each replayed several times with eager
+    work and synchronisation in between; every replay equals the eager run."""
+    import torch
+    W, H, D = 160, 96, 48
+    pairs = [synth.make_pair(W, H, D, "RS", seed=500 + i) for i in range(3)]
+    eager = SGM(W, H, D, 7, 86, 8, median=True, lrcheck=True)
+    graph = SGM(W, H, D, 7, 86, 8, median=True, lrcheck=True, graph=True)
+    bufs = [(_t(p.left, gpu), _t(p.right, gpu), torch.empty((H, W), dtype=torch.uint16, device=gpu))
+            for p in pairs]
+    want = [_np(eager.compute(l, r)) for l, r, _ in bufs]
+    for rep in range(4):
+        _say(f"graph replay round {rep}")
+        for i, (l, r, o) in enumerate(bufs):
+            o.view(torch.int16).zero_()
+            graph.compute(l, r, o)
+            eager.compute(l, r)  # eager work between replays
+            assert (_np(o) == want[i]).all(), (rep, i)
+    eager.close()
+    graph.close()
