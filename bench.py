@@ -4,7 +4,8 @@ A step is one pass of the whole pipeline (census, cost volume, aggregation
 along all paths, sum + winner-take-all with the right view, median,
 left-right check) over one 640x480 pair with 128 disparity levels and 4
 paths, inputs already resident in HBM.  The timed region keeps F frames in
-flight (F contexts, each with its own workspace and stream; default F = 2):
+flight (F contexts, each with its own workspace and stream; default F = 1,
+so that the stage events time each kernel alone):
 frame k runs on context k mod F.  Prints one JSON line:
 
   value         frames/s over the timed steps (whole job = one GPU);
@@ -71,16 +72,77 @@ def cpu_baseline(pair, cfg, budget_s: float = 12.0):
                       f"frames (median + LR), single thread, {dt:.1f} s"}
 
 
+def bench_batch(dev, steps: int, warmup: int = 3):
+    """The 64-pair heterogeneous batch: one launch per stage through the
+    batch API against 64 plain single-pair launches on one stream."""
+    import torch
+
+    from paper_1610_04121_amd import SGM, synth
+    from paper_1610_04121_amd.sgm import Batch
+
+    items = synth.batch_items(64)
+    pairs, cells = [], 0
+    for it in items:
+        pr = synth.make_pair(it["w"], it["h"], it["max_disp"], it["scene"], seed=it["seed"])
+        pairs.append(dict(left=torch.from_numpy(pr.left).to(dev), right=torch.from_numpy(pr.right).to(dev),
+                          max_disp=it["max_disp"], n_paths=it["n_paths"],
+                          out=torch.empty((it["h"], it["w"]), dtype=torch.uint16, device=dev)))
+        cells += it["w"] * it["h"] * it["max_disp"] * it["n_paths"]
+    b = Batch(synth.P1_DEFAULT, synth.P2_DEFAULT)
+    st = torch.cuda.current_stream()
+    for _ in range(warmup):
+        b.compute(pairs, stream=st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.compute(pairs, stream=st)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    footprint = b.footprint(pairs)
+    b.close()
+
+    ctxs = {}
+    for p in pairs:
+        h, w = p["left"].shape
+        key = (w, h, p["max_disp"], p["n_paths"])
+        if key not in ctxs:
+            ctxs[key] = SGM(w, h, p["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, p["n_paths"])
+    seq = [(ctxs[(p["left"].shape[1], p["left"].shape[0], p["max_disp"], p["n_paths"])], p) for p in pairs]
+
+    def run_seq():
+        for c, p in seq:
+            c.compute(p["left"], p["right"], p["out"], stream=st)
+
+    for _ in range(warmup):
+        run_seq()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run_seq()
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / steps
+    for c in ctxs.values():
+        c.close()
+    return {"pairs": len(pairs), "batches": steps, "ms_per_batch": round(t_batch * 1e3, 4),
+            "pairs_per_s": round(len(pairs) / t_batch, 1), "gcells_per_s": round(cells / t_batch / 1e9, 1),
+            "sequential_ms": round(t_seq * 1e3, 4), "sequential_pairs_per_s": round(len(pairs) / t_seq, 1),
+            "speedup_vs_sequential": round(t_seq / t_batch, 3), "workspace_bytes": footprint,
+            "shapes": "64 pairs, sizes from {320x240, 640x480, 1242x375, 1280x720}, D from {64, 128}, "
+                      "4 or 8 paths, no median/LR"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--inflight", type=int, default=2, help="frames in flight in the timed region")
+    ap.add_argument("--inflight", type=int, default=1, help="frames in flight in the timed region")
     ap.add_argument("--profile-every", type=int, default=8,
                     help="record stage events on every n-th frame of each context")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip serialized/latency/copy measurements")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batched measurement")
+    ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--latency-samples", type=int, default=300)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (a known-size "
@@ -233,6 +295,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         line["copy_calibration_bytes"] = n
+    if not args.no_batch:
+        print("bench: 64-pair batch vs sequential launches", file=sys.stderr, flush=True)
+        line["batched"] = bench_batch(dev, args.batch_steps)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(pair, cfg)

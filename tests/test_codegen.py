@@ -45,7 +45,7 @@ def test_no_packed_fp32(device_asm):
 
 
 def test_aggregation_kernels_do_not_spill(device_asm):
-    names = re.findall(r"^(_Z\S*aggregate_kernel\S*):", device_asm, re.M)
+    names = re.findall(r"^(_Z\S*aggregate_(?:batch_)?kernel\S*):", device_asm, re.M)
     assert names
     for n in names:
         meta = device_asm[device_asm.index(n + ":"):]

@@ -19,11 +19,12 @@ def _t(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
-def _pairs(specs, dev, seed0):
+def _pairs(specs, dev, seed0, scenes=None):
     import torch
     out = []
     for k, (w, h, d, p, med, lr) in enumerate(specs):
-        pair = synth.make_pair(w, h, d, "RS", seed=seed0 + k)
+        scene, seed = scenes[k] if scenes else ("RS", seed0 + k)
+        pair = synth.make_pair(w, h, d, scene, seed=seed)
         out.append(dict(left=_t(pair.left, dev), right=_t(pair.right, dev), max_disp=d, n_paths=p,
                         median=med, lrcheck=lr, lr_threshold=1,
                         out=torch.empty((h, w), dtype=torch.uint16, device=dev),
@@ -69,7 +70,7 @@ def test_workload_batch_matches_sequential_calls(gpu):
     import torch
     items = synth.batch_items(64)
     specs = [(it["w"], it["h"], it["max_disp"], it["n_paths"], False, False) for it in items]
-    pairs = _pairs(specs, gpu, 1610041213)
+    pairs = _pairs(specs, gpu, 0, [(it["scene"], it["seed"]) for it in items])
     _say("64-pair workload batch")
     b = Batch(7, 86)
     b.compute(pairs)
