@@ -131,6 +131,115 @@ def bench_batch(dev, steps: int, warmup: int = 3):
                       "4 or 8 paths, no median/LR"}
 
 
+SERVE_SIZES = ((640, 480), (1242, 375), (1280, 720), (1920, 1080))
+SERVE_DISP = (128, 256)
+
+
+def bench_serve(dev, qps_levels, n_req: int, seed: int = 1610041214):
+    """Poisson arrivals of 8-path median + LR requests of mixed sizes and
+    disparity ranges, served by the continuous-batching server and, on the
+    same arrival times, by plain per-request launches (one context per
+    shape, one stream, each request synchronised before the next starts)."""
+    import numpy as np
+    import torch
+
+    from paper_1610_04121_amd import SGM, synth
+    from paper_1610_04121_amd.sgm import REQ_DONE, SGM_EBUSY, SGMError, Server
+
+    kinds = [(w, h, d) for (w, h) in SERVE_SIZES for d in SERVE_DISP]
+    pool = []
+    for k, (w, h, d) in enumerate(kinds):
+        pr = synth.make_pair(w, h, d, "R", seed=seed * 100 + k)
+        pool.append((torch.from_numpy(pr.left).to(dev), torch.from_numpy(pr.right).to(dev)))
+    budget = 64 << 30
+    srv = Server(budget, slots=4, max_group=8)
+    ctxs = [SGM(w, h, d, synth.P1_DEFAULT, synth.P2_DEFAULT, 8, median=True, lrcheck=True) for (w, h, d) in kinds]
+    st = torch.cuda.current_stream()
+    outs = {k: [torch.empty((h, w), dtype=torch.uint16, device=dev) for _ in range(n_req)]
+            for k, (w, h, _) in enumerate(kinds)}
+
+    def req(k, j):
+        w, h, d = kinds[k]
+        return dict(left=pool[k][0], right=pool[k][1], out=outs[k][j], max_disp=d, n_paths=8,
+                    median=True, lrcheck=True, lr_threshold=1)
+
+    # warm-up: every kind once through both paths
+    for k in range(len(kinds)):
+        srv.wait(srv.submit(req(k, 0)))
+        ctxs[k].compute(pool[k][0], pool[k][1], outs[k][0], stream=st)
+    torch.cuda.synchronize()
+
+    rng = np.random.default_rng(seed)
+    cells = np.array([w * h * d * 8 for (w, h, d) in kinds], dtype=np.float64)
+    levels = []
+    for qps in qps_levels:
+        arrivals = np.cumsum(rng.exponential(1.0 / qps, n_req))
+        which = rng.integers(0, len(kinds), n_req)
+
+        def pace(t0, i):
+            target = t0 + arrivals[i]
+            while True:
+                now = time.perf_counter()
+                if now >= target:
+                    return
+                if target - now > 2e-3:
+                    time.sleep(target - now - 1e-3)
+
+        # server
+        g0 = srv.stats()
+        t0 = time.perf_counter() + 0.005
+        tickets, rejected = [], 0
+        for i in range(n_req):
+            pace(t0, i)
+            try:
+                tickets.append((i, srv.submit(req(int(which[i]), i))))
+            except SGMError as e:
+                if e.code != SGM_EBUSY:
+                    raise
+                rejected += 1
+        lat, done_at = [], []
+        for i, t in tickets:
+            status, l = srv.wait(t)
+            assert status == REQ_DONE
+            lat.append(l)
+            done_at.append(arrivals[i] + l)
+        g1 = srv.stats()
+        span = max(done_at) - arrivals[0]
+        served_cells = sum(cells[which[i]] for i, _ in tickets)
+        server_res = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                      "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                      "frames_per_s": round(len(lat) / span, 1),
+                      "gcells_per_s": round(served_cells / span / 1e9, 1),
+                      "rejected": rejected,
+                      "mean_group": round((g1["grouped_requests"] - g0["grouped_requests"]) /
+                                          max(1, g1["groups"] - g0["groups"]), 2)}
+        # plain per-request launches on the same schedule
+        t0 = time.perf_counter() + 0.005
+        plat = []
+        for i in range(n_req):
+            pace(t0, i)
+            k = int(which[i])
+            ctxs[k].compute(pool[k][0], pool[k][1], outs[k][i], stream=st)
+            st.synchronize()
+            plat.append(time.perf_counter() - (t0 + arrivals[i]))
+        pspan = (t0 + arrivals[-1] + plat[-1]) - (t0 + arrivals[0])
+        plain_res = {"p50_ms": round(float(np.percentile(plat, 50)) * 1e3, 3),
+                     "p99_ms": round(float(np.percentile(plat, 99)) * 1e3, 3),
+                     "frames_per_s": round(n_req / pspan, 1),
+                     "gcells_per_s": round(float(cells[which].sum()) / pspan / 1e9, 1)}
+        print(f"bench: serve qps={qps} server p99={server_res['p99_ms']} ms plain p99={plain_res['p99_ms']} ms",
+              file=sys.stderr, flush=True)
+        levels.append({"offered_qps": qps, "requests": n_req, "server": server_res, "plain": plain_res})
+    stats = srv.stats()
+    srv.close()
+    for c in ctxs:
+        c.close()
+    return {"levels": levels, "budget_bytes": budget, "slots": 4, "max_group": 8,
+            "peak_bytes": stats["peak_bytes"],
+            "mix": "Poisson arrivals; sizes from {640x480, 1242x375, 1280x720, 1920x1080}, D from {128, 256}, "
+                   "8 paths, median + LR check; latency = submission to observed completion"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +252,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip serialized/latency/copy measurements")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batched measurement")
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-requests measurement")
+    ap.add_argument("--serve-qps", default="50,200,500,1000,2000")
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--latency-samples", type=int, default=300)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (a known-size "
@@ -298,6 +410,9 @@ def main():
     if not args.no_batch:
         print("bench: 64-pair batch vs sequential launches", file=sys.stderr, flush=True)
         line["batched"] = bench_batch(dev, args.batch_steps)
+    if not args.no_serve:
+        print("bench: served requests", file=sys.stderr, flush=True)
+        line["served"] = bench_serve(dev, [float(q) for q in args.serve_qps.split(",")], args.serve_requests)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(pair, cfg)

@@ -149,6 +149,80 @@ void sgm_batch_destroy(sgm_batch *b);
 int sgm_compute_batch(const sgm_item *items, int n, int P1, int P2, int census_w, int census_h,
                       sgm_stream_t stream);
 
+/* ---- request server: continuous batching on one device ----
+ * A server owns a device workspace of a fixed byte budget (allocated once,
+ * kept resident), `max_slots` streams and a scheduler thread.  Requests (one
+ * stereo pair each, an sgm_item) may be submitted from any host thread at any
+ * time.  Whenever a stream is free, the scheduler takes queued requests in
+ * arrival order for as long as their workspaces fit in the free part of the
+ * budget (admission by HBM footprint; first fit) and launches them as one
+ * group through the batched kernels; requests arriving while groups run join
+ * the next group, so their work overlaps with the groups in flight.  A result
+ * is identical to sgm_compute's for the same pair, whatever else ran beside
+ * it.  While groups are in flight the scheduler thread polls their completion
+ * events (it keeps one host core busy).
+ *
+ * The caller's images and output of a request must stay valid and untouched
+ * until the request reaches a final state.  No call may use a server during
+ * or after sgm_server_destroy. */
+typedef struct sgm_server sgm_server;
+
+enum {
+    SGM_REQ_QUEUED = 0,   /* waiting for a stream and workspace */
+    SGM_REQ_RUNNING = 1,  /* launched; results not yet complete */
+    SGM_REQ_DONE = 2,     /* output written */
+    SGM_REQ_CANCELED = 3, /* removed before it started */
+    SGM_REQ_FAILED = 4    /* a launch or the device failed */
+};
+
+typedef struct {
+    uint64_t submitted, completed, rejected, canceled, failed;
+    uint64_t groups;           /* launch groups started */
+    uint64_t grouped_requests; /* requests over all groups (mean group size =
+                                  grouped_requests / groups) */
+    uint64_t pending, running; /* current queue length, requests in flight */
+    size_t bytes_in_use, peak_bytes, budget_bytes;
+} sgm_server_stats;
+
+/* Creates a server on the current HIP device.  hbm_budget_bytes: workspace
+ * bytes to reserve (rounded down to 256); max_slots in [1, 16]: groups in
+ * flight at once; P1, P2 and the census window apply to every request.
+ * NULL on error (SGM_EINVAL for bad parameters, SGM_ENOMEM if the budget
+ * cannot be allocated). */
+sgm_server *sgm_server_create(size_t hbm_budget_bytes, int max_slots, int P1, int P2, int census_w,
+                              int census_h);
+
+/* Largest group the scheduler forms (default 8, at most 256) and longest
+ * queue accepted (default 4096). */
+int sgm_server_set_policy(sgm_server *s, int max_group, int max_pending);
+
+/* Workspace bytes a request takes from the budget (0 if invalid). */
+size_t sgm_server_request_bytes(sgm_server *s, const sgm_item *req);
+
+/* Queues one request and returns its ticket.  SGM_EINVAL: invalid request
+ * (checked here, before queueing); SGM_ENOMEM: its workspace alone exceeds
+ * the budget, so it could never be admitted; SGM_EBUSY: the queue is full
+ * (the request is rejected, not queued). */
+int sgm_server_submit(sgm_server *s, const sgm_item *req, uint64_t *ticket);
+
+/* State of a request (SGM_REQ_*) and, once final, its latency in seconds
+ * from submission to completion.  A ticket is retired once a call has
+ * reported a final state; using it again gives SGM_EINVAL. */
+int sgm_server_poll(sgm_server *s, uint64_t ticket, int *status, double *latency_s);
+
+/* As sgm_server_poll, after waiting up to timeout_ms (< 0: no limit) for a
+ * final state. */
+int sgm_server_wait(sgm_server *s, uint64_t ticket, int timeout_ms, int *status, double *latency_s);
+
+/* Cancels a request that has not started (SGM_EBUSY if it has). */
+int sgm_server_cancel(sgm_server *s, uint64_t ticket);
+
+int sgm_server_get_stats(sgm_server *s, sgm_server_stats *out);
+
+/* Cancels queued requests, waits for running groups to complete, then frees
+ * everything.  NULL is accepted. */
+void sgm_server_destroy(sgm_server *s);
+
 /* ---- stage timing ----
  * sgm_profile_enable(ctx, n) with n > 0 makes every n-th sgm_compute record
  * HIP events on its stream before the first stage and after each of the four

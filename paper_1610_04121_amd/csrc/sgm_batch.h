@@ -17,16 +17,32 @@ struct BatchParams {
     bool csct;
 };
 
-// Per-pair plans and workspace offsets inside one arena, plus the offset of
-// the aggregation queue counter.
+// Per-pair plans and workspace offsets inside one arena.
 struct BatchLayout {
     std::vector<Plan> plans;
     std::vector<size_t> offsets;
-    size_t counter_offset = 0;
     size_t total = 0;
 };
 
+// Checks every item and lays their workspaces out back to back (each
+// rounded up to 256 bytes).  false with *why set if an item is invalid.
 bool batch_plan(const BatchParams& bp, const sgm_item* items, int n, BatchLayout& L, const char** why);
+
+// Bytes one item's workspace takes in an arena (a multiple of 256).
+size_t item_bytes(const Plan& p);
+
+// Descriptor tables (pinned host copy + device copy) and the aggregation
+// queue counter of one launch sequence.  A staging object may be reused once
+// the launches that last used it have completed.
+struct BatchStaging;
+BatchStaging* staging_create();  // nullptr if an allocation fails
+void staging_destroy(BatchStaging* st);
+
+// Enqueues the census, cost, aggregation, sum + WTA and post launches for n
+// validated items on `stream`; item i's workspace starts at ws_base[i]
+// (item_bytes(plans[i]) bytes, 256-byte aligned).  Returns an SGM_ code.
+int batch_enqueue(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_base, const sgm_item* items,
+                  int n, BatchStaging* st, hipStream_t stream);
 
 // Message returned by sgm_last_error on this thread.
 void set_last_error(const std::string& msg);

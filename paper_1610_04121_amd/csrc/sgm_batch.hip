@@ -190,43 +190,60 @@ bool batch_plan(const BatchParams& bp, const sgm_item* items, int n, BatchLayout
         }
         if (!plan_finish(p, why)) return false;
         L.offsets.push_back(L.total);
-        L.total += align256(workspace_bytes(p));
+        L.total += item_bytes(p);
         L.plans.push_back(p);
     }
-    L.counter_offset = L.total;
-    L.total += 256;
     return true;
 }
 
-}  // namespace sgm
+size_t item_bytes(const Plan& p) { return align256(workspace_bytes(p)); }
 
-using sgm::BatchItem;
-using sgm::WorkItem;
-
-struct sgm_batch {
-    sgm::BatchParams bp;
-    int device = 0;
-    void* arena = nullptr;
-    size_t arena_bytes = 0;
+struct BatchStaging {
     BatchItem* d_items = nullptr;
     WorkItem* d_work = nullptr;
     size_t items_cap = 0, work_cap = 0;
-    BatchItem* h_items = nullptr;  // pinned staging
+    BatchItem* h_items = nullptr;  // pinned
     WorkItem* h_work = nullptr;
-    hipEvent_t staged = nullptr;   // the last copy out of the staging buffers
+    unsigned* counter = nullptr;   // aggregation queue head (device)
+    hipEvent_t staged = nullptr;   // the last copy out of the pinned tables
     bool staged_pending = false;
 };
+
+BatchStaging* staging_create() {
+    BatchStaging* st = new (std::nothrow) BatchStaging;
+    if (!st) return nullptr;
+    if (hipMalloc((void**)&st->counter, 256) != hipSuccess ||
+        hipEventCreateWithFlags(&st->staged, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        staging_destroy(st);
+        return nullptr;
+    }
+    return st;
+}
+
+void staging_destroy(BatchStaging* st) {
+    if (!st) return;
+    if (st->staged_pending) (void)hipEventSynchronize(st->staged);
+    if (st->d_items) (void)hipFree(st->d_items);
+    if (st->d_work) (void)hipFree(st->d_work);
+    if (st->h_items) (void)hipHostFree(st->h_items);
+    if (st->h_work) (void)hipHostFree(st->h_work);
+    if (st->counter) (void)hipFree(st->counter);
+    if (st->staged) (void)hipEventDestroy(st->staged);
+    delete st;
+}
 
 namespace {
 
 int berr(int code, const std::string& m) {
-    sgm::set_last_error(m);
+    set_last_error(m);
     return code;
 }
 
 int bhip(hipError_t e, const char* what) { return berr(SGM_EHIP, std::string(what) + ": " + hipGetErrorString(e)); }
 
-int grow_staging(sgm_batch* b, size_t nitems, size_t nwork) {
+// Grows the tables; waits first for the last copy out of the pinned ones.
+int grow_staging(BatchStaging* b, size_t nitems, size_t nwork) {
     if (b->staged_pending) {
         hipError_t e = hipEventSynchronize(b->staged);
         if (e != hipSuccess) return bhip(e, "hipEventSynchronize");
@@ -240,8 +257,10 @@ int grow_staging(sgm_batch* b, size_t nitems, size_t nwork) {
         b->d_items = nullptr;
         b->items_cap = 0;
         if (hipHostMalloc((void**)&b->h_items, cap * sizeof(BatchItem), hipHostMallocDefault) != hipSuccess ||
-            hipMalloc((void**)&b->d_items, cap * sizeof(BatchItem)) != hipSuccess)
+            hipMalloc((void**)&b->d_items, cap * sizeof(BatchItem)) != hipSuccess) {
+            (void)hipGetLastError();
             return berr(SGM_ENOMEM, "batch descriptor allocation failed");
+        }
         b->items_cap = cap;
     }
     if (nwork > b->work_cap) {
@@ -252,8 +271,10 @@ int grow_staging(sgm_batch* b, size_t nitems, size_t nwork) {
         b->d_work = nullptr;
         b->work_cap = 0;
         if (hipHostMalloc((void**)&b->h_work, cap * sizeof(WorkItem), hipHostMallocDefault) != hipSuccess ||
-            hipMalloc((void**)&b->d_work, cap * sizeof(WorkItem)) != hipSuccess)
+            hipMalloc((void**)&b->d_work, cap * sizeof(WorkItem)) != hipSuccess) {
+            (void)hipGetLastError();
             return berr(SGM_ENOMEM, "batch work-queue allocation failed");
+        }
         b->work_cap = cap;
     }
     return SGM_OK;
@@ -261,92 +282,22 @@ int grow_staging(sgm_batch* b, size_t nitems, size_t nwork) {
 
 }  // namespace
 
-extern "C" {
-
-sgm_batch* sgm_batch_create(int P1, int P2, int census_w, int census_h) {
-    sgm::Plan probe;  // validate the batch-wide parameters on a 1x1 pair
-    probe.W = probe.H = probe.D = 1;
-    probe.P1 = P1;
-    probe.P2 = P2;
-    probe.n_paths = 2;
-    probe.cw = census_w;
-    probe.ch = census_h;
-    const char* why = "invalid parameters";
-    if (!sgm::plan_finish(probe, &why)) {
-        berr(SGM_EINVAL, why);
-        return nullptr;
-    }
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) {
-        bhip(e, "hipGetDevice");
-        return nullptr;
-    }
-    sgm_batch* b = new (std::nothrow) sgm_batch;
-    if (!b) {
-        berr(SGM_ENOMEM, "host allocation failed");
-        return nullptr;
-    }
-    b->bp = sgm::BatchParams{P1, P2, census_w, census_h, false};
-    b->device = dev;
-    e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        bhip(e, "hipEventCreate");
-        delete b;
-        return nullptr;
-    }
-    return b;
-}
-
-size_t sgm_batch_footprint(sgm_batch* b, const sgm_item* items, int n) {
-    if (!b) return 0;
-    sgm::BatchLayout L;
-    const char* why = "";
-    if (!sgm::batch_plan(b->bp, items, n, L, &why)) return 0;
-    return L.total;
-}
-
-int sgm_batch_compute(sgm_batch* b, const sgm_item* items, int n, sgm_stream_t stream) {
-    using namespace sgm;
-    if (!b) return berr(SGM_EINVAL, "null batch");
-    if (n == 0) return SGM_OK;
-    BatchLayout L;
-    const char* why = "invalid item";
-    if (!batch_plan(b->bp, items, n, L, &why)) return berr(SGM_EINVAL, why);
-    for (int i = 0; i < n; ++i) {
-        if (!items[i].left || !items[i].right || !items[i].out) return berr(SGM_EINVAL, "null buffer pointer");
-        if ((const void*)items[i].out == (const void*)items[i].left ||
-            (const void*)items[i].out == (const void*)items[i].right)
-            return berr(SGM_EINVAL, "output aliases an input");
-    }
-    hipStream_t s = (hipStream_t)stream;
-
-    // workspace: grows (after the device is idle) to the largest batch seen
-    if (L.total > b->arena_bytes) {
-        hipError_t e = hipDeviceSynchronize();
-        if (e != hipSuccess) return bhip(e, "hipDeviceSynchronize");
-        if (b->arena) (void)hipFree(b->arena);
-        b->arena = nullptr;
-        b->arena_bytes = 0;
-        e = hipMalloc(&b->arena, L.total);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return berr(SGM_ENOMEM, std::string("batch workspace allocation failed: ") + hipGetErrorString(e));
-        }
-        b->arena_bytes = L.total;
-    }
-
+int batch_enqueue(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_base, const sgm_item* items, int n,
+                  BatchStaging* st, hipStream_t s) {
+    if (n <= 0) return SGM_OK;
     // work items: every direction's slices of every pair, S per wavefront
     std::vector<WorkItem> work;
     size_t census_blocks = 0, cost_blocks = 0, wta_blocks = 0, post_blocks = 0;
     std::vector<BatchItem> desc(n);
-    const bool generic = !(b->bp.cw == 9 && b->bp.ch == 7);
+    const bool generic = !(bp.cw == 9 && bp.ch == 7);
     size_t cost_smem = 0, wta_smem = 0, post_smem = 0;
     for (int i = 0; i < n; ++i) {
-        const Plan& p = L.plans[i];
-        const Workspace ws = workspace_carve(p, static_cast<uint8_t*>(b->arena) + L.offsets[i]);
+        const Plan& p = plans[i];
+        const Workspace ws = workspace_carve(p, ws_base[i]);
         int gh, gv;
         default_lanes(p, &gh, &gv);
+        gh = gh == 32 ? 32 : 16;  // the batch kernel has 32- and 16-lane horizontal groups
+        gv = 16;
         BatchItem& d = desc[i];
         d.left = items[i].left;
         d.right = items[i].right;
@@ -391,38 +342,140 @@ int sgm_batch_compute(sgm_batch* b, const sgm_item* items, int n, sgm_stream_t s
             for (int f = 0; f < nsl; f += S) work.push_back(WorkItem{i, r, dir.rx, dir.ry, f, steps});
         }
     }
+    if (census_blocks > 0x7FFFFFFF || cost_blocks > 0x7FFFFFFF || work.size() > 0x7FFFFFFF)
+        return berr(SGM_EINVAL, "batch too large");
     // longest slices first (largest-processing-time-first order)
     std::stable_sort(work.begin(), work.end(), [](const WorkItem& a, const WorkItem& c) { return a.steps > c.steps; });
-    if (census_blocks > 0x7FFFFFFF || cost_blocks > 0x7FFFFFFF) return berr(SGM_EINVAL, "batch too large");
 
-    if (int rc = grow_staging(b, desc.size(), work.size())) return rc;
-    memcpy(b->h_items, desc.data(), desc.size() * sizeof(BatchItem));
-    memcpy(b->h_work, work.data(), work.size() * sizeof(WorkItem));
-    hipError_t e = hipMemcpyAsync(b->d_items, b->h_items, desc.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s);
+    if (int rc = grow_staging(st, desc.size(), work.size())) return rc;
+    memcpy(st->h_items, desc.data(), desc.size() * sizeof(BatchItem));
+    memcpy(st->h_work, work.data(), work.size() * sizeof(WorkItem));
+    hipError_t e = hipMemcpyAsync(st->d_items, st->h_items, desc.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_work, b->h_work, work.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipEventRecord(b->staged, s);
+        e = hipMemcpyAsync(st->d_work, st->h_work, work.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(st->staged, s);
     if (e != hipSuccess) return bhip(e, "descriptor copy");
-    b->staged_pending = true;
+    st->staged_pending = true;
 
-    unsigned* counter = reinterpret_cast<unsigned*>(static_cast<uint8_t*>(b->arena) + L.counter_offset);
-    hipLaunchKernelGGL(census_batch_kernel, dim3((unsigned)census_blocks), dim3(256), 0, s, b->d_items, n,
-                       generic ? 1 : 0, (b->bp.cw - 1) / 2, (b->bp.ch - 1) / 2, counter);
-    hipLaunchKernelGGL(cost_batch_kernel, dim3((unsigned)cost_blocks), dim3(256), cost_smem, s, b->d_items, n);
+    hipLaunchKernelGGL(census_batch_kernel, dim3((unsigned)census_blocks), dim3(256), 0, s, st->d_items, n,
+                       generic ? 1 : 0, (bp.cw - 1) / 2, (bp.ch - 1) / 2, st->counter);
+    hipLaunchKernelGGL(cost_batch_kernel, dim3((unsigned)cost_blocks), dim3(256), cost_smem, s, st->d_items, n);
     // persistent grid: at most two wavefronts per SIMD (256 CUs x 4 SIMDs)
     const int nwork = (int)work.size();
     const int waves = std::min(nwork, 2048);
-    hipLaunchKernelGGL(aggregate_batch_kernel, dim3((waves + 3) / 4), dim3(256), 0, s, b->d_items, b->d_work, nwork,
-                       counter, b->bp.P1, b->bp.P2);
-    hipLaunchKernelGGL(wta_batch_kernel, dim3((unsigned)wta_blocks), dim3(1024), wta_smem, s, b->d_items, n);
+    hipLaunchKernelGGL(aggregate_batch_kernel, dim3((waves + 3) / 4), dim3(256), 0, s, st->d_items, st->d_work, nwork,
+                       st->counter, bp.P1, bp.P2);
+    hipLaunchKernelGGL(wta_batch_kernel, dim3((unsigned)wta_blocks), dim3(1024), wta_smem, s, st->d_items, n);
     if (post_blocks > 0) {
         // pairs without a post stage own empty block ranges; the search for
         // the last pair whose range starts at or before a block skips them
-        hipLaunchKernelGGL(post_batch_kernel, dim3((unsigned)post_blocks), dim3(256), post_smem, s, b->d_items, n);
+        hipLaunchKernelGGL(post_batch_kernel, dim3((unsigned)post_blocks), dim3(256), post_smem, s, st->d_items, n);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return bhip(e, "batch kernel launch");
     return SGM_OK;
+}
+
+}  // namespace sgm
+
+struct sgm_batch {
+    sgm::BatchParams bp;
+    int device = 0;
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    sgm::BatchStaging* st = nullptr;
+};
+
+namespace {
+
+int api_err(int code, const std::string& m) {
+    sgm::set_last_error(m);
+    return code;
+}
+
+int api_hip(hipError_t e, const char* what) {
+    return api_err(SGM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+sgm_batch* sgm_batch_create(int P1, int P2, int census_w, int census_h) {
+    sgm::Plan probe;  // validate the batch-wide parameters on a 1x1 pair
+    probe.W = probe.H = probe.D = 1;
+    probe.P1 = P1;
+    probe.P2 = P2;
+    probe.n_paths = 2;
+    probe.cw = census_w;
+    probe.ch = census_h;
+    const char* why = "invalid parameters";
+    if (!sgm::plan_finish(probe, &why)) {
+        api_err(SGM_EINVAL, why);
+        return nullptr;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        api_hip(e, "hipGetDevice");
+        return nullptr;
+    }
+    sgm_batch* b = new (std::nothrow) sgm_batch;
+    if (!b) {
+        api_err(SGM_ENOMEM, "host allocation failed");
+        return nullptr;
+    }
+    b->bp = sgm::BatchParams{P1, P2, census_w, census_h, false};
+    b->device = dev;
+    b->st = sgm::staging_create();
+    if (!b->st) {
+        api_err(SGM_ENOMEM, "batch staging allocation failed");
+        delete b;
+        return nullptr;
+    }
+    return b;
+}
+
+size_t sgm_batch_footprint(sgm_batch* b, const sgm_item* items, int n) {
+    if (!b) return 0;
+    sgm::BatchLayout L;
+    const char* why = "";
+    if (!sgm::batch_plan(b->bp, items, n, L, &why)) return 0;
+    return L.total;
+}
+
+int sgm_batch_compute(sgm_batch* b, const sgm_item* items, int n, sgm_stream_t stream) {
+    using namespace sgm;
+    if (!b) return api_err(SGM_EINVAL, "null batch");
+    if (n == 0) return SGM_OK;
+    BatchLayout L;
+    const char* why = "invalid item";
+    if (!batch_plan(b->bp, items, n, L, &why)) return api_err(SGM_EINVAL, why);
+    for (int i = 0; i < n; ++i) {
+        if (!items[i].left || !items[i].right || !items[i].out) return api_err(SGM_EINVAL, "null buffer pointer");
+        if ((const void*)items[i].out == (const void*)items[i].left ||
+            (const void*)items[i].out == (const void*)items[i].right)
+            return api_err(SGM_EINVAL, "output aliases an input");
+    }
+    hipStream_t s = (hipStream_t)stream;
+
+    // workspace: grows (after the device is idle) to the largest batch seen
+    if (L.total > b->arena_bytes) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return api_hip(e, "hipDeviceSynchronize");
+        if (b->arena) (void)hipFree(b->arena);
+        b->arena = nullptr;
+        b->arena_bytes = 0;
+        e = hipMalloc(&b->arena, L.total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return api_err(SGM_ENOMEM, std::string("batch workspace allocation failed: ") + hipGetErrorString(e));
+        }
+        b->arena_bytes = L.total;
+    }
+    std::vector<uint8_t*> bases(n);
+    for (int i = 0; i < n; ++i) bases[i] = static_cast<uint8_t*>(b->arena) + L.offsets[i];
+    return batch_enqueue(b->bp, L.plans.data(), bases.data(), items, n, b->st, s);
 }
 
 void sgm_batch_destroy(sgm_batch* b) {
@@ -430,11 +483,7 @@ void sgm_batch_destroy(sgm_batch* b) {
     (void)hipSetDevice(b->device);
     (void)hipDeviceSynchronize();
     if (b->arena) (void)hipFree(b->arena);
-    if (b->d_items) (void)hipFree(b->d_items);
-    if (b->d_work) (void)hipFree(b->d_work);
-    if (b->h_items) (void)hipHostFree(b->h_items);
-    if (b->h_work) (void)hipHostFree(b->h_work);
-    if (b->staged) (void)hipEventDestroy(b->staged);
+    sgm::staging_destroy(b->st);
     delete b;
 }
 
@@ -445,7 +494,7 @@ int sgm_compute_batch(const sgm_item* items, int n, int P1, int P2, int census_w
     int rc = sgm_batch_compute(b, items, n, stream);
     if (rc == SGM_OK) {
         hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-        if (e != hipSuccess) rc = bhip(e, "hipStreamSynchronize");
+        if (e != hipSuccess) rc = api_hip(e, "hipStreamSynchronize");
     }
     sgm_batch_destroy(b);
     return rc;

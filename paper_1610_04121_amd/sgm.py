@@ -23,7 +23,19 @@ EXPORTS = [
     "sgm_debug_stage", "sgm_set_tuning", "sgm_get_tuning",
     "sgm_batch_create", "sgm_batch_compute", "sgm_batch_footprint", "sgm_batch_destroy",
     "sgm_compute_batch",
+    "sgm_server_create", "sgm_server_set_policy", "sgm_server_request_bytes", "sgm_server_submit",
+    "sgm_server_poll", "sgm_server_wait", "sgm_server_cancel", "sgm_server_get_stats", "sgm_server_destroy",
 ]
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELED, REQ_FAILED = range(5)
+FINAL = (REQ_DONE, REQ_CANCELED, REQ_FAILED)
+
+
+class ServerStats(ctypes.Structure):
+    """Mirror of sgm_server_stats."""
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "rejected", "canceled", "failed",
+                                              "groups", "grouped_requests", "pending", "running")] + \
+               [(n, ctypes.c_size_t) for n in ("bytes_in_use", "peak_bytes", "budget_bytes")]
 
 
 class Item(ctypes.Structure):
@@ -89,6 +101,24 @@ def lib() -> ctypes.CDLL:
     L.sgm_batch_destroy.restype = None
     L.sgm_compute_batch.argtypes = [ctypes.POINTER(Item), i, i, i, i, i, P]
     L.sgm_compute_batch.restype = i
+    L.sgm_server_create.argtypes = [ctypes.c_size_t, i, i, i, i, i]
+    L.sgm_server_create.restype = P
+    L.sgm_server_set_policy.argtypes = [P, i, i]
+    L.sgm_server_set_policy.restype = i
+    L.sgm_server_request_bytes.argtypes = [P, ctypes.POINTER(Item)]
+    L.sgm_server_request_bytes.restype = ctypes.c_size_t
+    L.sgm_server_submit.argtypes = [P, ctypes.POINTER(Item), ctypes.POINTER(ctypes.c_uint64)]
+    L.sgm_server_submit.restype = i
+    L.sgm_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_double)]
+    L.sgm_server_poll.restype = i
+    L.sgm_server_wait.argtypes = [P, ctypes.c_uint64, i, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_double)]
+    L.sgm_server_wait.restype = i
+    L.sgm_server_cancel.argtypes = [P, ctypes.c_uint64]
+    L.sgm_server_cancel.restype = i
+    L.sgm_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+    L.sgm_server_get_stats.restype = i
+    L.sgm_server_destroy.argtypes = [P]
+    L.sgm_server_destroy.restype = None
     L.sgm_set_tuning.argtypes = [P, i, i, i]
     L.sgm_set_tuning.restype = i
     L.sgm_get_tuning.argtypes = [P, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
@@ -289,6 +319,71 @@ class Batch:
         if getattr(self, "_b", None):
             lib().sgm_batch_destroy(self._b)
             self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request server (see sgm_server_create).
+
+    submit() takes device tensors and returns a ticket; the tensors are kept
+    referenced here until the request reaches a final state."""
+
+    def __init__(self, hbm_budget_bytes: int, slots: int = 4, P1=7, P2=86, census_w=9, census_h=7,
+                 max_group: int = 8, max_pending: int = 4096):
+        self._s = lib().sgm_server_create(hbm_budget_bytes, slots, P1, P2, census_w, census_h)
+        if not self._s:
+            raise SGMError(SGM_EINVAL, last_error())
+        self._held = {}
+        self.set_policy(max_group, max_pending)
+
+    def set_policy(self, max_group: int = 8, max_pending: int = 4096):
+        _check(lib().sgm_server_set_policy(self._s, max_group, max_pending))
+
+    def request_bytes(self, pair) -> int:
+        return lib().sgm_server_request_bytes(self._s, _items([pair]))
+
+    def submit(self, pair) -> int:
+        """pair: dict as for Batch.compute.  Raises SGMError (code SGM_EBUSY
+        when the queue is full)."""
+        arr = _items([pair])
+        t = ctypes.c_uint64()
+        _check(lib().sgm_server_submit(self._s, arr, ctypes.byref(t)))
+        self._held[t.value] = (pair["left"], pair["right"], pair["out"])
+        return t.value
+
+    def _report(self, fn, ticket, *extra):
+        st, lat = ctypes.c_int(), ctypes.c_double()
+        _check(fn(self._s, ticket, *extra, ctypes.byref(st), ctypes.byref(lat)))
+        if st.value in FINAL:
+            self._held.pop(ticket, None)
+            return st.value, lat.value
+        return st.value, None
+
+    def poll(self, ticket):
+        """(status, latency_s or None)."""
+        return self._report(lib().sgm_server_poll, ticket)
+
+    def wait(self, ticket, timeout_ms: int = -1):
+        return self._report(lib().sgm_server_wait, ticket, timeout_ms)
+
+    def cancel(self, ticket):
+        _check(lib().sgm_server_cancel(self._s, ticket))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().sgm_server_get_stats(self._s, ctypes.byref(st)))
+        return {n: getattr(st, n) for n, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_s", None):
+            lib().sgm_server_destroy(self._s)
+            self._s = None
+            self._held.clear()
 
     def __del__(self):
         try:
