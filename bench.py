@@ -135,7 +135,8 @@ SERVE_SIZES = ((640, 480), (1242, 375), (1280, 720), (1920, 1080))
 SERVE_DISP = (128, 256)
 
 
-def bench_serve(dev, qps_levels, n_req: int, seed: int = 1610041214):
+def bench_serve(dev, qps_levels, n_req: int, slots: int = 4, streams: int = 4, max_group: int = 8,
+                group_cells: int = 1 << 28, seed: int = 1610041214):
     """Poisson arrivals of 8-path median + LR requests of mixed sizes and
     disparity ranges, served by the continuous-batching server and, on the
     same arrival times, by plain per-request launches (one context per
@@ -152,7 +153,7 @@ def bench_serve(dev, qps_levels, n_req: int, seed: int = 1610041214):
         pr = synth.make_pair(w, h, d, "R", seed=seed * 100 + k)
         pool.append((torch.from_numpy(pr.left).to(dev), torch.from_numpy(pr.right).to(dev)))
     budget = 64 << 30
-    srv = Server(budget, slots=4, max_group=8)
+    srv = Server(budget, slots=slots, streams=streams, max_group=max_group, max_group_cells=group_cells)
     ctxs = [SGM(w, h, d, synth.P1_DEFAULT, synth.P2_DEFAULT, 8, median=True, lrcheck=True) for (w, h, d) in kinds]
     st = torch.cuda.current_stream()
     outs = {k: [torch.empty((h, w), dtype=torch.uint16, device=dev) for _ in range(n_req)]
@@ -234,7 +235,8 @@ def bench_serve(dev, qps_levels, n_req: int, seed: int = 1610041214):
     srv.close()
     for c in ctxs:
         c.close()
-    return {"levels": levels, "budget_bytes": budget, "slots": 4, "max_group": 8,
+    return {"levels": levels, "budget_bytes": budget, "slots": slots, "streams": streams, "max_group": max_group,
+            "max_group_cells": group_cells,
             "peak_bytes": stats["peak_bytes"],
             "mix": "Poisson arrivals; sizes from {640x480, 1242x375, 1280x720, 1920x1080}, D from {128, 256}, "
                    "8 paths, median + LR check; latency = submission to observed completion"}
@@ -253,8 +255,12 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batched measurement")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-requests measurement")
-    ap.add_argument("--serve-qps", default="50,200,500,1000,2000")
+    ap.add_argument("--serve-qps", default="50,200,500,1000,1500,2000")
     ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-max-group", type=int, default=8)
+    ap.add_argument("--serve-group-cells", type=int, default=1 << 28)
     ap.add_argument("--latency-samples", type=int, default=300)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (a known-size "
@@ -412,7 +418,9 @@ def main():
         line["batched"] = bench_batch(dev, args.batch_steps)
     if not args.no_serve:
         print("bench: served requests", file=sys.stderr, flush=True)
-        line["served"] = bench_serve(dev, [float(q) for q in args.serve_qps.split(",")], args.serve_requests)
+        line["served"] = bench_serve(dev, [float(q) for q in args.serve_qps.split(",")], args.serve_requests,
+                                     args.serve_slots, args.serve_streams, args.serve_max_group,
+                                     args.serve_group_cells)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(pair, cfg)

@@ -151,16 +151,19 @@ int sgm_compute_batch(const sgm_item *items, int n, int P1, int P2, int census_w
 
 /* ---- request server: continuous batching on one device ----
  * A server owns a device workspace of a fixed byte budget (allocated once,
- * kept resident), `max_slots` streams and a scheduler thread.  Requests (one
- * stereo pair each, an sgm_item) may be submitted from any host thread at any
- * time.  Whenever a stream is free, the scheduler takes queued requests in
- * arrival order for as long as their workspaces fit in the free part of the
- * budget (admission by HBM footprint; first fit) and launches them as one
- * group through the batched kernels; requests arriving while groups run join
- * the next group, so their work overlaps with the groups in flight.  A result
- * is identical to sgm_compute's for the same pair, whatever else ran beside
- * it.  While groups are in flight the scheduler thread polls their completion
- * events (it keeps one host core busy).
+ * kept resident), `max_slots` launch slots over `n_streams` streams and a
+ * scheduler thread.  Requests (one stereo pair each, an sgm_item) may be
+ * submitted from any host thread at any time.  Whenever a slot is free, the
+ * scheduler takes queued requests in arrival order for as long as their
+ * workspaces fit in the free part of the budget (admission by HBM footprint;
+ * first fit) and launches them as one group (a group of one through the
+ * single-pair kernels, larger groups through the batched kernels).  Slots
+ * sharing a stream run their groups back to back without waiting for the
+ * host; slots on different streams run concurrently.  Requests arriving while
+ * groups run join the next group.  A result is identical to sgm_compute's
+ * for the same pair, whatever else ran beside it.  While groups are in flight
+ * the scheduler thread polls their completion events (it keeps one host core
+ * busy).
  *
  * The caller's images and output of a request must stay valid and untouched
  * until the request reaches a final state.  No call may use a server during
@@ -186,15 +189,19 @@ typedef struct {
 
 /* Creates a server on the current HIP device.  hbm_budget_bytes: workspace
  * bytes to reserve (rounded down to 256); max_slots in [1, 16]: groups in
- * flight at once; P1, P2 and the census window apply to every request.
- * NULL on error (SGM_EINVAL for bad parameters, SGM_ENOMEM if the budget
- * cannot be allocated). */
-sgm_server *sgm_server_create(size_t hbm_budget_bytes, int max_slots, int P1, int P2, int census_w,
-                              int census_h);
+ * flight at once; n_streams in [1, max_slots]: streams the slots are spread
+ * over (1 = groups run one after another in admission order); P1, P2 and
+ * the census window apply to every request.  NULL on error (SGM_EINVAL for
+ * bad parameters, SGM_ENOMEM if the budget cannot be allocated). */
+sgm_server *sgm_server_create(size_t hbm_budget_bytes, int max_slots, int n_streams, int P1, int P2,
+                              int census_w, int census_h);
 
-/* Largest group the scheduler forms (default 8, at most 256) and longest
- * queue accepted (default 4096). */
-int sgm_server_set_policy(sgm_server *s, int max_group, int max_pending);
+/* Group limits and queue length.  A group takes at most max_group requests
+ * (default 8, at most 256) and, unless it holds a single request, at most
+ * max_group_cells cells in total (W * H * max_disp * n_paths summed over its
+ * requests; default 2^28): requests that fill the device alone run alone.
+ * The queue accepts at most max_pending requests (default 4096). */
+int sgm_server_set_policy(sgm_server *s, int max_group, int max_pending, uint64_t max_group_cells);
 
 /* Workspace bytes a request takes from the budget (0 if invalid). */
 size_t sgm_server_request_bytes(sgm_server *s, const sgm_item *req);

@@ -5,13 +5,20 @@
 //   * a workspace arena of a fixed byte budget, allocated once and kept
 //     resident; each admitted request takes a block of it (first fit) sized by
 //     its own footprint and gives it back when its results are complete;
-//   * `slots` streams (default priority); a slot runs one group of requests at
-//     a time through the batched kernels (one launch per stage for the group).
+//   * `slots` launch slots spread round-robin over `streams` streams (default
+//     priority).  A slot holds one group of requests at a time.  Slots on the
+//     same stream run their groups back to back in admission order (the
+//     device never waits for the host between them); slots on different
+//     streams run concurrently.
 // Whenever a slot is free, the scheduler takes requests in arrival order from
-// the head of the queue for as long as their workspaces fit and the group is
-// below the group-size limit, and launches them as one group.  Requests that
-// arrive while groups run are admitted into the next free slot, so their work
-// overlaps on the device with the groups in flight.  Latency is measured from
+// the head of the queue for as long as their workspaces fit and the group
+// stays within its limits (a request count, and a total of W * H * D * paths
+// cells: a request that fills the device on its own gains nothing from
+// sharing a launch, and would only delay the others), and launches them as
+// one group: a group of one
+// runs through the single-pair kernels, a larger group through the batched
+// kernels (one launch per stage for the group).  Requests that arrive while
+// groups run are admitted into the next free slot.  Latency is measured from
 // submission to the moment the scheduler sees the group's completion event.
 #include <hip/hip_runtime.h>
 
@@ -85,13 +92,14 @@ struct Request {
     sgm_item item{};
     sgm::Plan plan;
     size_t bytes = 0, offset = 0;
+    uint64_t cells = 0;  // W * H * D * paths
     Clock::time_point t_submit;
     int status = SGM_REQ_QUEUED;
     double latency_s = 0.0;
 };
 
 struct Slot {
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // shared with the other slots of its stream
     hipEvent_t done = nullptr;
     sgm::BatchStaging* st = nullptr;
     std::vector<Request*> group;  // empty = free
@@ -106,6 +114,7 @@ struct sgm_server {
     void* arena = nullptr;
     ArenaAllocator alloc;  // scheduler thread only
     std::vector<Slot> slots;
+    std::vector<hipStream_t> streams;
 
     std::mutex mu;
     std::condition_variable cv_work;  // new requests or shutdown
@@ -115,6 +124,7 @@ struct sgm_server {
     uint64_t next_ticket = 1;
     int max_group = 8;
     size_t max_pending = 4096;
+    uint64_t max_group_cells = uint64_t(1) << 28;
     bool stop = false;
     std::atomic<uint64_t> wake{0};  // bumped by every submission and by shutdown
     sgm_server_stats stats{};
@@ -172,9 +182,12 @@ void scheduler(sgm_server* s) {
         for (Slot& slot : s->slots) {
             if (s->pending.empty()) break;
             if (!slot.group.empty()) continue;
+            uint64_t cells = 0;
             while (!s->pending.empty() && (int)slot.group.size() < s->max_group) {
                 Request* r = s->pending.front();
+                if (!slot.group.empty() && cells + r->cells > s->max_group_cells) break;
                 if (!s->alloc.alloc(r->bytes, &r->offset)) break;
+                cells += r->cells;
                 s->pending.pop_front();
                 r->status = SGM_REQ_RUNNING;
                 slot.group.push_back(r);
@@ -197,8 +210,16 @@ void scheduler(sgm_server* s) {
             // enqueueing takes tens of microseconds: let submitters in meanwhile
             // (the slot and the allocator belong to this thread only)
             lk.unlock();
-            int rc = sgm::batch_enqueue(s->bp, plans.data(), bases.data(), items.data(), (int)items.size(), slot.st,
+            int rc = SGM_OK;
+            if (items.size() == 1) {
+                const sgm::Workspace ws = sgm::workspace_carve(plans[0], bases[0]);
+                if (sgm::launch_pipeline(plans[0], ws, items[0].left, items[0].right, items[0].out, slot.stream) !=
+                    hipSuccess)
+                    rc = SGM_EHIP;
+            } else {
+                rc = sgm::batch_enqueue(s->bp, plans.data(), bases.data(), items.data(), (int)items.size(), slot.st,
                                         slot.stream);
+            }
             if (rc == SGM_OK && hipEventRecord(slot.done, slot.stream) != hipSuccess) rc = SGM_EHIP;
             lk.lock();
             if (rc != SGM_OK) {
@@ -255,7 +276,8 @@ bool check_item(const sgm_server* s, const sgm_item* it, sgm::Plan* plan, size_t
 
 extern "C" {
 
-sgm_server* sgm_server_create(size_t hbm_budget_bytes, int max_slots, int P1, int P2, int census_w, int census_h) {
+sgm_server* sgm_server_create(size_t hbm_budget_bytes, int max_slots, int n_streams, int P1, int P2, int census_w,
+                              int census_h) {
     sgm::Plan probe;  // batch-wide parameters, checked on a 1x1 pair
     probe.W = probe.H = probe.D = 1;
     probe.P1 = P1;
@@ -268,8 +290,8 @@ sgm_server* sgm_server_create(size_t hbm_budget_bytes, int max_slots, int P1, in
         serr(SGM_EINVAL, why);
         return nullptr;
     }
-    if (max_slots < 1 || max_slots > 16) {
-        serr(SGM_EINVAL, "max_slots must be in [1, 16]");
+    if (max_slots < 1 || max_slots > 16 || n_streams < 1 || n_streams > max_slots) {
+        serr(SGM_EINVAL, "need 1 <= n_streams <= max_slots <= 16");
         return nullptr;
     }
     if (hbm_budget_bytes < 256) {
@@ -298,33 +320,40 @@ sgm_server* sgm_server_create(size_t hbm_budget_bytes, int max_slots, int P1, in
         return nullptr;
     }
     s->alloc.reset(s->budget);
+    s->streams.assign(n_streams, nullptr);
     s->slots.resize(max_slots);
-    for (Slot& slot : s->slots) {
-        slot.st = sgm::staging_create();
-        if (!slot.st || hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&slot.done, hipEventDisableTiming) != hipSuccess) {
-            (void)hipGetLastError();
-            serr(SGM_EHIP, "server stream setup failed");
-            for (Slot& t : s->slots) {
-                if (t.st) sgm::staging_destroy(t.st);
-                if (t.stream) (void)hipStreamDestroy(t.stream);
-                if (t.done) (void)hipEventDestroy(t.done);
-            }
-            (void)hipFree(s->arena);
-            delete s;
-            return nullptr;
+    bool ok = true;
+    for (hipStream_t& st : s->streams) ok = ok && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+    for (size_t k = 0; k < s->slots.size(); ++k) {
+        Slot& slot = s->slots[k];
+        slot.stream = s->streams[k % s->streams.size()];
+        slot.st = ok ? sgm::staging_create() : nullptr;
+        ok = ok && slot.st && hipEventCreateWithFlags(&slot.done, hipEventDisableTiming) == hipSuccess;
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        serr(SGM_EHIP, "server stream setup failed");
+        for (Slot& t : s->slots) {
+            if (t.st) sgm::staging_destroy(t.st);
+            if (t.done) (void)hipEventDestroy(t.done);
         }
+        for (hipStream_t st : s->streams)
+            if (st) (void)hipStreamDestroy(st);
+        (void)hipFree(s->arena);
+        delete s;
+        return nullptr;
     }
     s->worker = std::thread(scheduler, s);
     return s;
 }
 
-int sgm_server_set_policy(sgm_server* s, int max_group, int max_pending) {
+int sgm_server_set_policy(sgm_server* s, int max_group, int max_pending, uint64_t max_group_cells) {
     if (!s) return serr(SGM_EINVAL, "null server");
     if (max_group < 1 || max_group > 256 || max_pending < 1) return serr(SGM_EINVAL, "bad policy");
     std::lock_guard<std::mutex> lk(s->mu);
     s->max_group = max_group;
     s->max_pending = (size_t)max_pending;
+    s->max_group_cells = max_group_cells;
     return SGM_OK;
 }
 
@@ -350,6 +379,7 @@ int sgm_server_submit(sgm_server* s, const sgm_item* req, uint64_t* ticket) {
         return serr(SGM_ENOMEM, "request workspace exceeds the server's memory budget");
     }
     r->item = *req;
+    r->cells = (uint64_t)req->width * req->height * req->max_disp * req->n_paths;
     r->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -450,9 +480,9 @@ void sgm_server_destroy(sgm_server* s) {
     s->cv_done.notify_all();
     for (Slot& t : s->slots) {
         sgm::staging_destroy(t.st);
-        (void)hipStreamDestroy(t.stream);
         (void)hipEventDestroy(t.done);
     }
+    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     (void)hipFree(s->arena);
     for (auto& kv : s->live) delete kv.second;
     delete s;

@@ -38,7 +38,8 @@ def _alone(req):
     return res
 
 
-def test_mixed_concurrent_requests_match_alone(gpu):
+@pytest.mark.parametrize("slots,streams", [(4, 2), (4, 4), (2, 1)])
+def test_mixed_concurrent_requests_match_alone(gpu, slots, streams):
     import torch
     rng = np.random.default_rng(44)
     shapes = [(64, 48), (160, 90), (320, 240), (97, 31), (33, 65), (640, 480)]
@@ -47,14 +48,14 @@ def test_mixed_concurrent_requests_match_alone(gpu):
         w, h = shapes[k % len(shapes)]
         reqs.append(_req(gpu, w, h, int(rng.choice([16, 64, 128, 200])), int(rng.choice([2, 4, 8])),
                          bool(rng.integers(0, 2)), bool(rng.integers(0, 2)), 1000 + k))
-    srv = Server(8 << 30, slots=4, max_group=4)
+    srv = Server(8 << 30, slots=slots, streams=streams, max_group=4, max_group_cells=1 << 40)
     tickets = [None] * len(reqs)
 
     def submit(idx):
         for i in idx:
             tickets[i] = srv.submit(reqs[i])
 
-    _say("24 requests from two submitting threads")
+    _say(f"24 requests from two submitting threads, {slots} slots on {streams} streams")
     th = [threading.Thread(target=submit, args=(range(j, len(reqs), 2),)) for j in range(2)]
     for t in th:
         t.start()
@@ -66,6 +67,7 @@ def test_mixed_concurrent_requests_match_alone(gpu):
     stats = srv.stats()
     srv.close()
     assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    assert stats["groups"] < len(reqs)  # some requests were batched together
     assert stats["peak_bytes"] <= stats["budget_bytes"]
     torch.cuda.synchronize()
     for i, r in enumerate(reqs):
@@ -84,7 +86,7 @@ def test_admission_respects_memory_budget(gpu):
     one = probe.request_bytes(reqs[0])
     probe.close()
     budget = 2 * one + one // 2  # two requests fit at a time, never three
-    srv = Server(budget, slots=4, max_group=8)
+    srv = Server(budget, slots=4, streams=4, max_group=8)
     _say(f"budget {budget} bytes, {one} per request")
     ts = [srv.submit(r) for r in reqs]
     for t in ts:
@@ -95,6 +97,26 @@ def test_admission_respects_memory_budget(gpu):
     assert st["completed"] == 6
     want = _alone(reqs[0])
     assert (reqs[0]["out"].cpu().numpy() == want).all()
+
+
+def test_large_requests_run_alone(gpu):
+    """Requests above the group cell limit are never grouped; small ones are."""
+    big = [_req(gpu, 640, 480, 128, 8, False, False, 60 + k) for k in range(4)]  # 315M cells each
+    small = [_req(gpu, 64, 48, 32, 4, False, False, 80 + k) for k in range(6)]
+    srv = Server(16 << 30, slots=1, max_group=8, max_group_cells=1 << 28)
+    ts = [srv.submit(r) for r in big]
+    for t in ts:
+        assert srv.wait(t, 60000)[0] == REQ_DONE
+    st = srv.stats()
+    assert st["groups"] == 4 and st["grouped_requests"] == 4
+    ts = [srv.submit(r) for r in [big[0]] + small]  # the small ones queue behind a big one
+    for t in ts:
+        assert srv.wait(t, 60000)[0] == REQ_DONE
+    st = srv.stats()
+    srv.close()
+    assert st["groups"] < 4 + 7
+    for r in small[:2]:
+        assert (r["out"].cpu().numpy() == _alone(r)).all()
 
 
 def test_oversize_and_invalid_requests_rejected(gpu):
