@@ -282,16 +282,22 @@ def main():
     dev = torch.device("cuda:0")
     left = torch.from_numpy(pair.left).to(dev)
     right = torch.from_numpy(pair.right).to(dev)
-    fused = os.environ.get("SGM_FUSED", "0") == "1"
     F = max(1, args.inflight)
 
-    def make_ctx(graph=False):
+    def make_ctx(graph=False, tuning=None):
         c = SGM(W, H, D, synth.P1_DEFAULT, synth.P2_DEFAULT, P, median=cfg["median"],
                 lrcheck=cfg["lr"], graph=graph)
-        c.set_tuning(0, 0, fused)
+        if tuning:
+            c.set_tuning(*tuning)
         return c
 
-    ctxs = [make_ctx() for _ in range(F)]
+    # kernel shape: measured on this device for this workload (results do not depend on it)
+    probe = make_ctx()
+    tuned = probe.autotune(left, right, use_cache=False)
+    probe.close()
+    choice = tuple(tuned["choice"])
+    print(f"bench: autotuned kernel shape {choice}", file=sys.stderr, flush=True)
+    ctxs = [make_ctx(tuning=choice) for _ in range(F)]
     streams = [torch.cuda.Stream() for _ in range(F)]
     outs = [torch.empty((H, W), dtype=torch.uint16, device=dev) for _ in range(F)]
     print(f"bench: {WORKLOAD} inflight={F} warmup={args.warmup} steps={args.steps}",
@@ -328,7 +334,7 @@ def main():
         s0 = ctxs[0]
         st0 = torch.cuda.current_stream()
         for mode in ("eager", "graph"):
-            c = s0 if mode == "eager" else make_ctx(graph=True)
+            c = s0 if mode == "eager" else make_ctx(graph=True, tuning=choice)
             for _ in range(args.warmup):
                 c.compute(left, right, outs[0], stream=st0)
             torch.cuda.synchronize()
@@ -368,7 +374,10 @@ def main():
     # the aggregation kernel reads the cost volume (u8) and writes one L_r
     # plane (u8: Cmax + P2 = 148 < 256) per direction
     Dp = 64 if D <= 64 else (128 if D <= 128 else 256)
-    agg_bytes = P * W * H * Dp * (1 + 1)
+    if tuning[2]:  # fused: census words of both views in, L_r out
+        agg_bytes = P * W * H * (Dp + 2 * 8)
+    else:  # cost volume in, L_r out
+        agg_bytes = P * W * H * Dp * (1 + 1)
     agg_ms = stage_ms["aggregate"] / max(ncalls, 1)
     achieved = agg_bytes / (agg_ms * 1e-3) / 1e9
     roof = {"kernel": "aggregate_kernel", "bound": "hbm", "achieved": round(achieved, 1),
@@ -395,7 +404,8 @@ def main():
                    "census": "9x7 full", "P1": synth.P1_DEFAULT, "P2": synth.P2_DEFAULT,
                    "median": cfg["median"], "lr_check": cfg["lr"], "scene": cfg["scene"],
                    "seed": cfg["seed"], "frames_in_flight": F,
-                   "lanes_h": tuning[0], "lanes_v": tuning[1], "fused_cost": tuning[2]},
+                   "lanes_h": tuning[0], "lanes_v": tuning[1], "fused_cost": tuning[2],
+                   "autotune_ms_per_frame": tuned["candidates"]},
         "gcells_per_s": round(W * H * D * P * fps / 1e9, 2),
         "stage_ms": {k: round(v / max(ncalls, 1), 5) for k, v in stage_ms.items()},
         "roofline": roof,

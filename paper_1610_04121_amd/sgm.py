@@ -192,6 +192,7 @@ class SGM:
                  median=False, lrcheck=False, csct=False, lr_threshold=1, graph=False):
         self.width, self.height, self.max_disp = width, height, max_disp
         self.n_paths = n_paths
+        self.params = dict(P1=P1, P2=P2, census_w=census_w, census_h=census_h)
         self._ctx = lib().sgm_create(width, height, max_disp, P1, P2, n_paths, census_w, census_h)
         if not self._ctx:
             raise SGMError(SGM_EINVAL, last_error())
@@ -201,6 +202,12 @@ class SGM:
         flags = ((MEDIAN3 if median else 0) | (LRCHECK if lrcheck else 0) | (CENSUS_CSCT if csct else 0)
                  | (GRAPH if graph else 0))
         _check(lib().sgm_set_options(self._ctx, flags, lr_threshold))
+        self.params.update(median=median, lrcheck=lrcheck, csct=csct, lr_threshold=lr_threshold)
+
+    def autotune(self, left=None, right=None, **kw) -> dict:
+        """Times every aggregation kernel shape and keeps the fastest (see tune.py)."""
+        from . import tune
+        return tune.autotune(self, left, right, **kw)
 
     def set_tuning(self, lanes_h=0, lanes_v=0, fused=True):
         """Aggregation kernel shape (does not change results)."""

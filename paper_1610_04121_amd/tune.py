@@ -1,0 +1,114 @@
+"""Autotuner for the aggregation kernel shape of a context.
+
+The aggregation runs one group of G lanes per scanline slice (G = 16, 32 or
+64 for horizontal slices, 16 or 32 for the others; each lane holds D/G
+disparities), either reading the stored cost volume or computing costs from
+census words (fused).  None of this changes a result; the best shape depends
+on the image size, the disparity range and the path count.  The tuner times
+every valid shape on the caller's inputs (whole frames, HIP events on the
+context's stream), checks that every shape gives the same disparities, keeps
+the fastest and records it in a JSON cache keyed by the context's shape and
+parameters ($SGM_TUNE_CACHE, else sgm_tune_cache.json in the temp directory).
+"""
+from __future__ import annotations
+
+import json
+import os
+import tempfile
+
+
+def padded_disp(max_disp: int) -> int:
+    return 64 if max_disp <= 64 else (128 if max_disp <= 128 else 256)
+
+
+def candidates(max_disp: int):
+    """(lanes_h, lanes_v, fused) shapes the kernels provide for this range."""
+    pairs = [(16, 16), (32, 16), (32, 32)]
+    if padded_disp(max_disp) >= 128:
+        pairs += [(64, 16), (64, 32)]
+    return [(gh, gv, f) for gh, gv in pairs for f in (False, True)]
+
+
+def cache_path() -> str:
+    return os.environ.get("SGM_TUNE_CACHE") or os.path.join(tempfile.gettempdir(), "sgm_tune_cache.json")
+
+
+def cache_key(ctx) -> str:
+    p = ctx.params
+    return (f"{ctx.width}x{ctx.height}:d{ctx.max_disp}:p{ctx.n_paths}:P1={p['P1']}:P2={p['P2']}:"
+            f"census={p['census_w']}x{p['census_h']}:csct={int(p['csct'])}:median={int(p['median'])}:"
+            f"lr={int(p['lrcheck'])}")
+
+
+def load_cache(path: str | None = None) -> dict:
+    try:
+        with open(path or cache_path()) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def save_entry(key: str, entry: dict, path: str | None = None):
+    path = path or cache_path()
+    data = load_cache(path)
+    data[key] = entry
+    tmp = f"{path}.tmp{os.getpid()}"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _frame_ms(ctx, left, right, out, stream, reps: int) -> float:
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        ctx.compute(left, right, out, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def autotune(ctx, left=None, right=None, reps: int = 20, rounds: int = 2, use_cache: bool = True) -> dict:
+    """Picks and applies the fastest kernel shape for ``ctx``.  ``left`` and
+    ``right`` default to random images of the context's size.  Returns the
+    choice, its time per frame and every candidate's time (or the cached
+    entry, with ``cached`` set)."""
+    import torch
+    key = cache_key(ctx)
+    if use_cache:
+        hit = load_cache().get(key)
+        if hit and tuple(hit.get("choice", ())) in {tuple(c) for c in candidates(ctx.max_disp)}:
+            ctx.set_tuning(*hit["choice"])
+            return dict(hit, cached=True)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if left is None:
+        g = torch.Generator(device="cpu").manual_seed(1610)
+        left = torch.randint(0, 256, ctx.shape, dtype=torch.uint8, generator=g).to(dev)
+        right = torch.roll(left, shifts=ctx.max_disp // 4, dims=1)
+    stream = torch.cuda.current_stream()
+    out = torch.empty(ctx.shape, dtype=torch.uint16, device=dev)
+    ref = None
+    times = {}
+    for _ in range(rounds):
+        for cand in candidates(ctx.max_disp):
+            ctx.set_tuning(*cand)
+            ctx.compute(left, right, out, stream=stream)  # warm-up, and the result check
+            stream.synchronize()
+            if ref is None:
+                ref = out.clone()
+            elif not torch.equal(out, ref):
+                raise RuntimeError(f"kernel shape {cand} changed the disparities")
+            t = _frame_ms(ctx, left, right, out, stream, reps)
+            times[cand] = min(times.get(cand, float("inf")), t)
+    best = min(times, key=times.get)
+    ctx.set_tuning(*best)
+    entry = {"choice": list(best), "ms_per_frame": round(times[best], 5),
+             "candidates": {f"{gh},{gv},{int(f)}": round(t, 5) for (gh, gv, f), t in times.items()}}
+    if use_cache:
+        try:
+            save_entry(key, entry)
+        except OSError:
+            pass  # a read-only cache location only costs a re-tune later
+    return dict(entry, cached=False)

@@ -135,3 +135,19 @@ def test_create_without_gpu_fails_cleanly(lib):
     # invalid parameters are rejected before any HIP call
     assert not lib.sgm_create(0, 48, 16, 7, 86, 4, 9, 7)
     assert "width" in sgm.last_error()
+
+
+def test_tuner_candidates_and_cache(tmp_path, monkeypatch):
+    from paper_1610_04121_amd import tune
+    c64 = tune.candidates(64)
+    assert all(gh in (16, 32) and gv in (16, 32) for gh, gv, _ in c64)
+    assert len(c64) == 6 and len(tune.candidates(65)) == 10 and len(tune.candidates(256)) == 10
+    assert {f for *_, f in c64} == {False, True}
+    monkeypatch.setenv("SGM_TUNE_CACHE", str(tmp_path / "t.json"))
+    assert tune.load_cache() == {}
+    tune.save_entry("a", {"choice": [32, 16, False]})
+    tune.save_entry("b", {"choice": [16, 16, True]})
+    assert tune.load_cache()["a"]["choice"] == [32, 16, False]
+    assert set(tune.load_cache()) == {"a", "b"}
+    (tmp_path / "t.json").write_text("not json")
+    assert tune.load_cache() == {}

@@ -1,0 +1,31 @@
+"""Autotuner: picks a valid kernel shape, leaves results unchanged, caches."""
+import pytest
+
+from paper_1610_04121_amd import SGM, synth, tune
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_picks_candidate_and_caches(gpu, tmp_path, monkeypatch):
+    import torch
+    monkeypatch.setenv("SGM_TUNE_CACHE", str(tmp_path / "tune.json"))
+    pair = synth.make_pair(200, 120, 100, "RS", seed=5)
+    l = torch.from_numpy(pair.left).to(gpu)
+    r = torch.from_numpy(pair.right).to(gpu)
+    print("autotune 200x120 D=100", flush=True)
+    ref = SGM(200, 120, 100, 7, 86, 8, median=True, lrcheck=True)
+    want = ref.compute(l, r).cpu().numpy()
+    ref.close()
+    s = SGM(200, 120, 100, 7, 86, 8, median=True, lrcheck=True)
+    res = s.autotune(l, r, reps=3, rounds=1)
+    assert not res["cached"]
+    assert tuple(res["choice"]) in set(tune.candidates(100))
+    assert len(res["candidates"]) == len(tune.candidates(100))
+    assert s.tuning() == tuple(res["choice"])
+    assert (s.compute(l, r).cpu().numpy() == want).all()
+    s.close()
+    s2 = SGM(200, 120, 100, 7, 86, 8, median=True, lrcheck=True)
+    res2 = s2.autotune()
+    assert res2["cached"] and res2["choice"] == res["choice"]
+    assert s2.tuning() == tuple(res["choice"])
+    s2.close()
