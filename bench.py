@@ -36,23 +36,61 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = "vga_640x480_d128_p4"
 METRIC = "frames/s and Gcells/s (W·H·D·paths) at 640x480 D=128; p50/p99 latency served"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "aggregate_vga_640x480_d128_p4_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1610_04121_amd", "csrc", "sgm_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1610_04121_amd", "csrc", f)
+               for f in ("sgm_device.h", "sgm_kernels.hip", "sgm_common.h")]
 
 
 def _kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the sources the single-pair kernels are built from."""
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
-def _traffic():
+def _traffic(tuning):
     """HBM bytes per aggregation launch from committed rocprofv3 counters,
-    or None if the counters were taken on another version of the kernels."""
+    or None if the counters were taken on another version of the kernels or
+    another kernel shape."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != _kernel_sha():
+    if t.get("kernel_sha") != _kernel_sha() or list(t.get("tuning", [])) != [int(v) for v in tuning]:
         return None
     return t.get("bytes_per_launch")
+
+
+def summarize_counters(fetch_csv: str, write_csv: str, copy_mib: int, tuning) -> dict:
+    """Per-dispatch HBM bytes of every kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+    same counter reads for the device copy of copy_mib MiB that the profiled
+    run made (--copy-calibration-mb)."""
+    import csv
+    from collections import defaultdict
+
+    def means(path, counter):
+        acc = defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    fetch, write = means(fetch_csv, "FETCH_SIZE"), means(write_csv, "WRITE_SIZE")
+    copy_kib = copy_mib * 1024.0
+    copy_name = next(k for k in fetch if "copyBuffer" in k)
+    f_fetch, f_write = copy_kib / fetch[copy_name], copy_kib / write[copy_name]
+    kernels = {}
+    for k in fetch:
+        if k == copy_name or k not in write:
+            continue
+        rd, wr = fetch[k] * f_fetch * 1024, write[k] * f_write * 1024
+        kernels[k] = {"read_bytes": round(rd), "write_bytes": round(wr), "fetch_kib": round(fetch[k], 2),
+                      "write_kib": round(write[k], 2)}
+    agg = next(k for k in kernels if "aggregate_kernel<" in k)
+    return {"kernel": agg, "kernel_sha": _kernel_sha(), "tuning": [int(v) for v in tuning],
+            "fetch_scale": round(f_fetch, 4), "write_scale": round(f_write, 4),
+            "bytes_per_launch": kernels[agg]["read_bytes"] + kernels[agg]["write_bytes"], "kernels": kernels}
 
 
 def cpu_baseline(pair, cfg, budget_s: float = 12.0):
@@ -70,6 +108,34 @@ def cpu_baseline(pair, cfg, budget_s: float = 12.0):
     return {"value": round(n / dt, 4), "unit": "frames/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} full {cfg['w']}x{cfg['h']} D={cfg['max_disp']} {cfg['n_paths']}-path "
                       f"frames (median + LR), single thread, {dt:.1f} s"}
+
+
+def bench_paths(left, right, cfg, steps: int, warmup: int = 50):
+    """The paper's path-count axis: 2 (left-to-right and top-to-bottom), 4
+    and 8 paths on the headline pair, one frame at a time, autotuned."""
+    import torch
+
+    from paper_1610_04121_amd import SGM, synth
+    st = torch.cuda.current_stream()
+    out = {}
+    for P in (2, 4, 8):
+        c = SGM(cfg["w"], cfg["h"], cfg["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, P,
+                median=cfg["median"], lrcheck=cfg["lr"])
+        c.autotune(left, right, use_cache=False, reps=10, rounds=1)
+        o = torch.empty((cfg["h"], cfg["w"]), dtype=torch.uint16, device=left.device)
+        for _ in range(warmup):
+            c.compute(left, right, o, stream=st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            c.compute(left, right, o, stream=st)
+        torch.cuda.synchronize()
+        fps = steps / (time.perf_counter() - t0)
+        out[str(P)] = {"frames_per_s": round(fps, 1),
+                       "gcells_per_s": round(cfg["w"] * cfg["h"] * cfg["max_disp"] * P * fps / 1e9, 1),
+                       "lanes": list(c.tuning())}
+        c.close()
+    return out
 
 
 def bench_batch(dev, steps: int, warmup: int = 3):
@@ -251,6 +317,8 @@ def main():
     ap.add_argument("--profile-every", type=int, default=8,
                     help="record stage events on every n-th frame of each context")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning", default="", help="fixed kernel shape 'lanes_h,lanes_v,fused,census_cost' "
+                                                   "instead of autotuning (for profiler runs)")
     ap.add_argument("--no-extras", action="store_true", help="skip serialized/latency/copy measurements")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batched measurement")
     ap.add_argument("--batch-steps", type=int, default=20)
@@ -265,7 +333,14 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
+    ap.add_argument("--counters-from", default="",
+                    help="FETCH_CSV,WRITE_CSV: summarize rocprofv3 --pmc output (with --copy-calibration-mb "
+                         "and --tuning as in the profiled run) as JSON and exit")
     args = ap.parse_args()
+    if args.counters_from:
+        fcsv, wcsv = args.counters_from.split(",")
+        print(json.dumps(summarize_counters(fcsv, wcsv, args.copy_calibration_mb, args.tuning.split(",")), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(independent frames shard across GPUs with no exchange).", file=sys.stderr)
@@ -292,10 +367,15 @@ def main():
         return c
 
     # kernel shape: measured on this device for this workload (results do not depend on it)
-    probe = make_ctx()
-    tuned = probe.autotune(left, right, use_cache=False)
-    probe.close()
-    choice = tuple(tuned["choice"])
+    if args.tuning:
+        gh, gv, f, cc = (int(v) for v in args.tuning.split(","))
+        choice = (gh, gv, bool(f), bool(cc))
+        tuned = {"candidates": None}
+    else:
+        probe = make_ctx()
+        tuned = probe.autotune(left, right, use_cache=False)
+        probe.close()
+        choice = tuple(tuned["choice"])
     print(f"bench: autotuned kernel shape {choice}", file=sys.stderr, flush=True)
     ctxs = [make_ctx(tuning=choice) for _ in range(F)]
     streams = [torch.cuda.Stream() for _ in range(F)]
@@ -382,7 +462,7 @@ def main():
     achieved = agg_bytes / (agg_ms * 1e-3) / 1e9
     roof = {"kernel": "aggregate_kernel", "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": _traffic(), "alg_bytes_per_launch": agg_bytes, "mean_launch_ms": round(agg_ms, 5)}
+            "traffic": _traffic(tuning), "alg_bytes_per_launch": agg_bytes, "mean_launch_ms": round(agg_ms, 5)}
     if "copy_gbs" in extras:
         roof["measured_copy_gbs"] = extras["copy_gbs"]
         roof["frac_of_measured_copy"] = round(achieved / extras["copy_gbs"], 4)
@@ -405,6 +485,7 @@ def main():
                    "median": cfg["median"], "lr_check": cfg["lr"], "scene": cfg["scene"],
                    "seed": cfg["seed"], "frames_in_flight": F,
                    "lanes_h": tuning[0], "lanes_v": tuning[1], "fused_cost": tuning[2],
+                   "fused_census_cost": tuning[3],
                    "autotune_ms_per_frame": tuned["candidates"]},
         "gcells_per_s": round(W * H * D * P * fps / 1e9, 2),
         "stage_ms": {k: round(v / max(ncalls, 1), 5) for k, v in stage_ms.items()},
@@ -413,6 +494,7 @@ def main():
     if extras:
         line["serialized_fps"] = {"eager": extras["eager"], "graph": extras["graph"]}
         line["latency_ms"] = extras["latency_ms"]
+        line["paths_sweep"] = bench_paths(left, right, cfg, max(200, args.steps // 4))
     for c in ctxs:
         c.close()
     if args.copy_calibration_mb:

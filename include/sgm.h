@@ -90,13 +90,18 @@ int sgm_set_options(sgm_ctx *ctx, unsigned flags, int lr_threshold);
 int sgm_compute(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right, uint16_t *disp_out,
                 sgm_stream_t stream);
 
-/* Kernel shape of the aggregation (results never depend on it):
- *   lanes_h - lanes per horizontal slice (16, 32 or 64), lanes_v - lanes per
- *   vertical / diagonal slice (16 or 32); 0 and 0 select the built-in default.
- *   fused   - 0: a separate kernel writes the u8 cost volume C[H][W][Dp] that
- *   the aggregation reads (the default); 1: the aggregation computes the
- *   matching costs from census words itself (no cost volume in memory).
+/* Kernel shapes (results never depend on them):
+ *   lanes_h - lanes per horizontal aggregation slice (16, 32 or 64), lanes_v
+ *   - lanes per vertical / diagonal slice (16 or 32); 0 and 0 select the
+ *   built-in default.
+ *   fused   - bit SGM_TUNE_FUSED_AGG: the aggregation computes the matching
+ *   costs from census words itself (no cost volume in memory); otherwise a
+ *   cost kernel writes the u8 cost volume C[H][W][Dp] that the aggregation
+ *   reads.  Bit SGM_TUNE_FUSED_CENSUS_COST (9x7 windows): that cost volume
+ *   comes from one census + cost launch instead of a census launch and a cost
+ *   launch.  Default 0.
  * sgm_get_tuning reports the shape in effect. */
+enum { SGM_TUNE_FUSED_AGG = 1, SGM_TUNE_FUSED_CENSUS_COST = 2 };
 int sgm_set_tuning(sgm_ctx *ctx, int lanes_h, int lanes_v, int fused);
 int sgm_get_tuning(sgm_ctx *ctx, int *lanes_h, int *lanes_v, int *fused);
 

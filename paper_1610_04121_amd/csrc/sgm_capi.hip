@@ -149,6 +149,7 @@ int sgm_set_options(sgm_ctx* c, unsigned flags, int lr_threshold) {
     p.lanes_h = c->plan.lanes_h;
     p.lanes_v = c->plan.lanes_v;
     p.fused = c->plan.fused;
+    p.cc_fused = c->plan.cc_fused;
     c->plan = p;
     c->ws = sgm::workspace_carve(p, c->mem);
     c->use_graph = (flags & SGM_GRAPH) != 0;
@@ -172,7 +173,9 @@ int sgm_set_tuning(sgm_ctx* c, int lanes_h, int lanes_v, int fused) {
     if ((lanes_h == 0) != (lanes_v == 0)) return set_err(SGM_EINVAL, "set both lane counts or neither");
     c->plan.lanes_h = lanes_h;
     c->plan.lanes_v = lanes_v;
-    c->plan.fused = fused != 0;
+    if (fused & ~(SGM_TUNE_FUSED_AGG | SGM_TUNE_FUSED_CENSUS_COST)) return set_err(SGM_EINVAL, "unknown tuning bits");
+    c->plan.fused = (fused & SGM_TUNE_FUSED_AGG) != 0;
+    c->plan.cc_fused = (fused & SGM_TUNE_FUSED_CENSUS_COST) != 0;
     drop_graphs(c);
     return SGM_OK;
 }
@@ -183,7 +186,7 @@ int sgm_get_tuning(sgm_ctx* c, int* lanes_h, int* lanes_v, int* fused) {
     if (gh <= 0 || gv <= 0) sgm::default_lanes(c->plan, &gh, &gv);
     if (lanes_h) *lanes_h = gh;
     if (lanes_v) *lanes_v = gv;
-    if (fused) *fused = c->plan.fused ? 1 : 0;
+    if (fused) *fused = (c->plan.fused ? SGM_TUNE_FUSED_AGG : 0) | (c->plan.cc_fused ? SGM_TUNE_FUSED_CENSUS_COST : 0);
     return SGM_OK;
 }
 
@@ -308,8 +311,7 @@ int sgm_debug_sums(sgm_ctx* c, const uint8_t* left, const uint8_t* right, uint16
     if (!c) return set_err(SGM_EINVAL, "null context");
     if (int rc = check_ptrs(left, right, s_out)) return rc;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = sgm::launch_census(c->plan, c->ws, left, right, s);
-    if (e == hipSuccess && !c->plan.fused) e = sgm::launch_cost(c->plan, c->ws, s);
+    hipError_t e = sgm::launch_matching_cost(c->plan, c->ws, left, right, !c->plan.fused, s);
     if (e == hipSuccess) e = sgm::launch_aggregate(c->plan, c->ws, s);
     if (e == hipSuccess) e = sgm::launch_sum_planes(c->plan, c->ws, s_out, s);
     if (e != hipSuccess) return hip_err(e, "kernel launch");
@@ -322,8 +324,7 @@ int sgm_debug_stage(sgm_ctx* c, const uint8_t* left, const uint8_t* right, int w
     if (int rc = check_ptrs(left, right, out)) return rc;
     if (which < -1 || which >= c->plan.n_paths) return set_err(SGM_EINVAL, "stage index out of range");
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = sgm::launch_census(c->plan, c->ws, left, right, s);
-    if (e == hipSuccess && (which < 0 || !c->plan.fused)) e = sgm::launch_cost(c->plan, c->ws, s);
+    hipError_t e = sgm::launch_matching_cost(c->plan, c->ws, left, right, which < 0 || !c->plan.fused, s);
     if (e == hipSuccess && which >= 0) e = sgm::launch_aggregate(c->plan, c->ws, s);
     if (e == hipSuccess) e = sgm::launch_extract_plane(c->plan, c->ws, which, out, s);
     if (e != hipSuccess) return hip_err(e, "kernel launch");
@@ -339,8 +340,7 @@ int sgm_debug_raw_disparity(sgm_ctx* c, const uint8_t* left, const uint8_t* righ
     p.lrcheck = true;   // produce the right view too
     p.median = false;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = sgm::launch_census(p, c->ws, left, right, s);
-    if (e == hipSuccess && !p.fused) e = sgm::launch_cost(p, c->ws, s);
+    hipError_t e = sgm::launch_matching_cost(p, c->ws, left, right, !p.fused, s);
     if (e == hipSuccess) e = sgm::launch_aggregate(p, c->ws, s);
     if (e == hipSuccess) e = sgm::launch_wta(p, c->ws, nullptr, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dl_out, c->ws.dl, (size_t)p.W * p.H * 2, hipMemcpyDeviceToDevice, s);

@@ -46,35 +46,23 @@ __device__ inline uint32_t shift_in(uint32_t acc, int u, int v) {
     return __builtin_amdgcn_alignbit(acc, (uint32_t)(v - 1 - u), 31);
 }
 
-__device__ inline void census97_block(const CensusArgs& a, int bx, int by, int z) {
+// Census words (9x7 window, full or center-symmetric) of 4 consecutive
+// pixels of one row, from a byte tile with row pitch TW (a multiple of 4).
+// Pixel p (0..3) has its window on tile rows r0 .. r0+6 and columns
+// c0+p .. c0+p+8 (centre at row r0+3, column c0+p+4); c0 is a multiple of 4,
+// so each window row is read as 3 aligned dwords.
+__device__ inline void census_words4(const uint8_t* tile, int TW, int r0, int c0, bool csct, uint64_t words[4]) {
     constexpr int RY = 3, CW = 9;
-    constexpr int TW = kCenTX + 8, TH = kCenTY + 2 * RY;
-    __shared__ __align__(16) uint8_t tile[TH * TW];
-
-    const uint8_t* img = a.img[z];
-    const int x0 = bx * kCenTX, y0 = by * kCenTY;
-    for (int i = threadIdx.x; i < TH * TW; i += blockDim.x) {
-        const int r = i / TW, c = i - r * TW;
-        const int yy = clampi(y0 - RY + r, 0, a.H - 1), xx = clampi(x0 - 4 + c, 0, a.W - 1);
-        tile[i] = img[(size_t)yy * a.W + xx];
-    }
-    __syncthreads();
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int y = y0 + ty;
-    // window patch: rows ty .. ty+6, tile columns 4tx .. 4tx+11
     uint32_t dw[2 * RY + 1][3];
 #pragma unroll
     for (int j = 0; j < 2 * RY + 1; ++j)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) dw[j][k] = *reinterpret_cast<const uint32_t*>(&tile[(ty + j) * TW + 4 * tx + 4 * k]);
+        for (int k = 0; k < 3; ++k) dw[j][k] = *reinterpret_cast<const uint32_t*>(&tile[(r0 + j) * TW + c0 + 4 * k]);
     auto px = [&](int j, int b) -> int { return (int)((dw[j][b >> 2] >> (8 * (b & 3))) & 0xFF); };
-    uint64_t words[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-        // byte b of a patch row is image column x0 + 4tx + b - 4; pixel p's
-        // centre is byte p + 4
         uint32_t hi = 0, lo = 0;
-        if (!a.csct) {
+        if (!csct) {
             const int c = px(RY, p + 4);
 #pragma unroll
             for (int k = (2 * RY + 1) * CW - 1; k >= 0; --k) {
@@ -102,6 +90,33 @@ __device__ inline void census97_block(const CensusArgs& a, int bx, int by, int z
         }
         words[p] = ((uint64_t)hi << 32) | lo;
     }
+}
+
+__device__ inline void census97_block(const CensusArgs& a, int bx, int by, int z) {
+    constexpr int RY = 3;
+    constexpr int TW = kCenTX + 8, TH = kCenTY + 2 * RY;
+    __shared__ __align__(16) uint8_t tile[TH * TW];
+
+    const uint8_t* img = a.img[z];
+    const int x0 = bx * kCenTX, y0 = by * kCenTY;
+    // all loads first, then the LDS stores (the block has 256 threads)
+    constexpr int kIt = (TH * TW + 255) / 256;
+    uint32_t v[kIt];
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        const int r = i / TW, c = i - r * TW;
+        const int yy = clampi(y0 - RY + r, 0, a.H - 1), xx = clampi(x0 - 4 + c, 0, a.W - 1);
+        v[k] = i < TH * TW ? img[(size_t)yy * a.W + xx] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kIt; ++k)
+        if (threadIdx.x + 256 * k < TH * TW) tile[threadIdx.x + 256 * k] = (uint8_t)v[k];
+    __syncthreads();
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int y = y0 + ty;
+    uint64_t words[4];
+    census_words4(tile, TW, ty, 4 * tx, a.csct != 0, words);
     const int x = x0 + 4 * tx;
     if (y < a.H) {
         uint64_t* o = a.out[z] + (size_t)y * a.W + x;
@@ -219,6 +234,160 @@ __device__ inline void cost_block(const CostArgs& a, int bx, int y, uint64_t* cw
     for (int c = threadIdx.x; c < npx * nchunks; c += blockDim.x) {
         const int px = c / nchunks, k = c - px * nchunks;
         *reinterpret_cast<uint4*>(dst + 16 * c) = *reinterpret_cast<const uint4*>(tile + px * tpitch + 16 * k);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Census + matching cost in one pass (9x7 windows).  One block per (row y,
+// segment of kCcRuns runs of 64 base pixels).  The block stages the 7 image
+// rows around y of both views in LDS (clamp-to-edge): the base view over the
+// segment, the match view over the segment plus the D - 1 columns to its
+// left.  It computes every census word it needs exactly once into LDS, then
+// for each run of 64 pixels builds the costs in an LDS tile [64][Dp + 16]
+// (two tiles, alternating, so one run's copy-out overlaps the next run's
+// popcounts) and writes the run's slice of the cost volume with contiguous
+// 16-byte stores.  No census word goes through global memory.
+// ---------------------------------------------------------------------------
+constexpr int kCcRuns = 4;
+constexpr int kCcTX = 64 * kCcRuns;
+
+struct CensusCostArgs {
+    const uint8_t* left;
+    const uint8_t* right;
+    uint8_t* cost;
+    int W, H, D, Dp, cmax, csct;
+};
+
+// Byte sizes of the LDS regions of census_cost_block.
+struct CcLayout {
+    int twl, twr;     // tile row pitches (bytes), base / match view
+    int nr;           // match census words: kCcTX + D - 1, rounded up to 4
+    int words_off;    // byte offset of the census words (base, then match)
+    int tiles_off;    // byte offset of the two cost tiles
+    int tpitch;       // bytes per cost-tile row
+    int bytes;        // total
+};
+
+__host__ __device__ inline CcLayout cc_layout(int D, int Dp) {
+    CcLayout L;
+    L.twl = kCcTX + 8;
+    L.nr = (kCcTX + D - 1 + 3) & ~3;
+    L.twr = L.nr + 8;
+    L.words_off = (7 * (L.twl + L.twr) + 15) & ~15;
+    L.tiles_off = L.words_off + 8 * (kCcTX + L.nr);
+    L.tpitch = Dp + 16;
+    L.bytes = L.tiles_off + 2 * 64 * L.tpitch;
+    return L;
+}
+
+__device__ inline void census_cost_block(const CensusCostArgs& a, int bx, int y, uint8_t* smem) {
+    constexpr int RY = 3;
+    const int D = a.D, Dp = a.Dp;
+    const CcLayout L = cc_layout(D, Dp);
+    const int x0 = bx * kCcTX;
+    const int xs = x0 - (D - 1);  // first match column
+    uint8_t* tl = smem;           // base view tile: 7 rows, columns x0 - 4 ..
+    uint8_t* tr = smem + 7 * L.twl;  // match view tile: 7 rows, columns xs - 4 ..
+    uint64_t* cl = reinterpret_cast<uint64_t*>(smem + L.words_off);  // cl[i]: column x0 + i
+    uint64_t* cr = cl + kCcTX;                                        // cr[i]: column xs + i
+    uint8_t* tiles = smem + L.tiles_off;
+
+    // Stage the 7 image rows of both views.  Every load is issued before the
+    // first LDS store, so the loads' latencies overlap instead of adding up
+    // (the block has 256 threads; a base row has kCcTX + 8 <= 512 bytes, a
+    // match row at most 520 <= 768).
+    {
+        const int t = threadIdx.x;
+        uint32_t vl[7][2], vr[7][3];
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+            const size_t row = (size_t)clampi(y - RY + r, 0, a.H - 1) * a.W;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int c = t + 256 * k;
+                vl[r][k] = c < L.twl ? a.left[row + clampi(x0 - 4 + c, 0, a.W - 1)] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int c = t + 256 * k;
+                vr[r][k] = c < L.twr ? a.right[row + clampi(xs - 4 + c, 0, a.W - 1)] : 0u;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                if (t + 256 * k < L.twl) tl[r * L.twl + t + 256 * k] = (uint8_t)vl[r][k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (t + 256 * k < L.twr) tr[r * L.twr + t + 256 * k] = (uint8_t)vr[r][k];
+        }
+    }
+    __syncthreads();
+    {
+        const int nl4 = kCcTX / 4, nr4 = L.nr / 4;
+        for (int t = threadIdx.x; t < nl4 + nr4; t += blockDim.x) {
+            uint64_t w[4];
+            if (t < nl4) {
+                census_words4(tl, L.twl, 0, 4 * t, a.csct != 0, w);
+#pragma unroll
+                for (int p = 0; p < 4; ++p) cl[4 * t + p] = w[p];
+            } else {
+                const int u = t - nl4;
+                census_words4(tr, L.twr, 0, 4 * u, a.csct != 0, w);
+#pragma unroll
+                for (int p = 0; p < 4; ++p) cr[4 * u + p] = w[p];
+            }
+        }
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int nchunks = Dp >> 4;
+    for (int run = 0; run < kCcRuns; ++run) {
+        const int xr0 = x0 + 64 * run;
+        if (xr0 >= a.W) break;  // the same for the whole block
+        uint8_t* tile = tiles + (run & 1) * 64 * L.tpitch;
+        const int x = xr0 + lane;
+        const uint64_t base = cl[64 * run + lane];
+        for (int ch = wave; ch < nchunks; ch += nwaves) {
+            const int d0 = 16 * ch;
+            // match word of disparity d0 + j is cr[64 run + lane + D - 1 - d0 - j]
+            const uint64_t* m = cr + (64 * run + lane + D - 1 - d0 - 15);
+            uint32_t w[4];
+            if (xr0 >= d0 + 15 && d0 + 16 <= D) {  // all 16 disparities valid for every lane
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t word = 0;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) word |= (uint32_t)__popcll(base ^ m[15 - (4 * q + j)]) << (8 * j);
+                    w[q] = word;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t word = 0;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int d = d0 + 4 * q + j;
+                        uint32_t c = 0;  // padded levels d >= D
+                        if (d < D)
+                            c = x - d < 0 ? (uint32_t)a.cmax : (uint32_t)__popcll(base ^ m[15 - (4 * q + j)]);
+                        word |= c << (8 * j);
+                    }
+                    w[q] = word;
+                }
+            }
+            *reinterpret_cast<uint4*>(tile + lane * L.tpitch + d0) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        __syncthreads();
+        const int npx = min(64, a.W - xr0);
+        const int lg = Dp == 64 ? 2 : (Dp == 128 ? 3 : 4);  // log2(nchunks)
+        uint8_t* dst = a.cost + ((size_t)y * a.W + xr0) * Dp;
+        for (int c = threadIdx.x; c < npx * nchunks; c += blockDim.x) {
+            const int px = c >> lg, k = c & (nchunks - 1);
+            *reinterpret_cast<uint4*>(dst + 16 * c) = *reinterpret_cast<const uint4*>(tile + px * L.tpitch + 16 * k);
+        }
     }
 }
 
@@ -838,23 +1007,47 @@ struct PostArgs {
     int W, H, median, lrcheck, thr;
 };
 
+// One row of the post stage.  Each thread takes 4 columns per pass so that
+// the 36 neighbour loads of a pass are in flight together (a 640-wide row is
+// one pass of a 256-thread block).
 __device__ inline void post_row(const PostArgs& a, int y, uint16_t* rview) {
+    constexpr int U = 4;
+    const int nt = blockDim.x;
     if (a.lrcheck) {
-        for (int x = threadIdx.x; x < a.W; x += blockDim.x)
-            rview[x] = a.median ? (uint16_t)median9(a.dr, a.W, a.H, x, y) : a.dr[(size_t)y * a.W + x];
+        for (int x0 = threadIdx.x; x0 < a.W; x0 += U * nt) {
+            uint32_t v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int x = min(x0 + u * nt, a.W - 1);
+                v[u] = a.median ? median9(a.dr, a.W, a.H, x, y) : a.dr[(size_t)y * a.W + x];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (x0 + u * nt < a.W) rview[x0 + u * nt] = (uint16_t)v[u];
+        }
         __syncthreads();
     }
-    for (int x = threadIdx.x; x < a.W; x += blockDim.x) {
-        const int d = a.median ? (int)median9(a.dl, a.W, a.H, x, y) : (int)a.dl[(size_t)y * a.W + x];
-        int o = d;
-        if (a.lrcheck) {
-            o = kInvalid;
-            if (x - d >= 0) {
-                const int e = rview[x - d];
-                if (abs(d - e) <= a.thr) o = d;
-            }
+    for (int x0 = threadIdx.x; x0 < a.W; x0 += U * nt) {
+        int dv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int x = min(x0 + u * nt, a.W - 1);
+            dv[u] = a.median ? (int)median9(a.dl, a.W, a.H, x, y) : (int)a.dl[(size_t)y * a.W + x];
         }
-        a.out[(size_t)y * a.W + x] = (uint16_t)o;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int x = x0 + u * nt, d = dv[u];
+            if (x >= a.W) continue;
+            int o = d;
+            if (a.lrcheck) {
+                o = kInvalid;
+                if (x - d >= 0) {
+                    const int e = rview[x - d];
+                    if (abs(d - e) <= a.thr) o = d;
+                }
+            }
+            a.out[(size_t)y * a.W + x] = (uint16_t)o;
+        }
     }
 }
 

@@ -21,6 +21,11 @@ __global__ __launch_bounds__(256) void census_generic_kernel(CensusArgs a, int r
     census_generic_block(a, rx, ry, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
+__global__ __launch_bounds__(256) void census_cost_kernel(CensusCostArgs a) {
+    extern __shared__ __align__(16) uint8_t cc_smem[];
+    census_cost_block(a, blockIdx.x, blockIdx.y, cc_smem);
+}
+
 __global__ __launch_bounds__(256) void cost_kernel(CostArgs a) {
     extern __shared__ __align__(16) uint64_t cost_smem[];
     cost_block(a, blockIdx.x, blockIdx.y, cost_smem);
@@ -170,6 +175,25 @@ hipError_t launch_census(const Plan& p, const Workspace& ws, const uint8_t* left
     return launch_census_pair(p, left, right, ws.census_l, ws.census_r, 2, stream);
 }
 
+bool census_cost_fusable(const Plan& p) { return p.cc_fused && p.cw == 9 && p.ch == 7; }
+
+hipError_t launch_matching_cost(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right,
+                                bool need_cost, hipStream_t stream) {
+    const bool fusable = census_cost_fusable(p);
+    hipError_t e = hipSuccess;
+    if (need_cost && fusable) {
+        const CcLayout L = cc_layout(p.D, p.Dp);
+        CensusCostArgs a{left, right, ws.cost, p.W, p.H, p.D, p.Dp, p.cmax, p.csct ? 1 : 0};
+        hipLaunchKernelGGL(census_cost_kernel, dim3((p.W + kCcTX - 1) / kCcTX, p.H), dim3(256), L.bytes, stream, a);
+        e = hipGetLastError();
+    }
+    // census words in global memory: for the fused aggregation, and for the
+    // cost kernel of windows other than 9x7
+    if (e == hipSuccess && (p.fused || (need_cost && !fusable))) e = launch_census(p, ws, left, right, stream);
+    if (e == hipSuccess && need_cost && !fusable) e = launch_cost(p, ws, stream);
+    return e;
+}
+
 hipError_t launch_cost(const Plan& p, const Workspace& ws, hipStream_t stream) {
     CostArgs a{ws.census_l, ws.census_r, ws.cost, p.W, p.H, p.D, p.Dp, p.cmax};
     const int nright = kCostTX + p.D - 1;
@@ -289,8 +313,7 @@ hipError_t launch_pipeline(const Plan& p, const Workspace& ws, const uint8_t* le
         if (events && e == hipSuccess) e = hipEventRecord(events[i], stream);
     };
     mark(0);
-    if (e == hipSuccess) e = launch_census(p, ws, left, right, stream);
-    if (e == hipSuccess && !p.fused) e = launch_cost(p, ws, stream);
+    if (e == hipSuccess) e = launch_matching_cost(p, ws, left, right, !p.fused, stream);
     mark(1);
     if (e == hipSuccess) e = launch_aggregate(p, ws, stream);
     mark(2);

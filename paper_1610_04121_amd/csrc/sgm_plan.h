@@ -22,6 +22,7 @@ struct Plan {
     bool l16 = false;          // L_r stored as u16 (else u8: Cmax + P2 <= 255)
     bool fused = false;        // aggregation computes costs from census words
                                // instead of reading the cost volume
+    bool cc_fused = false;     // cost volume from one census + cost launch (9x7)
     int lanes_h = 0, lanes_v = 0;  // lanes per aggregation slice, horizontal / other
                                    // directions (16, 32, 64; 0 = default)
 };
@@ -46,6 +47,13 @@ Workspace workspace_carve(const Plan& p, void* base);
 hipError_t launch_census(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right,
                          hipStream_t stream);
 hipError_t launch_cost(const Plan& p, const Workspace& ws, hipStream_t stream);
+// Whatever the aggregation needs before it runs: the cost volume (if
+// need_cost; one census + cost launch when p.cc_fused and the window is 9x7,
+// else census then cost) and the census words (if the aggregation computes
+// costs itself).
+hipError_t launch_matching_cost(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right,
+                                bool need_cost, hipStream_t stream);
+bool census_cost_fusable(const Plan& p);
 hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stream);
 void default_lanes(const Plan& p, int* gh, int* gv);
 hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream);

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_PKG, "libsgm.so")
 
 SGM_OK, SGM_EINVAL, SGM_ENOMEM, SGM_EHIP, SGM_EBUSY, SGM_ECANCELED = 0, -1, -2, -3, -4, -5
 MEDIAN3, LRCHECK, CENSUS_CSCT, GRAPH = 1, 2, 4, 8
+TUNE_FUSED_AGG, TUNE_FUSED_CENSUS_COST = 1, 2
 INVALID = 0xFFFF
 
 EXPORTS = [
@@ -209,14 +210,19 @@ class SGM:
         from . import tune
         return tune.autotune(self, left, right, **kw)
 
-    def set_tuning(self, lanes_h=0, lanes_v=0, fused=True):
-        """Aggregation kernel shape (does not change results)."""
-        _check(lib().sgm_set_tuning(self._ctx, lanes_h, lanes_v, 1 if fused else 0))
+    def set_tuning(self, lanes_h=0, lanes_v=0, fused=False, census_cost=False):
+        """Kernel shapes (never change results): lanes per horizontal /
+        other aggregation slice (0, 0 = default); ``fused``: the aggregation
+        computes costs from census words (no cost volume); ``census_cost``:
+        one census + cost launch builds the cost volume (9x7 windows)."""
+        flags = (TUNE_FUSED_AGG if fused else 0) | (TUNE_FUSED_CENSUS_COST if census_cost else 0)
+        _check(lib().sgm_set_tuning(self._ctx, lanes_h, lanes_v, flags))
 
     def tuning(self):
+        """(lanes_h, lanes_v, fused, census_cost) in effect."""
         gh, gv, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(lib().sgm_get_tuning(self._ctx, ctypes.byref(gh), ctypes.byref(gv), ctypes.byref(f)))
-        return gh.value, gv.value, bool(f.value)
+        return gh.value, gv.value, bool(f.value & TUNE_FUSED_AGG), bool(f.value & TUNE_FUSED_CENSUS_COST)
 
     @property
     def shape(self):
@@ -340,8 +346,11 @@ class Server:
     submit() takes device tensors and returns a ticket; the tensors are kept
     referenced here until the request reaches a final state."""
 
-    def __init__(self, hbm_budget_bytes: int, slots: int = 4, streams: int = 4, P1=7, P2=86, census_w=9,
-                 census_h=7, max_group: int = 8, max_pending: int = 4096, max_group_cells: int = 1 << 28):
+    def __init__(self, hbm_budget_bytes: int, slots: int = 4, streams: int | None = None, P1=7, P2=86,
+                 census_w=9, census_h=7, max_group: int = 8, max_pending: int = 4096,
+                 max_group_cells: int = 1 << 28):
+        """streams defaults to one per slot (groups run concurrently)."""
+        streams = slots if streams is None else streams
         self._s = lib().sgm_server_create(hbm_budget_bytes, slots, streams, P1, P2, census_w, census_h)
         if not self._s:
             raise SGMError(SGM_EINVAL, last_error())

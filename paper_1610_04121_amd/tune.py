@@ -21,12 +21,15 @@ def padded_disp(max_disp: int) -> int:
     return 64 if max_disp <= 64 else (128 if max_disp <= 128 else 256)
 
 
-def candidates(max_disp: int):
-    """(lanes_h, lanes_v, fused) shapes the kernels provide for this range."""
+def candidates(max_disp: int, census_9x7: bool = True):
+    """(lanes_h, lanes_v, fused, census_cost) shapes the kernels provide for
+    this range: the cost volume from separate census and cost launches or
+    (9x7 windows) from one, or no cost volume at all (fused)."""
     pairs = [(16, 16), (32, 16), (32, 32)]
     if padded_disp(max_disp) >= 128:
         pairs += [(64, 16), (64, 32)]
-    return [(gh, gv, f) for gh, gv in pairs for f in (False, True)]
+    costs = [(False, False), (True, False)] + ([(False, True)] if census_9x7 else [])
+    return [(gh, gv, f, cc) for gh, gv in pairs for f, cc in costs]
 
 
 def cache_path() -> str:
@@ -59,6 +62,11 @@ def save_entry(key: str, entry: dict, path: str | None = None):
     os.replace(tmp, path)
 
 
+def _candidates(ctx):
+    p = ctx.params
+    return candidates(ctx.max_disp, p["census_w"] == 9 and p["census_h"] == 7)
+
+
 def _frame_ms(ctx, left, right, out, stream, reps: int) -> float:
     import torch
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -79,7 +87,7 @@ def autotune(ctx, left=None, right=None, reps: int = 20, rounds: int = 2, use_ca
     key = cache_key(ctx)
     if use_cache:
         hit = load_cache().get(key)
-        if hit and tuple(hit.get("choice", ())) in {tuple(c) for c in candidates(ctx.max_disp)}:
+        if hit and tuple(hit.get("choice", ())) in set(_candidates(ctx)):
             ctx.set_tuning(*hit["choice"])
             return dict(hit, cached=True)
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -92,7 +100,7 @@ def autotune(ctx, left=None, right=None, reps: int = 20, rounds: int = 2, use_ca
     ref = None
     times = {}
     for _ in range(rounds):
-        for cand in candidates(ctx.max_disp):
+        for cand in _candidates(ctx):
             ctx.set_tuning(*cand)
             ctx.compute(left, right, out, stream=stream)  # warm-up, and the result check
             stream.synchronize()
@@ -105,7 +113,7 @@ def autotune(ctx, left=None, right=None, reps: int = 20, rounds: int = 2, use_ca
     best = min(times, key=times.get)
     ctx.set_tuning(*best)
     entry = {"choice": list(best), "ms_per_frame": round(times[best], 5),
-             "candidates": {f"{gh},{gv},{int(f)}": round(t, 5) for (gh, gv, f), t in times.items()}}
+             "candidates": {f"{gh},{gv},{int(f)},{int(cc)}": round(t, 5) for (gh, gv, f, cc), t in times.items()}}
     if use_cache:
         try:
             save_entry(key, entry)

@@ -140,9 +140,10 @@ def test_create_without_gpu_fails_cleanly(lib):
 def test_tuner_candidates_and_cache(tmp_path, monkeypatch):
     from paper_1610_04121_amd import tune
     c64 = tune.candidates(64)
-    assert all(gh in (16, 32) and gv in (16, 32) for gh, gv, _ in c64)
-    assert len(c64) == 6 and len(tune.candidates(65)) == 10 and len(tune.candidates(256)) == 10
-    assert {f for *_, f in c64} == {False, True}
+    assert all(gh in (16, 32) and gv in (16, 32) for gh, gv, _, _ in c64)
+    assert len(c64) == 9 and len(tune.candidates(65)) == 15 and len(tune.candidates(256)) == 15
+    assert len(tune.candidates(128, census_9x7=False)) == 10
+    assert not any(f and cc for _, _, f, cc in tune.candidates(128))
     monkeypatch.setenv("SGM_TUNE_CACHE", str(tmp_path / "t.json"))
     assert tune.load_cache() == {}
     tune.save_entry("a", {"choice": [32, 16, False]})

@@ -52,8 +52,10 @@ def test_census_parity(gpu, W, H, cw, ch, csct):
     assert (got == want).all()
 
 
-TUNINGS = [(0, 0, True), (16, 16, True), (32, 32, True), (64, 16, True), (64, 32, True),
-           (32, 16, False), (16, 16, False), (64, 32, False)]
+# (lanes_h, lanes_v, fused aggregation, one census + cost launch)
+TUNINGS = [(0, 0, True, False), (16, 16, True, False), (32, 32, True, False), (64, 16, True, False),
+           (64, 32, True, False), (32, 16, False, False), (16, 16, False, False), (64, 32, False, False),
+           (32, 16, False, True), (16, 16, False, True)]
 
 
 @pytest.mark.parametrize("tuning", TUNINGS)
@@ -114,15 +116,15 @@ def test_raw_disparity_parity(gpu, W, H, D, P):
     assert (dr == want.dr_raw).all()
 
 
-@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("fused,census_cost", [(True, False), (False, False), (False, True)])
 @pytest.mark.parametrize("name", list(synth.WORKLOADS))
-def test_workload_full_size_bit_exact(gpu, name, fused):
+def test_workload_full_size_bit_exact(gpu, name, fused, census_cost):
     cfg = synth.WORKLOADS[name]
     pair = synth.workload_pair(name)
-    _say(f"workload {name} fused={fused}")
+    _say(f"workload {name} fused={fused} census_cost={census_cost}")
     s = SGM(cfg["w"], cfg["h"], cfg["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, cfg["n_paths"],
             median=cfg["median"], lrcheck=cfg["lr"])
-    s.set_tuning(0, 0, fused)
+    s.set_tuning(0, 0, fused, census_cost)
     got = _np(s.compute(_t(pair.left, gpu), _t(pair.right, gpu)))
     s.close()
     want = oracle.sgm(pair.left, pair.right, cfg["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT,
@@ -205,3 +207,22 @@ def test_graph_replay_matches_eager(gpu):
             assert (_np(o) == want[i]).all(), (rep, i)
     eager.close()
     graph.close()
+
+
+@pytest.mark.parametrize("cw,ch,csct,D", [(7, 5, False, 40), (5, 5, True, 70), (9, 7, True, 256), (3, 3, False, 1)])
+def test_pipeline_census_windows(gpu, cw, ch, csct, D):
+    """Other census windows take the census kernel + cost kernel route; 9x7
+    takes the fused census + cost kernel (CSCT and full)."""
+    rng = np.random.default_rng(cw * 100 + ch + D)
+    l, r = _rand_pair(rng, 300, 37)
+    _say(f"census window {cw}x{ch} csct={csct} D={D}")
+    s = SGM(300, 37, D, 7, 86, 8, cw, ch, median=True, lrcheck=True, csct=csct)
+    s.set_tuning(0, 0, False, True)  # one census + cost launch where the window allows it
+    got = _np(s.compute(_t(l, gpu), _t(r, gpu)))
+    cost = _np(s.debug_stage(_t(l, gpu), _t(r, gpu), -1))
+    s.close()
+    want = oracle.sgm(l, r, D, 7, 86, 8, cw, ch, median=True, lr=True, csct=csct).out
+    assert (got == want).all()
+    mc = oracle.cost_volume(oracle.census(l, cw, ch, csct), oracle.census(r, cw, ch, csct), D,
+                            oracle.cmax_of(cw, ch, csct))
+    assert (cost == mc).all()

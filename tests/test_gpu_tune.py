@@ -21,6 +21,9 @@ def test_autotune_picks_candidate_and_caches(gpu, tmp_path, monkeypatch):
     assert not res["cached"]
     assert tuple(res["choice"]) in set(tune.candidates(100))
     assert len(res["candidates"]) == len(tune.candidates(100))
+    s.set_tuning(32, 16, False, True)  # one census + cost launch
+    assert (s.compute(l, r).cpu().numpy() == want).all()
+    s.set_tuning(*res["choice"])
     assert s.tuning() == tuple(res["choice"])
     assert (s.compute(l, r).cpu().numpy() == want).all()
     s.close()
