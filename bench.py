@@ -197,10 +197,6 @@ def bench_batch(dev, steps: int, warmup: int = 3):
                       "4 or 8 paths, no median/LR"}
 
 
-SERVE_SIZES = ((640, 480), (1242, 375), (1280, 720), (1920, 1080))
-SERVE_DISP = (128, 256)
-
-
 def bench_serve(dev, qps_levels, n_req: int, slots: int = 4, streams: int = 4, max_group: int = 8,
                 group_cells: int = 1 << 28, seed: int = 1610041214):
     """Poisson arrivals of 8-path median + LR requests of mixed sizes and
@@ -213,10 +209,11 @@ def bench_serve(dev, qps_levels, n_req: int, slots: int = 4, streams: int = 4, m
     from paper_1610_04121_amd import SGM, synth
     from paper_1610_04121_amd.sgm import REQ_DONE, SGM_EBUSY, SGMError, Server
 
-    kinds = [(w, h, d) for (w, h) in SERVE_SIZES for d in SERVE_DISP]
+    specs = synth.serve_kinds(seed)
+    kinds = [(k["w"], k["h"], k["max_disp"]) for k in specs]
     pool = []
-    for k, (w, h, d) in enumerate(kinds):
-        pr = synth.make_pair(w, h, d, "R", seed=seed * 100 + k)
+    for k in specs:
+        pr = synth.make_pair(k["w"], k["h"], k["max_disp"], k["scene"], seed=k["seed"])
         pool.append((torch.from_numpy(pr.left).to(dev), torch.from_numpy(pr.right).to(dev)))
     budget = 64 << 30
     srv = Server(budget, slots=slots, streams=streams, max_group=max_group, max_group_cells=group_cells)

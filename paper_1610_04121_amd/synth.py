@@ -252,3 +252,16 @@ def batch_items(n: int = 64, seed: int = 1610041213):
         paths = (4, 8)[int(st.below(2)[0])]
         items.append(dict(w=w, h=h, max_disp=dmax, n_paths=paths, scene="R", seed=seed * 1000 + i))
     return items
+
+
+SERVE_SIZES = [(640, 480), (1242, 375), (1280, 720), (1920, 1080)]
+SERVE_DISP = [128, 256]
+
+
+def serve_kinds(seed: int = 1610041214):
+    """The (size, disparity range) combinations of the served request mix,
+    8 paths with median and LR check, one seeded pair each."""
+    kinds = []
+    for k, ((w, h), d) in enumerate((s, d) for s in SERVE_SIZES for d in SERVE_DISP):
+        kinds.append(dict(w=w, h=h, max_disp=d, n_paths=8, median=True, lr=True, scene="R", seed=seed * 100 + k))
+    return kinds

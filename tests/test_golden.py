@@ -1,0 +1,32 @@
+"""The stored oracle digests are reproducible: the generator still draws the
+same pairs and the oracle still gives the same disparities (checked on the
+smallest entries, CPU only)."""
+import hashlib
+import json
+import os
+
+import oracle
+from paper_1610_04121_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_hashes.json")
+
+
+def test_digests_reproduce_for_small_entries():
+    doc = json.load(open(GOLDEN))
+    assert (doc["P1"], doc["P2"]) == (synth.P1_DEFAULT, synth.P2_DEFAULT)
+    small = sorted(doc["batch64"], key=lambda g: g["w"] * g["h"] * g["max_disp"] * g["n_paths"])[:2]
+    for g in small:
+        pr = synth.make_pair(g["w"], g["h"], g["max_disp"], g["scene"], seed=g["seed"])
+        assert pr.sha_left == g["sha_left"] and pr.sha_right == g["sha_right"]
+        out = oracle.sgm(pr.left, pr.right, g["max_disp"], doc["P1"], doc["P2"], g["n_paths"]).out
+        assert hashlib.sha256(out.tobytes()).hexdigest() == g["out_sha256"]
+
+
+def test_digest_entries_match_the_workload_definitions():
+    doc = json.load(open(GOLDEN))
+    items = synth.batch_items(64)
+    assert [(i["w"], i["h"], i["max_disp"], i["n_paths"], i["seed"]) for i in items] == \
+        [(g["w"], g["h"], g["max_disp"], g["n_paths"], g["seed"]) for g in doc["batch64"]]
+    kinds = synth.serve_kinds()
+    assert [(k["w"], k["h"], k["max_disp"], k["seed"]) for k in kinds] == \
+        [(g["w"], g["h"], g["max_disp"], g["seed"]) for g in doc["serve_kinds"]]

@@ -2,6 +2,9 @@
 requests (exact equality), admission never exceeds the memory budget, and the
 failure paths (full queue, cancellation, oversize requests, shutdown with work
 queued) behave as documented."""
+import hashlib
+import json
+import os
 import threading
 
 import numpy as np
@@ -180,3 +183,35 @@ def test_shutdown_with_queued_work(gpu):
     s2.close()
     torch.cuda.synchronize()
     assert (r["out"].cpu().numpy() == _alone(r)).all()
+
+
+@pytest.mark.parametrize("grouped", [False, True])
+def test_served_mix_full_size_against_oracle_digests(gpu, grouped):
+    """Every (size, disparity range) of the served mix, up to 1920x1080 with
+    D=256, 8 paths, median + LR, submitted together; each output against the
+    oracle's digest (tests/golden/make_oracle_hashes.py).  grouped=True
+    forces the batched kernels, False the single-pair kernels."""
+    import torch
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_hashes.json")))["serve_kinds"]
+    kinds = synth.serve_kinds()
+    assert len(golden) == len(kinds)
+    reqs = []
+    for k, g in zip(kinds, golden):
+        pr = synth.make_pair(k["w"], k["h"], k["max_disp"], k["scene"], seed=k["seed"])
+        assert pr.sha_left == g["sha_left"] and pr.sha_right == g["sha_right"]
+        reqs.append(dict(left=torch.from_numpy(pr.left).to(gpu), right=torch.from_numpy(pr.right).to(gpu),
+                         max_disp=k["max_disp"], n_paths=8, median=True, lrcheck=True, lr_threshold=1,
+                         out=torch.zeros((k["h"], k["w"]), dtype=torch.uint16, device=gpu)))
+    _say(f"served mix at full size, grouped={grouped}")
+    srv = Server(48 << 30, slots=4, max_group=8, max_group_cells=(1 << 40) if grouped else (1 << 28))
+    ts = [srv.submit(r) for r in reqs]
+    for t in ts:
+        assert srv.wait(t, 120000)[0] == REQ_DONE
+    st = srv.stats()
+    srv.close()
+    if grouped:
+        assert st["groups"] < len(reqs)
+    torch.cuda.synchronize()
+    for r, g in zip(reqs, golden):
+        got = r["out"].cpu().numpy()
+        assert hashlib.sha256(got.tobytes()).hexdigest() == g["out_sha256"], (g["w"], g["h"], g["max_disp"])
