@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sgm_oracle.c")
 _LIB = os.path.join(_HERE, "libsgm_oracle.so")
 
-MEDIAN, LRCHECK, CSCT = 1, 2, 4
+MEDIAN, LRCHECK, CSCT, LRFULL = 1, 2, 4, 8
 OK, EINVAL, ENOMEM, EBOUND = 0, -1, -2, -3
 
 
@@ -49,6 +49,7 @@ def lib():
         L.oracle_census_full.argtypes = [P, i, i, i, i, P]
         L.oracle_census_csct.argtypes = [P, i, i, i, i, P]
         L.oracle_cost_volume.argtypes = [P, P, i, i, i, i, P]
+        L.oracle_cost_volume_right.argtypes = [P, P, i, i, i, i, P]
         L.oracle_aggregate.argtypes = [P, i, i, i, i, i, i, i, P, P]
         L.oracle_direction.argtypes = [i, i, P, P]
         L.oracle_wta_left.argtypes = [P, i, i, i, P]
@@ -56,7 +57,7 @@ def lib():
         L.oracle_median3.argtypes = [P, i, i, P]
         L.oracle_lr_check.argtypes = [P, P, i, i, i, P]
         L.oracle_sgm.argtypes = [P, P, i, i, i, i, i, i, i, i, ctypes.c_uint, i, P, P, P, P, P, P]
-        for f in ("oracle_census_full", "oracle_census_csct", "oracle_cost_volume",
+        for f in ("oracle_census_full", "oracle_census_csct", "oracle_cost_volume", "oracle_cost_volume_right",
                   "oracle_aggregate", "oracle_direction", "oracle_sgm"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -94,6 +95,18 @@ def cost_volume(cbase, cmatch, D, cmax) -> np.ndarray:
     H, W = cbase.shape
     mc = np.zeros((H, W, D), dtype=np.uint8)
     rc = lib().oracle_cost_volume(_p(cbase), _p(cmatch), W, H, D, cmax, _p(mc))
+    if rc:
+        raise ValueError(f"oracle cost rc={rc}")
+    return mc
+
+
+def cost_volume_right(cright, cleft, D, cmax) -> np.ndarray:
+    """Costs with the right image as base: C_R(x, d) = HD(cR(x), cL(x + d))."""
+    cright = np.ascontiguousarray(cright, dtype=np.uint64)
+    cleft = np.ascontiguousarray(cleft, dtype=np.uint64)
+    H, W = cright.shape
+    mc = np.zeros((H, W, D), dtype=np.uint8)
+    rc = lib().oracle_cost_volume_right(_p(cright), _p(cleft), W, H, D, cmax, _p(mc))
     if rc:
         raise ValueError(f"oracle cost rc={rc}")
     return mc
@@ -164,9 +177,10 @@ class Result:
 
 
 def sgm(left, right, max_disp, P1=7, P2=86, n_paths=4, cw=9, ch=7, median=False, lr=False,
-        csct=False, lr_thr=1, keep_sums=False) -> Result:
+        csct=False, lr_thr=1, keep_sums=False, lr_full=False) -> Result:
     """Whole pipeline for one pair; returns out, dl_raw, dr_raw, census_l/r
-    and (when keep_sums) the summed costs S[H][W][D]."""
+    and (when keep_sums) the summed costs S[H][W][D].  lr_full: the right
+    disparity comes from a second SGM with the right image as base."""
     left, right = _u8(left), _u8(right)
     H, W = left.shape
     assert right.shape == left.shape
@@ -176,7 +190,8 @@ def sgm(left, right, max_disp, P1=7, P2=86, n_paths=4, cw=9, ch=7, median=False,
     cl = np.zeros((H, W), dtype=np.uint64)
     cr = np.zeros((H, W), dtype=np.uint64)
     S = np.zeros((H, W, max_disp), dtype=np.uint32) if keep_sums else None
-    flags = (MEDIAN if median else 0) | (LRCHECK if lr else 0) | (CSCT if csct else 0)
+    flags = (MEDIAN if median else 0) | (LRCHECK if lr else 0) | (CSCT if csct else 0) | \
+        (LRFULL if lr_full else 0)
     rc = lib().oracle_sgm(_p(left), _p(right), W, H, max_disp, P1, P2, n_paths, cw, ch, flags,
                           lr_thr, _p(out), _p(cl), _p(cr), _p(S), _p(dl), _p(dr))
     if rc:

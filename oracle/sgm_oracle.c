@@ -124,6 +124,25 @@ int oracle_cost_volume(const uint64_t *cbase, const uint64_t *cmatch, int W, int
  * L_r[H][W][D] is written there; if sum is non-NULL, L_r is added into it.
  * Returns ORC_EBOUND if any value leaves [C, C + P2] (the bound that
  * the last term of Eq. 3 guarantees). */
+/* Matching cost with the RIGHT image as base (the second SGM of the
+ * full left-right check, a reading of the post-filter named in Sec. 5):
+ * C_R(x, y, d) = popcount(cR(x, y) XOR cL(x + d, y)) for x + d < W, and Cmax
+ * where x + d falls outside the image (the mirror of Eq. 2). */
+int oracle_cost_volume_right(const uint64_t *cright, const uint64_t *cleft, int W, int H, int D,
+                             int cmax, uint8_t *mc)
+{
+    if (W < 1 || H < 1 || D < 1 || cmax < 0 || cmax > 255) return ORC_EINVAL;
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++)
+            for (int d = 0; d < D; d++) {
+                int c = cmax;
+                if (x + d < W)
+                    c = popcount64(cright[(size_t)y * W + x] ^ cleft[(size_t)y * W + x + d]);
+                mc[((size_t)y * W + x) * D + d] = (uint8_t)c;
+            }
+    return ORC_OK;
+}
+
 int oracle_aggregate(const uint8_t *mc, int W, int H, int D, int P1, int P2, int rx, int ry,
                      int32_t *lr_out, uint32_t *sum)
 {
@@ -258,6 +277,7 @@ void oracle_lr_check(const uint16_t *dl, const uint16_t *dr, int W, int H, int t
 #define ORC_MEDIAN 1u
 #define ORC_LRCHECK 2u
 #define ORC_CSCT 4u
+#define ORC_LRFULL 8u /* D_R from a second SGM with the right image as base */
 
 /* The whole pipeline for one pair.  Optional outputs (NULL to skip):
  * census_l/census_r [H][W] u64, S [H][W][D] u32, dl_raw/dr_raw [H][W]. */
@@ -297,7 +317,26 @@ int oracle_sgm(const uint8_t *left, const uint8_t *right, int W, int H, int D, i
         if (S[i] > 65535u) { rc = ORC_EBOUND; goto done; }
 
     oracle_wta_left(S, W, H, D, dl);
-    oracle_wta_right(S, W, H, D, dr);
+    if (flags & ORC_LRFULL) {
+        /* the same pipeline with the right image as base: its own costs,
+         * the same path directions, the smallest minimising d */
+        uint32_t *SR = (uint32_t *)malloc(ncell * 4);
+        if (!SR) { rc = ORC_ENOMEM; goto done; }
+        rc = oracle_cost_volume_right(cr, cl, W, H, D, cmax, mc);
+        memset(SR, 0, ncell * 4);
+        for (int r = 0; r < n_paths && !rc; r++) {
+            int rx, ry;
+            oracle_direction(n_paths, r, &rx, &ry);
+            rc = oracle_aggregate(mc, W, H, D, P1, P2, rx, ry, NULL, SR);
+        }
+        for (size_t i = 0; i < ncell && !rc; i++)
+            if (SR[i] > 65535u) rc = ORC_EBOUND;
+        if (!rc) oracle_wta_left(SR, W, H, D, dr);
+        free(SR);
+        if (rc) goto done;
+    } else {
+        oracle_wta_right(S, W, H, D, dr);
+    }
     if (dl_raw) memcpy(dl_raw, dl, npx * 2);
     if (dr_raw) memcpy(dr_raw, dr, npx * 2);
     if (flags & ORC_MEDIAN) {

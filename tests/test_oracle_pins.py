@@ -398,3 +398,45 @@ def test_synthetic_scene_is_mostly_recovered():
     r = oracle.sgm(p.left, p.right, 64, 7, 86, 4)
     v = p.gt != 0xFFFF
     assert (np.abs(r.out[v].astype(int) - p.gt[v]) <= 1).mean() > 0.95
+
+
+# --------------------------------------------------------------------------
+# Left-right check against a second SGM with the right image as base.
+# --------------------------------------------------------------------------
+def test_right_base_cost_is_the_mirror_of_eq2():
+    """C_R(x, d) = HD(cR(x), cL(x + d)), Cmax beyond the right border: the
+    same as Eq. 2's cost on the mirrored pair with the views exchanged."""
+    l = RNG.integers(0, 256, (9, 23), dtype=np.uint8)
+    r = RNG.integers(0, 256, (9, 23), dtype=np.uint8)
+    cl, cr = oracle.census(l), oracle.census(r)
+    cR = oracle.cost_volume_right(cr, cl, 7, 62)
+    for y, x, d in itertools.product(range(9), range(23), range(7)):
+        want = 62 if x + d >= 23 else _popcount(cr[y, x] ^ cl[y, x + d])
+        assert cR[y, x, d] == want
+    cm = oracle.cost_volume(oracle.census(r[:, ::-1].copy()), oracle.census(l[:, ::-1].copy()), 7, 62)
+    assert (cR == cm[:, ::-1, :]).all()
+
+
+@pytest.mark.parametrize("n_paths", [4, 8])
+def test_full_lr_right_map_is_the_mirrored_left_map(n_paths):
+    """With the full census and a path set closed under x-mirroring, the
+    right-base SGM of (L, R) equals the left-base SGM of (mirror R, mirror L)
+    mirrored back: a symmetry that ties the second pass to the first."""
+    pair = synth.make_pair(61, 27, 16, "RS", seed=99)
+    res = oracle.sgm(pair.left, pair.right, 16, 7, 86, n_paths, lr=True, lr_full=True)
+    mir = oracle.sgm(pair.right[:, ::-1].copy(), pair.left[:, ::-1].copy(), 16, 7, 86, n_paths)
+    assert (res.dr_raw == mir.dl_raw[:, ::-1]).all()
+    # the left map is untouched by the option
+    plain = oracle.sgm(pair.left, pair.right, 16, 7, 86, n_paths, lr=True)
+    assert (res.dl_raw == plain.dl_raw).all()
+
+
+def test_full_lr_recovers_a_constant_shift():
+    """Noise pair with right(x) = left(x + s): the right-base disparity is s
+    wherever x + s stays inside the image away from the borders."""
+    s, W, H, D = 5, 80, 40, 12
+    base = RNG.integers(0, 256, (H, W + s), dtype=np.uint8)
+    left, right = base[:, :W].copy(), base[:, s:s + W].copy()
+    res = oracle.sgm(left, right, D, 7, 86, 4, lr=True, lr_full=True)
+    inner = res.dr_raw[8:H - 8, 8:W - s - 8]
+    assert (inner == s).mean() > 0.97
