@@ -138,6 +138,32 @@ def bench_paths(left, right, cfg, steps: int, warmup: int = 50):
     return out
 
 
+def bench_lr_full(left, right, cfg, tuning, steps: int, warmup: int = 50):
+    """The headline pair with the full left-right check (a second SGM with
+    the right image as base), one frame at a time."""
+    import torch
+
+    from paper_1610_04121_amd import SGM, synth
+    st = torch.cuda.current_stream()
+    c = SGM(cfg["w"], cfg["h"], cfg["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, cfg["n_paths"],
+            median=cfg["median"], lrcheck=True, lr_full=True)
+    c.set_tuning(*tuning)
+    o = torch.empty((cfg["h"], cfg["w"]), dtype=torch.uint16, device=left.device)
+    for _ in range(warmup):
+        c.compute(left, right, o, stream=st)
+    torch.cuda.synchronize()
+    c.profile(True, every=8)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        c.compute(left, right, o, stream=st)
+    torch.cuda.synchronize()
+    fps = steps / (time.perf_counter() - t0)
+    n, stage = c.profile_read()
+    c.close()
+    return {"frames_per_s": round(fps, 1), "stage_ms": {k: round(v / max(n, 1), 5) for k, v in stage.items()},
+            "note": "two SGMs per frame (left and right base); aggregation of both in one launch"}
+
+
 def bench_batch(dev, steps: int, warmup: int = 3):
     """The 64-pair heterogeneous batch: one launch per stage through the
     batch API against 64 plain single-pair launches on one stream."""
@@ -492,6 +518,7 @@ def main():
         line["serialized_fps"] = {"eager": extras["eager"], "graph": extras["graph"]}
         line["latency_ms"] = extras["latency_ms"]
         line["paths_sweep"] = bench_paths(left, right, cfg, max(200, args.steps // 4))
+        line["lr_full"] = bench_lr_full(left, right, cfg, choice, max(200, args.steps // 4))
     for c in ctxs:
         c.close()
     if args.copy_calibration_mb:

@@ -53,9 +53,18 @@ enum {
     SGM_LRCHECK = 2u,     /* left-right consistency check */
     SGM_CENSUS_CSCT = 4u, /* center-symmetric census (Eq. 1) instead of the
                              full-window census */
-    SGM_GRAPH = 8u        /* replay a captured HIP graph of the pipeline when
+    SGM_GRAPH = 8u,       /* replay a captured HIP graph of the pipeline when
                              sgm_compute is called again with the same
                              buffers (not while stage timing is enabled) */
+    SGM_LR_FULL = 16u     /* with SGM_LRCHECK: the right disparity map of the
+                             check comes from a second full SGM with the right
+                             image as base (costs C_R(x, d) = Hamming distance
+                             of the right word at x and the left word at
+                             x + d, Cmax past the right border; the same path
+                             directions; smallest minimising d), instead of
+                             the diagonal minimum of the left SGM's sums.
+                             Twice the cost and aggregation work; the
+                             workspace grows (sgm_set_options may allocate). */
 };
 
 /* Checks a parameter set without touching the GPU.  Returns SGM_OK or
@@ -259,7 +268,9 @@ int sgm_debug_sums(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right, uint
 /* One intermediate as u16 [H][W][max_disp] (d fastest): which = -1 gives the
  * matching cost C (Eq. 2); which = r in [0, n_paths) gives L_r of path
  * direction r (Eq. 3), directions numbered as for sgm_create: (1,0), (-1,0),
- * (0,1), (0,-1), (1,1), (-1,1), (1,-1), (-1,-1); with 2 paths (1,0), (0,1). */
+ * (0,1), (0,-1), (1,1), (-1,1), (1,-1), (-1,-1); with 2 paths (1,0), (0,1).
+ * With SGM_LR_FULL, which = -2 gives the right-base costs C_R and which =
+ * n_paths + r the right-base L_r of direction r. */
 int sgm_debug_stage(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right, int which,
                     uint16_t *out, sgm_stream_t stream);
 

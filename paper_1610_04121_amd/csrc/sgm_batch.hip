@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void cost_batch_kernel(const BatchItem* items,
     const int local = b - it.cost_blk0;
     const int nx = (it.W + kCostTX - 1) / kCostTX;
     CostArgs a{it.census_l, it.census_r, it.cost, it.W, it.H, it.D, it.Dp, it.cmax};
-    cost_block(a, local % nx, local / nx, cost_smem);
+    cost_block<false>(a, local % nx, local / nx, cost_smem);
 }
 
 template <typename LT, int Dp>

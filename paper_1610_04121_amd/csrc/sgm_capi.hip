@@ -44,10 +44,15 @@ bool make_plan(sgm::Plan& p, int w, int h, int d, int P1, int P2, int n_paths, i
     p.csct = (flags & SGM_CENSUS_CSCT) != 0;
     p.median = (flags & SGM_MEDIAN3) != 0;
     p.lrcheck = (flags & SGM_LRCHECK) != 0;
+    p.lr_full = (flags & SGM_LR_FULL) != 0;
     p.lr_thr = thr;
     const char* why = "invalid parameters";
-    if (flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK | SGM_CENSUS_CSCT | SGM_GRAPH)) {
+    if (flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK | SGM_CENSUS_CSCT | SGM_GRAPH | SGM_LR_FULL)) {
         set_err(SGM_EINVAL, "unknown flag bits");
+        return false;
+    }
+    if (p.lr_full && !p.lrcheck) {
+        set_err(SGM_EINVAL, "SGM_LR_FULL needs SGM_LRCHECK");
         return false;
     }
     if (!sgm::plan_finish(p, &why)) {
@@ -150,6 +155,23 @@ int sgm_set_options(sgm_ctx* c, unsigned flags, int lr_threshold) {
     p.lanes_v = c->plan.lanes_v;
     p.fused = c->plan.fused;
     p.cc_fused = c->plan.cc_fused;
+    // the full left-right check needs a second cost volume and L_r set
+    sgm::Plan big = p;
+    big.l16 = true;
+    const size_t need = sgm::workspace_bytes(big);
+    if (need > c->mem_bytes) {
+        hipError_t e = hipDeviceSynchronize();  // the old workspace may still be in use
+        if (e != hipSuccess) return hip_err(e, "hipDeviceSynchronize");
+        void* mem = nullptr;
+        e = hipMalloc(&mem, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_err(SGM_ENOMEM, std::string("hipMalloc of workspace failed: ") + hipGetErrorString(e));
+        }
+        (void)hipFree(c->mem);
+        c->mem = mem;
+        c->mem_bytes = need;
+    }
     c->plan = p;
     c->ws = sgm::workspace_carve(p, c->mem);
     c->use_graph = (flags & SGM_GRAPH) != 0;
@@ -322,7 +344,8 @@ int sgm_debug_stage(sgm_ctx* c, const uint8_t* left, const uint8_t* right, int w
                     sgm_stream_t stream) {
     if (!c) return set_err(SGM_EINVAL, "null context");
     if (int rc = check_ptrs(left, right, out)) return rc;
-    if (which < -1 || which >= c->plan.n_paths) return set_err(SGM_EINVAL, "stage index out of range");
+    const int nplanes = c->plan.n_paths * (c->plan.lr_full ? 2 : 1);
+    if (which < (c->plan.lr_full ? -2 : -1) || which >= nplanes) return set_err(SGM_EINVAL, "stage index out of range");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = sgm::launch_matching_cost(c->plan, c->ws, left, right, which < 0 || !c->plan.fused, s);
     if (e == hipSuccess && which >= 0) e = sgm::launch_aggregate(c->plan, c->ws, s);

@@ -176,13 +176,19 @@ struct CostArgs {
     int W, H, D, Dp, cmax;
 };
 
+// RB = false: base words cl = left view, match words cr = right view at x - d
+// (Eq. 2).  RB = true: base = right view, match = left view at x + d (the
+// right-base costs of the full left-right check).
+template <bool RB>
 __device__ inline void cost_block(const CostArgs& a, int bx, int y, uint64_t* cw_smem) {
     const int x0 = bx * kCostTX;
     const int D = a.D, Dp = a.Dp;
     const int nright = kCostTX + D - 1;
     const int tpitch = Dp + 16;  // bytes per tile row
     uint64_t* cl = cw_smem;
-    uint64_t* cr = cl + kCostTX;  // cr[i] = match word of column x0 - (D-1) + i
+    // cr[i] = match word of column xm0 + i
+    uint64_t* cr = cl + kCostTX;
+    const int xm0 = RB ? x0 : x0 - (D - 1);
     // the tile starts on a 16-byte boundary (an even number of words)
     uint8_t* tile = reinterpret_cast<uint8_t*>(cl + ((kCostTX + nright + 1) & ~1));
     const uint64_t* gl = a.cl + (size_t)y * a.W;
@@ -190,7 +196,7 @@ __device__ inline void cost_block(const CostArgs& a, int bx, int y, uint64_t* cw
     for (int i = threadIdx.x; i < kCostTX; i += blockDim.x)
         if (x0 + i < a.W) cl[i] = gl[x0 + i];
     for (int i = threadIdx.x; i < nright; i += blockDim.x) {
-        const int xr = x0 - (D - 1) + i;
+        const int xr = xm0 + i;
         if (xr >= 0 && xr < a.W) cr[i] = gr[xr];
     }
     __syncthreads();
@@ -201,29 +207,35 @@ __device__ inline void cost_block(const CostArgs& a, int bx, int y, uint64_t* cw
     const int nchunks = Dp >> 4;
     for (int ch = wave; ch < nchunks; ch += 4) {
         const int d0 = 16 * ch;
-        // match word of disparity d0 + j is cr[lane + D - 1 - d0 - j]
-        const uint64_t* m = cr + (lane + D - 1 - d0 - 15);
+        // match word of disparity d0 + j: cr[lane + D - 1 - d0 - j] (left
+        // base), cr[lane + d0 + j] (right base)
+        auto word = [&](int j) -> uint64_t { return RB ? cr[lane + d0 + j] : cr[lane + D - 1 - d0 - j]; };
+        // all 16 disparities inside the image for every lane of the run
+        const bool inside = RB ? (x0 + kCostTX - 1 + d0 + 15 < a.W) : (x0 >= d0 + 15);
         uint32_t w[4];
-        if (x0 >= d0 + 15 && d0 + 16 <= D) {  // all 16 disparities valid for every lane
+        if (inside && d0 + 16 <= D) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                uint32_t word = 0;
+                uint32_t wd = 0;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) word |= (uint32_t)__popcll(base ^ m[15 - (4 * q + j)]) << (8 * j);
-                w[q] = word;
+                for (int j = 0; j < 4; ++j) wd |= (uint32_t)__popcll(base ^ word(4 * q + j)) << (8 * j);
+                w[q] = wd;
             }
         } else {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                uint32_t word = 0;
+                uint32_t wd = 0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int d = d0 + 4 * q + j;
                     uint32_t c = 0;  // padded levels d >= D
-                    if (d < D) c = x - d < 0 ? (uint32_t)a.cmax : (uint32_t)__popcll(base ^ m[15 - (4 * q + j)]);
-                    word |= c << (8 * j);
+                    if (d < D) {
+                        const bool out = RB ? x + d >= a.W : x - d < 0;
+                        c = out ? (uint32_t)a.cmax : (uint32_t)__popcll(base ^ word(4 * q + j));
+                    }
+                    wd |= c << (8 * j);
                 }
-                w[q] = word;
+                w[q] = wd;
             }
         }
         *reinterpret_cast<uint4*>(tile + lane * tpitch + d0) = make_uint4(w[0], w[1], w[2], w[3]);

@@ -3,7 +3,6 @@
 // stereo pair.
 #include <hip/hip_runtime.h>
 
-#include <cstdio>
 #include <cstdlib>
 
 #include "sgm_device.h"
@@ -26,18 +25,22 @@ __global__ __launch_bounds__(256) void census_cost_kernel(CensusCostArgs a) {
     census_cost_block(a, blockIdx.x, blockIdx.y, cc_smem);
 }
 
+template <bool RB>
 __global__ __launch_bounds__(256) void cost_kernel(CostArgs a) {
     extern __shared__ __align__(16) uint64_t cost_smem[];
-    cost_block(a, blockIdx.x, blockIdx.y, cost_smem);
+    cost_block<RB>(a, blockIdx.x, blockIdx.y, cost_smem);
 }
 
-// Direction table of one pair's aggregation launch.
+// Direction table of one pair's aggregation launch: the directions of one
+// SGM, or of two (left-base and right-base, for the full left-right check).
+constexpr int kMaxLaunchDirs = 2 * kMaxDirs;
 struct AggArgs {
-    SliceArgs base;          // shared fields; rx, ry, lplane set per direction
+    SliceArgs base;          // shared fields; rx, ry, cost, lplane set per direction
     void* lbuf;              // all L_r planes
     int ndirs, total;
-    int start[kMaxDirs + 1];  // first wave of each direction
-    int rx[kMaxDirs], ry[kMaxDirs], plane_index[kMaxDirs];
+    int start[kMaxLaunchDirs + 1];  // first wave of each direction
+    int rx[kMaxLaunchDirs], ry[kMaxLaunchDirs], plane_index[kMaxLaunchDirs];
+    const uint8_t* cost[kMaxLaunchDirs];  // the cost volume each direction reads
 };
 
 // One launch covers every direction.  Horizontal slices (the longest when
@@ -53,6 +56,7 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
     SliceArgs s = a.base;
     s.rx = a.rx[r];
     s.ry = a.ry[r];
+    s.cost = a.cost[r];
     s.lplane = reinterpret_cast<LT*>(a.lbuf) + (size_t)s.plane * a.plane_index[r];
     if (s.ry == 0) {
         aggregate_wave<GH, Dp / GH, LT, kHoriz, FUSED>(s, (wave - a.start[r]) * (64 / GH), lane);
@@ -67,6 +71,19 @@ template <typename LT>
 __global__ __launch_bounds__(1024) void wta_kernel(WtaArgs a) {
     extern __shared__ uint32_t wta_smem[];
     wta_row<LT>(a, blockIdx.x, wta_smem);
+}
+
+// Winner-take-all of two SGMs in one launch (full left-right check): rows
+// 0 .. H-1 of the left-base sums give D_L, blocks H .. 2H-1 the rows of the
+// right-base sums, D_R.
+template <typename LT>
+__global__ __launch_bounds__(1024) void wta_pair_kernel(WtaArgs l, WtaArgs r) {
+    extern __shared__ uint32_t wta_smem[];
+    const int y = blockIdx.x;
+    if (y < l.H)
+        wta_row<LT>(l, y, wta_smem);
+    else
+        wta_row<LT>(r, y - l.H, wta_smem);
 }
 
 __global__ __launch_bounds__(256) void post_kernel(PostArgs a) {
@@ -134,8 +151,9 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 size_t workspace_bytes(const Plan& p) {
     const size_t npx = (size_t)p.W * p.H;
     const size_t cells = npx * p.Dp;
-    return align256(cells) + align256(cells * p.n_paths * (p.l16 ? 2 : 1)) + 2 * align256(npx * 2) +
-           2 * align256(8 * (npx + kCensusGuard));
+    const int nsgm = p.lr_full ? 2 : 1;
+    return align256(cells) + align256(cells * nsgm * p.n_paths * (p.l16 ? 2 : 1)) + 2 * align256(npx * 2) +
+           2 * align256(8 * (npx + kCensusGuard)) + (p.lr_full ? align256(cells) : 0);
 }
 
 Workspace workspace_carve(const Plan& p, void* base) {
@@ -146,7 +164,7 @@ Workspace workspace_carve(const Plan& p, void* base) {
     ws.cost = b;
     b += align256(cells);
     ws.lbuf = b;
-    b += align256(cells * p.n_paths * (p.l16 ? 2 : 1));
+    b += align256(cells * (p.lr_full ? 2 : 1) * p.n_paths * (p.l16 ? 2 : 1));
     ws.dl = reinterpret_cast<uint16_t*>(b);
     b += align256(npx * 2);
     ws.dr = reinterpret_cast<uint16_t*>(b);
@@ -154,6 +172,8 @@ Workspace workspace_carve(const Plan& p, void* base) {
     ws.census_l = reinterpret_cast<uint64_t*>(b) + kCensusGuard;
     b += align256(8 * (npx + kCensusGuard));
     ws.census_r = reinterpret_cast<uint64_t*>(b) + kCensusGuard;
+    b += align256(8 * (npx + kCensusGuard));
+    if (p.lr_full) ws.cost_r = b;
     return ws;
 }
 
@@ -179,6 +199,12 @@ bool census_cost_fusable(const Plan& p) { return p.cc_fused && p.cw == 9 && p.ch
 
 hipError_t launch_matching_cost(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right,
                                 bool need_cost, hipStream_t stream) {
+    if (p.lr_full) {  // census words, then both cost volumes
+        hipError_t e = launch_census(p, ws, left, right, stream);
+        if (e == hipSuccess) e = launch_cost(p, ws, stream, false);
+        if (e == hipSuccess) e = launch_cost(p, ws, stream, true);
+        return e;
+    }
     const bool fusable = census_cost_fusable(p);
     hipError_t e = hipSuccess;
     if (need_cost && fusable) {
@@ -194,12 +220,18 @@ hipError_t launch_matching_cost(const Plan& p, const Workspace& ws, const uint8_
     return e;
 }
 
-hipError_t launch_cost(const Plan& p, const Workspace& ws, hipStream_t stream) {
-    CostArgs a{ws.census_l, ws.census_r, ws.cost, p.W, p.H, p.D, p.Dp, p.cmax};
+hipError_t launch_cost(const Plan& p, const Workspace& ws, hipStream_t stream, bool right_base) {
     const int nright = kCostTX + p.D - 1;
     const size_t smem = 8 * (size_t)((kCostTX + nright + 1) & ~1) + (size_t)kCostTX * (p.Dp + 16);
     dim3 grid((p.W + kCostTX - 1) / kCostTX, p.H);
-    hipLaunchKernelGGL(cost_kernel, grid, dim3(256), smem, stream, a);
+    if (right_base) {
+        if (!ws.cost_r) return hipErrorInvalidValue;
+        CostArgs a{ws.census_r, ws.census_l, ws.cost_r, p.W, p.H, p.D, p.Dp, p.cmax};
+        hipLaunchKernelGGL(cost_kernel<true>, grid, dim3(256), smem, stream, a);
+    } else {
+        CostArgs a{ws.census_l, ws.census_r, ws.cost, p.W, p.H, p.D, p.Dp, p.cmax};
+        hipLaunchKernelGGL(cost_kernel<false>, grid, dim3(256), smem, stream, a);
+    }
     return hipGetLastError();
 }
 
@@ -207,26 +239,30 @@ static void fill_agg_args(const Plan& p, const Workspace& ws, int SH, int SV, Ag
     a.base = SliceArgs{ws.cost, ws.census_l, ws.census_r, nullptr, (uint32_t)((size_t)p.W * p.H * p.Dp),
                        p.W, p.H, p.D, p.P1, p.P2, p.cmax, 0, 0};
     a.lbuf = ws.lbuf;
-    a.ndirs = p.n_paths;
+    // directions of the left-base SGM (planes 0 .. P-1) and, for the full
+    // left-right check, of the right-base SGM (planes P .. 2P-1)
+    const int nsgm = p.lr_full ? 2 : 1;
+    a.ndirs = nsgm * p.n_paths;
     // longest slices first, so that they start first
-    int order[kMaxDirs], n = 0;
+    int order[kMaxLaunchDirs], n = 0;
     const bool horiz_first = p.W >= p.H;
     for (int pass = 0; pass < 2; ++pass)
-        for (int i = 0; i < p.n_paths; ++i) {
-            const bool horiz = direction(p.n_paths, i).ry == 0;
+        for (int i = 0; i < a.ndirs; ++i) {
+            const bool horiz = direction(p.n_paths, i % p.n_paths).ry == 0;
             if ((horiz == horiz_first) == (pass == 0)) order[n++] = i;
         }
     int acc = 0;
-    for (int k = 0; k < p.n_paths; ++k) {
-        const Dir d = direction(p.n_paths, order[k]);
+    for (int k = 0; k < a.ndirs; ++k) {
+        const Dir d = direction(p.n_paths, order[k] % p.n_paths);
         const int S = d.ry == 0 ? SH : SV;
         a.rx[k] = d.rx;
         a.ry[k] = d.ry;
         a.plane_index[k] = order[k];
+        a.cost[k] = order[k] < p.n_paths ? ws.cost : ws.cost_r;
         a.start[k] = acc;
         acc += (slice_count(p.W, p.H, d) + S - 1) / S;
     }
-    a.start[p.n_paths] = acc;
+    a.start[a.ndirs] = acc;
     a.total = acc;
 }
 
@@ -273,14 +309,9 @@ void default_lanes(const Plan& p, int* gh, int* gv) {
 hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stream) {
     int gh = p.lanes_h, gv = p.lanes_v;
     if (gh <= 0 || gv <= 0) default_lanes(p, &gh, &gv);
-    if (const char* env = getenv("SGM_LANES")) {  // "GH,GV" override for tuning sweeps
-        int a = 0, b = 0;
-        if (sscanf(env, "%d,%d", &a, &b) == 2) {
-            gh = a;
-            gv = b;
-        }
-    }
-    if (p.fused)
+    // the right-base SGM of the full left-right check reads its own cost
+    // volume, so both SGMs take the cost-volume route
+    if (p.fused && !p.lr_full)
         return p.l16 ? launch_agg_lt<uint16_t, true>(p, ws, gh, gv, stream)
                      : launch_agg_lt<uint8_t, true>(p, ws, gh, gv, stream);
     return p.l16 ? launch_agg_lt<uint16_t, false>(p, ws, gh, gv, stream)
@@ -288,6 +319,17 @@ hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stre
 }
 
 hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream) {
+    if (p.lr_full) {
+        const size_t plane = (size_t)p.W * p.H * p.Dp;
+        const void* rbuf = static_cast<const uint8_t*>(ws.lbuf) + plane * p.n_paths * (p.l16 ? 2 : 1);
+        WtaArgs l{ws.lbuf, plane, ws.dl, nullptr, p.W, p.H, p.D, p.Dp, p.n_paths};
+        WtaArgs r{rbuf, plane, ws.dr, nullptr, p.W, p.H, p.D, p.Dp, p.n_paths};
+        if (p.l16)
+            hipLaunchKernelGGL(wta_pair_kernel<uint16_t>, dim3(2 * p.H), dim3(1024), 0, stream, l, r);
+        else
+            hipLaunchKernelGGL(wta_pair_kernel<uint8_t>, dim3(2 * p.H), dim3(1024), 0, stream, l, r);
+        return hipGetLastError();
+    }
     const bool post = p.median || p.lrcheck;
     WtaArgs a{ws.lbuf, (size_t)p.W * p.H * p.Dp, post ? ws.dl : out, p.lrcheck ? ws.dr : nullptr,
               p.W, p.H, p.D, p.Dp, p.n_paths};
@@ -342,9 +384,9 @@ hipError_t launch_sum_planes(const Plan& p, const Workspace& ws, uint16_t* s_out
 hipError_t launch_extract_plane(const Plan& p, const Workspace& ws, int plane, uint16_t* out,
                                 hipStream_t stream) {
     const size_t cells = (size_t)p.W * p.H * p.Dp;
-    if (plane < 0)
-        hipLaunchKernelGGL(extract_plane_kernel<uint8_t>, dim3(1024), dim3(256), 0, stream, ws.cost, out, p.W, p.H,
-                           p.D, p.Dp);
+    if (plane < 0)  // -1: the cost volume, -2: the right-base cost volume
+        hipLaunchKernelGGL(extract_plane_kernel<uint8_t>, dim3(1024), dim3(256), 0, stream,
+                           plane == -2 ? ws.cost_r : ws.cost, out, p.W, p.H, p.D, p.Dp);
     else if (p.l16)
         hipLaunchKernelGGL(extract_plane_kernel<uint16_t>, dim3(1024), dim3(256), 0, stream,
                            reinterpret_cast<const uint16_t*>(ws.lbuf) + cells * plane, out, p.W, p.H, p.D, p.Dp);

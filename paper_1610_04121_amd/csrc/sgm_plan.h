@@ -17,6 +17,7 @@ struct Plan {
     int cw = 9, ch = 7;        // census window
     bool csct = false;         // center-symmetric census (Eq. 1)
     bool median = false, lrcheck = false;
+    bool lr_full = false;      // D_R from a second SGM with the right image as base
     int lr_thr = 1;
     int cmax = 0;              // largest matching cost
     bool l16 = false;          // L_r stored as u16 (else u8: Cmax + P2 <= 255)
@@ -30,7 +31,9 @@ struct Plan {
 // Device workspace of one pair.  All buffers are row-major, d fastest.
 struct Workspace {
     uint8_t* cost = nullptr;   // C   u8 [H][W][Dp]
-    void* lbuf = nullptr;      // L_r u8|u16 [n_paths][H][W][Dp]
+    void* lbuf = nullptr;      // L_r u8|u16 [n_paths][H][W][Dp]; with lr_full the
+                               // right-base planes follow: [2 * n_paths][H][W][Dp]
+    uint8_t* cost_r = nullptr; // right-base C_R u8 [H][W][Dp] (lr_full only)
     uint16_t* dl = nullptr;    // raw left disparity  u16 [H][W]
     uint16_t* dr = nullptr;    // raw right disparity u16 [H][W]
     uint64_t* census_l = nullptr;  // census words of the base image u64 [H][W]
@@ -46,7 +49,9 @@ Workspace workspace_carve(const Plan& p, void* base);
 // Enqueue the stages (all asynchronous on `stream`).
 hipError_t launch_census(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right,
                          hipStream_t stream);
-hipError_t launch_cost(const Plan& p, const Workspace& ws, hipStream_t stream);
+// right_base: C_R(x, d) from the right image's words against the left's at
+// x + d, into ws.cost_r
+hipError_t launch_cost(const Plan& p, const Workspace& ws, hipStream_t stream, bool right_base = false);
 // Whatever the aggregation needs before it runs: the cost volume (if
 // need_cost; one census + cost launch when p.cc_fused and the window is 9x7,
 // else census then cost) and the census words (if the aggregation computes

@@ -152,3 +152,15 @@ def test_tuner_candidates_and_cache(tmp_path, monkeypatch):
     assert set(tune.load_cache()) == {"a", "b"}
     (tmp_path / "t.json").write_text("not json")
     assert tune.load_cache() == {}
+
+
+def test_full_lr_flag_rules(lib):
+    from paper_1610_04121_amd import sgm
+    ok = lib.sgm_validate(64, 48, 32, 7, 86, 4, 9, 7, sgm.LRCHECK | sgm.LR_FULL)
+    assert ok == 0
+    assert lib.sgm_validate(64, 48, 32, 7, 86, 4, 9, 7, sgm.LR_FULL) == sgm.SGM_EINVAL
+    assert "SGM_LRCHECK" in sgm.last_error()
+    plain = lib.sgm_footprint_bytes(640, 480, 128, 4, sgm.LRCHECK)
+    full = lib.sgm_footprint_bytes(640, 480, 128, 4, sgm.LRCHECK | sgm.LR_FULL)
+    # a second cost volume (u8) and a second set of 4 L_r planes (counted as u16)
+    assert full - plain >= 640 * 480 * 128 * (1 + 4 * 2)

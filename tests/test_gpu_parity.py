@@ -226,3 +226,74 @@ def test_pipeline_census_windows(gpu, cw, ch, csct, D):
     mc = oracle.cost_volume(oracle.census(l, cw, ch, csct), oracle.census(r, cw, ch, csct), D,
                             oracle.cmax_of(cw, ch, csct))
     assert (cost == mc).all()
+
+
+def test_widest_image_with_right_view(gpu):
+    """The largest width (16000): the right-view keys of a row fill almost
+    all of the 64 KiB of LDS the WTA may use."""
+    rng = np.random.default_rng(16000)
+    l, r = _rand_pair(rng, 16000, 5)
+    _say("16000x5 D=256 2 paths median+LR")
+    s = SGM(16000, 5, 256, 7, 86, 2, median=True, lrcheck=True)
+    got = _np(s.compute(_t(l, gpu), _t(r, gpu)))
+    dl, dr = s.debug_raw_disparity(_t(l, gpu), _t(r, gpu))
+    s.close()
+    want = oracle.sgm(l, r, 256, 7, 86, 2, median=True, lr=True)
+    assert (_np(dr) == want.dr_raw).all()
+    assert (got == want.out).all()
+
+
+@pytest.mark.parametrize("W,H,D,P,csct,median", [
+    (37, 23, 16, 4, False, True), (29, 31, 20, 8, True, False), (70, 9, 130, 2, False, True),
+    (5, 1, 256, 8, False, False), (130, 40, 64, 8, False, True), (1, 9, 5, 4, False, True),
+])
+def test_full_lr_check_parity(gpu, W, H, D, P, csct, median):
+    """SGM_LR_FULL: right-base costs, right-base L_r of every direction, the
+    right map and the final output, each against the oracle."""
+    rng = np.random.default_rng(W * 11 + H + D + P)
+    l, r = _rand_pair(rng, W, H)
+    _say(f"full LR {W}x{H} D={D} P={P} csct={csct} median={median}")
+    s = SGM(W, H, D, 7, 86, P, median=median, lrcheck=True, csct=csct, lr_full=True)
+    tl, tr = _t(l, gpu), _t(r, gpu)
+    cl, cr = oracle.census(l, csct=csct), oracle.census(r, csct=csct)
+    cR = oracle.cost_volume_right(cr, cl, D, oracle.cmax_of(csct=csct))
+    assert (_np(s.debug_stage(tl, tr, -2)) == cR).all()
+    for k, (rx, ry) in enumerate(oracle.directions(P)):
+        assert (_np(s.debug_stage(tl, tr, P + k)) == oracle.aggregate(cR, 7, 86, rx, ry)).all(), (rx, ry)
+    want = oracle.sgm(l, r, D, 7, 86, P, median=median, lr=True, csct=csct, lr_full=True)
+    dl, dr = s.debug_raw_disparity(tl, tr)
+    assert (_np(dl) == want.dl_raw).all()
+    assert (_np(dr) == want.dr_raw).all()
+    assert (_np(s.compute(tl, tr)) == want.out).all()
+    s.close()
+
+
+def test_full_lr_check_headline_workload(gpu):
+    """640x480, D=128, 4 paths, median, full left-right check, full size."""
+    cfg = synth.WORKLOADS["vga_640x480_d128_p4"]
+    pair = synth.workload_pair("vga_640x480_d128_p4")
+    _say("headline workload with the full left-right check")
+    s = SGM(cfg["w"], cfg["h"], cfg["max_disp"], 7, 86, cfg["n_paths"], median=True, lrcheck=True, lr_full=True)
+    got = _np(s.compute(_t(pair.left, gpu), _t(pair.right, gpu)))
+    s.close()
+    want = oracle.sgm(pair.left, pair.right, cfg["max_disp"], 7, 86, cfg["n_paths"], median=True, lr=True,
+                      lr_full=True).out
+    assert (got == want).all()
+
+
+def test_full_lr_check_switch_on_existing_context(gpu):
+    """Turning the option on after creation grows the workspace; turning it
+    off again gives the plain check back."""
+    rng = np.random.default_rng(5)
+    l, r = _rand_pair(rng, 90, 50)
+    s = SGM(90, 50, 40, 7, 86, 8, median=True, lrcheck=True)
+    tl, tr = _t(l, gpu), _t(r, gpu)
+    plain = _np(s.compute(tl, tr))
+    s.set_options(median=True, lrcheck=True, lr_full=True)
+    full = _np(s.compute(tl, tr))
+    s.set_options(median=True, lrcheck=True)
+    again = _np(s.compute(tl, tr))
+    s.close()
+    assert (plain == oracle.sgm(l, r, 40, 7, 86, 8, median=True, lr=True).out).all()
+    assert (full == oracle.sgm(l, r, 40, 7, 86, 8, median=True, lr=True, lr_full=True).out).all()
+    assert (again == plain).all()
