@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sgm_oracle.c")
 _LIB = os.path.join(_HERE, "libsgm_oracle.so")
 
-MEDIAN, LRCHECK, CSCT, LRFULL = 1, 2, 4, 8
+MEDIAN, LRCHECK, CSCT, LRFULL, SUBPIXEL = 1, 2, 4, 8, 16
 OK, EINVAL, ENOMEM, EBOUND = 0, -1, -2, -3
 
 
@@ -56,6 +56,8 @@ def lib():
         L.oracle_wta_right.argtypes = [P, i, i, i, P]
         L.oracle_median3.argtypes = [P, i, i, P]
         L.oracle_lr_check.argtypes = [P, P, i, i, i, P]
+        L.oracle_lr_check_q4.argtypes = [P, P, i, i, i, P]
+        L.oracle_subpixel.argtypes = [P, P, i, i, i, P]
         L.oracle_sgm.argtypes = [P, P, i, i, i, i, i, i, i, i, ctypes.c_uint, i, P, P, P, P, P, P]
         for f in ("oracle_census_full", "oracle_census_csct", "oracle_cost_volume", "oracle_cost_volume_right",
                   "oracle_aggregate", "oracle_direction", "oracle_sgm"):
@@ -152,6 +154,25 @@ def wta_right(S):
     return out
 
 
+def subpixel(S, dl):
+    """Q4 left disparities from summed costs S[H][W][D] and winners dl."""
+    S = np.ascontiguousarray(S, dtype=np.uint32)
+    dl = np.ascontiguousarray(dl, dtype=np.uint16)
+    H, W, D = S.shape
+    out = np.zeros((H, W), dtype=np.uint16)
+    lib().oracle_subpixel(_p(S), _p(dl), W, H, D, _p(out))
+    return out
+
+
+def lr_check_q4(q, dr, thr=1):
+    q = np.ascontiguousarray(q, dtype=np.uint16)
+    dr = np.ascontiguousarray(dr, dtype=np.uint16)
+    H, W = q.shape
+    out = np.zeros_like(q)
+    lib().oracle_lr_check_q4(_p(q), _p(dr), W, H, thr, _p(out))
+    return out
+
+
 def median3(img):
     img = np.ascontiguousarray(img, dtype=np.uint16)
     H, W = img.shape
@@ -177,7 +198,7 @@ class Result:
 
 
 def sgm(left, right, max_disp, P1=7, P2=86, n_paths=4, cw=9, ch=7, median=False, lr=False,
-        csct=False, lr_thr=1, keep_sums=False, lr_full=False) -> Result:
+        csct=False, lr_thr=1, keep_sums=False, lr_full=False, subpixel=False) -> Result:
     """Whole pipeline for one pair; returns out, dl_raw, dr_raw, census_l/r
     and (when keep_sums) the summed costs S[H][W][D].  lr_full: the right
     disparity comes from a second SGM with the right image as base."""
@@ -191,7 +212,7 @@ def sgm(left, right, max_disp, P1=7, P2=86, n_paths=4, cw=9, ch=7, median=False,
     cr = np.zeros((H, W), dtype=np.uint64)
     S = np.zeros((H, W, max_disp), dtype=np.uint32) if keep_sums else None
     flags = (MEDIAN if median else 0) | (LRCHECK if lr else 0) | (CSCT if csct else 0) | \
-        (LRFULL if lr_full else 0)
+        (LRFULL if lr_full else 0) | (SUBPIXEL if subpixel else 0)
     rc = lib().oracle_sgm(_p(left), _p(right), W, H, max_disp, P1, P2, n_paths, cw, ch, flags,
                           lr_thr, _p(out), _p(cl), _p(cr), _p(S), _p(dl), _p(dr))
     if rc:

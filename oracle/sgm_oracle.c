@@ -237,6 +237,49 @@ void oracle_wta_right(const uint32_t *S, int W, int H, int D, uint16_t *dr)
 
 /* 3x3 median (Sec. 2, stage 4) with clamp-to-edge neighbours: the 5th
  * smallest of the 9 values. */
+/* Sub-pixel refinement (a reading of the sub-pixel estimation the paper
+ * names as later work, Sec. 5): the vertex of the parabola through
+ * (d-1, S(d-1)), (d, S(d)), (d+1, S(d+1)) at the winner d, in 1/16 pixel.
+ * With a = S(d-1), b = S(d), c = S(d+1) and den = a + c - 2b (>= 0 because
+ * b is the minimum), the vertex lies at d + (a - c) / (2 den); it is rounded
+ * half up to 1/16: f = floor((16 (a - c) + den) / (2 den)), in [-8, 8].
+ * f = 0 when d = 0, d = D - 1 or den = 0.  Output q = 16 d + f. */
+void oracle_subpixel(const uint32_t *S, const uint16_t *dl, int W, int H, int D, uint16_t *q)
+{
+    for (int i = 0; i < W * H; i++) {
+        int d = dl[i], f = 0;
+        if (d > 0 && d < D - 1) {
+            const uint32_t *s = S + (size_t)i * D;
+            long long a = s[d - 1], b = s[d], c = s[d + 1];
+            long long den = a + c - 2 * b;
+            if (den > 0) {
+                long long num = 16 * (a - c) + den, div = 2 * den;
+                long long fl = num / div;
+                if (num % div != 0 && num < 0) fl -= 1; /* floor for negative numerators */
+                f = (int)fl;
+            }
+        }
+        q[i] = (uint16_t)(16 * d + f);
+    }
+}
+
+/* Left-right check on sub-pixel left disparities: the rounded integer
+ * disparity di = (q + 8) / 16 indexes and is compared as in
+ * oracle_lr_check; a valid pixel keeps q. */
+void oracle_lr_check_q4(const uint16_t *q, const uint16_t *dr, int W, int H, int thr, uint16_t *out)
+{
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            int qq = q[y * W + x], di = (qq + 8) >> 4;
+            uint16_t o = 0xFFFF;
+            if (x - di >= 0) {
+                int e = dr[y * W + x - di];
+                if (abs(di - e) <= thr) o = (uint16_t)qq;
+            }
+            out[y * W + x] = o;
+        }
+}
+
 void oracle_median3(const uint16_t *in, int W, int H, uint16_t *out)
 {
     for (int y = 0; y < H; y++)
@@ -278,6 +321,7 @@ void oracle_lr_check(const uint16_t *dl, const uint16_t *dr, int W, int H, int t
 #define ORC_LRCHECK 2u
 #define ORC_CSCT 4u
 #define ORC_LRFULL 8u /* D_R from a second SGM with the right image as base */
+#define ORC_SUBPIXEL 16u /* left disparities in 1/16 pixel (oracle_subpixel) */
 
 /* The whole pipeline for one pair.  Optional outputs (NULL to skip):
  * census_l/census_r [H][W] u64, S [H][W][D] u32, dl_raw/dr_raw [H][W]. */
@@ -337,6 +381,10 @@ int oracle_sgm(const uint8_t *left, const uint8_t *right, int W, int H, int D, i
     } else {
         oracle_wta_right(S, W, H, D, dr);
     }
+    if (flags & ORC_SUBPIXEL) {
+        oracle_subpixel(S, dl, W, H, D, t1);
+        memcpy(dl, t1, npx * 2);
+    }
     if (dl_raw) memcpy(dl_raw, dl, npx * 2);
     if (dr_raw) memcpy(dr_raw, dr, npx * 2);
     if (flags & ORC_MEDIAN) {
@@ -345,7 +393,9 @@ int oracle_sgm(const uint8_t *left, const uint8_t *right, int W, int H, int D, i
         memcpy(dl, t1, npx * 2);
         memcpy(dr, t2, npx * 2);
     }
-    if (flags & ORC_LRCHECK)
+    if ((flags & ORC_LRCHECK) && (flags & ORC_SUBPIXEL))
+        oracle_lr_check_q4(dl, dr, W, H, lr_thr, out);
+    else if (flags & ORC_LRCHECK)
         oracle_lr_check(dl, dr, W, H, lr_thr, out);
     else
         memcpy(out, dl, npx * 2);

@@ -440,3 +440,62 @@ def test_full_lr_recovers_a_constant_shift():
     res = oracle.sgm(left, right, D, 7, 86, 4, lr=True, lr_full=True)
     inner = res.dr_raw[8:H - 8, 8:W - s - 8]
     assert (inner == s).mean() > 0.97
+
+
+# --------------------------------------------------------------------------
+# Sub-pixel refinement (later work in Sec. 5; the fixed-point reading of the
+# oracle's header): parabola vertex through S(d-1), S(d), S(d+1), 1/16 px.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("k", range(-7, 8))
+def test_subpixel_recovers_an_exact_parabola(k):
+    """S sampled from A (16 d - mu16)^2 + c: the parabola through three
+    samples is S itself, so its vertex mu16 / 16 comes back exactly."""
+    D, d0, A = 12, 6, 3
+    mu16 = 16 * d0 + k
+    d = np.arange(D)
+    S = (A * (16 * d - mu16) ** 2 + 1000).astype(np.uint32)
+    dl = np.array([[int(np.argmin(S))]], dtype=np.uint16)
+    assert int(oracle.subpixel(S.reshape(1, 1, D), dl)[0, 0]) == mu16
+
+
+def _q(values, d):
+    S = np.array(values, dtype=np.uint32).reshape(1, 1, len(values))
+    return int(oracle.subpixel(S, np.array([[d]], np.uint16))[0, 0])
+
+
+def test_subpixel_rules_at_the_edges_and_flat_minimum():
+    assert _q([5, 9, 9, 9, 9, 9], 0) == 0            # d = 0: no refinement
+    assert _q([9, 9, 9, 9, 9, 5], 5) == 16 * 5       # d = D - 1
+    assert _q([9, 4, 4, 4, 9, 9], 2) == 16 * 2       # flat: den = 0
+    # (0, 9), (1, 4), (2, 4): vertex at 1.5, a half rounded up
+    assert _q([9, 4, 4, 12, 9, 9], 1) == 16 + 8
+    # (1, 6), (2, 4), (3, 7): vertex at 2 + (6 - 7) / (2 * 5) = 1.9 -> 16 * 1.9 = 30.4 -> 30
+    assert _q([9, 6, 4, 7, 9, 9], 2) == 30
+
+
+def test_subpixel_mirror_symmetry():
+    """Reversing the three samples negates the fraction, up to the half-up
+    rounding of an exact half: f(a, b, c) + f(c, b, a) is 0 or 1."""
+    rng = np.random.default_rng(3)
+    for _ in range(300):
+        b = int(rng.integers(0, 100))
+        a, c = b + int(rng.integers(0, 300)), b + int(rng.integers(0, 300))
+        f = _q([a, b, c], 1) - 16
+        fm = _q([c, b, a], 1) - 16
+        assert -8 <= f <= 8
+        assert f + fm in (0, 1)
+
+
+def test_subpixel_in_the_pipeline():
+    """The Q4 map is 16 * the integer winner plus a fraction in [-8, 8]; with
+    the check, a pixel keeps its Q4 value exactly when the rounded integer
+    disparity passes the integer rule."""
+    pair = synth.make_pair(160, 96, 48, "RS", seed=41)
+    ip = oracle.sgm(pair.left, pair.right, 48, 7, 86, 8, lr=True, keep_sums=True)
+    sp = oracle.sgm(pair.left, pair.right, 48, 7, 86, 8, lr=True, subpixel=True)
+    q = sp.dl_raw.astype(np.int64)
+    assert ((q - 16 * ip.dl_raw >= -8) & (q - 16 * ip.dl_raw <= 8)).all()
+    assert (sp.dl_raw == oracle.subpixel(ip.S, ip.dl_raw)).all()
+    di = ((q + 8) >> 4).astype(np.uint16)
+    ok = oracle.lr_check(di, sp.dr_raw) != 0xFFFF
+    assert (sp.out[ok] == sp.dl_raw[ok]).all() and (sp.out[~ok] == 0xFFFF).all()
