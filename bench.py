@@ -138,15 +138,15 @@ def bench_paths(left, right, cfg, steps: int, warmup: int = 50):
     return out
 
 
-def bench_lr_full(left, right, cfg, tuning, steps: int, warmup: int = 50):
-    """The headline pair with the full left-right check (a second SGM with
-    the right image as base), one frame at a time."""
+def bench_variant(left, right, cfg, tuning, steps: int, warmup: int = 50, **opts):
+    """The headline pair with other output options (the full left-right
+    check, sub-pixel output), one frame at a time."""
     import torch
 
     from paper_1610_04121_amd import SGM, synth
     st = torch.cuda.current_stream()
     c = SGM(cfg["w"], cfg["h"], cfg["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, cfg["n_paths"],
-            median=cfg["median"], lrcheck=True, lr_full=True)
+            median=cfg["median"], lrcheck=True, **opts)
     c.set_tuning(*tuning)
     o = torch.empty((cfg["h"], cfg["w"]), dtype=torch.uint16, device=left.device)
     for _ in range(warmup):
@@ -160,8 +160,7 @@ def bench_lr_full(left, right, cfg, tuning, steps: int, warmup: int = 50):
     fps = steps / (time.perf_counter() - t0)
     n, stage = c.profile_read()
     c.close()
-    return {"frames_per_s": round(fps, 1), "stage_ms": {k: round(v / max(n, 1), 5) for k, v in stage.items()},
-            "note": "two SGMs per frame (left and right base); aggregation of both in one launch"}
+    return {"frames_per_s": round(fps, 1), "stage_ms": {k: round(v / max(n, 1), 5) for k, v in stage.items()}}
 
 
 def bench_batch(dev, steps: int, warmup: int = 3):
@@ -518,7 +517,8 @@ def main():
         line["serialized_fps"] = {"eager": extras["eager"], "graph": extras["graph"]}
         line["latency_ms"] = extras["latency_ms"]
         line["paths_sweep"] = bench_paths(left, right, cfg, max(200, args.steps // 4))
-        line["lr_full"] = bench_lr_full(left, right, cfg, choice, max(200, args.steps // 4))
+        line["lr_full"] = bench_variant(left, right, cfg, choice, max(200, args.steps // 4), lr_full=True)
+        line["subpixel"] = bench_variant(left, right, cfg, choice, max(200, args.steps // 4), subpixel=True)
     for c in ctxs:
         c.close()
     if args.copy_calibration_mb:

@@ -19,8 +19,8 @@
  *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Compute
  *    calls only enqueue work and return; the result is ready when the stream
  *    reaches that point.
- *  - Disparities are integers in [0, max_disp); 0xFFFF marks a pixel that
- *    fails the left-right check.
+ *  - Disparities are integers in [0, max_disp) (in 1/16 pixel with
+ *    SGM_SUBPIXEL); 0xFFFF marks a pixel that fails the left-right check.
  *  - Ties in the winner-take-all go to the smallest disparity.
  *  - Errors are reported as negative return codes (or NULL) before anything
  *    is enqueued; sgm_last_error() returns a message for the calling thread.
@@ -56,7 +56,7 @@ enum {
     SGM_GRAPH = 8u,       /* replay a captured HIP graph of the pipeline when
                              sgm_compute is called again with the same
                              buffers (not while stage timing is enabled) */
-    SGM_LR_FULL = 16u     /* with SGM_LRCHECK: the right disparity map of the
+    SGM_LR_FULL = 16u,    /* with SGM_LRCHECK: the right disparity map of the
                              check comes from a second full SGM with the right
                              image as base (costs C_R(x, d) = Hamming distance
                              of the right word at x and the left word at
@@ -65,6 +65,14 @@ enum {
                              the diagonal minimum of the left SGM's sums.
                              Twice the cost and aggregation work; the
                              workspace grows (sgm_set_options may allocate). */
+    SGM_SUBPIXEL = 32u    /* left disparities in 1/16 pixel: q = 16 d + f at
+                             the winner d, f = floor((16 (a - c) + den) /
+                             (2 den)) with a, b, c = S(d-1), S(d), S(d+1) and
+                             den = a + c - 2b (the parabola vertex rounded
+                             half up; f = 0 if d = 0, d = D-1 or den = 0);
+                             the median runs on q and the left-right check on
+                             (q + 8) >> 4; the output holds q (0xFFFF still
+                             marks a failed check) */
 };
 
 /* Checks a parameter set without touching the GPU.  Returns SGM_OK or

@@ -45,9 +45,10 @@ bool make_plan(sgm::Plan& p, int w, int h, int d, int P1, int P2, int n_paths, i
     p.median = (flags & SGM_MEDIAN3) != 0;
     p.lrcheck = (flags & SGM_LRCHECK) != 0;
     p.lr_full = (flags & SGM_LR_FULL) != 0;
+    p.subpixel = (flags & SGM_SUBPIXEL) != 0;
     p.lr_thr = thr;
     const char* why = "invalid parameters";
-    if (flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK | SGM_CENSUS_CSCT | SGM_GRAPH | SGM_LR_FULL)) {
+    if (flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK | SGM_CENSUS_CSCT | SGM_GRAPH | SGM_LR_FULL | SGM_SUBPIXEL)) {
         set_err(SGM_EINVAL, "unknown flag bits");
         return false;
     }

@@ -879,7 +879,14 @@ struct WtaArgs {
     uint16_t* dl;  // left disparity (raw, or the final output)
     uint16_t* dr;  // right disparity or nullptr
     int W, H, D, Dp, nplanes;
+    int subpixel = 0;  // dl in 1/16 pixel: parabola vertex through S(d-1), S(d), S(d+1)
 };
+
+// floor(num / den) for den > 0
+__device__ inline int floor_div(int num, int den) {
+    const int q = num / den;
+    return (num % den != 0 && num < 0) ? q - 1 : q;
+}
 
 constexpr int kWtaGuard = 256;  // >= max disparity
 
@@ -972,7 +979,34 @@ __device__ inline void wta_row(const WtaArgs& a, int y, uint32_t* keyR_smem) {
             }
         }
         best = lanes_min(best, G);
-        if (g == 0) a.dl[(size_t)y * a.W + x] = (uint16_t)(best & 0xFF);
+        const int dbest = (int)(best & 0xFF);
+        uint32_t outv = (uint32_t)dbest;
+        if (a.subpixel) {
+            // S(dbest - 1) and S(dbest + 1) from the lanes holding them; the
+            // vertex of the parabola through the three, rounded half up to
+            // 1/16: f = floor((16 (a - c) + den) / (2 den)), den = a + c - 2b
+            uint32_t va = ~0u, vc = ~0u;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                int dlo, dhi;
+                pair_disps<LT>(k, dlo, dhi);
+                const uint32_t slo = S[k] & 0xFFFFu, shi = S[k] >> 16;
+                if (d0 + dlo == dbest - 1) va = slo;
+                if (d0 + dhi == dbest - 1) va = shi;
+                if (d0 + dlo == dbest + 1) vc = slo;
+                if (d0 + dhi == dbest + 1) vc = shi;
+            }
+            va = lanes_min(va, G);
+            vc = lanes_min(vc, G);
+            int f = 0;
+            if (dbest > 0 && dbest < a.D - 1) {
+                const int b = (int)((best >> 8) & 0xFFFFu);
+                const int den = (int)va + (int)vc - 2 * b;
+                if (den > 0) f = floor_div(16 * ((int)va - (int)vc) + den, 2 * den);
+            }
+            outv = (uint32_t)(16 * dbest + f);
+        }
+        if (g == 0) a.dl[(size_t)y * a.W + x] = (uint16_t)outv;
     }
     if (right) {
         __syncthreads();
@@ -1017,6 +1051,7 @@ struct PostArgs {
     const uint16_t* dr;
     uint16_t* out;
     int W, H, median, lrcheck, thr;
+    int subpixel = 0;  // dl in 1/16 pixel: the check uses its rounding
 };
 
 // One row of the post stage.  Each thread takes 4 columns per pass so that
@@ -1048,14 +1083,15 @@ __device__ inline void post_row(const PostArgs& a, int y, uint16_t* rview) {
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int x = x0 + u * nt, d = dv[u];
+            const int x = x0 + u * nt, v = dv[u];
             if (x >= a.W) continue;
-            int o = d;
+            int o = v;
             if (a.lrcheck) {
+                const int d = a.subpixel ? (v + 8) >> 4 : v;  // integer disparity of the check
                 o = kInvalid;
                 if (x - d >= 0) {
                     const int e = rview[x - d];
-                    if (abs(d - e) <= a.thr) o = d;
+                    if (abs(d - e) <= a.thr) o = v;
                 }
             }
             a.out[(size_t)y * a.W + x] = (uint16_t)o;

@@ -322,7 +322,7 @@ hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStre
     if (p.lr_full) {
         const size_t plane = (size_t)p.W * p.H * p.Dp;
         const void* rbuf = static_cast<const uint8_t*>(ws.lbuf) + plane * p.n_paths * (p.l16 ? 2 : 1);
-        WtaArgs l{ws.lbuf, plane, ws.dl, nullptr, p.W, p.H, p.D, p.Dp, p.n_paths};
+        WtaArgs l{ws.lbuf, plane, ws.dl, nullptr, p.W, p.H, p.D, p.Dp, p.n_paths, p.subpixel ? 1 : 0};
         WtaArgs r{rbuf, plane, ws.dr, nullptr, p.W, p.H, p.D, p.Dp, p.n_paths};
         if (p.l16)
             hipLaunchKernelGGL(wta_pair_kernel<uint16_t>, dim3(2 * p.H), dim3(1024), 0, stream, l, r);
@@ -332,7 +332,7 @@ hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStre
     }
     const bool post = p.median || p.lrcheck;
     WtaArgs a{ws.lbuf, (size_t)p.W * p.H * p.Dp, post ? ws.dl : out, p.lrcheck ? ws.dr : nullptr,
-              p.W, p.H, p.D, p.Dp, p.n_paths};
+              p.W, p.H, p.D, p.Dp, p.n_paths, p.subpixel ? 1 : 0};
     const size_t smem = p.lrcheck ? 4 * (size_t)(p.W + kWtaGuard) : 0;
     if (p.l16)
         hipLaunchKernelGGL(wta_kernel<uint16_t>, dim3(p.H), dim3(1024), smem, stream, a);
@@ -343,7 +343,7 @@ hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStre
 
 hipError_t launch_post(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream) {
     if (!p.median && !p.lrcheck) return hipSuccess;  // the WTA wrote `out`
-    PostArgs a{ws.dl, ws.dr, out, p.W, p.H, p.median ? 1 : 0, p.lrcheck ? 1 : 0, p.lr_thr};
+    PostArgs a{ws.dl, ws.dr, out, p.W, p.H, p.median ? 1 : 0, p.lrcheck ? 1 : 0, p.lr_thr, p.subpixel ? 1 : 0};
     hipLaunchKernelGGL(post_kernel, dim3(p.H), dim3(256), p.lrcheck ? 2 * (size_t)p.W : 0, stream, a);
     return hipGetLastError();
 }

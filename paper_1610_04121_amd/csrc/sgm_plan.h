@@ -18,6 +18,7 @@ struct Plan {
     bool csct = false;         // center-symmetric census (Eq. 1)
     bool median = false, lrcheck = false;
     bool lr_full = false;      // D_R from a second SGM with the right image as base
+    bool subpixel = false;     // left disparities in 1/16 pixel
     int lr_thr = 1;
     int cmax = 0;              // largest matching cost
     bool l16 = false;          // L_r stored as u16 (else u8: Cmax + P2 <= 255)

@@ -297,3 +297,40 @@ def test_full_lr_check_switch_on_existing_context(gpu):
     assert (plain == oracle.sgm(l, r, 40, 7, 86, 8, median=True, lr=True).out).all()
     assert (full == oracle.sgm(l, r, 40, 7, 86, 8, median=True, lr=True, lr_full=True).out).all()
     assert (again == plain).all()
+
+
+@pytest.mark.parametrize("W,H,D,P,median,lr,lr_full,csct", [
+    (37, 23, 16, 4, False, False, False, False), (29, 31, 20, 8, True, True, False, True),
+    (70, 9, 130, 2, True, False, False, False), (5, 1, 256, 8, False, True, False, False),
+    (130, 40, 64, 8, True, True, True, False), (1, 9, 5, 4, True, True, False, False),
+    (64, 48, 3, 4, False, True, True, False), (90, 33, 200, 4, True, True, False, False),
+])
+def test_subpixel_parity(gpu, W, H, D, P, median, lr, lr_full, csct):
+    """SGM_SUBPIXEL: the 1/16-pixel left map (raw) and the output, with and
+    without median and check, against the oracle."""
+    rng = np.random.default_rng(W * 5 + H * 3 + D)
+    l, r = _rand_pair(rng, W, H)
+    if D > 8:  # smoother pairs so that minima have curvature
+        pr = synth.make_pair(W, H, D, "RS", seed=W + H + D)
+        l, r = pr.left, pr.right
+    _say(f"subpixel {W}x{H} D={D} P={P} median={median} lr={lr} lr_full={lr_full} csct={csct}")
+    s = SGM(W, H, D, 7, 86, P, median=median, lrcheck=lr, lr_full=lr_full, csct=csct, subpixel=True)
+    tl, tr = _t(l, gpu), _t(r, gpu)
+    got = _np(s.compute(tl, tr))
+    dl, dr = s.debug_raw_disparity(tl, tr)
+    s.close()
+    want = oracle.sgm(l, r, D, 7, 86, P, median=median, lr=lr, lr_full=lr_full, csct=csct, subpixel=True)
+    assert (_np(dl) == want.dl_raw).all()
+    assert (got == want.out).all()
+
+
+def test_subpixel_headline_workload(gpu):
+    cfg = synth.WORKLOADS["vga_640x480_d128_p4"]
+    pair = synth.workload_pair("vga_640x480_d128_p4")
+    _say("headline workload with sub-pixel output")
+    s = SGM(cfg["w"], cfg["h"], cfg["max_disp"], 7, 86, cfg["n_paths"], median=True, lrcheck=True, subpixel=True)
+    got = _np(s.compute(_t(pair.left, gpu), _t(pair.right, gpu)))
+    s.close()
+    want = oracle.sgm(pair.left, pair.right, cfg["max_disp"], 7, 86, cfg["n_paths"], median=True, lr=True,
+                      subpixel=True).out
+    assert (got == want).all()
