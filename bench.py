@@ -163,9 +163,10 @@ def bench_variant(left, right, cfg, tuning, steps: int, warmup: int = 50, **opts
     return {"frames_per_s": round(fps, 1), "stage_ms": {k: round(v / max(n, 1), 5) for k, v in stage.items()}}
 
 
-def bench_batch(dev, steps: int, warmup: int = 3):
+def bench_batch(dev, steps: int, warmup: int = 3, post: bool = False):
     """The 64-pair heterogeneous batch: one launch per stage through the
-    batch API against 64 plain single-pair launches on one stream."""
+    batch API against 64 plain single-pair launches on one stream (post:
+    every pair with median and left-right check)."""
     import torch
 
     from paper_1610_04121_amd import SGM, synth
@@ -176,7 +177,7 @@ def bench_batch(dev, steps: int, warmup: int = 3):
     for it in items:
         pr = synth.make_pair(it["w"], it["h"], it["max_disp"], it["scene"], seed=it["seed"])
         pairs.append(dict(left=torch.from_numpy(pr.left).to(dev), right=torch.from_numpy(pr.right).to(dev),
-                          max_disp=it["max_disp"], n_paths=it["n_paths"],
+                          max_disp=it["max_disp"], n_paths=it["n_paths"], median=post, lrcheck=post,
                           out=torch.empty((it["h"], it["w"]), dtype=torch.uint16, device=dev)))
         cells += it["w"] * it["h"] * it["max_disp"] * it["n_paths"]
     b = Batch(synth.P1_DEFAULT, synth.P2_DEFAULT)
@@ -197,7 +198,8 @@ def bench_batch(dev, steps: int, warmup: int = 3):
         h, w = p["left"].shape
         key = (w, h, p["max_disp"], p["n_paths"])
         if key not in ctxs:
-            ctxs[key] = SGM(w, h, p["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, p["n_paths"])
+            ctxs[key] = SGM(w, h, p["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, p["n_paths"],
+                            median=post, lrcheck=post)
     seq = [(ctxs[(p["left"].shape[1], p["left"].shape[0], p["max_disp"], p["n_paths"])], p) for p in pairs]
 
     def run_seq():
@@ -219,11 +221,11 @@ def bench_batch(dev, steps: int, warmup: int = 3):
             "sequential_ms": round(t_seq * 1e3, 4), "sequential_pairs_per_s": round(len(pairs) / t_seq, 1),
             "speedup_vs_sequential": round(t_seq / t_batch, 3), "workspace_bytes": footprint,
             "shapes": "64 pairs, sizes from {320x240, 640x480, 1242x375, 1280x720}, D from {64, 128}, "
-                      "4 or 8 paths, no median/LR"}
+                      "4 or 8 paths, " + ("median + LR check" if post else "no median/LR")}
 
 
 def bench_serve(dev, qps_levels, n_req: int, slots: int = 4, streams: int = 4, max_group: int = 8,
-                group_cells: int = 1 << 28, seed: int = 1610041214):
+                group_cells: int = 1 << 28, overlap_queue: int = 3, seed: int = 1610041214):
     """Poisson arrivals of 8-path median + LR requests of mixed sizes and
     disparity ranges, served by the continuous-batching server and, on the
     same arrival times, by plain per-request launches (one context per
@@ -241,7 +243,8 @@ def bench_serve(dev, qps_levels, n_req: int, slots: int = 4, streams: int = 4, m
         pr = synth.make_pair(k["w"], k["h"], k["max_disp"], k["scene"], seed=k["seed"])
         pool.append((torch.from_numpy(pr.left).to(dev), torch.from_numpy(pr.right).to(dev)))
     budget = 64 << 30
-    srv = Server(budget, slots=slots, streams=streams, max_group=max_group, max_group_cells=group_cells)
+    srv = Server(budget, slots=slots, streams=streams, max_group=max_group, max_group_cells=group_cells,
+                 overlap_queue=overlap_queue)
     ctxs = [SGM(w, h, d, synth.P1_DEFAULT, synth.P2_DEFAULT, 8, median=True, lrcheck=True) for (w, h, d) in kinds]
     st = torch.cuda.current_stream()
     outs = {k: [torch.empty((h, w), dtype=torch.uint16, device=dev) for _ in range(n_req)]
@@ -324,7 +327,7 @@ def bench_serve(dev, qps_levels, n_req: int, slots: int = 4, streams: int = 4, m
     for c in ctxs:
         c.close()
     return {"levels": levels, "budget_bytes": budget, "slots": slots, "streams": streams, "max_group": max_group,
-            "max_group_cells": group_cells,
+            "max_group_cells": group_cells, "overlap_queue": overlap_queue,
             "peak_bytes": stats["peak_bytes"],
             "mix": "Poisson arrivals; sizes from {640x480, 1242x375, 1280x720, 1920x1080}, D from {128, 256}, "
                    "8 paths, median + LR check; latency = submission to observed completion"}
@@ -351,6 +354,7 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--serve-max-group", type=int, default=8)
     ap.add_argument("--serve-group-cells", type=int, default=1 << 28)
+    ap.add_argument("--serve-overlap-queue", type=int, default=3)
     ap.add_argument("--latency-samples", type=int, default=300)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (a known-size "
@@ -532,11 +536,12 @@ def main():
     if not args.no_batch:
         print("bench: 64-pair batch vs sequential launches", file=sys.stderr, flush=True)
         line["batched"] = bench_batch(dev, args.batch_steps)
+        line["batched_median_lr"] = bench_batch(dev, args.batch_steps, post=True)
     if not args.no_serve:
         print("bench: served requests", file=sys.stderr, flush=True)
         line["served"] = bench_serve(dev, [float(q) for q in args.serve_qps.split(",")], args.serve_requests,
                                      args.serve_slots, args.serve_streams, args.serve_max_group,
-                                     args.serve_group_cells)
+                                     args.serve_group_cells, args.serve_overlap_queue)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(pair, cfg)

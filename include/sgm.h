@@ -218,12 +218,17 @@ typedef struct {
 sgm_server *sgm_server_create(size_t hbm_budget_bytes, int max_slots, int n_streams, int P1, int P2,
                               int census_w, int census_h);
 
-/* Group limits and queue length.  A group takes at most max_group requests
- * (default 8, at most 256) and, unless it holds a single request, at most
- * max_group_cells cells in total (W * H * max_disp * n_paths summed over its
- * requests; default 2^28): requests that fill the device alone run alone.
- * The queue accepts at most max_pending requests (default 4096). */
-int sgm_server_set_policy(sgm_server *s, int max_group, int max_pending, uint64_t max_group_cells);
+/* Group limits, queue length and overlap.  A group takes at most max_group
+ * requests (default 8, at most 256) and, unless it holds a single request,
+ * at most max_group_cells cells in total (W * H * max_disp * n_paths summed
+ * over its requests; default 2^28): requests that fill the device alone run
+ * alone.  The queue accepts at most max_pending requests (default 4096).
+ * While a group runs, a second one starts beside it only when at least
+ * overlap_queue requests are queued (default 3; 1 = whenever a slot is
+ * free): at light load a request waits for the running one rather than
+ * sharing the device with it. */
+int sgm_server_set_policy(sgm_server *s, int max_group, int max_pending, uint64_t max_group_cells,
+                          int overlap_queue);
 
 /* Workspace bytes a request takes from the budget (0 if invalid). */
 size_t sgm_server_request_bytes(sgm_server *s, const sgm_item *req);

@@ -125,6 +125,10 @@ struct sgm_server {
     int max_group = 8;
     size_t max_pending = 4096;
     uint64_t max_group_cells = uint64_t(1) << 28;
+    // while a group runs, another one starts beside it only if at least this
+    // many requests are queued: at light load a request then waits for the
+    // running one instead of sharing the device with it
+    int overlap_queue = 3;
     bool stop = false;
     std::atomic<uint64_t> wake{0};  // bumped by every submission and by shutdown
     sgm_server_stats stats{};
@@ -182,6 +186,7 @@ void scheduler(sgm_server* s) {
         for (Slot& slot : s->slots) {
             if (s->pending.empty()) break;
             if (!slot.group.empty()) continue;
+            if (any_busy && (int)s->pending.size() < s->overlap_queue) break;
             uint64_t cells = 0;
             while (!s->pending.empty() && (int)slot.group.size() < s->max_group) {
                 Request* r = s->pending.front();
@@ -347,13 +352,15 @@ sgm_server* sgm_server_create(size_t hbm_budget_bytes, int max_slots, int n_stre
     return s;
 }
 
-int sgm_server_set_policy(sgm_server* s, int max_group, int max_pending, uint64_t max_group_cells) {
+int sgm_server_set_policy(sgm_server* s, int max_group, int max_pending, uint64_t max_group_cells,
+                          int overlap_queue) {
     if (!s) return serr(SGM_EINVAL, "null server");
-    if (max_group < 1 || max_group > 256 || max_pending < 1) return serr(SGM_EINVAL, "bad policy");
+    if (max_group < 1 || max_group > 256 || max_pending < 1 || overlap_queue < 1) return serr(SGM_EINVAL, "bad policy");
     std::lock_guard<std::mutex> lk(s->mu);
     s->max_group = max_group;
     s->max_pending = (size_t)max_pending;
     s->max_group_cells = max_group_cells;
+    s->overlap_queue = overlap_queue;
     return SGM_OK;
 }
 

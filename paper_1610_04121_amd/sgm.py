@@ -104,7 +104,7 @@ def lib() -> ctypes.CDLL:
     L.sgm_compute_batch.restype = i
     L.sgm_server_create.argtypes = [ctypes.c_size_t, i, i, i, i, i, i]
     L.sgm_server_create.restype = P
-    L.sgm_server_set_policy.argtypes = [P, i, i, ctypes.c_uint64]
+    L.sgm_server_set_policy.argtypes = [P, i, i, ctypes.c_uint64, i]
     L.sgm_server_set_policy.restype = i
     L.sgm_server_request_bytes.argtypes = [P, ctypes.POINTER(Item)]
     L.sgm_server_request_bytes.restype = ctypes.c_size_t
@@ -357,17 +357,18 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int, slots: int = 4, streams: int | None = None, P1=7, P2=86,
                  census_w=9, census_h=7, max_group: int = 8, max_pending: int = 4096,
-                 max_group_cells: int = 1 << 28):
+                 max_group_cells: int = 1 << 28, overlap_queue: int = 3):
         """streams defaults to one per slot (groups run concurrently)."""
         streams = slots if streams is None else streams
         self._s = lib().sgm_server_create(hbm_budget_bytes, slots, streams, P1, P2, census_w, census_h)
         if not self._s:
             raise SGMError(SGM_EINVAL, last_error())
         self._held = {}
-        self.set_policy(max_group, max_pending, max_group_cells)
+        self.set_policy(max_group, max_pending, max_group_cells, overlap_queue)
 
-    def set_policy(self, max_group: int = 8, max_pending: int = 4096, max_group_cells: int = 1 << 28):
-        _check(lib().sgm_server_set_policy(self._s, max_group, max_pending, max_group_cells))
+    def set_policy(self, max_group: int = 8, max_pending: int = 4096, max_group_cells: int = 1 << 28,
+                   overlap_queue: int = 3):
+        _check(lib().sgm_server_set_policy(self._s, max_group, max_pending, max_group_cells, overlap_queue))
 
     def request_bytes(self, pair) -> int:
         return lib().sgm_server_request_bytes(self._s, _items([pair]))
