@@ -135,8 +135,9 @@ size_t sgm_footprint_bytes(int width, int height, int max_disp, int n_paths, uns
 
 /* ---- batches: many pairs of different shapes in one set of launches ----
  * One item is one stereo pair with its own size, disparity range, path count
- * and options (flags: SGM_MEDIAN3, SGM_LRCHECK; the census window and P1, P2
- * belong to the batch).  Buffers follow the conventions above. */
+ * and options (flags: SGM_MEDIAN3, SGM_LRCHECK, SGM_SUBPIXEL; the census
+ * window and P1, P2 belong to the batch).  Buffers follow the conventions
+ * above. */
 typedef struct {
     int width, height, max_disp, n_paths;
     unsigned flags;

@@ -39,7 +39,7 @@ struct BatchItem {
     void* lbuf;
     uint16_t* dl;
     uint16_t* dr;
-    int W, H, D, Dp, P, cmax, l16, median, lrcheck, thr, csct, gh;
+    int W, H, D, Dp, P, cmax, l16, median, lrcheck, thr, csct, gh, subpixel;
     int census_blk0, cost_blk0, wta_blk0, post_blk0;  // first block in each launch
 };
 
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(1024) void wta_batch_kernel(const BatchItem* items,
     const BatchItem& it = items[find_item<&BatchItem::wta_blk0>(items, n, b)];
     const bool post = it.median || it.lrcheck;
     WtaArgs a{it.lbuf, (size_t)it.W * it.H * it.Dp, post ? it.dl : it.out, it.lrcheck ? it.dr : nullptr,
-              it.W, it.H, it.D, it.Dp, it.P};
+              it.W, it.H, it.D, it.Dp, it.P, it.subpixel};
     if (it.l16)
         wta_row<uint16_t>(a, b - it.wta_blk0, wta_smem);
     else
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void post_batch_kernel(const BatchItem* items,
     extern __shared__ uint16_t post_smem[];
     const int b = blockIdx.x;
     const BatchItem& it = items[find_item<&BatchItem::post_blk0>(items, n, b)];
-    PostArgs a{it.dl, it.dr, it.out, it.W, it.H, it.median, it.lrcheck, it.thr};
+    PostArgs a{it.dl, it.dr, it.out, it.W, it.H, it.median, it.lrcheck, it.thr, it.subpixel};
     post_row(a, b - it.post_blk0, post_smem);
 }
 
@@ -183,9 +183,10 @@ bool batch_plan(const BatchParams& bp, const sgm_item* items, int n, BatchLayout
         p.csct = bp.csct;
         p.median = (it.flags & SGM_MEDIAN3) != 0;
         p.lrcheck = (it.flags & SGM_LRCHECK) != 0;
+        p.subpixel = (it.flags & SGM_SUBPIXEL) != 0;
         p.lr_thr = it.lr_threshold;
-        if (it.flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK)) {
-            *why = "item flags may only hold SGM_MEDIAN3 and SGM_LRCHECK";
+        if (it.flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK | SGM_SUBPIXEL)) {
+            *why = "item flags may only hold SGM_MEDIAN3, SGM_LRCHECK and SGM_SUBPIXEL";
             return false;
         }
         if (!plan_finish(p, why)) return false;
@@ -320,6 +321,7 @@ int batch_enqueue(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_b
         d.thr = p.lr_thr;
         d.csct = p.csct ? 1 : 0;
         d.gh = gh;
+        d.subpixel = p.subpixel ? 1 : 0;
         d.census_blk0 = (int)census_blocks;
         census_blocks += generic ? (size_t)2 * ((p.W + 15) / 16) * ((p.H + 15) / 16)
                                  : (size_t)2 * ((p.W + kCenTX - 1) / kCenTX) * ((p.H + kCenTY - 1) / kCenTY);

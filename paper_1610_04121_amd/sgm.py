@@ -309,11 +309,12 @@ class SGM:
 
 def _items(pairs):
     """pairs: dicts with left, right, out (device tensors), max_disp, n_paths and
-    optional median, lrcheck, lr_threshold."""
+    optional median, lrcheck, subpixel, lr_threshold."""
     arr = (Item * len(pairs))()
     for k, p in enumerate(pairs):
         h, w = p["left"].shape
-        flags = (MEDIAN3 if p.get("median") else 0) | (LRCHECK if p.get("lrcheck") else 0)
+        flags = (MEDIAN3 if p.get("median") else 0) | (LRCHECK if p.get("lrcheck") else 0) | \
+            (SUBPIXEL if p.get("subpixel") else 0)
         arr[k] = Item(w, h, p["max_disp"], p["n_paths"], flags, p.get("lr_threshold", 1),
                       _ptr(p["left"], "torch.uint8", (h, w)), _ptr(p["right"], "torch.uint8", (h, w)),
                       _ptr(p["out"], "torch.uint16", (h, w)))

@@ -129,3 +129,21 @@ def test_batch_rejects_invalid_items(gpu):
     with pytest.raises(SGMError):
         b.compute([pairs[0], bad])
     b.close()
+
+
+def test_batch_subpixel_items(gpu):
+    """Pairs with 1/16-pixel output beside integer ones in one batch."""
+    import torch
+    specs = [(64, 48, 40, 4, True, True), (97, 31, 64, 8, False, False), (40, 70, 130, 2, True, False)]
+    pairs = _pairs(specs, gpu, 1300)
+    for k, p in enumerate(pairs):
+        p["subpixel"] = k != 1
+    _say("batch with sub-pixel items")
+    b = Batch(7, 86)
+    b.compute(pairs)
+    torch.cuda.synchronize()
+    for k, p in enumerate(pairs):
+        want = oracle.sgm(p["np_left"], p["np_right"], p["max_disp"], 7, 86, p["n_paths"],
+                          median=p["median"], lr=p["lrcheck"], subpixel=p["subpixel"]).out
+        assert (p["out"].cpu().numpy() == want).all(), k
+    b.close()

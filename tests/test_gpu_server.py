@@ -33,7 +33,8 @@ def _alone(req):
     """The same pair through a single-pair context, on its own."""
     import torch
     h, w = req["left"].shape
-    c = SGM(w, h, req["max_disp"], 7, 86, req["n_paths"], median=req["median"], lrcheck=req["lrcheck"])
+    c = SGM(w, h, req["max_disp"], 7, 86, req["n_paths"], median=req["median"], lrcheck=req["lrcheck"],
+            subpixel=req.get("subpixel", False))
     out = c.compute(req["left"], req["right"])
     torch.cuda.synchronize()
     res = out.cpu().numpy()
@@ -51,6 +52,7 @@ def test_mixed_concurrent_requests_match_alone(gpu, slots, streams):
         w, h = shapes[k % len(shapes)]
         reqs.append(_req(gpu, w, h, int(rng.choice([16, 64, 128, 200])), int(rng.choice([2, 4, 8])),
                          bool(rng.integers(0, 2)), bool(rng.integers(0, 2)), 1000 + k))
+        reqs[-1]["subpixel"] = k % 3 == 0
     srv = Server(8 << 30, slots=slots, streams=streams, max_group=4, max_group_cells=1 << 40)
     tickets = [None] * len(reqs)
 
@@ -79,7 +81,7 @@ def test_mixed_concurrent_requests_match_alone(gpu, slots, streams):
     for i in (0, 3, 7):  # small ones against the oracle as well
         r = reqs[i]
         want = oracle.sgm(r["np_left"], r["np_right"], r["max_disp"], 7, 86, r["n_paths"],
-                          median=r["median"], lr=r["lrcheck"]).out
+                          median=r["median"], lr=r["lrcheck"], subpixel=r["subpixel"]).out
         assert (reqs[i]["out"].cpu().numpy() == want).all(), i
 
 
