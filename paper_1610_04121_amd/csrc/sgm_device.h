@@ -242,9 +242,10 @@ __device__ inline void cost_block(const CostArgs& a, int bx, int y, uint64_t* cw
     }
     __syncthreads();
     const int npx = min(kCostTX, a.W - x0);
+    const int lg = Dp == 64 ? 2 : (Dp == 128 ? 3 : 4);  // log2(nchunks)
     uint8_t* dst = a.cost + ((size_t)y * a.W + x0) * Dp;
     for (int c = threadIdx.x; c < npx * nchunks; c += blockDim.x) {
-        const int px = c / nchunks, k = c - px * nchunks;
+        const int px = c >> lg, k = c & (nchunks - 1);
         *reinterpret_cast<uint4*>(dst + 16 * c) = *reinterpret_cast<const uint4*>(tile + px * tpitch + 16 * k);
     }
 }
