@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sgm_oracle.c")
 _LIB = os.path.join(_HERE, "libsgm_oracle.so")
 
-MEDIAN, LRCHECK, CSCT, LRFULL, SUBPIXEL = 1, 2, 4, 8, 16
+MEDIAN, LRCHECK, CSCT, LRFULL, SUBPIXEL, ADAPTIVE = 1, 2, 4, 8, 16, 32
 OK, EINVAL, ENOMEM, EBOUND = 0, -1, -2, -3
 
 
@@ -51,6 +51,7 @@ def lib():
         L.oracle_cost_volume.argtypes = [P, P, i, i, i, i, P]
         L.oracle_cost_volume_right.argtypes = [P, P, i, i, i, i, P]
         L.oracle_aggregate.argtypes = [P, i, i, i, i, i, i, i, P, P]
+        L.oracle_aggregate_img.argtypes = [P, P, i, i, i, i, i, i, i, P, P]
         L.oracle_direction.argtypes = [i, i, P, P]
         L.oracle_wta_left.argtypes = [P, i, i, i, P]
         L.oracle_wta_right.argtypes = [P, i, i, i, P]
@@ -60,7 +61,7 @@ def lib():
         L.oracle_subpixel.argtypes = [P, P, i, i, i, P]
         L.oracle_sgm.argtypes = [P, P, i, i, i, i, i, i, i, i, ctypes.c_uint, i, P, P, P, P, P, P]
         for f in ("oracle_census_full", "oracle_census_csct", "oracle_cost_volume", "oracle_cost_volume_right",
-                  "oracle_aggregate", "oracle_direction", "oracle_sgm"):
+                  "oracle_aggregate", "oracle_aggregate_img", "oracle_direction", "oracle_sgm"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -114,12 +115,19 @@ def cost_volume_right(cright, cleft, D, cmax) -> np.ndarray:
     return mc
 
 
-def aggregate(mc, P1, P2, rx, ry, check_bound=True) -> np.ndarray:
-    """L_r[H][W][D] (int32) of one direction from a cost volume [H][W][D]."""
+def aggregate(mc, P1, P2, rx, ry, check_bound=True, img=None) -> np.ndarray:
+    """L_r[H][W][D] (int32) of one direction from a cost volume [H][W][D];
+    with img (u8 [H][W], the base image) the P2 of each step adapts to the
+    intensity change along the path."""
     mc = np.ascontiguousarray(mc, dtype=np.uint8)
     H, W, D = mc.shape
     out = np.zeros((H, W, D), dtype=np.int32)
-    rc = lib().oracle_aggregate(_p(mc), W, H, D, P1, P2, rx, ry, _p(out), None)
+    if img is None:
+        rc = lib().oracle_aggregate(_p(mc), W, H, D, P1, P2, rx, ry, _p(out), None)
+    else:
+        img = _u8(img)
+        assert img.shape == (H, W)
+        rc = lib().oracle_aggregate_img(_p(mc), _p(img), W, H, D, P1, P2, rx, ry, _p(out), None)
     if rc == EBOUND and not check_bound:
         rc = OK
     if rc:
@@ -198,7 +206,7 @@ class Result:
 
 
 def sgm(left, right, max_disp, P1=7, P2=86, n_paths=4, cw=9, ch=7, median=False, lr=False,
-        csct=False, lr_thr=1, keep_sums=False, lr_full=False, subpixel=False) -> Result:
+        csct=False, lr_thr=1, keep_sums=False, lr_full=False, subpixel=False, adaptive=False) -> Result:
     """Whole pipeline for one pair; returns out, dl_raw, dr_raw, census_l/r
     and (when keep_sums) the summed costs S[H][W][D].  lr_full: the right
     disparity comes from a second SGM with the right image as base."""
@@ -212,7 +220,7 @@ def sgm(left, right, max_disp, P1=7, P2=86, n_paths=4, cw=9, ch=7, median=False,
     cr = np.zeros((H, W), dtype=np.uint64)
     S = np.zeros((H, W, max_disp), dtype=np.uint32) if keep_sums else None
     flags = (MEDIAN if median else 0) | (LRCHECK if lr else 0) | (CSCT if csct else 0) | \
-        (LRFULL if lr_full else 0) | (SUBPIXEL if subpixel else 0)
+        (LRFULL if lr_full else 0) | (SUBPIXEL if subpixel else 0) | (ADAPTIVE if adaptive else 0)
     rc = lib().oracle_sgm(_p(left), _p(right), W, H, max_disp, P1, P2, n_paths, cw, ch, flags,
                           lr_thr, _p(out), _p(cl), _p(cr), _p(S), _p(dl), _p(dr))
     if rc:

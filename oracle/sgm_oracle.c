@@ -143,8 +143,13 @@ int oracle_cost_volume_right(const uint64_t *cright, const uint64_t *cleft, int 
     return ORC_OK;
 }
 
-int oracle_aggregate(const uint8_t *mc, int W, int H, int D, int P1, int P2, int rx, int ry,
-                     int32_t *lr_out, uint32_t *sum)
+/* Eq. 3 along direction r.  With img == NULL the penalty P2 is the constant
+ * of Eq. 3.  With the base image img, the P2 of a step from p - r to p is
+ * max(P1, floor(P2 / (1 + |I(p) - I(p - r)|))): smaller across intensity
+ * edges (a reading of the adaptive P2 the paper lists as later work,
+ * Sec. 5). */
+int oracle_aggregate_img(const uint8_t *mc, const uint8_t *img, int W, int H, int D, int P1, int P2,
+                         int rx, int ry, int32_t *lr_out, uint32_t *sum)
 {
     if (W < 1 || H < 1 || D < 1 || P1 < 0 || P2 < 0) return ORC_EINVAL;
     if (rx < -1 || rx > 1 || ry < -1 || ry > 1 || (rx == 0 && ry == 0)) return ORC_EINVAL;
@@ -167,16 +172,22 @@ int oracle_aggregate(const uint8_t *mc, int W, int H, int D, int P1, int P2, int
                 const int32_t *lp = (ry == 0 ? cur : prev) + (size_t)px * D;
                 int32_t m = lp[0];
                 for (int k = 1; k < D; k++) if (lp[k] < m) m = lp[k];
+                int p2 = P2;
+                if (img) {
+                    int g = abs((int)img[(size_t)y * W + x] - (int)img[(size_t)py * W + px]);
+                    p2 = P2 / (1 + g);
+                    if (p2 < P1) p2 = P1;
+                }
                 for (int d = 0; d < D; d++) {
                     int32_t best = lp[d];
                     if (d >= 1 && lp[d - 1] + P1 < best) best = lp[d - 1] + P1;
                     if (d <= D - 2 && lp[d + 1] + P1 < best) best = lp[d + 1] + P1;
-                    if (m + P2 < best) best = m + P2;
+                    if (m + p2 < best) best = m + p2;
                     l[d] = c[d] + best - m;
                 }
             }
             for (int d = 0; d < D; d++) {
-                if (l[d] < c[d] || l[d] > c[d] + P2) rc = ORC_EBOUND;
+                if (l[d] < c[d] || l[d] > c[d] + (P1 > P2 ? P1 : P2)) rc = ORC_EBOUND;
                 if (lr_out) lr_out[((size_t)y * W + x) * D + d] = l[d];
                 if (sum) sum[((size_t)y * W + x) * D + d] += (uint32_t)l[d];
             }
@@ -186,6 +197,12 @@ int oracle_aggregate(const uint8_t *mc, int W, int H, int D, int P1, int P2, int
     free(prev);
     free(cur);
     return rc;
+}
+
+int oracle_aggregate(const uint8_t *mc, int W, int H, int D, int P1, int P2, int rx, int ry,
+                     int32_t *lr_out, uint32_t *sum)
+{
+    return oracle_aggregate_img(mc, NULL, W, H, D, P1, P2, rx, ry, lr_out, sum);
 }
 
 /* The path directions: 2 paths = left-to-right and top-to-bottom (Sec. 4);
@@ -322,6 +339,7 @@ void oracle_lr_check(const uint16_t *dl, const uint16_t *dr, int W, int H, int t
 #define ORC_CSCT 4u
 #define ORC_LRFULL 8u /* D_R from a second SGM with the right image as base */
 #define ORC_SUBPIXEL 16u /* left disparities in 1/16 pixel (oracle_subpixel) */
+#define ORC_ADAPTIVE 32u /* P2 of each step from the base image's gradient */
 
 /* The whole pipeline for one pair.  Optional outputs (NULL to skip):
  * census_l/census_r [H][W] u64, S [H][W][D] u32, dl_raw/dr_raw [H][W]. */
@@ -354,7 +372,7 @@ int oracle_sgm(const uint8_t *left, const uint8_t *right, int W, int H, int D, i
     for (int r = 0; r < n_paths; r++) {
         int rx, ry;
         oracle_direction(n_paths, r, &rx, &ry);
-        int a = oracle_aggregate(mc, W, H, D, P1, P2, rx, ry, NULL, S);
+        int a = oracle_aggregate_img(mc, (flags & ORC_ADAPTIVE) ? left : NULL, W, H, D, P1, P2, rx, ry, NULL, S);
         if (a) { rc = a; goto done; }
     }
     for (size_t i = 0; i < ncell; i++)
@@ -371,7 +389,7 @@ int oracle_sgm(const uint8_t *left, const uint8_t *right, int W, int H, int D, i
         for (int r = 0; r < n_paths && !rc; r++) {
             int rx, ry;
             oracle_direction(n_paths, r, &rx, &ry);
-            rc = oracle_aggregate(mc, W, H, D, P1, P2, rx, ry, NULL, SR);
+            rc = oracle_aggregate_img(mc, (flags & ORC_ADAPTIVE) ? right : NULL, W, H, D, P1, P2, rx, ry, NULL, SR);
         }
         for (size_t i = 0; i < ncell && !rc; i++)
             if (SR[i] > 65535u) rc = ORC_EBOUND;

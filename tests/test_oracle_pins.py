@@ -499,3 +499,60 @@ def test_subpixel_in_the_pipeline():
     di = ((q + 8) >> 4).astype(np.uint16)
     ok = oracle.lr_check(di, sp.dr_raw) != 0xFFFF
     assert (sp.out[ok] == sp.dl_raw[ok]).all() and (sp.out[~ok] == 0xFFFF).all()
+
+
+# --------------------------------------------------------------------------
+# Adaptive P2 (later work in Sec. 5; the oracle header's reading): the P2 of
+# the step p - r -> p is max(P1, floor(P2 / (1 + |I(p) - I(p - r)|))).
+# --------------------------------------------------------------------------
+def _brute_path_steps(costs, P1, p2s):
+    """As _brute_path with the P2 of step i (from i-1 to i) = p2s[i]."""
+    n1, D = costs.shape
+    out = np.zeros_like(costs, dtype=np.int64)
+    prevE = None
+    for n in range(n1):
+        E = np.full(D, 1 << 60, dtype=np.int64)
+        for seq in itertools.product(range(D), repeat=n + 1):
+            e = sum(int(costs[i, seq[i]]) for i in range(n + 1))
+            e += sum(_V(seq[i - 1], seq[i], P1, p2s[i]) for i in range(1, n + 1))
+            E[seq[-1]] = min(E[seq[-1]], e)
+        out[n] = E if prevE is None else E - prevE.min()
+        prevE = E
+    return out
+
+
+@pytest.mark.parametrize("trial", range(6))
+def test_adaptive_p2_matches_brute_force_with_per_step_penalties(trial):
+    """Eq. 3 with a P2 that changes from step to step is still the minimum
+    path energy (the induction never uses a constant P2); the intensities of a
+    random row give the per-step P2 of the definition."""
+    rng = np.random.default_rng(700 + trial)
+    D = int(rng.integers(1, 5))
+    n1 = int(rng.integers(2, 7))
+    P1 = int(rng.integers(0, 8))
+    P2 = int(rng.integers(P1, 60))
+    costs = rng.integers(0, 20, (n1, D)).astype(np.uint8)
+    row = rng.integers(0, 256, n1).astype(np.uint8)
+    row[: n1 // 2] = row[0]  # some flat steps (full P2), some edges
+    p2s = [0] + [max(P1, P2 // (1 + abs(int(row[i]) - int(row[i - 1])))) for i in range(1, n1)]
+    want = _brute_path_steps(costs, P1, p2s)
+    got = oracle.aggregate(costs[None, :, :], P1, P2, 1, 0, img=row[None, :])[0]
+    assert (got == want).all()
+    # the same path right to left: the step i -> i-1 uses |I(i-1) - I(i)|
+    got = oracle.aggregate(costs[None, ::-1, :], P1, P2, -1, 0, img=row[None, ::-1])[0, ::-1]
+    assert (got == want).all()
+    # and down a column
+    got = oracle.aggregate(costs[:, None, :], P1, P2, 0, 1, img=row[:, None])[:, 0]
+    assert (got == want).all()
+
+
+def test_adaptive_p2_on_a_flat_image_is_plain_sgm():
+    pair = synth.make_pair(70, 40, 24, "RS", seed=5)
+    flat = np.full_like(pair.left, 90)
+    mc = oracle.cost_volume(oracle.census(pair.left), oracle.census(pair.right), 24, 62)
+    for rx, ry in oracle.directions(8):
+        assert (oracle.aggregate(mc, 7, 86, rx, ry, img=flat) == oracle.aggregate(mc, 7, 86, rx, ry)).all()
+    # the pipeline flag uses the base images
+    a = oracle.sgm(pair.left, pair.right, 24, 7, 86, 4, adaptive=True, keep_sums=True)
+    S = sum(oracle.aggregate(mc, 7, 86, rx, ry, img=pair.left) for rx, ry in oracle.directions(4))
+    assert (a.S == S).all()
