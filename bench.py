@@ -523,6 +523,7 @@ def main():
         line["paths_sweep"] = bench_paths(left, right, cfg, max(200, args.steps // 4))
         line["lr_full"] = bench_variant(left, right, cfg, choice, max(200, args.steps // 4), lr_full=True)
         line["subpixel"] = bench_variant(left, right, cfg, choice, max(200, args.steps // 4), subpixel=True)
+        line["adaptive_p2"] = bench_variant(left, right, cfg, choice, max(200, args.steps // 4), adaptive_p2=True)
     for c in ctxs:
         c.close()
     if args.copy_calibration_mb:

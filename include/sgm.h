@@ -65,7 +65,7 @@ enum {
                              the diagonal minimum of the left SGM's sums.
                              Twice the cost and aggregation work; the
                              workspace grows (sgm_set_options may allocate). */
-    SGM_SUBPIXEL = 32u    /* left disparities in 1/16 pixel: q = 16 d + f at
+    SGM_SUBPIXEL = 32u,   /* left disparities in 1/16 pixel: q = 16 d + f at
                              the winner d, f = floor((16 (a - c) + den) /
                              (2 den)) with a, b, c = S(d-1), S(d), S(d+1) and
                              den = a + c - 2b (the parabola vertex rounded
@@ -73,6 +73,11 @@ enum {
                              the median runs on q and the left-right check on
                              (q + 8) >> 4; the output holds q (0xFFFF still
                              marks a failed check) */
+    SGM_ADAPTIVE_P2 = 64u /* the P2 of each aggregation step from p - r to p
+                             is max(P1, floor(P2 / (1 + |I(p) - I(p - r)|)))
+                             on the SGM's base image: smaller across
+                             intensity edges (uses the cost-volume
+                             aggregation) */
 };
 
 /* Checks a parameter set without touching the GPU.  Returns SGM_OK or

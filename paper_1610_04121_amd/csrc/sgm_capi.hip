@@ -46,9 +46,11 @@ bool make_plan(sgm::Plan& p, int w, int h, int d, int P1, int P2, int n_paths, i
     p.lrcheck = (flags & SGM_LRCHECK) != 0;
     p.lr_full = (flags & SGM_LR_FULL) != 0;
     p.subpixel = (flags & SGM_SUBPIXEL) != 0;
+    p.adaptive = (flags & SGM_ADAPTIVE_P2) != 0;
     p.lr_thr = thr;
     const char* why = "invalid parameters";
-    if (flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK | SGM_CENSUS_CSCT | SGM_GRAPH | SGM_LR_FULL | SGM_SUBPIXEL)) {
+    if (flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK | SGM_CENSUS_CSCT | SGM_GRAPH | SGM_LR_FULL | SGM_SUBPIXEL |
+                            SGM_ADAPTIVE_P2)) {
         set_err(SGM_EINVAL, "unknown flag bits");
         return false;
     }
@@ -334,8 +336,8 @@ int sgm_debug_sums(sgm_ctx* c, const uint8_t* left, const uint8_t* right, uint16
     if (!c) return set_err(SGM_EINVAL, "null context");
     if (int rc = check_ptrs(left, right, s_out)) return rc;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = sgm::launch_matching_cost(c->plan, c->ws, left, right, !c->plan.fused, s);
-    if (e == hipSuccess) e = sgm::launch_aggregate(c->plan, c->ws, s);
+    hipError_t e = sgm::launch_matching_cost(c->plan, c->ws, left, right, !sgm::fused_aggregation(c->plan), s);
+    if (e == hipSuccess) e = sgm::launch_aggregate(c->plan, c->ws, s, left, right);
     if (e == hipSuccess) e = sgm::launch_sum_planes(c->plan, c->ws, s_out, s);
     if (e != hipSuccess) return hip_err(e, "kernel launch");
     return SGM_OK;
@@ -348,8 +350,9 @@ int sgm_debug_stage(sgm_ctx* c, const uint8_t* left, const uint8_t* right, int w
     const int nplanes = c->plan.n_paths * (c->plan.lr_full ? 2 : 1);
     if (which < (c->plan.lr_full ? -2 : -1) || which >= nplanes) return set_err(SGM_EINVAL, "stage index out of range");
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = sgm::launch_matching_cost(c->plan, c->ws, left, right, which < 0 || !c->plan.fused, s);
-    if (e == hipSuccess && which >= 0) e = sgm::launch_aggregate(c->plan, c->ws, s);
+    hipError_t e =
+        sgm::launch_matching_cost(c->plan, c->ws, left, right, which < 0 || !sgm::fused_aggregation(c->plan), s);
+    if (e == hipSuccess && which >= 0) e = sgm::launch_aggregate(c->plan, c->ws, s, left, right);
     if (e == hipSuccess) e = sgm::launch_extract_plane(c->plan, c->ws, which, out, s);
     if (e != hipSuccess) return hip_err(e, "kernel launch");
     return SGM_OK;
@@ -364,8 +367,8 @@ int sgm_debug_raw_disparity(sgm_ctx* c, const uint8_t* left, const uint8_t* righ
     p.lrcheck = true;   // produce the right view too
     p.median = false;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = sgm::launch_matching_cost(p, c->ws, left, right, !p.fused, s);
-    if (e == hipSuccess) e = sgm::launch_aggregate(p, c->ws, s);
+    hipError_t e = sgm::launch_matching_cost(p, c->ws, left, right, !sgm::fused_aggregation(p), s);
+    if (e == hipSuccess) e = sgm::launch_aggregate(p, c->ws, s, left, right);
     if (e == hipSuccess) e = sgm::launch_wta(p, c->ws, nullptr, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dl_out, c->ws.dl, (size_t)p.W * p.H * 2, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dr_out, c->ws.dr, (size_t)p.W * p.H * 2, hipMemcpyDeviceToDevice, s);

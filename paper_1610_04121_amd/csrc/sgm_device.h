@@ -435,7 +435,22 @@ struct SliceArgs {
     void* lplane;              // this direction's L_r plane [H][W][Dp]
     uint32_t plane;            // elements per plane = H * W * Dp
     int W, H, D, P1, P2, cmax, rx, ry;
+    const uint8_t* img = nullptr;  // base image u8 [H][W] (adaptive P2)
 };
+
+// Adaptive P2 of one step: max(P1, floor(P2 / (1 + g))) for an intensity
+// change g in [0, 255].  The quotient comes from the hardware reciprocal,
+// whose error is far below 1 for P2 < 2^24, and one correction either way
+// makes it exact.
+__device__ inline uint32_t adaptive_p2(uint32_t P1, uint32_t P2, uint32_t g) {
+    const uint32_t d = 1u + g;
+    uint32_t q = (uint32_t)((float)P2 * __builtin_amdgcn_rcpf((float)d));
+    if (q * d > P2)
+        q -= 1u;
+    else if ((q + 1u) * d <= P2)
+        q += 1u;
+    return q > P1 ? q : P1;
+}
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ inline u16x2 as2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
@@ -680,10 +695,14 @@ __device__ inline uint32_t pack_selector(int k, int d0, int D) {
 template <int CPL> struct Prefetch { static constexpr int N = CPL >= 16 ? 8 : 16; };
 template <int CPL> struct FusedPrefetch { static constexpr int N = CPL >= 16 ? 2 : 4; };
 
-template <int G, int CPL, typename LT, int KIND, bool FUSED>
+// ADAPT: the P2 of each step adapts to the base image's intensity change
+// along the path (adaptive_p2); the intensities are prefetched with the costs.
+template <int G, int CPL, typename LT, int KIND, bool FUSED, bool ADAPT = false>
 __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int lane) {
+    static_assert(!(FUSED && ADAPT), "adaptive P2 uses the cost-volume variant");
     constexpr int NP = CPL / 2;
     constexpr int Dp = G * CPL;
+    constexpr int kDpShift = Dp == 64 ? 6 : (Dp == 128 ? 7 : 8);
     constexpr int PF = FUSED ? FusedPrefetch<CPL>::N : Prefetch<CPL>::N;
     // per-step input: raw cost bytes, or census words (fused variant)
     using RawT = std::conditional_t<FUSED, CensusStep<CPL>, typename Raw<CPL>::T>;
@@ -713,6 +732,7 @@ __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int l
     const __amdgpu_buffer_rsrc_t rcr =
         buffer_rsrc(a.census_r - kCensusGuard, FUSED ? census_bytes + 8u * kCensusGuard : 0u);
     const __amdgpu_buffer_rsrc_t rl = buffer_rsrc(a.lplane, plane_bytes * (uint32_t)sizeof(LT));
+    const __amdgpu_buffer_rsrc_t rim = buffer_rsrc(a.img, ADAPT ? (uint32_t)W * (uint32_t)H : 0u);
 
     // Group 0's position: byte offset `bo` of its pixel in a u8 [H][W][Dp]
     // plane and, for diagonal slices, its column xc (kept in [0, W)).
@@ -758,7 +778,8 @@ __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int l
     // smallest column any group of the wavefront is at (uniform): when it is
     // >= Dp - 1, every lane's disparities are valid (x - d >= 0)
     int xmin_all = 0;
-    auto step = [&](const RawT& raw) {
+    uint32_t iprev = 0;  // intensity of the previous pixel on the path (ADAPT)
+    auto step = [&](const RawT& raw, uint32_t iv) {
         if constexpr (FUSED) {
             if constexpr (KIND == kHoriz)
                 xmin_all = xc;
@@ -802,7 +823,14 @@ __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int l
         const uint32_t next = from_upper<G>(as1(lp[0])) | edge_hi;
         const u16x2 lo0 = as2(__builtin_amdgcn_alignbit(as1(lp[NP - 1]), prev, 16));
         const u16x2 hiN = as2(__builtin_amdgcn_alignbit(next, as1(lp[0]), 16));
-        const u16x2 mp2 = vadds(mm, P2v);
+        u16x2 p2v = P2v;
+        if constexpr (ADAPT) {
+            // at a path start L and mm are 0, so this step's P2 does not matter
+            const uint32_t g = iv > iprev ? iv - iprev : iprev - iv;
+            iprev = iv;
+            p2v = as2(adaptive_p2((uint32_t)a.P1, (uint32_t)a.P2, g) * 0x10001u);
+        }
+        const u16x2 mp2 = vadds(mm, p2v);
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             const u16x2 lo = k == 0 ? lo0 : lp[k - 1];
@@ -841,26 +869,38 @@ __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int l
             return buffer_load_raw<CPL>(rc, lane_ofs(b, x));
         }
     };
+    // intensity of the lane's group pixel (ADAPT): pixel index = (byte
+    // offset - qofs) / Dp; past the image the range check returns 0
+    auto load_i = [&](int b, int x) -> uint32_t {
+        if constexpr (ADAPT)
+            return __builtin_amdgcn_raw_buffer_load_b8(rim, (lane_ofs(b, x) - (uint32_t)qofs) >> kDpShift, 0, 0);
+        else
+            return 0u;
+    };
     RawT ring[PF];
+    uint32_t iring[ADAPT ? PF : 1];
     int ba = bo, xa = xc;
 #pragma unroll
     for (int j = 0; j < PF; ++j) {
         if (j) advance(ba, xa);
         ring[j] = load(ba, xa);
+        if constexpr (ADAPT) iring[j] = load_i(ba, xa);
     }
     int k = 0;
     for (; k + PF <= steps; k += PF) {
 #pragma unroll
         for (int j = 0; j < PF; ++j) {
             const RawT raw = ring[j];
+            const uint32_t iv = ADAPT ? iring[ADAPT ? j : 0] : 0u;
             advance(ba, xa);
             ring[j] = load(ba, xa);
-            step(raw);
+            if constexpr (ADAPT) iring[j] = load_i(ba, xa);
+            step(raw, iv);
         }
     }
 #pragma unroll
     for (int j = 0; j < PF; ++j)
-        if (k + j < steps) step(ring[j]);
+        if (k + j < steps) step(ring[j], ADAPT ? iring[ADAPT ? j : 0] : 0u);
 }
 
 // ---------------------------------------------------------------------------

@@ -41,12 +41,13 @@ struct AggArgs {
     int start[kMaxLaunchDirs + 1];  // first wave of each direction
     int rx[kMaxLaunchDirs], ry[kMaxLaunchDirs], plane_index[kMaxLaunchDirs];
     const uint8_t* cost[kMaxLaunchDirs];  // the cost volume each direction reads
+    const uint8_t* img[kMaxLaunchDirs];   // its SGM's base image (adaptive P2)
 };
 
 // One launch covers every direction.  Horizontal slices (the longest when
 // W > H) may use a different group width GH than the others (GV), so that
 // the longest dependency chains get the fewest instructions per step.
-template <int GH, int GV, int Dp, typename LT, bool FUSED>
+template <int GH, int GV, int Dp, typename LT, bool FUSED, bool ADAPT>
 __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
@@ -57,13 +58,14 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
     s.rx = a.rx[r];
     s.ry = a.ry[r];
     s.cost = a.cost[r];
+    s.img = a.img[r];
     s.lplane = reinterpret_cast<LT*>(a.lbuf) + (size_t)s.plane * a.plane_index[r];
     if (s.ry == 0) {
-        aggregate_wave<GH, Dp / GH, LT, kHoriz, FUSED>(s, (wave - a.start[r]) * (64 / GH), lane);
+        aggregate_wave<GH, Dp / GH, LT, kHoriz, FUSED, ADAPT>(s, (wave - a.start[r]) * (64 / GH), lane);
     } else if (s.rx == 0) {
-        aggregate_wave<GV, Dp / GV, LT, kVert, FUSED>(s, (wave - a.start[r]) * (64 / GV), lane);
+        aggregate_wave<GV, Dp / GV, LT, kVert, FUSED, ADAPT>(s, (wave - a.start[r]) * (64 / GV), lane);
     } else {
-        aggregate_wave<GV, Dp / GV, LT, kDiag, FUSED>(s, (wave - a.start[r]) * (64 / GV), lane);
+        aggregate_wave<GV, Dp / GV, LT, kDiag, FUSED, ADAPT>(s, (wave - a.start[r]) * (64 / GV), lane);
     }
 }
 
@@ -215,7 +217,8 @@ hipError_t launch_matching_cost(const Plan& p, const Workspace& ws, const uint8_
     }
     // census words in global memory: for the fused aggregation, and for the
     // cost kernel of windows other than 9x7
-    if (e == hipSuccess && (p.fused || (need_cost && !fusable))) e = launch_census(p, ws, left, right, stream);
+    if (e == hipSuccess && (fused_aggregation(p) || (need_cost && !fusable)))
+        e = launch_census(p, ws, left, right, stream);
     if (e == hipSuccess && need_cost && !fusable) e = launch_cost(p, ws, stream);
     return e;
 }
@@ -235,7 +238,8 @@ hipError_t launch_cost(const Plan& p, const Workspace& ws, hipStream_t stream, b
     return hipGetLastError();
 }
 
-static void fill_agg_args(const Plan& p, const Workspace& ws, int SH, int SV, AggArgs& a) {
+static void fill_agg_args(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right, int SH,
+                          int SV, AggArgs& a) {
     a.base = SliceArgs{ws.cost, ws.census_l, ws.census_r, nullptr, (uint32_t)((size_t)p.W * p.H * p.Dp),
                        p.W, p.H, p.D, p.P1, p.P2, p.cmax, 0, 0};
     a.lbuf = ws.lbuf;
@@ -259,6 +263,7 @@ static void fill_agg_args(const Plan& p, const Workspace& ws, int SH, int SV, Ag
         a.ry[k] = d.ry;
         a.plane_index[k] = order[k];
         a.cost[k] = order[k] < p.n_paths ? ws.cost : ws.cost_r;
+        a.img[k] = order[k] < p.n_paths ? left : right;
         a.start[k] = acc;
         acc += (slice_count(p.W, p.H, d) + S - 1) / S;
     }
@@ -266,37 +271,43 @@ static void fill_agg_args(const Plan& p, const Workspace& ws, int SH, int SV, Ag
     a.total = acc;
 }
 
-template <int GH, int GV, int Dp, typename LT, bool FUSED>
-static hipError_t launch_agg_t(const Plan& p, const Workspace& ws, hipStream_t stream) {
+// Images of the two SGMs (base left / base right) for the adaptive P2.
+struct Images {
+    const uint8_t *left, *right;
+};
+
+template <int GH, int GV, int Dp, typename LT, bool FUSED, bool ADAPT>
+static hipError_t launch_agg_t(const Plan& p, const Workspace& ws, Images im, hipStream_t stream) {
     AggArgs a;
-    fill_agg_args(p, ws, 64 / GH, 64 / GV, a);
-    hipLaunchKernelGGL((aggregate_kernel<GH, GV, Dp, LT, FUSED>), dim3((a.total + 3) / 4), dim3(256), 0, stream, a);
+    fill_agg_args(p, ws, im.left, im.right, 64 / GH, 64 / GV, a);
+    hipLaunchKernelGGL((aggregate_kernel<GH, GV, Dp, LT, FUSED, ADAPT>), dim3((a.total + 3) / 4), dim3(256), 0,
+                       stream, a);
     return hipGetLastError();
 }
 
-template <int Dp, typename LT, bool FUSED>
-static hipError_t launch_agg_dp(const Plan& p, const Workspace& ws, int gh, int gv, hipStream_t stream) {
+template <int Dp, typename LT, bool FUSED, bool ADAPT>
+static hipError_t launch_agg_dp(const Plan& p, const Workspace& ws, Images im, int gh, int gv, hipStream_t stream) {
     switch (gh * 100 + gv) {
-        case 1616: return launch_agg_t<16, 16, Dp, LT, FUSED>(p, ws, stream);
-        case 3216: return launch_agg_t<32, 16, Dp, LT, FUSED>(p, ws, stream);
-        case 3232: return launch_agg_t<32, 32, Dp, LT, FUSED>(p, ws, stream);
+        case 1616: return launch_agg_t<16, 16, Dp, LT, FUSED, ADAPT>(p, ws, im, stream);
+        case 3216: return launch_agg_t<32, 16, Dp, LT, FUSED, ADAPT>(p, ws, im, stream);
+        case 3232: return launch_agg_t<32, 32, Dp, LT, FUSED, ADAPT>(p, ws, im, stream);
         default: break;
     }
     if constexpr (Dp >= 128) {  // 64 lanes need at least 2 levels per lane
-        if (gh == 64 && gv == 16) return launch_agg_t<64, 16, Dp, LT, FUSED>(p, ws, stream);
-        if (gh == 64 && gv == 32) return launch_agg_t<64, 32, Dp, LT, FUSED>(p, ws, stream);
+        if (gh == 64 && gv == 16) return launch_agg_t<64, 16, Dp, LT, FUSED, ADAPT>(p, ws, im, stream);
+        if (gh == 64 && gv == 32) return launch_agg_t<64, 32, Dp, LT, FUSED, ADAPT>(p, ws, im, stream);
     }
     return hipErrorInvalidValue;
 }
 
-template <typename LT, bool FUSED>
-static hipError_t launch_agg_lt(const Plan& p, const Workspace& ws, int gh, int gv, hipStream_t stream) {
+template <typename LT, bool FUSED, bool ADAPT>
+static hipError_t launch_agg_lt(const Plan& p, const Workspace& ws, Images im, int gh, int gv, hipStream_t stream) {
     if (p.Dp == 64) {
         // Dp = 64 has only 4 levels per lane at G = 16 and 2 at G = 32
-        return launch_agg_dp<64, LT, FUSED>(p, ws, gh == 64 ? 32 : gh, gv == 64 ? 32 : gv, stream);
+        return launch_agg_dp<64, LT, FUSED, ADAPT>(p, ws, im, gh == 64 ? 32 : gh, gv == 64 ? 32 : gv, stream);
     }
-    if (p.Dp == 128) return launch_agg_dp<128, LT, FUSED>(p, ws, gh, gv, stream);
-    return launch_agg_dp<256, LT, FUSED>(p, ws, gh, gv, stream);
+    if (p.Dp == 128) return launch_agg_dp<128, LT, FUSED, ADAPT>(p, ws, im, gh, gv, stream);
+    return launch_agg_dp<256, LT, FUSED, ADAPT>(p, ws, im, gh, gv, stream);
 }
 
 // Group widths: horizontal slices are the longest chains on wide images,
@@ -306,16 +317,23 @@ void default_lanes(const Plan& p, int* gh, int* gv) {
     *gv = 16;
 }
 
-hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stream) {
+bool fused_aggregation(const Plan& p) { return p.fused && !p.lr_full && !p.adaptive; }
+
+hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stream, const uint8_t* left,
+                            const uint8_t* right) {
     int gh = p.lanes_h, gv = p.lanes_v;
     if (gh <= 0 || gv <= 0) default_lanes(p, &gh, &gv);
-    // the right-base SGM of the full left-right check reads its own cost
-    // volume, so both SGMs take the cost-volume route
-    if (p.fused && !p.lr_full)
-        return p.l16 ? launch_agg_lt<uint16_t, true>(p, ws, gh, gv, stream)
-                     : launch_agg_lt<uint8_t, true>(p, ws, gh, gv, stream);
-    return p.l16 ? launch_agg_lt<uint16_t, false>(p, ws, gh, gv, stream)
-                 : launch_agg_lt<uint8_t, false>(p, ws, gh, gv, stream);
+    const Images im{left, right};
+    if (p.adaptive) {
+        if (!left || (p.lr_full && !right)) return hipErrorInvalidValue;
+        return p.l16 ? launch_agg_lt<uint16_t, false, true>(p, ws, im, gh, gv, stream)
+                     : launch_agg_lt<uint8_t, false, true>(p, ws, im, gh, gv, stream);
+    }
+    if (fused_aggregation(p))
+        return p.l16 ? launch_agg_lt<uint16_t, true, false>(p, ws, im, gh, gv, stream)
+                     : launch_agg_lt<uint8_t, true, false>(p, ws, im, gh, gv, stream);
+    return p.l16 ? launch_agg_lt<uint16_t, false, false>(p, ws, im, gh, gv, stream)
+                 : launch_agg_lt<uint8_t, false, false>(p, ws, im, gh, gv, stream);
 }
 
 hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream) {
@@ -355,9 +373,9 @@ hipError_t launch_pipeline(const Plan& p, const Workspace& ws, const uint8_t* le
         if (events && e == hipSuccess) e = hipEventRecord(events[i], stream);
     };
     mark(0);
-    if (e == hipSuccess) e = launch_matching_cost(p, ws, left, right, !p.fused, stream);
+    if (e == hipSuccess) e = launch_matching_cost(p, ws, left, right, !fused_aggregation(p), stream);
     mark(1);
-    if (e == hipSuccess) e = launch_aggregate(p, ws, stream);
+    if (e == hipSuccess) e = launch_aggregate(p, ws, stream, left, right);
     mark(2);
     if (e == hipSuccess) e = launch_wta(p, ws, out, stream);
     mark(3);

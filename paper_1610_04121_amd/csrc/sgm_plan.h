@@ -19,6 +19,7 @@ struct Plan {
     bool median = false, lrcheck = false;
     bool lr_full = false;      // D_R from a second SGM with the right image as base
     bool subpixel = false;     // left disparities in 1/16 pixel
+    bool adaptive = false;     // P2 of each step from the base image's intensity change
     int lr_thr = 1;
     int cmax = 0;              // largest matching cost
     bool l16 = false;          // L_r stored as u16 (else u8: Cmax + P2 <= 255)
@@ -60,7 +61,12 @@ hipError_t launch_cost(const Plan& p, const Workspace& ws, hipStream_t stream, b
 hipError_t launch_matching_cost(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right,
                                 bool need_cost, hipStream_t stream);
 bool census_cost_fusable(const Plan& p);
-hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stream);
+// left / right: the caller's images (the base images of the adaptive P2)
+hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stream, const uint8_t* left = nullptr,
+                            const uint8_t* right = nullptr);
+// whether the aggregation computes costs from census words (the tuning asks
+// for it and no option needs the cost volume)
+bool fused_aggregation(const Plan& p);
 void default_lanes(const Plan& p, int* gh, int* gv);
 hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream);
 hipError_t launch_post(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream);

@@ -13,7 +13,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsgm.so")
 
 SGM_OK, SGM_EINVAL, SGM_ENOMEM, SGM_EHIP, SGM_EBUSY, SGM_ECANCELED = 0, -1, -2, -3, -4, -5
-MEDIAN3, LRCHECK, CENSUS_CSCT, GRAPH, LR_FULL, SUBPIXEL = 1, 2, 4, 8, 16, 32
+MEDIAN3, LRCHECK, CENSUS_CSCT, GRAPH, LR_FULL, SUBPIXEL, ADAPTIVE_P2 = 1, 2, 4, 8, 16, 32, 64
 TUNE_FUSED_AGG, TUNE_FUSED_CENSUS_COST = 1, 2
 INVALID = 0xFFFF
 
@@ -191,7 +191,7 @@ class SGM:
 
     def __init__(self, width, height, max_disp, P1=7, P2=86, n_paths=4, census_w=9, census_h=7,
                  median=False, lrcheck=False, csct=False, lr_threshold=1, graph=False, lr_full=False,
-                 subpixel=False):
+                 subpixel=False, adaptive_p2=False):
         self.width, self.height, self.max_disp = width, height, max_disp
         self.n_paths = n_paths
         self.params = dict(P1=P1, P2=P2, census_w=census_w, census_h=census_h)
@@ -199,18 +199,20 @@ class SGM:
         if not self._ctx:
             raise SGMError(SGM_EINVAL, last_error())
         self.set_options(median=median, lrcheck=lrcheck, csct=csct, lr_threshold=lr_threshold, graph=graph,
-                         lr_full=lr_full, subpixel=subpixel)
+                         lr_full=lr_full, subpixel=subpixel, adaptive_p2=adaptive_p2)
 
     def set_options(self, median=False, lrcheck=False, csct=False, lr_threshold=1, graph=False, lr_full=False,
-                    subpixel=False):
+                    subpixel=False, adaptive_p2=False):
         """lr_full (with lrcheck): the right map of the check comes from a
         second SGM with the right image as base.  subpixel: output in 1/16
-        pixel (see SGM_SUBPIXEL in sgm.h)."""
+        pixel (see SGM_SUBPIXEL in sgm.h).  adaptive_p2: the P2 of each step
+        shrinks with the base image's intensity change (SGM_ADAPTIVE_P2)."""
         flags = ((MEDIAN3 if median else 0) | (LRCHECK if lrcheck else 0) | (CENSUS_CSCT if csct else 0)
-                 | (GRAPH if graph else 0) | (LR_FULL if lr_full else 0) | (SUBPIXEL if subpixel else 0))
+                 | (GRAPH if graph else 0) | (LR_FULL if lr_full else 0) | (SUBPIXEL if subpixel else 0)
+                 | (ADAPTIVE_P2 if adaptive_p2 else 0))
         _check(lib().sgm_set_options(self._ctx, flags, lr_threshold))
         self.params.update(median=median, lrcheck=lrcheck, csct=csct, lr_threshold=lr_threshold, lr_full=lr_full,
-                           subpixel=subpixel)
+                           subpixel=subpixel, adaptive_p2=adaptive_p2)
 
     def autotune(self, left=None, right=None, **kw) -> dict:
         """Times every aggregation kernel shape and keeps the fastest (see tune.py)."""

@@ -40,7 +40,8 @@ def cache_key(ctx) -> str:
     p = ctx.params
     return (f"{ctx.width}x{ctx.height}:d{ctx.max_disp}:p{ctx.n_paths}:P1={p['P1']}:P2={p['P2']}:"
             f"census={p['census_w']}x{p['census_h']}:csct={int(p['csct'])}:median={int(p['median'])}:"
-            f"lr={int(p['lrcheck'])}:lrfull={int(p.get('lr_full', False))}:sub={int(p.get('subpixel', False))}")
+            f"lr={int(p['lrcheck'])}:lrfull={int(p.get('lr_full', False))}:sub={int(p.get('subpixel', False))}:"
+            f"adapt={int(p.get('adaptive_p2', False))}")
 
 
 def load_cache(path: str | None = None) -> dict:

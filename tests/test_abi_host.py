@@ -58,7 +58,7 @@ def test_validate_accepts_the_workload_shapes(lib):
     ((10, 10, 8, -1, 86, 4, 9, 7, 0), "P1"),
     ((10, 10, 8, 7, -2, 4, 9, 7, 0), "P1 and P2"),
     ((10, 10, 8, 7, 8200, 8, 9, 7, 0), "65535"),
-    ((10, 10, 8, 7, 86, 4, 9, 7, 64), "flag"),
+    ((10, 10, 8, 7, 86, 4, 9, 7, 1 << 10), "flag"),
     ((20000, 10, 8, 7, 86, 4, 9, 7, 0), "width"),
 ])
 def test_validate_rejects(lib, args, frag):

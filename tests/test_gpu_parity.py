@@ -334,3 +334,52 @@ def test_subpixel_headline_workload(gpu):
     want = oracle.sgm(pair.left, pair.right, cfg["max_disp"], 7, 86, cfg["n_paths"], median=True, lr=True,
                       subpixel=True).out
     assert (got == want).all()
+
+
+@pytest.mark.parametrize("tuning", [(0, 0, False, False), (16, 16, False, False), (64, 32, False, False),
+                                    (32, 32, True, False)])
+@pytest.mark.parametrize("W,H,D,P", [(37, 23, 16, 8), (70, 9, 130, 4), (130, 40, 64, 8), (5, 33, 256, 2)])
+def test_adaptive_p2_per_direction_parity(gpu, W, H, D, P, tuning):
+    """SGM_ADAPTIVE_P2: every direction's L_r against the oracle with the
+    per-step P2 of the base image (a fused tuning falls back to the cost
+    volume)."""
+    pr = synth.make_pair(W, H, D, "RS", seed=W * H + D)
+    l, r = pr.left, pr.right
+    _say(f"adaptive P2 {W}x{H} D={D} P={P} tuning={tuning}")
+    s = SGM(W, H, D, 7, 86, P, adaptive_p2=True)
+    s.set_tuning(*tuning)
+    tl, tr = _t(l, gpu), _t(r, gpu)
+    mc = oracle.cost_volume(oracle.census(l), oracle.census(r), D, 62)
+    for k, (rx, ry) in enumerate(oracle.directions(P)):
+        got = _np(s.debug_stage(tl, tr, k))
+        want = oracle.aggregate(mc, 7, 86, rx, ry, img=l)
+        bad = np.argwhere(got != want)
+        assert len(bad) == 0, f"L_r ({rx},{ry}): {len(bad)} cells differ, first {bad[:3].tolist()}"
+    s.close()
+
+
+@pytest.mark.parametrize("W,H,D,P,median,lr,lr_full,subpixel", [
+    (64, 48, 32, 4, True, True, False, False), (97, 31, 64, 8, False, True, True, False),
+    (40, 70, 130, 2, True, False, False, True), (200, 60, 48, 8, True, True, True, True),
+])
+def test_adaptive_p2_pipeline_parity(gpu, W, H, D, P, median, lr, lr_full, subpixel):
+    pr = synth.make_pair(W, H, D, "RS", seed=W + 7 * H)
+    _say(f"adaptive P2 pipeline {W}x{H} D={D} P={P} median={median} lr={lr} full={lr_full} sub={subpixel}")
+    s = SGM(W, H, D, 7, 86, P, median=median, lrcheck=lr, lr_full=lr_full, subpixel=subpixel, adaptive_p2=True)
+    got = _np(s.compute(_t(pr.left, gpu), _t(pr.right, gpu)))
+    s.close()
+    want = oracle.sgm(pr.left, pr.right, D, 7, 86, P, median=median, lr=lr, lr_full=lr_full, subpixel=subpixel,
+                      adaptive=True).out
+    assert (got == want).all()
+
+
+def test_adaptive_p2_headline_workload(gpu):
+    cfg = synth.WORKLOADS["vga_640x480_d128_p4"]
+    pair = synth.workload_pair("vga_640x480_d128_p4")
+    _say("headline workload with adaptive P2")
+    s = SGM(cfg["w"], cfg["h"], cfg["max_disp"], 7, 86, cfg["n_paths"], median=True, lrcheck=True, adaptive_p2=True)
+    got = _np(s.compute(_t(pair.left, gpu), _t(pair.right, gpu)))
+    s.close()
+    want = oracle.sgm(pair.left, pair.right, cfg["max_disp"], 7, 86, cfg["n_paths"], median=True, lr=True,
+                      adaptive=True).out
+    assert (got == want).all()
