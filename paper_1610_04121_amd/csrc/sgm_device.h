@@ -435,21 +435,22 @@ struct SliceArgs {
     void* lplane;              // this direction's L_r plane [H][W][Dp]
     uint32_t plane;            // elements per plane = H * W * Dp
     int W, H, D, P1, P2, cmax, rx, ry;
-    const uint8_t* img = nullptr;  // base image u8 [H][W] (adaptive P2)
+    const uint8_t* img = nullptr;      // base image u8 [H][W] (adaptive P2)
+    const uint16_t* p2lut = nullptr;   // LDS: adaptive P2 of each intensity change 0..255
 };
 
 // Adaptive P2 of one step: max(P1, floor(P2 / (1 + g))) for an intensity
-// change g in [0, 255].  The quotient comes from the hardware reciprocal,
-// whose error is far below 1 for P2 < 2^24, and one correction either way
-// makes it exact.
+// change g in [0, 255].  A block tabulates it once in LDS (fill_p2_lut) and
+// the recurrence looks values up.
 __device__ inline uint32_t adaptive_p2(uint32_t P1, uint32_t P2, uint32_t g) {
-    const uint32_t d = 1u + g;
-    uint32_t q = (uint32_t)((float)P2 * __builtin_amdgcn_rcpf((float)d));
-    if (q * d > P2)
-        q -= 1u;
-    else if ((q + 1u) * d <= P2)
-        q += 1u;
+    const uint32_t q = P2 / (1u + g);
     return q > P1 ? q : P1;
+}
+
+// Fills lut[0..255] with adaptive_p2 (all threads of the block take part;
+// the caller synchronizes before use).
+__device__ inline void fill_p2_lut(uint16_t* lut, int P1, int P2) {
+    for (int g = threadIdx.x; g < 256; g += blockDim.x) lut[g] = (uint16_t)adaptive_p2((uint32_t)P1, (uint32_t)P2, (uint32_t)g);
 }
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -778,8 +779,10 @@ __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int l
     // smallest column any group of the wavefront is at (uniform): when it is
     // >= Dp - 1, every lane's disparities are valid (x - d >= 0)
     int xmin_all = 0;
-    uint32_t iprev = 0;  // intensity of the previous pixel on the path (ADAPT)
-    auto step = [&](const RawT& raw, uint32_t iv) {
+    // ADAPT: this step's P2 (looked up during the previous step; at a path
+    // start L and mm are 0 and the P2 of that step does not matter)
+    uint32_t p2cur = (uint32_t)a.P2;
+    auto step = [&](const RawT& raw, uint32_t iv, uint32_t inext) {
         if constexpr (FUSED) {
             if constexpr (KIND == kHoriz)
                 xmin_all = xc;
@@ -824,11 +827,13 @@ __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int l
         const u16x2 lo0 = as2(__builtin_amdgcn_alignbit(as1(lp[NP - 1]), prev, 16));
         const u16x2 hiN = as2(__builtin_amdgcn_alignbit(next, as1(lp[0]), 16));
         u16x2 p2v = P2v;
+        uint32_t p2next = 0;
         if constexpr (ADAPT) {
-            // at a path start L and mm are 0, so this step's P2 does not matter
-            const uint32_t g = iv > iprev ? iv - iprev : iprev - iv;
-            iprev = iv;
-            p2v = as2(adaptive_p2((uint32_t)a.P1, (uint32_t)a.P2, g) * 0x10001u);
+            p2v = as2(p2cur * 0x10001u);
+            // the next step's P2, from the intensity change to the next pixel;
+            // the LDS read completes while this step runs
+            const uint32_t g = inext > iv ? inext - iv : iv - inext;
+            p2next = a.p2lut[g];
         }
         const u16x2 mp2 = vadds(mm, p2v);
 #pragma unroll
@@ -850,6 +855,7 @@ __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int l
         mm = as2(group_min<G>(as1(tm)));
         store_l<CPL, LT>(rl, lane_ofs(bo, xc) * (uint32_t)sizeof(LT), L);
         advance(bo, xc);
+        if constexpr (ADAPT) p2cur = p2next;
     };
 
     // ring[j] holds the raw costs of the step congruent to j modulo PF.  The
@@ -891,16 +897,19 @@ __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int l
 #pragma unroll
         for (int j = 0; j < PF; ++j) {
             const RawT raw = ring[j];
+            // slot j + 1 (mod PF) holds the next step's intensity: slot 0 was
+            // refilled with step k + PF at j = 0
             const uint32_t iv = ADAPT ? iring[ADAPT ? j : 0] : 0u;
             advance(ba, xa);
             ring[j] = load(ba, xa);
             if constexpr (ADAPT) iring[j] = load_i(ba, xa);
-            step(raw, iv);
+            step(raw, iv, ADAPT ? iring[ADAPT ? (j + 1) % PF : 0] : 0u);
         }
     }
 #pragma unroll
     for (int j = 0; j < PF; ++j)
-        if (k + j < steps) step(ring[j], ADAPT ? iring[ADAPT ? j : 0] : 0u);
+        if (k + j < steps)
+            step(ring[j], ADAPT ? iring[ADAPT ? j : 0] : 0u, ADAPT ? iring[ADAPT ? (j + 1) % PF : 0] : 0u);
 }
 
 // ---------------------------------------------------------------------------

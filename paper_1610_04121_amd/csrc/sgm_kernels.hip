@@ -49,6 +49,11 @@ struct AggArgs {
 // the longest dependency chains get the fewest instructions per step.
 template <int GH, int GV, int Dp, typename LT, bool FUSED, bool ADAPT>
 __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
+    __shared__ uint16_t p2lut[ADAPT ? 256 : 1];
+    if constexpr (ADAPT) {  // every wave of the block takes part before any leaves
+        fill_p2_lut(p2lut, a.base.P1, a.base.P2);
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (wave >= a.total) return;
@@ -59,6 +64,7 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
     s.ry = a.ry[r];
     s.cost = a.cost[r];
     s.img = a.img[r];
+    s.p2lut = ADAPT ? p2lut : nullptr;
     s.lplane = reinterpret_cast<LT*>(a.lbuf) + (size_t)s.plane * a.plane_index[r];
     if (s.ry == 0) {
         aggregate_wave<GH, Dp / GH, LT, kHoriz, FUSED, ADAPT>(s, (wave - a.start[r]) * (64 / GH), lane);
