@@ -383,3 +383,26 @@ def test_adaptive_p2_headline_workload(gpu):
     want = oracle.sgm(pair.left, pair.right, cfg["max_disp"], 7, 86, cfg["n_paths"], median=True, lr=True,
                       adaptive=True).out
     assert (got == want).all()
+
+
+def test_graph_replay_with_all_options(gpu):
+    """Graph replay of the two-SGM pipeline with sub-pixel output and
+    adaptive P2: every replay equals the oracle, with eager work between."""
+    import torch
+    W, H, D = 120, 72, 40
+    pairs = [synth.make_pair(W, H, D, "RS", seed=800 + i) for i in range(2)]
+    opts = dict(median=True, lrcheck=True, lr_full=True, subpixel=True, adaptive_p2=True)
+    graph = SGM(W, H, D, 7, 86, 8, graph=True, **opts)
+    eager = SGM(W, H, D, 7, 86, 8, **opts)
+    bufs = [(_t(p.left, gpu), _t(p.right, gpu), torch.empty((H, W), dtype=torch.uint16, device=gpu)) for p in pairs]
+    want = [oracle.sgm(p.left, p.right, D, 7, 86, 8, median=True, lr=True, lr_full=True, subpixel=True,
+                       adaptive=True).out for p in pairs]
+    for rep in range(3):
+        _say(f"graph replay with all options, round {rep}")
+        for i, (l, r, o) in enumerate(bufs):
+            o.view(torch.int16).zero_()
+            graph.compute(l, r, o)
+            eager.compute(l, r)
+            assert (_np(o) == want[i]).all(), (rep, i)
+    graph.close()
+    eager.close()
