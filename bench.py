@@ -15,6 +15,9 @@ frame k runs on context k mod F.  Prints one JSON line:
                 with HIP events recorded around it on its own stream in the
                 timed region, on every 8th frame of each context (with F > 1
                 other frames share the GPU meanwhile);
+  pipeline      census through WTA (median and LR excluded) against HBM:
+                the path's algorithmic bytes per frame / the event-timed
+                span of those stages;
   serialized    one frame at a time on one stream (eager and graph replay);
   latency_ms    p50/p99 of single frames, event-bracketed;
   cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
@@ -91,6 +94,25 @@ def summarize_counters(fetch_csv: str, write_csv: str, copy_mib: int, tuning) ->
     return {"kernel": agg, "kernel_sha": _kernel_sha(), "tuning": [int(v) for v in tuning],
             "fetch_scale": round(f_fetch, 4), "write_scale": round(f_write, 4),
             "bytes_per_launch": kernels[agg]["read_bytes"] + kernels[agg]["write_bytes"], "kernels": kernels}
+
+
+def pipeline_bytes(W: int, H: int, Dp: int, P: int, tuning) -> int:
+    """Algorithmic bytes of census, cost, aggregation and WTA for one frame
+    (each byte read or written once per kernel that needs it): images in,
+    u64 census words of both views, the u8 cost volume, P u8 L_r planes
+    written and read back, the raw D_L and D_R maps out."""
+    px, N = W * H, W * H * Dp
+    fused, census_cost = bool(tuning[2]), bool(tuning[3])
+    census = 2 * px + 16 * px              # both images in, both census maps out
+    if fused:                              # no cost volume: each direction reads census words
+        agg = P * 16 * px + P * N
+        cost = 0
+    elif census_cost:                      # census words stay on chip
+        census, cost, agg = 0, 2 * px + N, 2 * P * N
+    else:
+        cost, agg = 16 * px + N, 2 * P * N
+    wta = P * N + 4 * px
+    return census + cost + agg + wta
 
 
 def cpu_baseline(pair, cfg, budget_s: float = 12.0):
@@ -493,6 +515,17 @@ def main():
         roof["measured_copy_gbs"] = extras["copy_gbs"]
         roof["frac_of_measured_copy"] = round(achieved / extras["copy_gbs"], 4)
 
+    # the whole path from the first census launch to the end of the WTA
+    # (median and LR excluded), event-timed like the stages it spans
+    pipe_ms = sum(stage_ms[k] for k in ("census_cost", "aggregate", "wta")) / max(ncalls, 1)
+    pipe_bytes = pipeline_bytes(W, H, Dp, P, tuning)
+    pipe_gbs = pipe_bytes / (pipe_ms * 1e-3) / 1e9
+    pipe = {"stages": "census..wta", "ms_per_frame": round(pipe_ms, 5), "alg_bytes": pipe_bytes,
+            "achieved": round(pipe_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(pipe_gbs / HBM_PEAK_GBS, 4)}
+    if "copy_gbs" in extras:
+        pipe["frac_of_measured_copy"] = round(pipe_gbs / extras["copy_gbs"], 4)
+
     line = {
         "metric": METRIC,
         "value": round(fps, 2),
@@ -516,6 +549,7 @@ def main():
         "gcells_per_s": round(W * H * D * P * fps / 1e9, 2),
         "stage_ms": {k: round(v / max(ncalls, 1), 5) for k, v in stage_ms.items()},
         "roofline": roof,
+        "pipeline": pipe,
     }
     if extras:
         line["serialized_fps"] = {"eager": extras["eager"], "graph": extras["graph"]}

@@ -1,0 +1,69 @@
+"""Host-side pieces of bench.py: the algorithmic byte counts it divides by,
+the hardware-counter summary it builds from rocprofv3 output, and its
+one-GPU guard.  No GPU is used."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+from conftest import ROOT
+
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_pipeline_bytes_counts_each_kernel_once():
+    W, H, Dp, P = 4, 2, 64, 4
+    px, N = W * H, W * H * Dp
+    # census: 2 images in, 2 u64 maps out; cost: 2 maps in, N out;
+    # aggregation: N in and N out per direction; WTA: P planes in, 2 u16 maps out
+    expect = (2 * px + 16 * px) + (16 * px + N) + 2 * P * N + (P * N + 4 * px)
+    assert bench.pipeline_bytes(W, H, Dp, P, (32, 16, 0, 0)) == expect == (3 * P + 1) * N + 38 * px
+    # the headline workload
+    assert bench.pipeline_bytes(640, 480, 128, 4, (32, 16, 0, 0)) == 522_854_400
+
+
+def test_pipeline_bytes_of_the_fused_variants():
+    W, H, Dp, P = 8, 3, 128, 8
+    px, N = W * H, W * H * Dp
+    fused = (2 * px + 16 * px) + P * (16 * px + N) + (P * N + 4 * px)
+    assert bench.pipeline_bytes(W, H, Dp, P, (32, 16, 1, 0)) == fused
+    census_cost = (2 * px + N) + 2 * P * N + (P * N + 4 * px)
+    assert bench.pipeline_bytes(W, H, Dp, P, (32, 16, 0, 1)) == census_cost
+
+
+def _write_pmc(path, counter, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for name, value in rows:
+            w.writerow({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": value})
+
+
+def test_counter_summary_scales_by_the_copy(tmp_path):
+    copy = "__amd_rocclr_copyBuffer"
+    agg = "void sgm::aggregate_kernel<32, 16, 128, unsigned char, false, false>(sgm::AggArgs)"
+    cost = "void sgm::cost_kernel<false>(sgm::CostArgs)"
+    mib = 256
+    # FETCH_SIZE reads half of a copy's bytes, WRITE_SIZE all of them
+    _write_pmc(tmp_path / "f.csv", "FETCH_SIZE",
+               [(copy, mib * 512.0), (agg, 1000.0), (agg, 1002.0), (cost, 10.0)])
+    _write_pmc(tmp_path / "w.csv", "WRITE_SIZE", [(copy, mib * 1024.0), (agg, 3000.0), (cost, 20.0)])
+    s = bench.summarize_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), mib, ["32", "16", "0", "0"])
+    assert s["kernel"] == agg and s["tuning"] == [32, 16, 0, 0]
+    assert s["fetch_scale"] == 2.0 and s["write_scale"] == 1.0
+    assert s["bytes_per_launch"] == 1001.0 * 2 * 1024 + 3000.0 * 1024
+    assert s["kernels"][cost]["read_bytes"] == 20 * 1024
+    assert copy not in s["kernels"]
+    json.dumps(s)
+
+
+@pytest.mark.parametrize("n", [0, 2, 8])
+def test_bench_runs_on_one_gpu_only(n):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
