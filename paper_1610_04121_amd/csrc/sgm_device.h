@@ -221,7 +221,23 @@ __device__ inline void cost_block(const CostArgs& a, int bx, int y, uint64_t* cw
                 for (int j = 0; j < 4; ++j) wd |= (uint32_t)__popcll(base ^ word(4 * q + j)) << (8 * j);
                 w[q] = wd;
             }
-        } else {
+        } else if (d0 + 16 <= D) {
+            // a run at the image border: every lane's LDS word exists, so
+            // every lane takes the popcount and a select puts Cmax where the
+            // match pixel is outside the image (no per-lane branch)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t wd = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int d = d0 + 4 * q + j;
+                    const uint32_t pc = (uint32_t)__popcll(base ^ word(4 * q + j));
+                    const bool out = RB ? x + d >= a.W : x - d < 0;
+                    wd |= (out ? (uint32_t)a.cmax : pc) << (8 * j);
+                }
+                w[q] = wd;
+            }
+        } else {  // the chunk holding D - 1 and the padded levels
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 uint32_t wd = 0;
@@ -230,8 +246,9 @@ __device__ inline void cost_block(const CostArgs& a, int bx, int y, uint64_t* cw
                     const int d = d0 + 4 * q + j;
                     uint32_t c = 0;  // padded levels d >= D
                     if (d < D) {
+                        const uint32_t pc = (uint32_t)__popcll(base ^ word(4 * q + j));
                         const bool out = RB ? x + d >= a.W : x - d < 0;
-                        c = out ? (uint32_t)a.cmax : (uint32_t)__popcll(base ^ word(4 * q + j));
+                        c = out ? (uint32_t)a.cmax : pc;
                     }
                     wd |= c << (8 * j);
                 }
@@ -376,7 +393,18 @@ __device__ inline void census_cost_block(const CensusCostArgs& a, int bx, int y,
                     for (int j = 0; j < 4; ++j) word |= (uint32_t)__popcll(base ^ m[15 - (4 * q + j)]) << (8 * j);
                     w[q] = word;
                 }
-            } else {
+            } else if (d0 + 16 <= D) {  // at the border: popcount on every lane, then a select
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t word = 0;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const uint32_t pc = (uint32_t)__popcll(base ^ m[15 - (4 * q + j)]);
+                        word |= (x - (d0 + 4 * q + j) < 0 ? (uint32_t)a.cmax : pc) << (8 * j);
+                    }
+                    w[q] = word;
+                }
+            } else {  // the chunk holding D - 1 and the padded levels
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     uint32_t word = 0;
@@ -384,8 +412,10 @@ __device__ inline void census_cost_block(const CensusCostArgs& a, int bx, int y,
                     for (int j = 0; j < 4; ++j) {
                         const int d = d0 + 4 * q + j;
                         uint32_t c = 0;  // padded levels d >= D
-                        if (d < D)
-                            c = x - d < 0 ? (uint32_t)a.cmax : (uint32_t)__popcll(base ^ m[15 - (4 * q + j)]);
+                        if (d < D) {
+                            const uint32_t pc = (uint32_t)__popcll(base ^ m[15 - (4 * q + j)]);
+                            c = x - d < 0 ? (uint32_t)a.cmax : pc;
+                        }
                         word |= c << (8 * j);
                     }
                     w[q] = word;
@@ -459,6 +489,20 @@ __device__ inline uint32_t as1(u16x2 v) { return __builtin_bit_cast(uint32_t, v)
 __device__ inline u16x2 vmin(u16x2 a, u16x2 b) { return __builtin_elementwise_min(a, b); }
 __device__ inline u16x2 vadds(u16x2 a, u16x2 b) { return __builtin_elementwise_add_sat(a, b); }
 
+// Minimum of three packed u16 pairs in one v_pk_minimum3_f16.  Exact for
+// halves below 0x7C00: those bit patterns are the non-negative finite f16
+// values (zero, subnormals, normals), whose order is the order of the
+// patterns read as unsigned integers, and a minimum returns one of its
+// inputs unchanged.  f16 subnormals are not flushed in these kernels (the
+// f16/f64 denormal mode keeps them), so small integers compare correctly.
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+__device__ inline u16x2 vmin3h(u16x2 a, u16x2 b, u16x2 c) {
+    const h16x2 m = __builtin_elementwise_minimum(__builtin_elementwise_minimum(__builtin_bit_cast(h16x2, a),
+                                                                                __builtin_bit_cast(h16x2, b)),
+                                                  __builtin_bit_cast(h16x2, c));
+    return __builtin_bit_cast(u16x2, m);
+}
+
 // DPP controls (GFX9 encoding).
 constexpr int kDppQuadPerm1032 = 0xB1;
 constexpr int kDppQuadPerm2301 = 0x4E;
@@ -530,9 +574,10 @@ __device__ inline void unpack_costs(const typename Raw<CPL>::T& r, const uint32_
 }
 
 // Selector of pair k for a lane whose first disparity is d0: low half b_k,
-// high half b_{k+CPL/2} (bytes of the v_perm source pair), 0xFFFF for d >= D.
+// high half b_{k+CPL/2} (bytes of the v_perm source pair), and the padding
+// value `pad` (a 16-bit v_perm selector) for d >= D.
 template <int CPL>
-__device__ inline uint32_t unpack_selector(int k, int d0, int D) {
+__device__ inline uint32_t unpack_selector(int k, int d0, int D, uint32_t pad) {
     constexpr int NP = CPL / 2;
     uint32_t lo, hi;
     if constexpr (CPL == 2) {
@@ -545,8 +590,8 @@ __device__ inline uint32_t unpack_selector(int k, int d0, int D) {
         lo = k % 4;
         hi = 4 + k % 4;
     }
-    const uint32_t slo = (d0 + k < D) ? (lo | 0x0C00u) : 0x0D0Du;
-    const uint32_t shi = (d0 + k + NP < D) ? (hi | 0x0C00u) : 0x0D0Du;
+    const uint32_t slo = (d0 + k < D) ? (lo | 0x0C00u) : pad;
+    const uint32_t shi = (d0 + k + NP < D) ? (hi | 0x0C00u) : pad;
     return slo | (shi << 16);
 }
 
@@ -682,12 +727,12 @@ __device__ inline void census_costs(const CensusStep<CPL>& cs, int valid_c, uint
 }
 
 // Selector of pair k for the fused variant: low half = cell k (S1 byte 0),
-// high half = cell k + CPL/2 (S0 byte 0, selector 4); 0xFFFF for d >= D.
+// high half = cell k + CPL/2 (S0 byte 0, selector 4); `pad` for d >= D.
 template <int CPL>
-__device__ inline uint32_t pack_selector(int k, int d0, int D) {
+__device__ inline uint32_t pack_selector(int k, int d0, int D, uint32_t pad) {
     constexpr int NP = CPL / 2;
-    const uint32_t slo = (d0 + k < D) ? 0x0C00u : 0x0D0Du;
-    const uint32_t shi = (d0 + k + NP < D) ? 0x0C04u : 0x0D0Du;
+    const uint32_t slo = (d0 + k < D) ? 0x0C00u : pad;
+    const uint32_t shi = (d0 + k + NP < D) ? 0x0C04u : pad;
     return slo | (shi << 16);
 }
 
@@ -716,13 +761,29 @@ __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int l
     // groups past the last slice repeat the last slice (identical stores)
     const int jg = min(grp, nslices - 1 - first_slice);
 
+    // Byte planes (Cmax + largest step penalty <= 255) keep every register
+    // value far below 0x7C00, so the minimum of three runs as one packed f16
+    // minimum (vmin3h).  That needs finite stand-ins for "no candidate":
+    //   * padded levels d >= D get cost 255 (not 0xFFFF).  Their L stays in
+    //     [255, 255 + P2] and never undercuts a real level: real L <= Cmax +
+    //     P2 <= 255, and the path minimum m is at most Cmax, so m + P2 <=
+    //     255 <= L(pad) + P1.
+    //   * the d - 1 / d + 1 candidate beyond the lane group's ends is 0x0FFF
+    //     (OR-ed into a value below 0x1000), above every real candidate.
+    //   * P1 is capped at the largest step penalty: a larger P1 never wins
+    //     against m + P2 in Eq. 3 (L(d +- 1) >= m), and neither does the cap.
+    // 16-bit planes keep saturating u16 arithmetic with 0xFFFF.
+    constexpr bool kF16 = sizeof(LT) == 1;
+    const uint32_t pad = kF16 ? 0x0C0Du : 0x0D0Du;  // v_perm bytes: 0x00FF or 0xFFFF
     uint32_t sel[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k)
-        sel[k] = FUSED ? pack_selector<CPL>(k, q * CPL, a.D) : unpack_selector<CPL>(k, q * CPL, a.D);
-    const uint32_t edge_lo = q == 0 ? 0xFFFF0000u : 0u;      // no d-1 below d = 0
-    const uint32_t edge_hi = q == G - 1 ? 0x0000FFFFu : 0u;  // no d+1 above Dp-1
-    const u16x2 P1v = as2((uint32_t)a.P1 * 0x10001u), P2v = as2((uint32_t)a.P2 * 0x10001u);
+        sel[k] = FUSED ? pack_selector<CPL>(k, q * CPL, a.D, pad) : unpack_selector<CPL>(k, q * CPL, a.D, pad);
+    const uint32_t inf = kF16 ? 0x0FFFu : 0xFFFFu;
+    const uint32_t edge_lo = q == 0 ? inf << 16 : 0u;  // no d-1 below d = 0
+    const uint32_t edge_hi = q == G - 1 ? inf : 0u;    // no d+1 above Dp-1
+    const uint32_t P1c = kF16 ? (uint32_t)(ADAPT ? a.P1 : min(a.P1, a.P2)) : (uint32_t)a.P1;
+    const u16x2 P1v = as2(P1c * 0x10001u), P2v = as2((uint32_t)a.P2 * 0x10001u);
 
     const uint32_t plane_bytes = (uint32_t)a.plane;  // cost plane, u8
     const __amdgpu_buffer_rsrc_t rc = buffer_rsrc(a.cost, FUSED ? 0u : plane_bytes);
@@ -840,18 +901,27 @@ __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int l
         for (int k = 0; k < NP; ++k) {
             const u16x2 lo = k == 0 ? lo0 : lp[k - 1];
             const u16x2 hi = k == NP - 1 ? hiN : lp[k + 1];
-            const u16x2 R = vmin(vmin(lo, hi), vmin(L[k], mp2));
+            const u16x2 R = kF16 ? vmin(vmin3h(lo, hi, L[k]), mp2) : vmin(vmin(lo, hi), vmin(L[k], mp2));
             L[k] = vadds(R - mm, c[k]);
         }
-        // minimum over the lane's cells as a tree, replicated in both halves
-        u16x2 t[NP];
+        // minimum over the lane's cells, replicated in both halves
+        u16x2 tm;
+        if constexpr (kF16 && NP >= 4) {
+            u16x2 t = vmin3h(L[0], L[1], L[2]);
 #pragma unroll
-        for (int k = 0; k < NP; ++k) t[k] = L[k];
+            for (int k = 3; k + 1 < NP; k += 2) t = vmin3h(t, L[k], L[k + 1]);
+            if constexpr (NP % 2 == 0) t = vmin(t, L[NP - 1]);
+            tm = vmin(t, t.yx);
+        } else {
+            u16x2 t[NP];
 #pragma unroll
-        for (int w = 1; w < NP; w *= 2)
+            for (int k = 0; k < NP; ++k) t[k] = L[k];
 #pragma unroll
-            for (int k = 0; k + w < NP; k += 2 * w) t[k] = vmin(t[k], t[k + w]);
-        const u16x2 tm = vmin(t[0], t[0].yx);
+            for (int w = 1; w < NP; w *= 2)
+#pragma unroll
+                for (int k = 0; k + w < NP; k += 2 * w) t[k] = vmin(t[k], t[k + w]);
+            tm = vmin(t[0], t[0].yx);
+        }
         mm = as2(group_min<G>(as1(tm)));
         store_l<CPL, LT>(rl, lane_ofs(bo, xc) * (uint32_t)sizeof(LT), L);
         advance(bo, xc);

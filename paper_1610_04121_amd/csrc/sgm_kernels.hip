@@ -1,6 +1,7 @@
 // Single-pair SGM kernels for gfx950 and their host-side launchers.  The
 // stage bodies live in sgm_device.h; each kernel here maps its grid onto one
 // stereo pair.
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -143,11 +144,15 @@ bool plan_finish(Plan& p, const char** why) {
     if (p.P1 < 0 || p.P2 < 0) return fail("P1 and P2 must be >= 0");
     if (p.P1 > 65535) return fail("P1 must be <= 65535");
     p.cmax = p.csct ? (p.cw * p.ch - 1) / 2 : p.cw * p.ch - 1;
-    if ((long long)p.n_paths * (p.cmax + (long long)p.P2) > 65535)
-        return fail("n_paths * (Cmax + P2) must be <= 65535 (16-bit summed costs)");
+    // the largest penalty of one step bounds L_r <= Cmax + penalty: P2, or
+    // with adaptive P2 (max(P1, P2 / (1 + g)) per step) the larger of P1, P2
+    const long long pmax = p.adaptive ? std::max(p.P1, p.P2) : p.P2;
+    if ((long long)p.n_paths * (p.cmax + pmax) > 65535)
+        return fail(p.adaptive ? "n_paths * (Cmax + max(P1, P2)) must be <= 65535 (16-bit summed costs, adaptive P2)"
+                               : "n_paths * (Cmax + P2) must be <= 65535 (16-bit summed costs)");
     if (p.lr_thr < 0) return fail("lr threshold must be >= 0");
     p.Dp = padded_disp(p.D);
-    p.l16 = p.cmax + p.P2 > 255;
+    p.l16 = p.cmax + pmax > 255;
     // one L_r plane (u16) must stay below 2 GiB: kernels address planes with
     // 32-bit byte offsets
     if ((long long)p.W * p.H * p.Dp > (1LL << 30)) return fail("width * height * padded disparities must be <= 2^30");

@@ -164,3 +164,13 @@ def test_full_lr_flag_rules(lib):
     full = lib.sgm_footprint_bytes(640, 480, 128, 4, sgm.LRCHECK | sgm.LR_FULL)
     # a second cost volume (u8) and a second set of 4 L_r planes (counted as u16)
     assert full - plain >= 640 * 480 * 128 * (1 + 4 * 2)
+
+
+def test_adaptive_p2_bounds_use_the_larger_penalty(lib):
+    # a step's adaptive penalty is max(P1, P2 / (1 + g)): with P1 > P2 the
+    # 16-bit sum bound counts P1
+    p1 = 65535 // 8 - 62 + 1
+    assert sgm.validate(64, 64, 64, p1, 7, 8) == 0
+    assert sgm.validate(64, 64, 64, p1, 7, 8, flags=sgm.ADAPTIVE_P2) == sgm.SGM_EINVAL
+    assert "max(P1, P2)" in sgm.last_error()
+    assert sgm.validate(64, 64, 64, p1 - 1, 7, 8, flags=sgm.ADAPTIVE_P2) == 0

@@ -373,6 +373,31 @@ def test_adaptive_p2_pipeline_parity(gpu, W, H, D, P, median, lr, lr_full, subpi
     assert (got == want).all()
 
 
+@pytest.mark.parametrize("W,H,D,P", [(53, 29, 32, 4), (24, 61, 64, 8)])
+def test_adaptive_p2_with_p1_above_p2(gpu, W, H, D, P):
+    """With P1 > P2 a step's adaptive penalty max(P1, P2 / (1 + g)) can be P1,
+    so L_r reaches Cmax + P1: here 62 + 200 > 255 >= 62 + 100, and the
+    planes must be 16-bit although Cmax + P2 fits a byte."""
+    pr = synth.make_pair(W, H, D, "RS", seed=W * 5 + H)
+    l, r = pr.left, pr.right
+    _say(f"adaptive P2 with P1 > P2 {W}x{H} D={D} P={P}")
+    s = SGM(W, H, D, 200, 100, P, median=True, lrcheck=True, adaptive_p2=True)
+    tl, tr = _t(l, gpu), _t(r, gpu)
+    mc = oracle.cost_volume(oracle.census(l), oracle.census(r), D, 62)
+    top = 0
+    for k, (rx, ry) in enumerate(oracle.directions(P)):
+        got = _np(s.debug_stage(tl, tr, k))
+        want = oracle.aggregate(mc, 200, 100, rx, ry, img=l)
+        top = max(top, int(want.max()))
+        bad = np.argwhere(got != want)
+        assert len(bad) == 0, f"L_r ({rx},{ry}): {len(bad)} cells differ, first {bad[:3].tolist()}"
+    assert top > 255  # the case the byte planes could not hold
+    got = _np(s.compute(tl, tr))
+    s.close()
+    want = oracle.sgm(l, r, D, 200, 100, P, median=True, lr=True, adaptive=True).out
+    assert (got == want).all()
+
+
 def test_adaptive_p2_headline_workload(gpu):
     cfg = synth.WORKLOADS["vga_640x480_d128_p4"]
     pair = synth.workload_pair("vga_640x480_d128_p4")
