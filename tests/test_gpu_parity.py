@@ -102,6 +102,37 @@ def test_summed_costs_parity(gpu, W, H, D, P, csct, P1, P2):
     assert len(bad) == 0, f"{len(bad)} cells differ, first {bad[:5].tolist()}"
 
 
+@pytest.mark.parametrize("W,H,D,P,csct,P1,P2", [
+    (45, 33, 40, 8, False, 60000, 7),    # P1 far above P2 (byte planes)
+    (38, 41, 100, 4, False, 500, 193),   # Cmax + P2 = 255: the byte-plane limit
+    (50, 20, 64, 8, True, 300, 224),     # CSCT: Cmax + P2 = 255
+    (30, 30, 128, 2, False, 0, 193),     # P1 = 0
+    (40, 25, 48, 4, False, 9000, 194),   # Cmax + P2 = 256: 16-bit planes
+])
+@pytest.mark.parametrize("fused", [False, True])
+def test_penalty_extremes_per_direction(gpu, W, H, D, P, csct, P1, P2, fused):
+    """Every direction's L_r and the output at the ends of the penalty range:
+    P1 above P2 (it can never win against m + P2), P2 at the largest value
+    byte planes hold, and just past it."""
+    rng = np.random.default_rng(W * 11 + H + P1 + P2)
+    l, r = _rand_pair(rng, W, H)
+    _say(f"penalties {W}x{H} D={D} P={P} csct={csct} P1={P1} P2={P2} fused={fused}")
+    s = SGM(W, H, D, P1, P2, P, csct=csct, median=True, lrcheck=True)
+    s.set_tuning(0, 0, fused, False)
+    tl, tr = _t(l, gpu), _t(r, gpu)
+    mc = oracle.cost_volume(oracle.census(l, csct=csct), oracle.census(r, csct=csct), D,
+                            oracle.cmax_of(csct=csct))
+    for k, (rx, ry) in enumerate(oracle.directions(P)):
+        got = _np(s.debug_stage(tl, tr, k))
+        want = oracle.aggregate(mc, P1, P2, rx, ry)
+        bad = np.argwhere(got != want)
+        assert len(bad) == 0, f"L_r ({rx},{ry}): {len(bad)} cells differ, first {bad[:5].tolist()}"
+    got = _np(s.compute(tl, tr))
+    s.close()
+    want = oracle.sgm(l, r, D, P1, P2, P, csct=csct, median=True, lr=True).out
+    assert (got == want).all()
+
+
 @pytest.mark.parametrize("W,H,D,P", [(41, 27, 24, 4), (66, 19, 70, 8), (8, 12, 30, 4)])
 def test_raw_disparity_parity(gpu, W, H, D, P):
     rng = np.random.default_rng(W + H + D)
