@@ -41,9 +41,31 @@ struct CensusArgs {
     int W, H, csct;
 };
 
-__device__ inline uint32_t shift_in(uint32_t acc, int u, int v) {
-    // (acc << 1) | [u >= v]
-    return __builtin_amdgcn_alignbit(acc, (uint32_t)(v - 1 - u), 31);
+// Byte-parallel comparison: bit 7 of byte b of the result is [u_b >= v_b]
+// for unsigned bytes (the other bits are don't-care).  vlo = v & 0x7F7F7F7F.
+// (u | 0x80) - (v & 0x7F) per byte lies in [1, 255], so no borrow crosses a
+// byte, and its bit 7 compares the low 7 bits; the top bits decide whenever
+// they differ.
+__device__ inline uint32_t ge_bytes(uint32_t u, uint32_t v, uint32_t vlo) {
+    const uint32_t d = (u | 0x80808080u) - vlo;
+    return (u & ~v) | (~(u ^ v) & d);
+}
+
+// Moves each byte of acc down one bit and puts bit 7 of the byte of g on top.
+__device__ inline uint32_t push_bits(uint32_t acc, uint32_t g) {
+    return ((acc >> 1) & 0x7F7F7F7Fu) | (g & 0x80808080u);
+}
+
+// o[p] byte b = a[b] byte p (4x4 byte transpose).
+__device__ inline void transpose_bytes4(const uint32_t (&a)[4], uint32_t (&o)[4]) {
+    const uint32_t t01l = __builtin_amdgcn_perm(a[1], a[0], 0x05010400u);
+    const uint32_t t01h = __builtin_amdgcn_perm(a[1], a[0], 0x07030602u);
+    const uint32_t t23l = __builtin_amdgcn_perm(a[3], a[2], 0x05010400u);
+    const uint32_t t23h = __builtin_amdgcn_perm(a[3], a[2], 0x07030602u);
+    o[0] = __builtin_amdgcn_perm(t23l, t01l, 0x05040100u);
+    o[1] = __builtin_amdgcn_perm(t23l, t01l, 0x07060302u);
+    o[2] = __builtin_amdgcn_perm(t23h, t01h, 0x05040100u);
+    o[3] = __builtin_amdgcn_perm(t23h, t01h, 0x07060302u);
 }
 
 // Census words (9x7 window, full or center-symmetric) of 4 consecutive
@@ -51,6 +73,12 @@ __device__ inline uint32_t shift_in(uint32_t acc, int u, int v) {
 // Pixel p (0..3) has its window on tile rows r0 .. r0+6 and columns
 // c0+p .. c0+p+8 (centre at row r0+3, column c0+p+4); c0 is a multiple of 4,
 // so each window row is read as 3 aligned dwords.
+//
+// The 4 pixels' samples at one window offset are 4 consecutive bytes of a
+// tile row, so one dword holds them and ge_bytes compares all four.  Byte b
+// of the census word (bits 8b .. 8b+7) is gathered for the 4 pixels in the
+// 4 bytes of acc[b], one push_bits per bit; a byte transpose then turns the
+// per-bit-byte registers into per-pixel words.
 __device__ inline void census_words4(const uint8_t* tile, int TW, int r0, int c0, bool csct, uint64_t words[4]) {
     constexpr int RY = 3, CW = 9;
     uint32_t dw[2 * RY + 1][3];
@@ -58,25 +86,35 @@ __device__ inline void census_words4(const uint8_t* tile, int TW, int r0, int c0
     for (int j = 0; j < 2 * RY + 1; ++j)
 #pragma unroll
         for (int k = 0; k < 3; ++k) dw[j][k] = *reinterpret_cast<const uint32_t*>(&tile[(r0 + j) * TW + c0 + 4 * k]);
-    auto px = [&](int j, int b) -> int { return (int)((dw[j][b >> 2] >> (8 * (b & 3))) & 0xFF); };
+    // bytes b .. b+3 of window row j (b in 0..8): column offset b - 4 of the 4 pixels
+    auto at = [&](int j, int b) -> uint32_t {
+        const int q = b >> 2, s = b & 3;
+        return s == 0 ? dw[j][q] : __builtin_amdgcn_alignbit(dw[j][q + 1], dw[j][q], 8 * s);
+    };
+    uint32_t acc[8];
+    if (!csct) {
+        // bit k = (j, i) of the window: k = j * 9 + i, j in 0..6, i in 0..8
+        const uint32_t c = at(RY, 4), clo = c & 0x7F7F7F7Fu;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        uint32_t hi = 0, lo = 0;
-        if (!csct) {
-            const int c = px(RY, p + 4);
+        for (int b = 0; b < 8; ++b) {
+            uint32_t a = 0;
+            const int nb = b < 7 ? 8 : (2 * RY + 1) * CW - 56;  // 7 bits in the top byte
 #pragma unroll
-            for (int k = (2 * RY + 1) * CW - 1; k >= 0; --k) {
-                const int j = k / CW, i = k % CW;  // bit k = (j, i) of the window
-                const int u = px(j, p + i);
-                if (k >= 32)
-                    hi = shift_in(hi, u, c);
-                else
-                    lo = shift_in(lo, u, c);
+            for (int t = 0; t < nb; ++t) {
+                const int k = 8 * b + t;
+                a = push_bits(a, ge_bytes(at(k / CW, k % CW), c, clo));
             }
-        } else {
-            // pairs in order k = 0..30: i = 1..4 with j = -3..3, then (0, j), j = 1..3
+            acc[b] = nb == 8 ? a : (a >> (8 - nb)) & (0xFFu >> (8 - nb)) * 0x01010101u;
+        }
+    } else {
+        // pairs in order k = 0..30: i = 1..4 with j = -3..3, then (0, j), j = 1..3
 #pragma unroll
-            for (int k = 30; k >= 0; --k) {
+        for (int b = 0; b < 4; ++b) {
+            uint32_t a = 0;
+            const int nb = b < 3 ? 8 : 7;
+#pragma unroll
+            for (int t = 0; t < nb; ++t) {
+                const int k = 8 * b + t;
                 int i, j;
                 if (k < 28) {
                     i = 1 + k / 7;
@@ -85,11 +123,19 @@ __device__ inline void census_words4(const uint8_t* tile, int TW, int r0, int c0
                     i = 0;
                     j = k - 27;
                 }
-                lo = shift_in(lo, px(RY + j, p + 4 + i), px(RY - j, p + 4 - i));
+                const uint32_t u = at(RY + j, 4 + i), v = at(RY - j, 4 - i);
+                a = push_bits(a, ge_bytes(u, v, v & 0x7F7F7F7Fu));
             }
+            acc[b] = nb == 8 ? a : (a >> 1) & 0x7F7F7F7Fu;
         }
-        words[p] = ((uint64_t)hi << 32) | lo;
+#pragma unroll
+        for (int b = 4; b < 8; ++b) acc[b] = 0;
     }
+    uint32_t lo[4], hi[4];
+    transpose_bytes4({acc[0], acc[1], acc[2], acc[3]}, lo);
+    transpose_bytes4({acc[4], acc[5], acc[6], acc[7]}, hi);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) words[p] = ((uint64_t)hi[p] << 32) | lo[p];
 }
 
 __device__ inline void census97_block(const CensusArgs& a, int bx, int by, int z) {
