@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void census_batch_kernel(const BatchItem* item
     }
 }
 
-__global__ __launch_bounds__(256) void cost_batch_kernel(const BatchItem* items, int n) {
+__global__ __launch_bounds__(kCostThreads) void cost_batch_kernel(const BatchItem* items, int n) {
     extern __shared__ __align__(16) uint64_t cost_smem[];
     const int b = blockIdx.x;
     const BatchItem& it = items[find_item<&BatchItem::cost_blk0>(items, n, b)];
@@ -361,7 +361,7 @@ int batch_enqueue(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_b
 
     hipLaunchKernelGGL(census_batch_kernel, dim3((unsigned)census_blocks), dim3(256), 0, s, st->d_items, n,
                        generic ? 1 : 0, (bp.cw - 1) / 2, (bp.ch - 1) / 2, st->counter);
-    hipLaunchKernelGGL(cost_batch_kernel, dim3((unsigned)cost_blocks), dim3(256), cost_smem, s, st->d_items, n);
+    hipLaunchKernelGGL(cost_batch_kernel, dim3((unsigned)cost_blocks), dim3(kCostThreads), cost_smem, s, st->d_items, n);
     // persistent grid: at most two wavefronts per SIMD (256 CUs x 4 SIMDs)
     const int nwork = (int)work.size();
     const int waves = std::min(nwork, 2048);

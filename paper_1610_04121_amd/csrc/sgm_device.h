@@ -214,6 +214,7 @@ __device__ inline void census_generic_block(const CensusArgs& a, int rx, int ry,
 // to the cost volume with contiguous 16-byte stores.
 // ---------------------------------------------------------------------------
 constexpr int kCostTX = 64;
+constexpr int kCostThreads = 256;  // block size of every launch of cost_block
 
 struct CostArgs {
     const uint64_t* cl;
@@ -239,11 +240,26 @@ __device__ inline void cost_block(const CostArgs& a, int bx, int y, uint64_t* cw
     uint8_t* tile = reinterpret_cast<uint8_t*>(cl + ((kCostTX + nright + 1) & ~1));
     const uint64_t* gl = a.cl + (size_t)y * a.W;
     const uint64_t* gr = a.cr + (size_t)y * a.W;
-    for (int i = threadIdx.x; i < kCostTX; i += blockDim.x)
-        if (x0 + i < a.W) cl[i] = gl[x0 + i];
-    for (int i = threadIdx.x; i < nright; i += blockDim.x) {
-        const int xr = xm0 + i;
-        if (xr >= 0 && xr < a.W) cr[i] = gr[xr];
+    // Every global load is issued before the first LDS store, so the loads'
+    // latencies overlap instead of adding up.  The block has kCostThreads
+    // threads: one base word each for the first 64, and the match words
+    // (nright <= kCostTX + 255 < 2 * kCostThreads) in two rounds.
+    {
+        const int t = threadIdx.x;
+        uint64_t vl = 0, vr[2] = {0, 0};
+        const bool hl = t < kCostTX && x0 + t < a.W;
+        if (hl) vl = gl[x0 + t];
+        bool hr[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int i = t + kCostThreads * k, xr = xm0 + i;
+            hr[k] = i < nright && xr >= 0 && xr < a.W;
+            if (hr[k]) vr[k] = gr[xr];
+        }
+        if (hl) cl[t] = vl;
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            if (hr[k]) cr[t + kCostThreads * k] = vr[k];
     }
     __syncthreads();
 

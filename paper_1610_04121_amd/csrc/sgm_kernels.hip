@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void census_cost_kernel(CensusCostArgs a) {
 }
 
 template <bool RB>
-__global__ __launch_bounds__(256) void cost_kernel(CostArgs a) {
+__global__ __launch_bounds__(kCostThreads) void cost_kernel(CostArgs a) {
     extern __shared__ __align__(16) uint64_t cost_smem[];
     cost_block<RB>(a, blockIdx.x, blockIdx.y, cost_smem);
 }
@@ -241,10 +241,10 @@ hipError_t launch_cost(const Plan& p, const Workspace& ws, hipStream_t stream, b
     if (right_base) {
         if (!ws.cost_r) return hipErrorInvalidValue;
         CostArgs a{ws.census_r, ws.census_l, ws.cost_r, p.W, p.H, p.D, p.Dp, p.cmax};
-        hipLaunchKernelGGL(cost_kernel<true>, grid, dim3(256), smem, stream, a);
+        hipLaunchKernelGGL(cost_kernel<true>, grid, dim3(kCostThreads), smem, stream, a);
     } else {
         CostArgs a{ws.census_l, ws.census_r, ws.cost, p.W, p.H, p.D, p.Dp, p.cmax};
-        hipLaunchKernelGGL(cost_kernel<false>, grid, dim3(256), smem, stream, a);
+        hipLaunchKernelGGL(cost_kernel<false>, grid, dim3(kCostThreads), smem, stream, a);
     }
     return hipGetLastError();
 }
