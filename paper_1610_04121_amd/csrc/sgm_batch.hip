@@ -88,7 +88,12 @@ __global__ __launch_bounds__(kCostThreads) void cost_batch_kernel(const BatchIte
     const int local = b - it.cost_blk0;
     const int nx = (it.W + kCostTX - 1) / kCostTX;
     CostArgs a{it.census_l, it.census_r, it.cost, it.W, it.H, it.D, it.Dp, it.cmax};
-    cost_block<false>(a, local % nx, local / nx, cost_smem);
+    if (it.Dp == 64)
+        cost_block<false, 64>(a, local % nx, local / nx, cost_smem);
+    else if (it.Dp == 128)
+        cost_block<false, 128>(a, local % nx, local / nx, cost_smem);
+    else
+        cost_block<false, 256>(a, local % nx, local / nx, cost_smem);
 }
 
 template <typename LT, int Dp>

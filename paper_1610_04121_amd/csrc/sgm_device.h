@@ -225,13 +225,17 @@ struct CostArgs {
 
 // RB = false: base words cl = left view, match words cr = right view at x - d
 // (Eq. 2).  RB = true: base = right view, match = left view at x + d (the
-// right-base costs of the full left-right check).
-template <bool RB>
+// right-base costs of the full left-right check).  DP = a.Dp (64, 128 or
+// 256) as a constant, so the chunk and copy loops unroll and the tile pitch
+// is an immediate.
+template <bool RB, int DP>
 __device__ inline void cost_block(const CostArgs& a, int bx, int y, uint64_t* cw_smem) {
+    static_assert(DP == 64 || DP == 128 || DP == 256, "padded disparity range");
     const int x0 = bx * kCostTX;
-    const int D = a.D, Dp = a.Dp;
+    const int D = a.D;
+    constexpr int Dp = DP;
     const int nright = kCostTX + D - 1;
-    const int tpitch = Dp + 16;  // bytes per tile row
+    constexpr int tpitch = Dp + 16;  // bytes per tile row
     uint64_t* cl = cw_smem;
     // cr[i] = match word of column xm0 + i
     uint64_t* cr = cl + kCostTX;
@@ -266,8 +270,11 @@ __device__ inline void cost_block(const CostArgs& a, int bx, int y, uint64_t* cw
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int x = x0 + lane;
     const uint64_t base = cl[lane];
-    const int nchunks = Dp >> 4;
-    for (int ch = wave; ch < nchunks; ch += 4) {
+    constexpr int nchunks = Dp >> 4;
+    constexpr int nwaves = kCostThreads / 64;
+#pragma unroll
+    for (int it = 0; it < nchunks / nwaves; ++it) {
+        const int ch = wave + nwaves * it;
         const int d0 = 16 * ch;
         // match word of disparity d0 + j: cr[lane + D - 1 - d0 - j] (left
         // base), cr[lane + d0 + j] (right base)
@@ -321,11 +328,20 @@ __device__ inline void cost_block(const CostArgs& a, int bx, int y, uint64_t* cw
     }
     __syncthreads();
     const int npx = min(kCostTX, a.W - x0);
-    const int lg = Dp == 64 ? 2 : (Dp == 128 ? 3 : 4);  // log2(nchunks)
     uint8_t* dst = a.cost + ((size_t)y * a.W + x0) * Dp;
-    for (int c = threadIdx.x; c < npx * nchunks; c += blockDim.x) {
-        const int px = c >> lg, k = c & (nchunks - 1);
-        *reinterpret_cast<uint4*>(dst + 16 * c) = *reinterpret_cast<const uint4*>(tile + px * tpitch + 16 * k);
+    // kCostTX * nchunks 16-byte pieces, nchunks / nwaves per thread: all LDS
+    // reads first, then the stores
+    constexpr int nper = kCostTX * nchunks / kCostThreads;
+    uint4 v[nper];
+#pragma unroll
+    for (int j = 0; j < nper; ++j) {
+        const int c = threadIdx.x + kCostThreads * j;
+        v[j] = *reinterpret_cast<const uint4*>(tile + (c / nchunks) * tpitch + 16 * (c % nchunks));
+    }
+#pragma unroll
+    for (int j = 0; j < nper; ++j) {
+        const int c = threadIdx.x + kCostThreads * j;
+        if (c < npx * nchunks) *reinterpret_cast<uint4*>(dst + 16 * c) = v[j];
     }
 }
 

@@ -26,10 +26,10 @@ __global__ __launch_bounds__(256) void census_cost_kernel(CensusCostArgs a) {
     census_cost_block(a, blockIdx.x, blockIdx.y, cc_smem);
 }
 
-template <bool RB>
+template <bool RB, int DP>
 __global__ __launch_bounds__(kCostThreads) void cost_kernel(CostArgs a) {
     extern __shared__ __align__(16) uint64_t cost_smem[];
-    cost_block<RB>(a, blockIdx.x, blockIdx.y, cost_smem);
+    cost_block<RB, DP>(a, blockIdx.x, blockIdx.y, cost_smem);
 }
 
 // Direction table of one pair's aggregation launch: the directions of one
@@ -238,14 +238,12 @@ hipError_t launch_cost(const Plan& p, const Workspace& ws, hipStream_t stream, b
     const int nright = kCostTX + p.D - 1;
     const size_t smem = 8 * (size_t)((kCostTX + nright + 1) & ~1) + (size_t)kCostTX * (p.Dp + 16);
     dim3 grid((p.W + kCostTX - 1) / kCostTX, p.H);
-    if (right_base) {
-        if (!ws.cost_r) return hipErrorInvalidValue;
-        CostArgs a{ws.census_r, ws.census_l, ws.cost_r, p.W, p.H, p.D, p.Dp, p.cmax};
-        hipLaunchKernelGGL(cost_kernel<true>, grid, dim3(kCostThreads), smem, stream, a);
-    } else {
-        CostArgs a{ws.census_l, ws.census_r, ws.cost, p.W, p.H, p.D, p.Dp, p.cmax};
-        hipLaunchKernelGGL(cost_kernel<false>, grid, dim3(kCostThreads), smem, stream, a);
-    }
+    if (right_base && !ws.cost_r) return hipErrorInvalidValue;
+    const CostArgs a = right_base ? CostArgs{ws.census_r, ws.census_l, ws.cost_r, p.W, p.H, p.D, p.Dp, p.cmax}
+                                  : CostArgs{ws.census_l, ws.census_r, ws.cost, p.W, p.H, p.D, p.Dp, p.cmax};
+    auto k = right_base ? (p.Dp == 64 ? cost_kernel<true, 64> : p.Dp == 128 ? cost_kernel<true, 128> : cost_kernel<true, 256>)
+                        : (p.Dp == 64 ? cost_kernel<false, 64> : p.Dp == 128 ? cost_kernel<false, 128> : cost_kernel<false, 256>);
+    hipLaunchKernelGGL(k, grid, dim3(kCostThreads), smem, stream, a);
     return hipGetLastError();
 }
 
