@@ -1253,47 +1253,77 @@ struct PostArgs {
 };
 
 // One row of the post stage.  Each thread takes 4 columns per pass so that
-// the 36 neighbour loads of a pass are in flight together (a 640-wide row is
-// one pass of a 256-thread block).
-__device__ inline void post_row(const PostArgs& a, int y, uint16_t* rview) {
+// the neighbour loads of a pass are in flight together (a 640-wide row is
+// one pass of a 256-thread block); the median and check switches are
+// template constants, so no branch splits those loads.  With the check on,
+// the first pass loads the D_L and D_R neighbourhoods together (72 loads),
+// so the two maps' load latencies overlap; the D_R medians of the whole row
+// go to LDS before the barrier, and the check after it reads them at x - d.
+template <bool LR, bool MED>
+__device__ inline void post_row_impl(const PostArgs& a, int y, uint16_t* rview) {
     constexpr int U = 4;
-    const int nt = blockDim.x;
-    if (a.lrcheck) {
-        for (int x0 = threadIdx.x; x0 < a.W; x0 += U * nt) {
-            uint32_t v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int x = min(x0 + u * nt, a.W - 1);
-                v[u] = a.median ? median9(a.dr, a.W, a.H, x, y) : a.dr[(size_t)y * a.W + x];
+    const int nt = blockDim.x, x0 = threadIdx.x;
+    auto med = [&](const uint16_t* img, int x) -> uint32_t {
+        if constexpr (MED)
+            return median9(img, a.W, a.H, x, y);
+        else
+            return img[(size_t)y * a.W + x];
+    };
+    auto finish = [&](int x, int v) {
+        if (x >= a.W) return;
+        int o = v;
+        if constexpr (LR) {
+            const int d = a.subpixel ? (v + 8) >> 4 : v;  // integer disparity of the check
+            o = kInvalid;
+            if (x - d >= 0) {
+                const int e = rview[x - d];
+                if (abs(d - e) <= a.thr) o = v;
             }
+        }
+        a.out[(size_t)y * a.W + x] = (uint16_t)o;
+    };
+    // first pass: columns x0 + u * nt
+    uint32_t dv[U], rv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int x = min(x0 + u * nt, a.W - 1);
+        dv[u] = med(a.dl, x);
+        if constexpr (LR) rv[u] = med(a.dr, x);
+    }
+    if constexpr (LR) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (x0 + u * nt < a.W) rview[x0 + u * nt] = (uint16_t)rv[u];
+        for (int xb = x0 + U * nt; xb < a.W; xb += U * nt) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) rv[u] = med(a.dr, min(xb + u * nt, a.W - 1));
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (x0 + u * nt < a.W) rview[x0 + u * nt] = (uint16_t)v[u];
+                if (xb + u * nt < a.W) rview[xb + u * nt] = (uint16_t)rv[u];
         }
         __syncthreads();
     }
-    for (int x0 = threadIdx.x; x0 < a.W; x0 += U * nt) {
-        int dv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int x = min(x0 + u * nt, a.W - 1);
-            dv[u] = a.median ? (int)median9(a.dl, a.W, a.H, x, y) : (int)a.dl[(size_t)y * a.W + x];
-        }
+    for (int u = 0; u < U; ++u) finish(x0 + u * nt, (int)dv[u]);
+    for (int xb = x0 + U * nt; xb < a.W; xb += U * nt) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int x = x0 + u * nt, v = dv[u];
-            if (x >= a.W) continue;
-            int o = v;
-            if (a.lrcheck) {
-                const int d = a.subpixel ? (v + 8) >> 4 : v;  // integer disparity of the check
-                o = kInvalid;
-                if (x - d >= 0) {
-                    const int e = rview[x - d];
-                    if (abs(d - e) <= a.thr) o = v;
-                }
-            }
-            a.out[(size_t)y * a.W + x] = (uint16_t)o;
-        }
+        for (int u = 0; u < U; ++u) dv[u] = med(a.dl, min(xb + u * nt, a.W - 1));
+#pragma unroll
+        for (int u = 0; u < U; ++u) finish(xb + u * nt, (int)dv[u]);
+    }
+}
+
+__device__ inline void post_row(const PostArgs& a, int y, uint16_t* rview) {
+    if (a.lrcheck) {
+        if (a.median)
+            post_row_impl<true, true>(a, y, rview);
+        else
+            post_row_impl<true, false>(a, y, rview);
+    } else {
+        if (a.median)
+            post_row_impl<false, true>(a, y, rview);
+        else
+            post_row_impl<false, false>(a, y, rview);
     }
 }
 
