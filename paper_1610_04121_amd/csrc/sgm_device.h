@@ -1088,17 +1088,21 @@ __device__ inline int floor_div(int num, int den) {
 
 constexpr int kWtaGuard = 256;  // >= max disparity
 
-// Sums of 16 disparities d0..d0+15 of one pixel as 8 packed pairs; pair k
-// holds disparities dpair(k) (see below).
-template <typename LT>
-__device__ inline void sum16(const LT* base, size_t plane, int nplanes, uint32_t (&S)[8]) {
+// Sums of 16 disparities d0..d0+15 of one pixel over NPL planes as 8 packed
+// pairs; pair k holds disparities dpair(k) (see below).  Every plane's load
+// is issued before the first add, so a lane has all NPL loads in flight.
+template <typename LT, int NPL>
+__device__ inline void sum16(const LT* base, size_t plane, uint32_t (&S)[8]) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) S[k] = 0;
     if constexpr (sizeof(LT) == 1) {
         // bytes b0..b3 of dword i -> pairs (b0, b2) and (b1, b3)
+        uint4 q[NPL];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) S[k] = 0;
-        for (int p = 0; p < nplanes; ++p) {
-            const uint4 q = *reinterpret_cast<const uint4*>(base + plane * p);
-            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+        for (int p = 0; p < NPL; ++p) q[p] = *reinterpret_cast<const uint4*>(base + plane * p);
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) {
+            const uint32_t w[4] = {q[p].x, q[p].y, q[p].z, q[p].w};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 S[2 * i] = as1(as2(S[2 * i]) + as2(__builtin_amdgcn_perm(0u, w[i], 0x0C020C00u)));
@@ -1107,12 +1111,16 @@ __device__ inline void sum16(const LT* base, size_t plane, int nplanes, uint32_t
         }
     } else {
         // u16 pairs are already (d, d + 1)
+        uint4 q[NPL][2];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) S[k] = 0;
-        for (int p = 0; p < nplanes; ++p) {
-            const uint4 q0 = reinterpret_cast<const uint4*>(base + plane * p)[0];
-            const uint4 q1 = reinterpret_cast<const uint4*>(base + plane * p)[1];
-            const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+        for (int p = 0; p < NPL; ++p) {
+            q[p][0] = reinterpret_cast<const uint4*>(base + plane * p)[0];
+            q[p][1] = reinterpret_cast<const uint4*>(base + plane * p)[1];
+        }
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) {
+            const uint32_t w[8] = {q[p][0].x, q[p][0].y, q[p][0].z, q[p][0].w,
+                                   q[p][1].x, q[p][1].y, q[p][1].z, q[p][1].w};
 #pragma unroll
             for (int k = 0; k < 8; ++k) S[k] = as1(as2(S[k]) + as2(w[k]));
         }
@@ -1142,8 +1150,8 @@ __device__ inline uint32_t lanes_min(uint32_t v, int G) {
     return v;
 }
 
-template <typename LT>
-__device__ inline void wta_row(const WtaArgs& a, int y, uint32_t* keyR_smem) {
+template <typename LT, int NPL>
+__device__ inline void wta_row_impl(const WtaArgs& a, int y, uint32_t* keyR_smem) {
     uint32_t* keyR = keyR_smem + kWtaGuard;  // keyR[t], t in [-kWtaGuard, W)
     const bool right = a.dr != nullptr;
     if (right)
@@ -1158,7 +1166,7 @@ __device__ inline void wta_row(const WtaArgs& a, int y, uint32_t* keyR_smem) {
         const int x = i >> gshift, g = i & (G - 1);
         const int d0 = 16 * g;
         uint32_t S[8];
-        sum16<LT>(planes + ((size_t)y * a.W + x) * a.Dp + d0, a.plane, a.nplanes, S);
+        sum16<LT, NPL>(planes + ((size_t)y * a.W + x) * a.Dp + d0, a.plane, S);
         uint32_t best = ~0u;
         // right-view targets x - d0 - 15 .. x - d0 from one base address
         uint32_t* tgt = keyR + (x - d0 - 15);
@@ -1211,6 +1219,18 @@ __device__ inline void wta_row(const WtaArgs& a, int y, uint32_t* keyR_smem) {
         for (int i = threadIdx.x; i < a.W; i += blockDim.x)
             a.dr[(size_t)y * a.W + i] = (uint16_t)(keyR[i] & 0xFF);
     }
+}
+
+// One row of the WTA; the plane count (2, 4 or 8) is a template constant of
+// the row's code, so the plane loads unroll.
+template <typename LT>
+__device__ inline void wta_row(const WtaArgs& a, int y, uint32_t* keyR_smem) {
+    if (a.nplanes == 2)
+        wta_row_impl<LT, 2>(a, y, keyR_smem);
+    else if (a.nplanes == 4)
+        wta_row_impl<LT, 4>(a, y, keyR_smem);
+    else
+        wta_row_impl<LT, 8>(a, y, keyR_smem);
 }
 
 // ---------------------------------------------------------------------------
