@@ -43,6 +43,9 @@ struct AggArgs {
     int rx[kMaxLaunchDirs], ry[kMaxLaunchDirs], plane_index[kMaxLaunchDirs];
     const uint8_t* cost[kMaxLaunchDirs];  // the cost volume each direction reads
     const uint8_t* img[kMaxLaunchDirs];   // its SGM's base image (adaptive P2)
+    // paired[k]: directions k and k + 1 are opposite, axis-aligned and have
+    // the same wave count; their waves interleave (see aggregate_kernel)
+    int paired[kMaxLaunchDirs];
 };
 
 // One launch covers every direction.  Horizontal slices (the longest when
@@ -60,6 +63,26 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
     if (wave >= a.total) return;
     int r = 0;
     while (r + 1 < a.ndirs && wave >= a.start[r + 1]) ++r;
+    int local = wave - a.start[r];
+    // The 2n waves of a pair of opposite directions over the same n slice
+    // groups interleave two by two (A, A, B, B per workgroup), so both
+    // directions' waves over the same slices share a CU and its L2: the
+    // second read of a slice's costs can hit where the two walks pass close
+    // in time.  A bijection between the pair's waves and (direction, slice
+    // group); an odd n ends with one wave of each.
+    const int r0 = (r > 0 && a.paired[r - 1]) ? r - 1 : r;
+    if (a.paired[r0]) {
+        const int n = a.start[r0 + 1] - a.start[r0];
+        const int j = wave - a.start[r0];
+        const int g = j >> 2, w4 = j & 3;
+        if (4 * g + 4 <= 2 * n) {
+            r = r0 + (w4 >> 1);
+            local = 2 * g + (w4 & 1);
+        } else {
+            r = r0 + (w4 & 1);
+            local = 2 * g;
+        }
+    }
     SliceArgs s = a.base;
     s.rx = a.rx[r];
     s.ry = a.ry[r];
@@ -68,11 +91,11 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
     s.p2lut = ADAPT ? p2lut : nullptr;
     s.lplane = reinterpret_cast<LT*>(a.lbuf) + (size_t)s.plane * a.plane_index[r];
     if (s.ry == 0) {
-        aggregate_wave<GH, Dp / GH, LT, kHoriz, FUSED, ADAPT>(s, (wave - a.start[r]) * (64 / GH), lane);
+        aggregate_wave<GH, Dp / GH, LT, kHoriz, FUSED, ADAPT>(s, local * (64 / GH), lane);
     } else if (s.rx == 0) {
-        aggregate_wave<GV, Dp / GV, LT, kVert, FUSED, ADAPT>(s, (wave - a.start[r]) * (64 / GV), lane);
+        aggregate_wave<GV, Dp / GV, LT, kVert, FUSED, ADAPT>(s, local * (64 / GV), lane);
     } else {
-        aggregate_wave<GV, Dp / GV, LT, kDiag, FUSED, ADAPT>(s, (wave - a.start[r]) * (64 / GV), lane);
+        aggregate_wave<GV, Dp / GV, LT, kDiag, FUSED, ADAPT>(s, local * (64 / GV), lane);
     }
 }
 
@@ -278,6 +301,13 @@ static void fill_agg_args(const Plan& p, const Workspace& ws, const uint8_t* lef
     }
     a.start[a.ndirs] = acc;
     a.total = acc;
+    for (int k = 0; k < a.ndirs; ++k) {
+        a.paired[k] = 0;
+        if (k + 1 < a.ndirs && !(k > 0 && a.paired[k - 1]) && a.rx[k] == -a.rx[k + 1] && a.ry[k] == -a.ry[k + 1] &&
+            (a.rx[k] == 0 || a.ry[k] == 0) && order[k] / p.n_paths == order[k + 1] / p.n_paths &&
+            a.start[k + 1] - a.start[k] == a.start[k + 2] - a.start[k + 1])
+            a.paired[k] = 1;
+    }
 }
 
 // Images of the two SGMs (base left / base right) for the adaptive P2.
