@@ -88,7 +88,9 @@ enum {
  *   w*h <= 64; CSCT: (w*h - 1)/2 <= 64); P1, P2 >= 0;
  *   n_paths * (Cmax + P2) <= 65535, where Cmax = w*h - 1 (full) or
  *   (w*h - 1)/2 (CSCT), so that summed costs fit in 16 bits (the bound
- *   L_r <= C + P2 follows from the last term of Eq. 3). */
+ *   L_r <= C + P2 follows from the last term of Eq. 3); with
+ *   SGM_ADAPTIVE_P2 the bound uses max(P1, P2), the largest penalty a step
+ *   can take.  Also P1 <= 65535, and unknown flag bits are rejected. */
 int sgm_validate(int width, int height, int max_disp, int P1, int P2, int n_paths,
                  int census_w, int census_h, unsigned flags);
 
