@@ -12,6 +12,7 @@ namespace sgm {
 
 constexpr int kMaxDirs = 8;
 constexpr int kMaxDisp = 256;
+constexpr long long kMallBytes = 256ll << 20;  // MI355X memory-side (Infinity) cache
 constexpr int kMaxWidth = 16000;  // the WTA keeps 4 * (W + 256) bytes of keys in LDS (< 64 KiB)
 constexpr uint32_t kInvalid = 0xFFFF;
 // words of addressable space in front of each census buffer in the workspace

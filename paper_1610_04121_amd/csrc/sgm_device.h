@@ -698,42 +698,49 @@ __device__ inline typename Raw<CPL>::T buffer_load_raw(__amdgpu_buffer_rsrc_t r,
     }
 }
 
+// AUX is the cache-policy operand of the store: 0, or 2 for non-temporal
+// (the L_r planes of a frame larger than the memory-side cache stream past it).
+template <int AUX>
 __device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint16_t v) {
-    __builtin_amdgcn_raw_buffer_store_b16(v, r, ofs, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, ofs, 0, AUX);
 }
+template <int AUX>
 __device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint32_t v) {
-    __builtin_amdgcn_raw_buffer_store_b32(v, r, ofs, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, ofs, 0, AUX);
 }
+template <int AUX>
 __device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint2 v) {
-    __builtin_amdgcn_raw_buffer_store_b64((unsigned __attribute__((ext_vector_type(2)))){v.x, v.y}, r, ofs, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64((unsigned __attribute__((ext_vector_type(2)))){v.x, v.y}, r, ofs, 0, AUX);
 }
+template <int AUX>
 __device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint4 v) {
     __builtin_amdgcn_raw_buffer_store_b128((unsigned __attribute__((ext_vector_type(4)))){v.x, v.y, v.z, v.w}, r, ofs,
-                                           0, 0);
+                                           0, AUX);
 }
 
 // Packs a lane's L values in natural disparity order (u8 or u16) and stores
-// them at byte offset `ofs` of the L_r plane.
-template <int CPL, typename LT>
+// them at byte offset `ofs` of the L_r plane (NT: non-temporal stores).
+template <int CPL, typename LT, bool NT = false>
 __device__ inline void store_l(__amdgpu_buffer_rsrc_t r, uint32_t ofs, const u16x2 (&l)[CPL / 2]) {
+    constexpr int A = NT ? 2 : 0;
     constexpr uint32_t kLoBytes = 0x06020400u;  // (a.b0, b.b0, a.b2, b.b2) of perm(b, a)
     constexpr uint32_t kPairLo = 0x05040100u;   // (a.lo16, b.lo16)
     constexpr uint32_t kPairHi = 0x07060302u;   // (a.hi16, b.hi16)
     if constexpr (sizeof(LT) == 1) {
         if constexpr (CPL == 2) {
-            buffer_store(r, ofs, (uint16_t)__builtin_amdgcn_perm(0u, as1(l[0]), 0x0C0C0200u));
+            buffer_store<A>(r, ofs, (uint16_t)__builtin_amdgcn_perm(0u, as1(l[0]), 0x0C0C0200u));
         } else if constexpr (CPL == 4) {
-            buffer_store(r, ofs, (uint32_t)__builtin_amdgcn_perm(as1(l[1]), as1(l[0]), kLoBytes));
+            buffer_store<A>(r, ofs, (uint32_t)__builtin_amdgcn_perm(as1(l[1]), as1(l[0]), kLoBytes));
         } else if constexpr (CPL == 8) {
             const uint32_t t01 = __builtin_amdgcn_perm(as1(l[1]), as1(l[0]), kLoBytes);
             const uint32_t t23 = __builtin_amdgcn_perm(as1(l[3]), as1(l[2]), kLoBytes);
-            buffer_store(r, ofs, make_uint2(__builtin_amdgcn_perm(t23, t01, kPairLo),
+            buffer_store<A>(r, ofs, make_uint2(__builtin_amdgcn_perm(t23, t01, kPairLo),
                                             __builtin_amdgcn_perm(t23, t01, kPairHi)));
         } else {
             uint32_t t[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) t[i] = __builtin_amdgcn_perm(as1(l[2 * i + 1]), as1(l[2 * i]), kLoBytes);
-            buffer_store(r, ofs, make_uint4(__builtin_amdgcn_perm(t[1], t[0], kPairLo),
+            buffer_store<A>(r, ofs, make_uint4(__builtin_amdgcn_perm(t[1], t[0], kPairLo),
                                             __builtin_amdgcn_perm(t[3], t[2], kPairLo),
                                             __builtin_amdgcn_perm(t[1], t[0], kPairHi),
                                             __builtin_amdgcn_perm(t[3], t[2], kPairHi)));
@@ -741,7 +748,7 @@ __device__ inline void store_l(__amdgpu_buffer_rsrc_t r, uint32_t ofs, const u16
     } else {
         constexpr int NP = CPL / 2;
         if constexpr (CPL == 2) {
-            buffer_store(r, ofs, as1(l[0]));
+            buffer_store<A>(r, ofs, as1(l[0]));
         } else {
             // dword i = (d_2i, d_2i+1) from pairs 2i and 2i+1 (low halves,
             // then high halves)
@@ -752,11 +759,11 @@ __device__ inline void store_l(__amdgpu_buffer_rsrc_t r, uint32_t ofs, const u16
                 w[NP / 2 + i] = __builtin_amdgcn_perm(as1(l[2 * i + 1]), as1(l[2 * i]), kPairHi);
             }
             if constexpr (NP == 2) {
-                buffer_store(r, ofs, make_uint2(w[0], w[1]));
+                buffer_store<A>(r, ofs, make_uint2(w[0], w[1]));
             } else {
 #pragma unroll
                 for (int i = 0; i < NP / 4; ++i)
-                    buffer_store(r, ofs + 16 * i, make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]));
+                    buffer_store<A>(r, ofs + 16 * i, make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]));
             }
         }
     }
@@ -821,7 +828,7 @@ template <int CPL> struct FusedPrefetch { static constexpr int N = CPL >= 16 ? 2
 
 // ADAPT: the P2 of each step adapts to the base image's intensity change
 // along the path (adaptive_p2); the intensities are prefetched with the costs.
-template <int G, int CPL, typename LT, int KIND, bool FUSED, bool ADAPT = false>
+template <int G, int CPL, typename LT, int KIND, bool FUSED, bool ADAPT = false, bool NT = false>
 __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int lane) {
     static_assert(!(FUSED && ADAPT), "adaptive P2 uses the cost-volume variant");
     constexpr int NP = CPL / 2;
@@ -1001,7 +1008,7 @@ __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int l
             tm = vmin(t[0], t[0].yx);
         }
         mm = as2(group_min<G>(as1(tm)));
-        store_l<CPL, LT>(rl, lane_ofs(bo, xc) * (uint32_t)sizeof(LT), L);
+        store_l<CPL, LT, NT>(rl, lane_ofs(bo, xc) * (uint32_t)sizeof(LT), L);
         advance(bo, xc);
         if constexpr (ADAPT) p2cur = p2next;
     };

@@ -51,7 +51,7 @@ struct AggArgs {
 // One launch covers every direction.  Horizontal slices (the longest when
 // W > H) may use a different group width GH than the others (GV), so that
 // the longest dependency chains get the fewest instructions per step.
-template <int GH, int GV, int Dp, typename LT, bool FUSED, bool ADAPT>
+template <int GH, int GV, int Dp, typename LT, bool FUSED, bool ADAPT, bool NT>
 __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
     __shared__ uint16_t p2lut[ADAPT ? 256 : 1];
     if constexpr (ADAPT) {  // every wave of the block takes part before any leaves
@@ -91,11 +91,11 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
     s.p2lut = ADAPT ? p2lut : nullptr;
     s.lplane = reinterpret_cast<LT*>(a.lbuf) + (size_t)s.plane * a.plane_index[r];
     if (s.ry == 0) {
-        aggregate_wave<GH, Dp / GH, LT, kHoriz, FUSED, ADAPT>(s, local * (64 / GH), lane);
+        aggregate_wave<GH, Dp / GH, LT, kHoriz, FUSED, ADAPT, NT>(s, local * (64 / GH), lane);
     } else if (s.rx == 0) {
-        aggregate_wave<GV, Dp / GV, LT, kVert, FUSED, ADAPT>(s, local * (64 / GV), lane);
+        aggregate_wave<GV, Dp / GV, LT, kVert, FUSED, ADAPT, NT>(s, local * (64 / GV), lane);
     } else {
-        aggregate_wave<GV, Dp / GV, LT, kDiag, FUSED, ADAPT>(s, local * (64 / GV), lane);
+        aggregate_wave<GV, Dp / GV, LT, kDiag, FUSED, ADAPT, NT>(s, local * (64 / GV), lane);
     }
 }
 
@@ -176,6 +176,16 @@ bool plan_finish(Plan& p, const char** why) {
     if (p.lr_thr < 0) return fail("lr threshold must be >= 0");
     p.Dp = padded_disp(p.D);
     p.l16 = p.cmax + pmax > 255;
+    // Normal stores leave a frame's L_r planes in the 256 MiB memory-side
+    // cache for the WTA to read back.  When the planes and the cost volume
+    // do not fit, the dirty planes would be written back while the WTA reads,
+    // so they are stored non-temporally instead.
+    {
+        const long long cells = (long long)p.W * p.H * p.Dp;
+        const long long nsgm = p.lr_full ? 2 : 1;
+        const long long bytes = nsgm * cells * (p.n_paths * (p.l16 ? 2 : 1) + 1);
+        p.nt_store = bytes > kMallBytes;
+    }
     // one L_r plane (u16) must stay below 2 GiB: kernels address planes with
     // 32-bit byte offsets
     if ((long long)p.W * p.H * p.Dp > (1LL << 30)) return fail("width * height * padded disparities must be <= 2^30");
@@ -315,38 +325,38 @@ struct Images {
     const uint8_t *left, *right;
 };
 
-template <int GH, int GV, int Dp, typename LT, bool FUSED, bool ADAPT>
+template <int GH, int GV, int Dp, typename LT, bool FUSED, bool ADAPT, bool NT>
 static hipError_t launch_agg_t(const Plan& p, const Workspace& ws, Images im, hipStream_t stream) {
     AggArgs a;
     fill_agg_args(p, ws, im.left, im.right, 64 / GH, 64 / GV, a);
-    hipLaunchKernelGGL((aggregate_kernel<GH, GV, Dp, LT, FUSED, ADAPT>), dim3((a.total + 3) / 4), dim3(256), 0,
+    hipLaunchKernelGGL((aggregate_kernel<GH, GV, Dp, LT, FUSED, ADAPT, NT>), dim3((a.total + 3) / 4), dim3(256), 0,
                        stream, a);
     return hipGetLastError();
 }
 
-template <int Dp, typename LT, bool FUSED, bool ADAPT>
+template <int Dp, typename LT, bool FUSED, bool ADAPT, bool NT>
 static hipError_t launch_agg_dp(const Plan& p, const Workspace& ws, Images im, int gh, int gv, hipStream_t stream) {
     switch (gh * 100 + gv) {
-        case 1616: return launch_agg_t<16, 16, Dp, LT, FUSED, ADAPT>(p, ws, im, stream);
-        case 3216: return launch_agg_t<32, 16, Dp, LT, FUSED, ADAPT>(p, ws, im, stream);
-        case 3232: return launch_agg_t<32, 32, Dp, LT, FUSED, ADAPT>(p, ws, im, stream);
+        case 1616: return launch_agg_t<16, 16, Dp, LT, FUSED, ADAPT, NT>(p, ws, im, stream);
+        case 3216: return launch_agg_t<32, 16, Dp, LT, FUSED, ADAPT, NT>(p, ws, im, stream);
+        case 3232: return launch_agg_t<32, 32, Dp, LT, FUSED, ADAPT, NT>(p, ws, im, stream);
         default: break;
     }
     if constexpr (Dp >= 128) {  // 64 lanes need at least 2 levels per lane
-        if (gh == 64 && gv == 16) return launch_agg_t<64, 16, Dp, LT, FUSED, ADAPT>(p, ws, im, stream);
-        if (gh == 64 && gv == 32) return launch_agg_t<64, 32, Dp, LT, FUSED, ADAPT>(p, ws, im, stream);
+        if (gh == 64 && gv == 16) return launch_agg_t<64, 16, Dp, LT, FUSED, ADAPT, NT>(p, ws, im, stream);
+        if (gh == 64 && gv == 32) return launch_agg_t<64, 32, Dp, LT, FUSED, ADAPT, NT>(p, ws, im, stream);
     }
     return hipErrorInvalidValue;
 }
 
-template <typename LT, bool FUSED, bool ADAPT>
+template <typename LT, bool FUSED, bool ADAPT, bool NT>
 static hipError_t launch_agg_lt(const Plan& p, const Workspace& ws, Images im, int gh, int gv, hipStream_t stream) {
     if (p.Dp == 64) {
         // Dp = 64 has only 4 levels per lane at G = 16 and 2 at G = 32
-        return launch_agg_dp<64, LT, FUSED, ADAPT>(p, ws, im, gh == 64 ? 32 : gh, gv == 64 ? 32 : gv, stream);
+        return launch_agg_dp<64, LT, FUSED, ADAPT, NT>(p, ws, im, gh == 64 ? 32 : gh, gv == 64 ? 32 : gv, stream);
     }
-    if (p.Dp == 128) return launch_agg_dp<128, LT, FUSED, ADAPT>(p, ws, im, gh, gv, stream);
-    return launch_agg_dp<256, LT, FUSED, ADAPT>(p, ws, im, gh, gv, stream);
+    if (p.Dp == 128) return launch_agg_dp<128, LT, FUSED, ADAPT, NT>(p, ws, im, gh, gv, stream);
+    return launch_agg_dp<256, LT, FUSED, ADAPT, NT>(p, ws, im, gh, gv, stream);
 }
 
 // Group widths: horizontal slices are the longest chains on wide images,
@@ -365,14 +375,19 @@ hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stre
     const Images im{left, right};
     if (p.adaptive) {
         if (!left || (p.lr_full && !right)) return hipErrorInvalidValue;
-        return p.l16 ? launch_agg_lt<uint16_t, false, true>(p, ws, im, gh, gv, stream)
-                     : launch_agg_lt<uint8_t, false, true>(p, ws, im, gh, gv, stream);
+        return p.l16 ? launch_agg_lt<uint16_t, false, true, false>(p, ws, im, gh, gv, stream)
+                     : launch_agg_lt<uint8_t, false, true, false>(p, ws, im, gh, gv, stream);
     }
     if (fused_aggregation(p))
-        return p.l16 ? launch_agg_lt<uint16_t, true, false>(p, ws, im, gh, gv, stream)
-                     : launch_agg_lt<uint8_t, true, false>(p, ws, im, gh, gv, stream);
-    return p.l16 ? launch_agg_lt<uint16_t, false, false>(p, ws, im, gh, gv, stream)
-                 : launch_agg_lt<uint8_t, false, false>(p, ws, im, gh, gv, stream);
+        return p.l16 ? launch_agg_lt<uint16_t, true, false, false>(p, ws, im, gh, gv, stream)
+                     : launch_agg_lt<uint8_t, true, false, false>(p, ws, im, gh, gv, stream);
+    // the store policy is an instruction operand: a second instantiation of
+    // the plain (stored-cost, constant-P2) kernels
+    if (p.nt_store)
+        return p.l16 ? launch_agg_lt<uint16_t, false, false, true>(p, ws, im, gh, gv, stream)
+                     : launch_agg_lt<uint8_t, false, false, true>(p, ws, im, gh, gv, stream);
+    return p.l16 ? launch_agg_lt<uint16_t, false, false, false>(p, ws, im, gh, gv, stream)
+                 : launch_agg_lt<uint8_t, false, false, false>(p, ws, im, gh, gv, stream);
 }
 
 hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream) {

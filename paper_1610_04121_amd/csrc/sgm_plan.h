@@ -23,6 +23,8 @@ struct Plan {
     int lr_thr = 1;
     int cmax = 0;              // largest matching cost
     bool l16 = false;          // L_r stored as u16 (else u8: Cmax + P2 <= 255)
+    bool nt_store = false;     // L_r stores non-temporal: the planes and cost
+                               // volume of a frame exceed the memory-side cache
     bool fused = false;        // aggregation computes costs from census words
                                // instead of reading the cost volume
     bool cc_fused = false;     // cost volume from one census + cost launch (9x7)
