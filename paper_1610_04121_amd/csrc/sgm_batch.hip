@@ -96,20 +96,22 @@ __global__ __launch_bounds__(kCostThreads) void cost_batch_kernel(const BatchIte
         cost_block<false, 256>(a, local % nx, local / nx, cost_smem);
 }
 
-template <typename LT, int Dp>
+// NT: non-temporal L_r stores (the batch's planes exceed the memory-side cache)
+template <typename LT, int Dp, bool NT>
 __device__ inline void aggregate_item(const SliceArgs& s, int kind, int gh, int first, int lane) {
     if (kind == kHoriz) {
         if (gh == 32)
-            aggregate_wave<32, Dp / 32, LT, kHoriz, false>(s, first, lane);
+            aggregate_wave<32, Dp / 32, LT, kHoriz, false, false, NT>(s, first, lane);
         else
-            aggregate_wave<16, Dp / 16, LT, kHoriz, false>(s, first, lane);
+            aggregate_wave<16, Dp / 16, LT, kHoriz, false, false, NT>(s, first, lane);
     } else if (kind == kVert) {
-        aggregate_wave<16, Dp / 16, LT, kVert, false>(s, first, lane);
+        aggregate_wave<16, Dp / 16, LT, kVert, false, false, NT>(s, first, lane);
     } else {
-        aggregate_wave<16, Dp / 16, LT, kDiag, false>(s, first, lane);
+        aggregate_wave<16, Dp / 16, LT, kDiag, false, false, NT>(s, first, lane);
     }
 }
 
+template <bool NT>
 __global__ __launch_bounds__(256) void aggregate_batch_kernel(const BatchItem* items, const WorkItem* work,
                                                               int nwork, unsigned* queue_counter, int P1, int P2) {
     const int lane = threadIdx.x & 63;
@@ -127,13 +129,13 @@ __global__ __launch_bounds__(256) void aggregate_batch_kernel(const BatchItem* i
                           w.ry};
         const int kind = w.ry == 0 ? kHoriz : (w.rx == 0 ? kVert : kDiag);
         if (it.l16) {
-            if (it.Dp == 64) aggregate_item<uint16_t, 64>(s, kind, it.gh, w.first, lane);
-            else if (it.Dp == 128) aggregate_item<uint16_t, 128>(s, kind, it.gh, w.first, lane);
-            else aggregate_item<uint16_t, 256>(s, kind, it.gh, w.first, lane);
+            if (it.Dp == 64) aggregate_item<uint16_t, 64, NT>(s, kind, it.gh, w.first, lane);
+            else if (it.Dp == 128) aggregate_item<uint16_t, 128, NT>(s, kind, it.gh, w.first, lane);
+            else aggregate_item<uint16_t, 256, NT>(s, kind, it.gh, w.first, lane);
         } else {
-            if (it.Dp == 64) aggregate_item<uint8_t, 64>(s, kind, it.gh, w.first, lane);
-            else if (it.Dp == 128) aggregate_item<uint8_t, 128>(s, kind, it.gh, w.first, lane);
-            else aggregate_item<uint8_t, 256>(s, kind, it.gh, w.first, lane);
+            if (it.Dp == 64) aggregate_item<uint8_t, 64, NT>(s, kind, it.gh, w.first, lane);
+            else if (it.Dp == 128) aggregate_item<uint8_t, 128, NT>(s, kind, it.gh, w.first, lane);
+            else aggregate_item<uint8_t, 256, NT>(s, kind, it.gh, w.first, lane);
         }
     }
 }
@@ -370,8 +372,13 @@ int batch_enqueue(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_b
     // persistent grid: at most two wavefronts per SIMD (256 CUs x 4 SIMDs)
     const int nwork = (int)work.size();
     const int waves = std::min(nwork, 2048);
-    hipLaunchKernelGGL(aggregate_batch_kernel, dim3((waves + 3) / 4), dim3(256), 0, s, st->d_items, st->d_work, nwork,
-                       st->counter, bp.P1, bp.P2);
+    // the planes and cost volumes of the whole batch against the memory-side
+    // cache: the store policy of the single-pair path (Plan::nt_store)
+    long long fbytes = 0;
+    for (const BatchItem& d : desc) fbytes += (long long)d.W * d.H * d.Dp * (d.P * (d.l16 ? 2 : 1) + 1);
+    hipLaunchKernelGGL(fbytes > kMallBytes ? aggregate_batch_kernel<true> : aggregate_batch_kernel<false>,
+                       dim3((waves + 3) / 4), dim3(256), 0, s, st->d_items, st->d_work, nwork, st->counter, bp.P1,
+                       bp.P2);
     hipLaunchKernelGGL(wta_batch_kernel, dim3((unsigned)wta_blocks), dim3(1024), wta_smem, s, st->d_items, n);
     if (post_blocks > 0) {
         // pairs without a post stage own empty block ranges; the search for
