@@ -44,10 +44,15 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_1610_04121_amd", "csrc", f)
 
 
 def _kernel_sha() -> str:
-    """Hash of the sources the single-pair kernels are built from."""
+    """Hash of the sources the single-pair kernels are built from, with
+    comments and whitespace removed (edits to those do not change a kernel)."""
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SRCS:
-        h.update(open(f, "rb").read())
+        text = open(f).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -29,9 +29,8 @@ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > 
 // A block covers 64 x 16 pixels of one image (blockIdx.z); each thread makes
 // 4 consecutive census words of one row.  The block stages a (16 + 6) x 72
 // tile (clamp-to-edge), and each thread reads its 12 x 7 window patch as
-// 3 aligned dwords per row.  A comparison bit s(u, v) = [u >= v] is the
-// sign of v - 1 - u, shifted into the word with one v_alignbit, most
-// significant bit first.
+// 3 aligned dwords per row.  The comparisons s(u, v) = [u >= v] of the 4
+// pixels run byte-parallel in one dword (census_words4).
 // ---------------------------------------------------------------------------
 constexpr int kCenTX = 64, kCenTY = 16;
 
