@@ -67,3 +67,23 @@ def test_bench_runs_on_one_gpu_only(n):
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_kernel_hash_ignores_comments_only(tmp_path, monkeypatch):
+    a = tmp_path / "a.h"
+    a.write_text("int f(int x) {  // one\n    return x + 1; /* two */\n}\n")
+    monkeypatch.setattr(bench, "KERNEL_SRCS", [str(a)])
+    h0 = bench._kernel_sha()
+    a.write_text("int f(int x) {\n  // another comment\n  return x + 1;\n}\n")
+    assert bench._kernel_sha() == h0
+    a.write_text("int f(int x) {\n    return x + 2;\n}\n")
+    assert bench._kernel_sha() != h0
+
+
+def test_committed_traffic_summary_matches_the_kernels():
+    # the byte counters in profiles/ were taken from the kernels as they are
+    # now; otherwise bench.py reports traffic null
+    summary = json.load(open(bench.TRAFFIC_FILE))
+    assert summary["kernel_sha"] == bench._kernel_sha()
+    assert bench._traffic(tuple(summary["tuning"])) == summary["bytes_per_launch"]
+    assert 0.9 * 314572800 < summary["bytes_per_launch"] < 1.1 * 314572800
