@@ -366,6 +366,9 @@ def main():
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--inflight", type=int, default=1, help="frames in flight in the timed region")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="single-pair workload of synth.WORKLOADS to time (profiler runs of the other "
+                         "workloads; the default is the headline workload)")
     ap.add_argument("--profile-every", type=int, default=8,
                     help="record stage events on every n-th frame of each context")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -404,9 +407,13 @@ def main():
 
     from paper_1610_04121_amd import SGM, synth
 
-    cfg = synth.WORKLOADS[WORKLOAD]
+    workload = args.workload
+    if workload not in synth.WORKLOADS:
+        print(f"unknown workload {workload}; choose from {sorted(synth.WORKLOADS)}", file=sys.stderr)
+        sys.exit(2)
+    cfg = synth.WORKLOADS[workload]
     W, H, D, P = cfg["w"], cfg["h"], cfg["max_disp"], cfg["n_paths"]
-    pair = synth.workload_pair(WORKLOAD)
+    pair = synth.workload_pair(workload)
     dev = torch.device("cuda:0")
     left = torch.from_numpy(pair.left).to(dev)
     right = torch.from_numpy(pair.right).to(dev)
@@ -433,7 +440,7 @@ def main():
     ctxs = [make_ctx(tuning=choice) for _ in range(F)]
     streams = [torch.cuda.Stream() for _ in range(F)]
     outs = [torch.empty((H, W), dtype=torch.uint16, device=dev) for _ in range(F)]
-    print(f"bench: {WORKLOAD} inflight={F} warmup={args.warmup} steps={args.steps}",
+    print(f"bench: {workload} inflight={F} warmup={args.warmup} steps={args.steps}",
           file=sys.stderr, flush=True)
 
     def run(n):
@@ -515,7 +522,7 @@ def main():
     achieved = agg_bytes / (agg_ms * 1e-3) / 1e9
     roof = {"kernel": "aggregate_kernel", "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": _traffic(tuning), "alg_bytes_per_launch": agg_bytes, "mean_launch_ms": round(agg_ms, 5)}
+            "traffic": _traffic(tuning) if workload == WORKLOAD else None, "alg_bytes_per_launch": agg_bytes, "mean_launch_ms": round(agg_ms, 5)}
     if "copy_gbs" in extras:
         roof["measured_copy_gbs"] = extras["copy_gbs"]
         roof["frac_of_measured_copy"] = round(achieved / extras["copy_gbs"], 4)
@@ -544,7 +551,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "width": W, "height": H, "max_disp": D, "n_paths": P,
+        "config": {"workload": workload, "width": W, "height": H, "max_disp": D, "n_paths": P,
                    "census": "9x7 full", "P1": synth.P1_DEFAULT, "P2": synth.P2_DEFAULT,
                    "median": cfg["median"], "lr_check": cfg["lr"], "scene": cfg["scene"],
                    "seed": cfg["seed"], "frames_in_flight": F,
