@@ -87,3 +87,10 @@ def test_committed_traffic_summary_matches_the_kernels():
     assert summary["kernel_sha"] == bench._kernel_sha()
     assert bench._traffic(tuple(summary["tuning"])) == summary["bytes_per_launch"]
     assert 0.9 * 314572800 < summary["bytes_per_launch"] < 1.1 * 314572800
+
+
+def test_bench_rejects_an_unknown_workload():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "no_such_workload"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "unknown workload" in r.stderr
