@@ -137,6 +137,54 @@ def cpu_baseline(pair, cfg, budget_s: float = 12.0):
                       f"frames (median + LR), single thread, {dt:.1f} s"}
 
 
+def _oracle_frame(spec):
+    """Seconds for one oracle frame of a pair spec (worker of oracle_timing)."""
+    import oracle
+    from paper_1610_04121_amd import synth
+    pr = synth.make_pair(spec["w"], spec["h"], spec["max_disp"], spec["scene"], seed=spec["seed"])
+    t0 = time.perf_counter()
+    oracle.sgm(pr.left, pr.right, spec["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, spec["n_paths"],
+               median=spec.get("median", False), lr=spec.get("lr", False))
+    return time.perf_counter() - t0
+
+
+def oracle_timing() -> dict:
+    """The CPU oracle beside the GPU on every workload, on this host: single-
+    thread seconds per frame of each single-pair workload (median of 3 for the
+    smallest), the makespan of the 64-pair batch with one oracle process per
+    core, and single-thread seconds for each (size, D) of the served mix (run
+    side by side, one process each)."""
+    import multiprocessing as mp
+
+    import oracle
+    from paper_1610_04121_amd import synth
+    oracle.build()
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    out = {"cores": cores, "workloads": {}, "served_kinds": []}
+    for name, cfg in synth.WORKLOADS.items():
+        spec = dict(w=cfg["w"], h=cfg["h"], max_disp=cfg["max_disp"], n_paths=cfg["n_paths"], scene=cfg["scene"],
+                    seed=cfg["seed"], median=cfg["median"], lr=cfg["lr"])
+        runs = [_oracle_frame(spec) for _ in range(3 if cfg["w"] * cfg["h"] <= 320 * 240 else 1)]
+        t = sorted(runs)[len(runs) // 2]
+        out["workloads"][name] = {"s_per_frame": round(t, 3), "frames_per_s": round(1 / t, 4), "runs": len(runs)}
+        print(f"bench: oracle {name}: {t:.2f} s per frame", file=sys.stderr, flush=True)
+    ctx = mp.get_context("spawn")
+    items = [dict(it, median=False, lr=False) for it in synth.batch_items(64)]
+    with ctx.Pool(cores) as pool:
+        t0 = time.perf_counter()
+        per = pool.map(_oracle_frame, items, chunksize=1)
+        out["batch_64"] = {"makespan_s": round(time.perf_counter() - t0, 2), "pairs_per_s": round(64 / (time.perf_counter() - t0), 3),
+                           "sum_single_thread_s": round(sum(per), 1), "processes": cores}
+    print(f"bench: oracle 64-pair batch: {out['batch_64']['makespan_s']} s on {cores} processes", file=sys.stderr,
+          flush=True)
+    kinds = synth.serve_kinds()
+    with ctx.Pool(min(cores, len(kinds))) as pool:
+        per = pool.map(_oracle_frame, kinds, chunksize=1)
+    out["served_kinds"] = [{"size": f"{k['w']}x{k['h']}", "max_disp": k["max_disp"], "s_per_frame": round(t, 2)}
+                           for k, t in zip(kinds, per)]
+    return out
+
+
 def bench_paths(left, right, cfg, steps: int, warmup: int = 50):
     """The paper's path-count axis: 2 (left-to-right and top-to-bottom), 4
     and 8 paths on the headline pair, one frame at a time, autotuned."""
@@ -372,6 +420,9 @@ def main():
     ap.add_argument("--profile-every", type=int, default=8,
                     help="record stage events on every n-th frame of each context")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="also time the CPU oracle on every workload (single-pair latencies, the 64-pair "
+                         "batch over all cores, the served mix); takes a few minutes")
     ap.add_argument("--tuning", default="", help="fixed kernel shape 'lanes_h,lanes_v,fused,census_cost' "
                                                    "instead of autotuning (for profiler runs)")
     ap.add_argument("--no-extras", action="store_true", help="skip serialized/latency/copy measurements")
@@ -592,6 +643,9 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(pair, cfg)
+    if args.oracle_timing:
+        print("bench: timing the CPU oracle on every workload", file=sys.stderr, flush=True)
+        line["oracle_timing"] = oracle_timing()
     print(json.dumps(line), flush=True)
 
 
