@@ -697,8 +697,8 @@ __device__ inline typename Raw<CPL>::T buffer_load_raw(__amdgpu_buffer_rsrc_t r,
     }
 }
 
-// AUX is the cache-policy operand of the store: 0, or 2 for non-temporal
-// (the L_r planes of a frame larger than the memory-side cache stream past it).
+// AUX is the cache-policy operand of the store (gfx950: 2 = non-temporal,
+// 16 = device scope, sc1).
 template <int AUX>
 __device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint16_t v) {
     __builtin_amdgcn_raw_buffer_store_b16(v, r, ofs, 0, AUX);
@@ -718,10 +718,14 @@ __device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint
 }
 
 // Packs a lane's L values in natural disparity order (u8 or u16) and stores
-// them at byte offset `ofs` of the L_r plane (NT: non-temporal stores).
+// them at byte offset `ofs` of the L_r plane.  NT: non-temporal stores (the
+// frame's planes exceed the memory-side cache); otherwise device-scope (sc1)
+// stores, which measured faster than plain ones: the planes still reach the
+// memory-side cache for the WTA, and the L2 keeps more of the cost lines
+// that the opposite direction of a slice re-reads.
 template <int CPL, typename LT, bool NT = false>
 __device__ inline void store_l(__amdgpu_buffer_rsrc_t r, uint32_t ofs, const u16x2 (&l)[CPL / 2]) {
-    constexpr int A = NT ? 2 : 0;
+    constexpr int A = NT ? 2 : 16;
     constexpr uint32_t kLoBytes = 0x06020400u;  // (a.b0, b.b0, a.b2, b.b2) of perm(b, a)
     constexpr uint32_t kPairLo = 0x05040100u;   // (a.lo16, b.lo16)
     constexpr uint32_t kPairHi = 0x07060302u;   // (a.hi16, b.hi16)
