@@ -24,6 +24,15 @@ namespace dev {
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// 16-byte store at byte offset `ofs` of [base, base + bytes) through a
+// range-checked buffer resource, with device scope (sc1): measured faster
+// than plain stores for the intermediate volumes the next kernel reads.
+__device__ inline void store16_sc1(void* base, uint32_t bytes, uint32_t ofs, uint4 v) {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, 0x00020000);
+    __builtin_amdgcn_raw_buffer_store_b128((unsigned __attribute__((ext_vector_type(4)))){v.x, v.y, v.z, v.w}, r, ofs,
+                                           0, 16);
+}
+
 // ---------------------------------------------------------------------------
 // Census kernel: 9x7 windows (full or center-symmetric), register blocked.
 // A block covers 64 x 16 pixels of one image (blockIdx.z); each thread makes
@@ -166,8 +175,12 @@ __device__ inline void census97_block(const CensusArgs& a, int bx, int by, int z
     if (y < a.H) {
         uint64_t* o = a.out[z] + (size_t)y * a.W + x;
         if (x + 3 < a.W && ((a.W & 1) == 0)) {
-            reinterpret_cast<ulonglong2*>(o)[0] = make_ulonglong2(words[0], words[1]);
-            reinterpret_cast<ulonglong2*>(o)[1] = make_ulonglong2(words[2], words[3]);
+            uint64_t* row = a.out[z] + (size_t)y * a.W;
+            auto u4 = [](uint64_t p, uint64_t q) {
+                return make_uint4((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)q, (uint32_t)(q >> 32));
+            };
+            store16_sc1(row, 8u * (uint32_t)a.W, 8u * (uint32_t)x, u4(words[0], words[1]));
+            store16_sc1(row, 8u * (uint32_t)a.W, 8u * (uint32_t)x + 16u, u4(words[2], words[3]));
         } else {
 #pragma unroll
             for (int p = 0; p < 4; ++p)
@@ -340,7 +353,7 @@ __device__ inline void cost_block(const CostArgs& a, int bx, int y, uint64_t* cw
 #pragma unroll
     for (int j = 0; j < nper; ++j) {
         const int c = threadIdx.x + kCostThreads * j;
-        if (c < npx * nchunks) *reinterpret_cast<uint4*>(dst + 16 * c) = v[j];
+        if (c < npx * nchunks) store16_sc1(dst, (uint32_t)(npx * Dp), 16u * (uint32_t)c, v[j]);
     }
 }
 
@@ -506,7 +519,8 @@ __device__ inline void census_cost_block(const CensusCostArgs& a, int bx, int y,
         uint8_t* dst = a.cost + ((size_t)y * a.W + xr0) * Dp;
         for (int c = threadIdx.x; c < npx * nchunks; c += blockDim.x) {
             const int px = c >> lg, k = c & (nchunks - 1);
-            *reinterpret_cast<uint4*>(dst + 16 * c) = *reinterpret_cast<const uint4*>(tile + px * L.tpitch + 16 * k);
+            store16_sc1(dst, (uint32_t)(npx * Dp), 16u * (uint32_t)c,
+                        *reinterpret_cast<const uint4*>(tile + px * L.tpitch + 16 * k));
         }
     }
 }
