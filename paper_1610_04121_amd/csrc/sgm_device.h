@@ -26,7 +26,8 @@ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > 
 
 // 16-byte store at byte offset `ofs` of [base, base + bytes) through a
 // range-checked buffer resource, with device scope (sc1): measured faster
-// than plain stores for the intermediate volumes the next kernel reads.
+// than plain stores for the cost volume, whose wavefronts store contiguous
+// runs (whole lines).
 __device__ inline void store16_sc1(void* base, uint32_t bytes, uint32_t ofs, uint4 v) {
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, 0x00020000);
     __builtin_amdgcn_raw_buffer_store_b128((unsigned __attribute__((ext_vector_type(4)))){v.x, v.y, v.z, v.w}, r, ofs,
@@ -175,12 +176,11 @@ __device__ inline void census97_block(const CensusArgs& a, int bx, int by, int z
     if (y < a.H) {
         uint64_t* o = a.out[z] + (size_t)y * a.W + x;
         if (x + 3 < a.W && ((a.W & 1) == 0)) {
-            uint64_t* row = a.out[z] + (size_t)y * a.W;
-            auto u4 = [](uint64_t p, uint64_t q) {
-                return make_uint4((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)q, (uint32_t)(q >> 32));
-            };
-            store16_sc1(row, 8u * (uint32_t)a.W, 8u * (uint32_t)x, u4(words[0], words[1]));
-            store16_sc1(row, 8u * (uint32_t)a.W, 8u * (uint32_t)x + 16u, u4(words[2], words[3]));
+            // plain (write-back) stores: a thread's two 16-byte stores fill
+            // the two halves of its 32 bytes, which the L2 merges; with
+            // device scope each half would be written through on its own
+            reinterpret_cast<ulonglong2*>(o)[0] = make_ulonglong2(words[0], words[1]);
+            reinterpret_cast<ulonglong2*>(o)[1] = make_ulonglong2(words[2], words[3]);
         } else {
 #pragma unroll
             for (int p = 0; p < 4; ++p)
