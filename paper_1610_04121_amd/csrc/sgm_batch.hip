@@ -140,6 +140,7 @@ __global__ __launch_bounds__(256) void aggregate_batch_kernel(const BatchItem* i
     }
 }
 
+template <bool NT>
 __global__ __launch_bounds__(1024) void wta_batch_kernel(const BatchItem* items, int n) {
     extern __shared__ uint32_t wta_smem[];
     const int b = blockIdx.x;
@@ -148,9 +149,9 @@ __global__ __launch_bounds__(1024) void wta_batch_kernel(const BatchItem* items,
     WtaArgs a{it.lbuf, (size_t)it.W * it.H * it.Dp, post ? it.dl : it.out, it.lrcheck ? it.dr : nullptr,
               it.W, it.H, it.D, it.Dp, it.P, it.subpixel};
     if (it.l16)
-        wta_row<uint16_t>(a, b - it.wta_blk0, wta_smem);
+        wta_row<uint16_t, NT>(a, b - it.wta_blk0, wta_smem);
     else
-        wta_row<uint8_t>(a, b - it.wta_blk0, wta_smem);
+        wta_row<uint8_t, NT>(a, b - it.wta_blk0, wta_smem);
 }
 
 __global__ __launch_bounds__(256) void post_batch_kernel(const BatchItem* items, int n) {
@@ -376,10 +377,12 @@ int batch_enqueue(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_b
     // cache: the store policy of the single-pair path (Plan::nt_store)
     long long fbytes = 0;
     for (const BatchItem& d : desc) fbytes += (long long)d.W * d.H * d.Dp * (d.P * (d.l16 ? 2 : 1) + 1);
-    hipLaunchKernelGGL(fbytes > kMallBytes ? aggregate_batch_kernel<true> : aggregate_batch_kernel<false>,
+    const bool nt = fbytes > kMallBytes;
+    hipLaunchKernelGGL(nt ? aggregate_batch_kernel<true> : aggregate_batch_kernel<false>,
                        dim3((waves + 3) / 4), dim3(256), 0, s, st->d_items, st->d_work, nwork, st->counter, bp.P1,
                        bp.P2);
-    hipLaunchKernelGGL(wta_batch_kernel, dim3((unsigned)wta_blocks), dim3(1024), wta_smem, s, st->d_items, n);
+    hipLaunchKernelGGL(nt ? wta_batch_kernel<true> : wta_batch_kernel<false>, dim3((unsigned)wta_blocks), dim3(1024),
+                       wta_smem, s, st->d_items, n);
     if (post_blocks > 0) {
         // pairs without a post stage own empty block ranges; the search for
         // the last pair whose range starts at or before a block skips them

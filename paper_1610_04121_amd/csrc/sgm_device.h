@@ -1115,7 +1115,20 @@ constexpr int kWtaGuard = 256;  // >= max disparity
 // Sums of 16 disparities d0..d0+15 of one pixel over NPL planes as 8 packed
 // pairs; pair k holds disparities dpair(k) (see below).  Every plane's load
 // is issued before the first add, so a lane has all NPL loads in flight.
-template <typename LT, int NPL>
+// NT: the loads are non-temporal (planes that did not fit the memory-side
+// cache are streamed once).
+template <bool NT>
+__device__ inline uint4 load16(const void* p) {
+    typedef unsigned v4 __attribute__((ext_vector_type(4)));
+    if constexpr (NT) {
+        const v4 t = __builtin_nontemporal_load(reinterpret_cast<const v4*>(p));
+        return make_uint4(t.x, t.y, t.z, t.w);
+    } else {
+        return *reinterpret_cast<const uint4*>(p);
+    }
+}
+
+template <typename LT, int NPL, bool NT>
 __device__ inline void sum16(const LT* base, size_t plane, uint32_t (&S)[8]) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) S[k] = 0;
@@ -1123,7 +1136,7 @@ __device__ inline void sum16(const LT* base, size_t plane, uint32_t (&S)[8]) {
         // bytes b0..b3 of dword i -> pairs (b0, b2) and (b1, b3)
         uint4 q[NPL];
 #pragma unroll
-        for (int p = 0; p < NPL; ++p) q[p] = *reinterpret_cast<const uint4*>(base + plane * p);
+        for (int p = 0; p < NPL; ++p) q[p] = load16<NT>(base + plane * p);
 #pragma unroll
         for (int p = 0; p < NPL; ++p) {
             const uint32_t w[4] = {q[p].x, q[p].y, q[p].z, q[p].w};
@@ -1138,8 +1151,8 @@ __device__ inline void sum16(const LT* base, size_t plane, uint32_t (&S)[8]) {
         uint4 q[NPL][2];
 #pragma unroll
         for (int p = 0; p < NPL; ++p) {
-            q[p][0] = reinterpret_cast<const uint4*>(base + plane * p)[0];
-            q[p][1] = reinterpret_cast<const uint4*>(base + plane * p)[1];
+            q[p][0] = load16<NT>(base + plane * p);
+            q[p][1] = load16<NT>(base + plane * p + 8);
         }
 #pragma unroll
         for (int p = 0; p < NPL; ++p) {
@@ -1174,7 +1187,7 @@ __device__ inline uint32_t lanes_min(uint32_t v, int G) {
     return v;
 }
 
-template <typename LT, int NPL>
+template <typename LT, int NPL, bool NT>
 __device__ inline void wta_row_impl(const WtaArgs& a, int y, uint32_t* keyR_smem) {
     uint32_t* keyR = keyR_smem + kWtaGuard;  // keyR[t], t in [-kWtaGuard, W)
     const bool right = a.dr != nullptr;
@@ -1190,7 +1203,7 @@ __device__ inline void wta_row_impl(const WtaArgs& a, int y, uint32_t* keyR_smem
         const int x = i >> gshift, g = i & (G - 1);
         const int d0 = 16 * g;
         uint32_t S[8];
-        sum16<LT, NPL>(planes + ((size_t)y * a.W + x) * a.Dp + d0, a.plane, S);
+        sum16<LT, NPL, NT>(planes + ((size_t)y * a.W + x) * a.Dp + d0, a.plane, S);
         uint32_t best = ~0u;
         // right-view targets x - d0 - 15 .. x - d0 from one base address
         uint32_t* tgt = keyR + (x - d0 - 15);
@@ -1246,15 +1259,17 @@ __device__ inline void wta_row_impl(const WtaArgs& a, int y, uint32_t* keyR_smem
 }
 
 // One row of the WTA; the plane count (2, 4 or 8) is a template constant of
-// the row's code, so the plane loads unroll.
-template <typename LT>
+// the row's code, so the plane loads unroll.  NT: non-temporal plane loads,
+// for planes that exceed the memory-side cache (they were stored
+// non-temporally too).
+template <typename LT, bool NT = false>
 __device__ inline void wta_row(const WtaArgs& a, int y, uint32_t* keyR_smem) {
     if (a.nplanes == 2)
-        wta_row_impl<LT, 2>(a, y, keyR_smem);
+        wta_row_impl<LT, 2, NT>(a, y, keyR_smem);
     else if (a.nplanes == 4)
-        wta_row_impl<LT, 4>(a, y, keyR_smem);
+        wta_row_impl<LT, 4, NT>(a, y, keyR_smem);
     else
-        wta_row_impl<LT, 8>(a, y, keyR_smem);
+        wta_row_impl<LT, 8, NT>(a, y, keyR_smem);
 }
 
 // ---------------------------------------------------------------------------

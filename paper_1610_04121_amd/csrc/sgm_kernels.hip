@@ -99,23 +99,23 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
     }
 }
 
-template <typename LT>
+template <typename LT, bool NT>
 __global__ __launch_bounds__(1024) void wta_kernel(WtaArgs a) {
     extern __shared__ uint32_t wta_smem[];
-    wta_row<LT>(a, blockIdx.x, wta_smem);
+    wta_row<LT, NT>(a, blockIdx.x, wta_smem);
 }
 
 // Winner-take-all of two SGMs in one launch (full left-right check): rows
 // 0 .. H-1 of the left-base sums give D_L, blocks H .. 2H-1 the rows of the
 // right-base sums, D_R.
-template <typename LT>
+template <typename LT, bool NT>
 __global__ __launch_bounds__(1024) void wta_pair_kernel(WtaArgs l, WtaArgs r) {
     extern __shared__ uint32_t wta_smem[];
     const int y = blockIdx.x;
     if (y < l.H)
-        wta_row<LT>(l, y, wta_smem);
+        wta_row<LT, NT>(l, y, wta_smem);
     else
-        wta_row<LT>(r, y - l.H, wta_smem);
+        wta_row<LT, NT>(r, y - l.H, wta_smem);
 }
 
 __global__ __launch_bounds__(256) void post_kernel(PostArgs a) {
@@ -396,20 +396,20 @@ hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStre
         const void* rbuf = static_cast<const uint8_t*>(ws.lbuf) + plane * p.n_paths * (p.l16 ? 2 : 1);
         WtaArgs l{ws.lbuf, plane, ws.dl, nullptr, p.W, p.H, p.D, p.Dp, p.n_paths, p.subpixel ? 1 : 0};
         WtaArgs r{rbuf, plane, ws.dr, nullptr, p.W, p.H, p.D, p.Dp, p.n_paths};
-        if (p.l16)
-            hipLaunchKernelGGL(wta_pair_kernel<uint16_t>, dim3(2 * p.H), dim3(1024), 0, stream, l, r);
-        else
-            hipLaunchKernelGGL(wta_pair_kernel<uint8_t>, dim3(2 * p.H), dim3(1024), 0, stream, l, r);
+        auto k = p.l16 ? (p.nt_store ? wta_pair_kernel<uint16_t, true> : wta_pair_kernel<uint16_t, false>)
+                       : (p.nt_store ? wta_pair_kernel<uint8_t, true> : wta_pair_kernel<uint8_t, false>);
+        hipLaunchKernelGGL(k, dim3(2 * p.H), dim3(1024), 0, stream, l, r);
         return hipGetLastError();
     }
     const bool post = p.median || p.lrcheck;
     WtaArgs a{ws.lbuf, (size_t)p.W * p.H * p.Dp, post ? ws.dl : out, p.lrcheck ? ws.dr : nullptr,
               p.W, p.H, p.D, p.Dp, p.n_paths, p.subpixel ? 1 : 0};
     const size_t smem = p.lrcheck ? 4 * (size_t)(p.W + kWtaGuard) : 0;
-    if (p.l16)
-        hipLaunchKernelGGL(wta_kernel<uint16_t>, dim3(p.H), dim3(1024), smem, stream, a);
-    else
-        hipLaunchKernelGGL(wta_kernel<uint8_t>, dim3(p.H), dim3(1024), smem, stream, a);
+    // the planes are read the way they were stored: non-temporally when they
+    // exceed the memory-side cache
+    auto k = p.l16 ? (p.nt_store ? wta_kernel<uint16_t, true> : wta_kernel<uint16_t, false>)
+                   : (p.nt_store ? wta_kernel<uint8_t, true> : wta_kernel<uint8_t, false>);
+    hipLaunchKernelGGL(k, dim3(p.H), dim3(1024), smem, stream, a);
     return hipGetLastError();
 }
 
