@@ -120,21 +120,57 @@ def pipeline_bytes(W: int, H: int, Dp: int, P: int, tuning) -> int:
     return census + cost + agg + wta
 
 
-def cpu_baseline(pair, cfg, budget_s: float = 12.0):
+def host_cpu() -> dict:
+    """The host's CPU model and core counts (for the CPU baseline's record)."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "available": len(os.sched_getaffinity(0))}
+
+
+def _pinned_oracle_loop(core, left, right, cfg, budget_s, conn):
+    """Child process of cpu_baseline: pinned to one core, runs whole oracle
+    frames for about budget_s seconds and sends (frames, seconds) back."""
+    os.sched_setaffinity(0, {core})
     import oracle
     oracle.build()
     t0 = time.perf_counter()
     n = 0
     while True:
-        oracle.sgm(pair.left, pair.right, cfg["max_disp"], 7, 86, cfg["n_paths"],
-                   median=cfg["median"], lr=cfg["lr"])
+        oracle.sgm(left, right, cfg["max_disp"], 7, 86, cfg["n_paths"], median=cfg["median"], lr=cfg["lr"])
         n += 1
         if time.perf_counter() - t0 >= budget_s:
             break
-    dt = time.perf_counter() - t0
+    conn.send((n, time.perf_counter() - t0, sorted(os.sched_getaffinity(0))))
+    conn.close()
+
+
+def cpu_baseline(pair, cfg, budget_s: float = 12.0):
+    """The C oracle (single-threaded, never tuned) on whole frames of the
+    workload, in a spawned child process pinned to one host core with
+    sched_setaffinity (the GPU process's own threads stay elsewhere)."""
+    import multiprocessing as mp
+    core = min(os.sched_getaffinity(0))
+    ctx = mp.get_context("spawn")
+    rd, wr = ctx.Pipe(duplex=False)
+    p = ctx.Process(target=_pinned_oracle_loop, args=(core, pair.left, pair.right, cfg, budget_s, wr))
+    p.start()
+    wr.close()
+    while not rd.poll(1.0):  # a child that dies never sends
+        if not p.is_alive():
+            raise RuntimeError(f"cpu_baseline child exited with code {p.exitcode}")
+    n, dt, pinned = rd.recv()
+    p.join()
     return {"value": round(n / dt, 4), "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "pinned_to": pinned, "host_cpu": host_cpu(),
             "sample": f"{n} full {cfg['w']}x{cfg['h']} D={cfg['max_disp']} {cfg['n_paths']}-path "
-                      f"frames (median + LR), single thread, {dt:.1f} s"}
+                      f"frames ({'median + LR' if cfg['median'] else 'WTA only'}), single thread pinned to core {core}, "
+                      f"{dt:.1f} s"}
 
 
 def _oracle_frame(spec):

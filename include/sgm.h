@@ -141,18 +141,22 @@ const char *sgm_last_error(void);
 size_t sgm_footprint_bytes(int width, int height, int max_disp, int n_paths, unsigned flags);
 
 /* ---- batches: many pairs of different shapes in one set of launches ----
- * One item is one stereo pair with its own size, disparity range, path count
- * and options (flags: SGM_MEDIAN3, SGM_LRCHECK, SGM_SUBPIXEL; the census
- * window and P1, P2 belong to the batch).  Buffers follow the conventions
- * above. */
+ * One item is one stereo pair with its own size (w x h), disparity range,
+ * path count and options; the census window and P1, P2 belong to the batch
+ * (or server).  Buffers follow the conventions above.  Item flags:
+ * SGM_MEDIAN3, SGM_LRCHECK, SGM_SUBPIXEL, and the item's left-right
+ * threshold as SGM_ITEM_LR_THRESHOLD(t), t in [0, 255]; without it the
+ * threshold is 1 (as for sgm_set_options). */
 typedef struct {
-    int width, height, max_disp, n_paths;
+    int w, h, max_disp, n_paths;
     unsigned flags;
-    int lr_threshold;
     const uint8_t *left;
     const uint8_t *right;
     uint16_t *out;
 } sgm_item;
+
+#define SGM_ITEM_THRESHOLD_SET 0x100u
+#define SGM_ITEM_LR_THRESHOLD(t) (SGM_ITEM_THRESHOLD_SET | (((unsigned)(t) & 0xFFu) << 16))
 
 typedef struct sgm_batch sgm_batch;
 
@@ -219,12 +223,19 @@ typedef struct {
 
 /* Creates a server on the current HIP device.  hbm_budget_bytes: workspace
  * bytes to reserve (rounded down to 256); max_slots in [1, 16]: groups in
- * flight at once; n_streams in [1, max_slots]: streams the slots are spread
- * over (1 = groups run one after another in admission order); P1, P2 and
- * the census window apply to every request.  NULL on error (SGM_EINVAL for
- * bad parameters, SGM_ENOMEM if the budget cannot be allocated). */
-sgm_server *sgm_server_create(size_t hbm_budget_bytes, int max_slots, int n_streams, int P1, int P2,
-                              int census_w, int census_h);
+ * flight at once, each slot on a stream of its own (slots on different
+ * streams run concurrently); P1, P2 and the census window apply to every
+ * request.  NULL on error (SGM_EINVAL for bad parameters, SGM_ENOMEM if the
+ * budget cannot be allocated). */
+sgm_server *sgm_server_create(size_t hbm_budget_bytes, int max_slots, int P1, int P2, int census_w,
+                              int census_h);
+
+/* As sgm_server_create, with the slots spread round-robin over n_streams
+ * streams, n_streams in [1, max_slots] (1 = groups run one after another in
+ * admission order; slots sharing a stream run their groups back to back
+ * without waiting for the host). */
+sgm_server *sgm_server_create_ex(size_t hbm_budget_bytes, int max_slots, int n_streams, int P1, int P2,
+                                 int census_w, int census_h);
 
 /* Group limits, queue length and overlap.  A group takes at most max_group
  * requests (default 8, at most 256) and, unless it holds a single request,
@@ -285,6 +296,18 @@ int sgm_debug_census(sgm_ctx *ctx, const uint8_t *img, uint64_t *census_out,
  * (d fastest), S(p, d) = sum over directions of L_r(p, d). */
 int sgm_debug_sums(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right, uint16_t *s_out,
                    sgm_stream_t stream);
+
+/* Partial sums of the aggregation schedule, u16 [H][W][max_disp] (d
+ * fastest).  The last direction of the path set (right-to-left; with 2 paths
+ * left-to-right) is the one the final pass fuses with the sum and the
+ * winner-take-all (Sec. 3.3), so the schedule has two phases:
+ *   phase 0: S_0(p, d) = sum of L_r(p, d) over every other direction (the
+ *            planes the first aggregation launch stores);
+ *   phase 1: S(p, d) = S_0(p, d) + L_last(p, d), the sums the final pass
+ *            takes its winners from (Eq. 4).
+ * Other phases return SGM_EINVAL. */
+int sgm_debug_phase_sums(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right, int phase,
+                         uint16_t *s_out, sgm_stream_t stream);
 
 /* One intermediate as u16 [H][W][max_disp] (d fastest): which = -1 gives the
  * matching cost C (Eq. 2); which = r in [0, n_paths) gives L_r of path

@@ -28,6 +28,12 @@ struct BatchLayout {
 // rounded up to 256 bytes).  false with *why set if an item is invalid.
 bool batch_plan(const BatchParams& bp, const sgm_item* items, int n, BatchLayout& L, const char** why);
 
+// The left-right threshold an item's flags carry (SGM_ITEM_LR_THRESHOLD),
+// 1 when they carry none.
+inline int item_lr_threshold(unsigned flags) {
+    return (flags & SGM_ITEM_THRESHOLD_SET) ? (int)((flags >> 16) & 0xFFu) : 1;
+}
+
 // Bytes one item's workspace takes in an arena (a multiple of 256).
 size_t item_bytes(const Plan& p);
 

@@ -180,8 +180,8 @@ bool batch_plan(const BatchParams& bp, const sgm_item* items, int n, BatchLayout
     for (int i = 0; i < n; ++i) {
         const sgm_item& it = items[i];
         Plan p;
-        p.W = it.width;
-        p.H = it.height;
+        p.W = it.w;
+        p.H = it.h;
         p.D = it.max_disp;
         p.P1 = bp.P1;
         p.P2 = bp.P2;
@@ -192,9 +192,9 @@ bool batch_plan(const BatchParams& bp, const sgm_item* items, int n, BatchLayout
         p.median = (it.flags & SGM_MEDIAN3) != 0;
         p.lrcheck = (it.flags & SGM_LRCHECK) != 0;
         p.subpixel = (it.flags & SGM_SUBPIXEL) != 0;
-        p.lr_thr = it.lr_threshold;
-        if (it.flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK | SGM_SUBPIXEL)) {
-            *why = "item flags may only hold SGM_MEDIAN3, SGM_LRCHECK and SGM_SUBPIXEL";
+        p.lr_thr = item_lr_threshold(it.flags);
+        if (it.flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK | SGM_SUBPIXEL | SGM_ITEM_THRESHOLD_SET | 0x00FF0000u)) {
+            *why = "item flags may only hold SGM_MEDIAN3, SGM_LRCHECK, SGM_SUBPIXEL and SGM_ITEM_LR_THRESHOLD(t)";
             return false;
         }
         if (!plan_finish(p, why)) return false;

@@ -31,8 +31,12 @@ int hip_err(hipError_t e, const char* what) {
     return set_err(SGM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-bool make_plan(sgm::Plan& p, int w, int h, int d, int P1, int P2, int n_paths, int cw, int ch,
-               unsigned flags, int thr) {
+}  // namespace
+
+namespace sgm {
+
+bool plan_from_options(Plan& p, int w, int h, int d, int P1, int P2, int n_paths, int cw, int ch, unsigned flags,
+                       int thr) {
     p.W = w;
     p.H = h;
     p.D = d;
@@ -58,14 +62,14 @@ bool make_plan(sgm::Plan& p, int w, int h, int d, int P1, int P2, int n_paths, i
         set_err(SGM_EINVAL, "SGM_LR_FULL needs SGM_LRCHECK");
         return false;
     }
-    if (!sgm::plan_finish(p, &why)) {
+    if (!plan_finish(p, &why)) {
         set_err(SGM_EINVAL, why);
         return false;
     }
     return true;
 }
 
-}  // namespace
+}  // namespace sgm
 
 struct sgm_ctx {
     sgm::Plan plan;
@@ -104,7 +108,7 @@ const char* sgm_last_error(void) { return g_err.c_str(); }
 int sgm_validate(int width, int height, int max_disp, int P1, int P2, int n_paths, int census_w,
                  int census_h, unsigned flags) {
     sgm::Plan p;
-    if (!make_plan(p, width, height, max_disp, P1, P2, n_paths, census_w, census_h, flags, 1))
+    if (!sgm::plan_from_options(p, width, height, max_disp, P1, P2, n_paths, census_w, census_h, flags, 1))
         return SGM_EINVAL;
     return SGM_OK;
 }
@@ -112,7 +116,7 @@ int sgm_validate(int width, int height, int max_disp, int P1, int P2, int n_path
 size_t sgm_footprint_bytes(int width, int height, int max_disp, int n_paths, unsigned flags) {
     // the u8/u16 choice of L_r depends on P2; count the larger case
     sgm::Plan p;
-    if (!make_plan(p, width, height, max_disp, 0, 0, n_paths, 9, 7, flags, 1)) return 0;
+    if (!sgm::plan_from_options(p, width, height, max_disp, 0, 0, n_paths, 9, 7, flags, 1)) return 0;
     p.l16 = true;
     return sgm::workspace_bytes(p);
 }
@@ -120,7 +124,7 @@ size_t sgm_footprint_bytes(int width, int height, int max_disp, int n_paths, uns
 sgm_ctx* sgm_create(int width, int height, int max_disp, int P1, int P2, int n_paths, int census_w,
                     int census_h) {
     sgm::Plan p;
-    if (!make_plan(p, width, height, max_disp, P1, P2, n_paths, census_w, census_h, 0, 1)) return nullptr;
+    if (!sgm::plan_from_options(p, width, height, max_disp, P1, P2, n_paths, census_w, census_h, 0, 1)) return nullptr;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) {
@@ -152,7 +156,7 @@ sgm_ctx* sgm_create(int width, int height, int max_disp, int P1, int P2, int n_p
 int sgm_set_options(sgm_ctx* c, unsigned flags, int lr_threshold) {
     if (!c) return set_err(SGM_EINVAL, "null context");
     sgm::Plan p = c->plan;
-    if (!make_plan(p, p.W, p.H, p.D, p.P1, p.P2, p.n_paths, p.cw, p.ch, flags, lr_threshold))
+    if (!sgm::plan_from_options(p, p.W, p.H, p.D, p.P1, p.P2, p.n_paths, p.cw, p.ch, flags, lr_threshold))
         return SGM_EINVAL;
     p.lanes_h = c->plan.lanes_h;
     p.lanes_v = c->plan.lanes_v;
@@ -339,6 +343,19 @@ int sgm_debug_sums(sgm_ctx* c, const uint8_t* left, const uint8_t* right, uint16
     hipError_t e = sgm::launch_matching_cost(c->plan, c->ws, left, right, !sgm::fused_aggregation(c->plan), s);
     if (e == hipSuccess) e = sgm::launch_aggregate(c->plan, c->ws, s, left, right);
     if (e == hipSuccess) e = sgm::launch_sum_planes(c->plan, c->ws, s_out, s);
+    if (e != hipSuccess) return hip_err(e, "kernel launch");
+    return SGM_OK;
+}
+
+int sgm_debug_phase_sums(sgm_ctx* c, const uint8_t* left, const uint8_t* right, int phase, uint16_t* s_out,
+                         sgm_stream_t stream) {
+    if (!c) return set_err(SGM_EINVAL, "null context");
+    if (int rc = check_ptrs(left, right, s_out)) return rc;
+    if (phase < 0 || phase > 1) return set_err(SGM_EINVAL, "phase must be 0 or 1");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = sgm::launch_matching_cost(c->plan, c->ws, left, right, !sgm::fused_aggregation(c->plan), s);
+    if (e == hipSuccess) e = sgm::launch_aggregate(c->plan, c->ws, s, left, right);
+    if (e == hipSuccess) e = sgm::launch_sum_planes(c->plan, c->ws, s_out, s, phase == 0 ? sgm::last_direction(c->plan) : -1);
     if (e != hipSuccess) return hip_err(e, "kernel launch");
     return SGM_OK;
 }

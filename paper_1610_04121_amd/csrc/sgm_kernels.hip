@@ -124,14 +124,16 @@ __global__ __launch_bounds__(256) void post_kernel(PostArgs a) {
 }
 
 // Debug tap: S = sum of planes, u16 [H][W][D].
+// Plane `skip` (-1: none) is left out.
 template <typename LT>
 __global__ void sum_planes_kernel(const void* lbuf, size_t plane, uint16_t* s, int W, int H, int D,
-                                  int Dp, int nplanes) {
+                                  int Dp, int nplanes, int skip) {
     const size_t n = (size_t)W * H * D;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const size_t p = i / D, d = i - p * D;
         uint32_t acc = 0;
-        for (int k = 0; k < nplanes; ++k) acc += reinterpret_cast<const LT*>(lbuf)[plane * k + p * Dp + d];
+        for (int k = 0; k < nplanes; ++k)
+            if (k != skip) acc += reinterpret_cast<const LT*>(lbuf)[plane * k + p * Dp + d];
         s[i] = (uint16_t)acc;
     }
 }
@@ -442,14 +444,14 @@ hipError_t launch_census_only(const Plan& p, const uint8_t* img, uint64_t* out, 
     return launch_census_pair(p, img, img, out, out, 1, stream);
 }
 
-hipError_t launch_sum_planes(const Plan& p, const Workspace& ws, uint16_t* s_out, hipStream_t stream) {
+hipError_t launch_sum_planes(const Plan& p, const Workspace& ws, uint16_t* s_out, hipStream_t stream, int skip) {
     const size_t plane = (size_t)p.W * p.H * p.Dp;
     if (p.l16)
         hipLaunchKernelGGL(sum_planes_kernel<uint16_t>, dim3(1024), dim3(256), 0, stream, ws.lbuf, plane, s_out,
-                           p.W, p.H, p.D, p.Dp, p.n_paths);
+                           p.W, p.H, p.D, p.Dp, p.n_paths, skip);
     else
         hipLaunchKernelGGL(sum_planes_kernel<uint8_t>, dim3(1024), dim3(256), 0, stream, ws.lbuf, plane, s_out,
-                           p.W, p.H, p.D, p.Dp, p.n_paths);
+                           p.W, p.H, p.D, p.Dp, p.n_paths, skip);
     return hipGetLastError();
 }
 

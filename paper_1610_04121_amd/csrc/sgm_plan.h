@@ -4,6 +4,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "sgm_common.h"
 
 namespace sgm {
@@ -46,6 +48,12 @@ struct Workspace {
 
 // Fills the derived fields of a plan; returns false if invalid (message set).
 bool plan_finish(Plan& p, const char** why);
+// A plan from sgm_create's parameters and sgm_set_options' flags and
+// threshold; false if invalid (message in sgm_last_error).
+bool plan_from_options(Plan& p, int w, int h, int d, int P1, int P2, int n_paths, int cw, int ch, unsigned flags,
+                       int thr);
+// Message returned by sgm_last_error on this thread.
+void set_last_error(const std::string& msg);
 size_t workspace_bytes(const Plan& p);
 // Carves a workspace out of one device allocation of workspace_bytes(p).
 Workspace workspace_carve(const Plan& p, void* base);
@@ -72,6 +80,11 @@ bool fused_aggregation(const Plan& p);
 void default_lanes(const Plan& p, int* gh, int* gv);
 hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream);
 hipError_t launch_post(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream);
+// The direction the final pass fuses with the sum and the winner-take-all
+// (Sec. 3.3): right-to-left (direction index 1), or left-to-right (index 0)
+// in the 2-path set, which has no right-to-left direction.
+inline int last_direction(const Plan& p) { return p.n_paths == 2 ? 0 : 1; }
+
 // Stages of one pipeline pass, in launch order.
 enum Stage { kStageCensusCost = 0, kStageAggregate = 1, kStageWta = 2, kStagePost = 3, kNumStages = 4 };
 
@@ -84,8 +97,9 @@ hipError_t launch_pipeline(const Plan& p, const Workspace& ws, const uint8_t* le
 // Debug taps.
 hipError_t launch_census_only(const Plan& p, const uint8_t* img, uint64_t* out,
                               hipStream_t stream);
+// S = sum of the L_r planes, leaving out plane `skip` (-1: none).
 hipError_t launch_sum_planes(const Plan& p, const Workspace& ws, uint16_t* s_out,
-                             hipStream_t stream);
+                             hipStream_t stream, int skip = -1);
 // Copies plane `plane` of L_r (or the cost volume when plane < 0) out as u16
 // [H][W][D].
 hipError_t launch_extract_plane(const Plan& p, const Workspace& ws, int plane, uint16_t* out,

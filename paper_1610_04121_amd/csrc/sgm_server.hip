@@ -281,8 +281,12 @@ bool check_item(const sgm_server* s, const sgm_item* it, sgm::Plan* plan, size_t
 
 extern "C" {
 
-sgm_server* sgm_server_create(size_t hbm_budget_bytes, int max_slots, int n_streams, int P1, int P2, int census_w,
-                              int census_h) {
+sgm_server* sgm_server_create(size_t hbm_budget_bytes, int max_slots, int P1, int P2, int census_w, int census_h) {
+    return sgm_server_create_ex(hbm_budget_bytes, max_slots, max_slots, P1, P2, census_w, census_h);
+}
+
+sgm_server* sgm_server_create_ex(size_t hbm_budget_bytes, int max_slots, int n_streams, int P1, int P2,
+                                 int census_w, int census_h) {
     sgm::Plan probe;  // batch-wide parameters, checked on a 1x1 pair
     probe.W = probe.H = probe.D = 1;
     probe.P1 = P1;
@@ -386,7 +390,7 @@ int sgm_server_submit(sgm_server* s, const sgm_item* req, uint64_t* ticket) {
         return serr(SGM_ENOMEM, "request workspace exceeds the server's memory budget");
     }
     r->item = *req;
-    r->cells = (uint64_t)req->width * req->height * req->max_disp * req->n_paths;
+    r->cells = (uint64_t)req->w * req->h * req->max_disp * req->n_paths;
     r->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(s->mu);

@@ -26,6 +26,7 @@ EXPORTS = [
     "sgm_compute_batch",
     "sgm_server_create", "sgm_server_set_policy", "sgm_server_request_bytes", "sgm_server_submit",
     "sgm_server_poll", "sgm_server_wait", "sgm_server_cancel", "sgm_server_get_stats", "sgm_server_destroy",
+    "sgm_server_create_ex", "sgm_debug_phase_sums",
 ]
 
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELED, REQ_FAILED = range(5)
@@ -41,9 +42,19 @@ class ServerStats(ctypes.Structure):
 
 class Item(ctypes.Structure):
     """Mirror of sgm_item."""
-    _fields_ = [("width", ctypes.c_int), ("height", ctypes.c_int), ("max_disp", ctypes.c_int),
-                ("n_paths", ctypes.c_int), ("flags", ctypes.c_uint), ("lr_threshold", ctypes.c_int),
+    _fields_ = [("w", ctypes.c_int), ("h", ctypes.c_int), ("max_disp", ctypes.c_int),
+                ("n_paths", ctypes.c_int), ("flags", ctypes.c_uint),
                 ("left", ctypes.c_void_p), ("right", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+ITEM_THRESHOLD_SET = 0x100
+
+
+def item_lr_threshold(t: int) -> int:
+    """SGM_ITEM_LR_THRESHOLD(t): an item's left-right threshold as flag bits."""
+    if not 0 <= t <= 255:
+        raise ValueError("item lr_threshold must be in [0, 255]")
+    return ITEM_THRESHOLD_SET | (t << 16)
 STAGES = ("census_cost", "aggregate", "wta", "post")
 
 
@@ -102,8 +113,12 @@ def lib() -> ctypes.CDLL:
     L.sgm_batch_destroy.restype = None
     L.sgm_compute_batch.argtypes = [ctypes.POINTER(Item), i, i, i, i, i, P]
     L.sgm_compute_batch.restype = i
-    L.sgm_server_create.argtypes = [ctypes.c_size_t, i, i, i, i, i, i]
+    L.sgm_server_create.argtypes = [ctypes.c_size_t, i, i, i, i, i]
     L.sgm_server_create.restype = P
+    L.sgm_server_create_ex.argtypes = [ctypes.c_size_t, i, i, i, i, i, i]
+    L.sgm_server_create_ex.restype = P
+    L.sgm_debug_phase_sums.argtypes = [P, P, P, i, P, P]
+    L.sgm_debug_phase_sums.restype = i
     L.sgm_server_set_policy.argtypes = [P, i, i, ctypes.c_uint64, i]
     L.sgm_server_set_policy.restype = i
     L.sgm_server_request_bytes.argtypes = [P, ctypes.POINTER(Item)]
@@ -264,6 +279,17 @@ class SGM:
                                     _ptr(out, "torch.uint16", shape), _stream(stream)))
         return out
 
+    def debug_phase_sums(self, left, right, phase, stream=None):
+        """Partial sums u16 [H][W][D]: phase 0 = every direction but the one
+        the final pass fuses, phase 1 = all directions (sgm_debug_phase_sums)."""
+        import torch
+        shape = (self.height, self.width, self.max_disp)
+        out = torch.empty(shape, dtype=torch.uint16, device=left.device)
+        _check(lib().sgm_debug_phase_sums(self._ctx, _ptr(left, "torch.uint8", self.shape),
+                                          _ptr(right, "torch.uint8", self.shape), phase,
+                                          _ptr(out, "torch.uint16", shape), _stream(stream)))
+        return out
+
     def debug_stage(self, left, right, which, stream=None):
         """which = -1: cost volume C; which = r: L_r of direction r (u16
         [H][W][D]); with lr_full, -2: right-base costs, n_paths + r: right-base
@@ -311,13 +337,16 @@ class SGM:
 
 def _items(pairs):
     """pairs: dicts with left, right, out (device tensors), max_disp, n_paths and
-    optional median, lrcheck, subpixel, lr_threshold."""
+    optional median, lrcheck, subpixel, lr_full, adaptive_p2, lr_threshold."""
     arr = (Item * len(pairs))()
     for k, p in enumerate(pairs):
         h, w = p["left"].shape
         flags = (MEDIAN3 if p.get("median") else 0) | (LRCHECK if p.get("lrcheck") else 0) | \
-            (SUBPIXEL if p.get("subpixel") else 0)
-        arr[k] = Item(w, h, p["max_disp"], p["n_paths"], flags, p.get("lr_threshold", 1),
+            (SUBPIXEL if p.get("subpixel") else 0) | (LR_FULL if p.get("lr_full") else 0) | \
+            (ADAPTIVE_P2 if p.get("adaptive_p2") else 0)
+        if p.get("lr_threshold", 1) != 1:
+            flags |= item_lr_threshold(p["lr_threshold"])
+        arr[k] = Item(w, h, p["max_disp"], p["n_paths"], flags,
                       _ptr(p["left"], "torch.uint8", (h, w)), _ptr(p["right"], "torch.uint8", (h, w)),
                       _ptr(p["out"], "torch.uint16", (h, w)))
     return arr
@@ -362,8 +391,10 @@ class Server:
                  census_w=9, census_h=7, max_group: int = 8, max_pending: int = 4096,
                  max_group_cells: int = 1 << 28, overlap_queue: int = 3):
         """streams defaults to one per slot (groups run concurrently)."""
-        streams = slots if streams is None else streams
-        self._s = lib().sgm_server_create(hbm_budget_bytes, slots, streams, P1, P2, census_w, census_h)
+        if streams is None:
+            self._s = lib().sgm_server_create(hbm_budget_bytes, slots, P1, P2, census_w, census_h)
+        else:
+            self._s = lib().sgm_server_create_ex(hbm_budget_bytes, slots, streams, P1, P2, census_w, census_h)
         if not self._s:
             raise SGMError(SGM_EINVAL, last_error())
         self._held = {}

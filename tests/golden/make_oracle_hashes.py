@@ -1,9 +1,10 @@
 """Writes the oracle's disparities, as SHA-256 digests, for the full-size
-64-pair batch workload and for each (size, disparity range) of the served
-request mix.  It calls only the CPU oracle and the seeded generator; the GPU
-tests compare the HIP path's outputs with these digests.
+64-pair batch workload (without, and with median + left-right check on every
+pair) and for each (size, disparity range) of the served request mix.  It
+calls only the CPU oracle and the seeded generator; the GPU tests compare the
+HIP path's outputs with these digests.
 
-    python tests/golden/make_oracle_hashes.py     (about a minute on 6 cores)
+    python tests/golden/make_oracle_hashes.py     (a few minutes on 8 cores)
 """
 import hashlib
 import json
@@ -34,11 +35,13 @@ def main():
     from paper_1610_04121_amd import synth
     oracle.build()
     batch = synth.batch_items(64)
+    batch_post = [dict(it, median=True, lr=True) for it in batch]
     serve = synth.serve_kinds()
-    with Pool(6) as pool:
+    with Pool(min(8, os.cpu_count() or 1)) as pool:
         b = pool.map(_one, batch, chunksize=1)
+        bp = pool.map(_one, batch_post, chunksize=1)
         s = pool.map(_one, serve, chunksize=1)
-    doc = {"P1": P1, "P2": P2, "census": "9x7 full", "batch64": b, "serve_kinds": s}
+    doc = {"P1": P1, "P2": P2, "census": "9x7 full", "batch64": b, "batch64_median_lr": bp, "serve_kinds": s}
     with open(os.path.join(HERE, "oracle_hashes.json"), "w") as f:
         json.dump(doc, f, indent=1)
 

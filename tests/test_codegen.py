@@ -58,3 +58,46 @@ def test_no_scalar_cache_writes(device_asm):
     for pat in (r"\bs_store_", r"\bs_atomic_", r"\bs_buffer_store", r"\bs_buffer_atomic", r"\bs_dcache_wb",
                 r"\bs_dcache_discard"):
         assert not re.search(pat, device_asm), pat
+
+
+def _kernel_bodies(asm):
+    """{kernel symbol: its instructions} for every function in the listing."""
+    out = {}
+    for m in re.finditer(r"^(_Z\S+):(?:[ \t]*;[^\n]*)?$", asm, re.M):
+        name = m.group(1)
+        end = asm.find(".Lfunc_end", m.end())
+        out[name] = asm[m.end():end if end >= 0 else len(asm)]
+    return out
+
+
+def _descriptor(asm, name):
+    i = asm.index(f".amdhsa_kernel {name}\n")
+    return asm[i:asm.index(".end_amdhsa_kernel", i)]
+
+
+def test_f16_minimum_kernels_keep_f16_denormals(device_asm):
+    # On u8 planes the three-way minimum is a packed f16 minimum over integer
+    # bit patterns below 0x1000, most of them f16 subnormals: it equals the
+    # integer minimum only while the kernel keeps f16 denormals (mode 3 = no
+    # flushing of inputs or outputs).
+    users = [n for n, body in _kernel_bodies(device_asm).items() if "v_pk_minimum3_f16" in body]
+    assert any("aggregate_kernel" in n for n in users)
+    for n in users:
+        assert re.search(r"\.amdhsa_float_denorm_mode_16_64 3\b", _descriptor(device_asm, n)), n
+
+
+def test_f16_order_equals_unsigned_order_below_0x1000():
+    # Exhaustive over every pair of u16 patterns below 0x1000 (zero, the f16
+    # subnormals and the small normals): the IEEE minimum of the two values
+    # read as f16 is the smaller pattern read as an unsigned integer.
+    import numpy as np
+    a = np.arange(0x1000, dtype=np.uint16)
+    fa = a.view(np.float16)
+    for lo in range(0, 0x1000, 0x400):
+        b = np.arange(lo, lo + 0x400, dtype=np.uint16)
+        got = np.minimum(fa[:, None], b.view(np.float16)[None, :]).view(np.uint16)
+        want = np.minimum(a[:, None], b[None, :])
+        assert np.array_equal(got, want)
+    # and 0x0FFF (the kernels' stand-in for a missing neighbour) is above every
+    # real candidate: Cmax + largest penalty <= 255 < 0x0FFF
+    assert float(np.uint16(0x0FFF).view(np.float16)) > float(np.uint16(255 + 255).view(np.float16))

@@ -20,13 +20,22 @@ def test_digests_reproduce_for_small_entries():
         assert pr.sha_left == g["sha_left"] and pr.sha_right == g["sha_right"]
         out = oracle.sgm(pr.left, pr.right, g["max_disp"], doc["P1"], doc["P2"], g["n_paths"]).out
         assert hashlib.sha256(out.tobytes()).hexdigest() == g["out_sha256"]
+    small = sorted(doc["batch64_median_lr"], key=lambda g: g["w"] * g["h"] * g["max_disp"] * g["n_paths"])[:1]
+    for g in small:
+        assert g["median"] and g["lr"]
+        pr = synth.make_pair(g["w"], g["h"], g["max_disp"], g["scene"], seed=g["seed"])
+        out = oracle.sgm(pr.left, pr.right, g["max_disp"], doc["P1"], doc["P2"], g["n_paths"], median=True,
+                         lr=True).out
+        assert hashlib.sha256(out.tobytes()).hexdigest() == g["out_sha256"]
+        assert int((out == 0xFFFF).sum()) == g["invalid"]
 
 
 def test_digest_entries_match_the_workload_definitions():
     doc = json.load(open(GOLDEN))
     items = synth.batch_items(64)
-    assert [(i["w"], i["h"], i["max_disp"], i["n_paths"], i["seed"]) for i in items] == \
-        [(g["w"], g["h"], g["max_disp"], g["n_paths"], g["seed"]) for g in doc["batch64"]]
+    for key in ("batch64", "batch64_median_lr"):
+        assert [(i["w"], i["h"], i["max_disp"], i["n_paths"], i["seed"]) for i in items] == \
+            [(g["w"], g["h"], g["max_disp"], g["n_paths"], g["seed"]) for g in doc[key]]
     kinds = synth.serve_kinds()
     assert [(k["w"], k["h"], k["max_disp"], k["seed"]) for k in kinds] == \
         [(g["w"], g["h"], g["max_disp"], g["seed"]) for g in doc["serve_kinds"]]

@@ -147,3 +147,55 @@ def test_batch_subpixel_items(gpu):
                           median=p["median"], lr=p["lrcheck"], subpixel=p["subpixel"]).out
         assert (p["out"].cpu().numpy() == want).all(), k
     b.close()
+
+
+def test_workload_batch_median_lr_matches_oracle_digests(gpu):
+    """The 64-pair mixed batch with median + left-right check on every pair
+    (the configuration the benchmark times as batched_median_lr): every pair
+    against the oracle's digest and against a single-pair call."""
+    import torch
+    items = synth.batch_items(64)
+    specs = [(it["w"], it["h"], it["max_disp"], it["n_paths"], True, True) for it in items]
+    pairs = _pairs(specs, gpu, 0, [(it["scene"], it["seed"]) for it in items])
+    _say("64-pair workload batch with median + LR")
+    b = Batch(7, 86)
+    b.compute(pairs)
+    torch.cuda.synchronize()
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_hashes.json")))
+    golden = golden["batch64_median_lr"]
+    assert len(golden) == len(pairs)
+    seq = {}
+    for k, (p, g) in enumerate(zip(pairs, golden)):
+        assert (g["w"], g["h"], g["max_disp"], g["n_paths"], g["median"], g["lr"]) == \
+            (items[k]["w"], items[k]["h"], items[k]["max_disp"], items[k]["n_paths"], True, True)
+        assert hashlib.sha256(p["np_left"].tobytes()).hexdigest() == g["sha_left"], k
+        got = p["out"].cpu().numpy()
+        assert hashlib.sha256(got.tobytes()).hexdigest() == g["out_sha256"], k
+        h, w = p["left"].shape
+        key = (w, h, p["max_disp"], p["n_paths"])
+        if key not in seq:
+            seq[key] = SGM(w, h, p["max_disp"], 7, 86, p["n_paths"], median=True, lrcheck=True)
+        one = seq[key].compute(p["left"], p["right"])
+        torch.cuda.synchronize()
+        assert (one.cpu().numpy() == got).all(), k
+    for c in seq.values():
+        c.close()
+    b.close()
+
+
+def test_batch_item_thresholds(gpu):
+    """Per-item left-right thresholds carried in the item flags."""
+    import torch
+    specs = [(64, 48, 40, 4, True, True), (50, 30, 32, 8, False, True), (40, 40, 24, 2, True, True)]
+    pairs = _pairs(specs, gpu, 1500)
+    for p, thr in zip(pairs, (0, 3, 1)):
+        p["lr_threshold"] = thr
+    _say("batch with per-item thresholds")
+    b = Batch(7, 86)
+    b.compute(pairs)
+    torch.cuda.synchronize()
+    for k, p in enumerate(pairs):
+        want = oracle.sgm(p["np_left"], p["np_right"], p["max_disp"], 7, 86, p["n_paths"],
+                          median=p["median"], lr=p["lrcheck"], lr_thr=p["lr_threshold"]).out
+        assert (p["out"].cpu().numpy() == want).all(), k
+    b.close()

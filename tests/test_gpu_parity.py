@@ -462,3 +462,51 @@ def test_graph_replay_with_all_options(gpu):
             assert (_np(o) == want[i]).all(), (rep, i)
     graph.close()
     eager.close()
+
+
+@pytest.mark.parametrize("P", [2, 4, 8])
+def test_paths_sweep_full_size_every_kernel_shape(gpu, P):
+    """The headline pair at each path count of the benchmark's path sweep, with
+    every kernel shape the autotuner may pick for it (the sweep times the
+    tuner's choice): bit-exact with the oracle at full size."""
+    cfg = synth.WORKLOADS["vga_640x480_d128_p4"]
+    pair = synth.workload_pair("vga_640x480_d128_p4")
+    want = oracle.sgm(pair.left, pair.right, cfg["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, P,
+                      median=cfg["median"], lr=cfg["lr"]).out
+    tl, tr = _t(pair.left, gpu), _t(pair.right, gpu)
+    s = SGM(cfg["w"], cfg["h"], cfg["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, P,
+            median=cfg["median"], lrcheck=cfg["lr"])
+    for gh, gv in [(16, 16), (32, 16), (32, 32), (64, 16), (64, 32)]:
+        for census_cost in (False, True):
+            _say(f"path sweep P={P} lanes=({gh},{gv}) census_cost={census_cost}")
+            s.set_tuning(gh, gv, False, census_cost)
+            got = _np(s.compute(tl, tr))
+            bad = np.argwhere(got != want)
+            assert len(bad) == 0, (gh, gv, census_cost, f"{len(bad)} pixels differ, first {bad[:5].tolist()}")
+    s.close()
+
+
+@pytest.mark.parametrize("W,H,D,P,csct", [
+    (37, 23, 16, 4, False), (29, 31, 20, 8, True), (70, 9, 130, 2, False), (64, 40, 64, 8, False),
+    (1, 5, 7, 4, False), (5, 1, 256, 2, False),
+])
+def test_phase_sums_parity(gpu, W, H, D, P, csct):
+    """sgm_debug_phase_sums: phase 0 sums every direction but the one the
+    final pass fuses (right-to-left; left-to-right with 2 paths), phase 1
+    all of them."""
+    rng = np.random.default_rng(W * 5 + H * 3 + D)
+    l, r = _rand_pair(rng, W, H)
+    _say(f"phase sums {W}x{H} D={D} P={P} csct={csct}")
+    s = SGM(W, H, D, 7, 86, P, csct=csct)
+    tl, tr = _t(l, gpu), _t(r, gpu)
+    cl, cr = oracle.census(l, csct=csct), oracle.census(r, csct=csct)
+    mc = oracle.cost_volume(cl, cr, D, oracle.cmax_of(csct=csct))
+    dirs = oracle.directions(P)
+    last = (1, 0) if P == 2 else (-1, 0)
+    s0 = sum(oracle.aggregate(mc, 7, 86, rx, ry).astype(np.int64) for rx, ry in dirs if (rx, ry) != last)
+    s1 = s0 + oracle.aggregate(mc, 7, 86, *last)
+    for phase, want in ((0, s0), (1, s1)):
+        got = _np(s.debug_phase_sums(tl, tr, phase))
+        bad = np.argwhere(got != want)
+        assert len(bad) == 0, (phase, f"{len(bad)} cells differ, first {bad[:5].tolist()}")
+    s.close()
