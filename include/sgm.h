@@ -140,6 +140,28 @@ const char *sgm_last_error(void);
  * images and output are not counted).  0 if the shape is invalid. */
 size_t sgm_footprint_bytes(int width, int height, int max_disp, int n_paths, unsigned flags);
 
+/* ---- allocation-free computation ----
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the whole
+ * pipeline of sgm_create + sgm_set_options + sgm_compute in one call that
+ * allocates nothing.  The pair's workspace (sgm_footprint_bytes-like: cost
+ * volume, L_r planes, census words, raw maps) lives in a static device array
+ * of SGM_NOALLOC_MAX_BYTES bytes inside the library, which every GPU the
+ * library runs on holds until the process ends.  A shape whose workspace
+ * exceeds it returns SGM_ENOMEM (640x480, D = 128, 4 paths with u8 planes
+ * needs 193 MiB; the full left-right check doubles the planes).  Arguments
+ * are those of sgm_create and sgm_set_options (SGM_GRAPH is rejected) plus
+ * the buffers of sgm_compute; the default kernel shapes are used.
+ * Every call on a device shares that device's array and leaves its
+ * contents behind (nothing needs clearing: each call writes every workspace
+ * byte it reads): calls whose work overlaps on one device - on different
+ * streams, or from different threads - race, so serialize them (one stream).
+ * Asynchronous like sgm_compute. */
+#define SGM_NOALLOC_MAX_BYTES ((size_t)256 << 20)
+int sgm_compute_noalloc(int width, int height, int max_disp, int P1, int P2, int n_paths, int census_w,
+                        int census_h, unsigned flags, int lr_threshold, const uint8_t *left,
+                        const uint8_t *right, uint16_t *disp_out, sgm_stream_t stream);
+
 /* ---- batches: many pairs of different shapes in one set of launches ----
  * One item is one stereo pair with its own size (w x h), disparity range,
  * path count and options; the census window and P1, P2 belong to the batch

@@ -26,8 +26,9 @@ EXPORTS = [
     "sgm_compute_batch",
     "sgm_server_create", "sgm_server_set_policy", "sgm_server_request_bytes", "sgm_server_submit",
     "sgm_server_poll", "sgm_server_wait", "sgm_server_cancel", "sgm_server_get_stats", "sgm_server_destroy",
-    "sgm_server_create_ex", "sgm_debug_phase_sums",
+    "sgm_server_create_ex", "sgm_debug_phase_sums", "sgm_compute_noalloc",
 ]
+NOALLOC_MAX_BYTES = 256 << 20
 
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELED, REQ_FAILED = range(5)
 FINAL = (REQ_DONE, REQ_CANCELED, REQ_FAILED)
@@ -145,6 +146,8 @@ def lib() -> ctypes.CDLL:
     L.sgm_profile_enable.restype = i
     L.sgm_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     L.sgm_profile_read.restype = i
+    L.sgm_compute_noalloc.argtypes = [i, i, i, i, i, i, i, i, u, i, P, P, P, P]
+    L.sgm_compute_noalloc.restype = i
     _lib = L
     return L
 
@@ -165,6 +168,24 @@ def validate(width, height, max_disp, P1=7, P2=86, n_paths=4, census_w=9, census
 
 def footprint_bytes(width, height, max_disp, n_paths=4, flags=0) -> int:
     return lib().sgm_footprint_bytes(width, height, max_disp, n_paths, flags)
+
+
+def compute_noalloc(left, right, max_disp, P1=7, P2=86, n_paths=4, census_w=9, census_h=7, median=False,
+                    lrcheck=False, csct=False, lr_threshold=1, lr_full=False, subpixel=False, adaptive_p2=False,
+                    out=None, stream=None):
+    """sgm_compute_noalloc: the whole pipeline with its workspace in the
+    library's static device scratch (no device allocation by the library;
+    ``out`` is allocated here only when not given)."""
+    import torch
+    h, w = left.shape
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.uint16, device=left.device)
+    flags = ((MEDIAN3 if median else 0) | (LRCHECK if lrcheck else 0) | (CENSUS_CSCT if csct else 0)
+             | (LR_FULL if lr_full else 0) | (SUBPIXEL if subpixel else 0) | (ADAPTIVE_P2 if adaptive_p2 else 0))
+    _check(lib().sgm_compute_noalloc(w, h, max_disp, P1, P2, n_paths, census_w, census_h, flags, lr_threshold,
+                                     _ptr(left, "torch.uint8", (h, w)), _ptr(right, "torch.uint8", (h, w)),
+                                     _ptr(out, "torch.uint16", (h, w)), _stream(stream)))
+    return out
 
 
 def path_walk(width, height, rx, ry, slice_index):

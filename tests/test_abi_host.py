@@ -174,3 +174,19 @@ def test_adaptive_p2_bounds_use_the_larger_penalty(lib):
     assert sgm.validate(64, 64, 64, p1, 7, 8, flags=sgm.ADAPTIVE_P2) == sgm.SGM_EINVAL
     assert "max(P1, P2)" in sgm.last_error()
     assert sgm.validate(64, 64, 64, p1 - 1, 7, 8, flags=sgm.ADAPTIVE_P2) == 0
+
+
+def test_noalloc_rejects_oversized_and_invalid_calls_before_the_gpu():
+    # checked on the host before any device call, so this runs without a GPU
+    import ctypes
+    L = sgm.lib()
+    buf = ctypes.c_void_p(4096)  # never dereferenced: the call fails first
+    assert L.sgm_compute_noalloc(1920, 1080, 256, 7, 86, 8, 9, 7, 0, 1, buf, buf, ctypes.c_void_p(8192),
+                                 None) == sgm.SGM_ENOMEM
+    assert "static scratch" in sgm.last_error()
+    assert L.sgm_compute_noalloc(640, 480, 128, 7, 86, 3, 9, 7, 0, 1, buf, buf, ctypes.c_void_p(8192),
+                                 None) == sgm.SGM_EINVAL
+    assert L.sgm_compute_noalloc(64, 48, 32, 7, 86, 4, 9, 7, sgm.GRAPH, 1, buf, buf, ctypes.c_void_p(8192),
+                                 None) == sgm.SGM_EINVAL
+    assert L.sgm_compute_noalloc(64, 48, 32, 7, 86, 4, 9, 7, 0, 1, buf, buf, buf, None) == sgm.SGM_EINVAL
+    assert sgm.NOALLOC_MAX_BYTES == 256 << 20
