@@ -105,9 +105,15 @@ def pipeline_bytes(W: int, H: int, Dp: int, P: int, tuning) -> int:
     """Algorithmic bytes of census, cost, aggregation and WTA for one frame
     (each byte read or written once per kernel that needs it): images in,
     u64 census words of both views, the u8 cost volume, P u8 L_r planes
-    written and read back, the raw D_L and D_R maps out."""
+    written and read back, the raw D_L and D_R maps out.  With the final pass
+    (tuning[4]) the last direction's plane is neither written nor read: the
+    aggregation launch moves 2 (P - 1) N, the final pass reads the cost
+    volume and the P - 1 planes."""
     px, N = W * H, W * H * Dp
     fused, census_cost = bool(tuning[2]), bool(tuning[3])
+    if len(tuning) > 4 and bool(tuning[4]) and not fused:
+        census, cost = (0, 2 * px + N) if census_cost else (2 * px + 16 * px, 16 * px + N)
+        return census + cost + 2 * (P - 1) * N + (N + (P - 1) * N + 4 * px)
     census = 2 * px + 16 * px              # both images in, both census maps out
     if fused:                              # no cost volume: each direction reads census words
         agg = P * 16 * px + P * N
@@ -459,7 +465,7 @@ def main():
     ap.add_argument("--oracle-timing", action="store_true",
                     help="also time the CPU oracle on every workload (single-pair latencies, the 64-pair "
                          "batch over all cores, the served mix); takes a few minutes")
-    ap.add_argument("--tuning", default="", help="fixed kernel shape 'lanes_h,lanes_v,fused,census_cost' "
+    ap.add_argument("--tuning", default="", help="fixed kernel shape 'lanes_h,lanes_v,fused,census_cost[,final_pass]' "
                                                    "instead of autotuning (for profiler runs)")
     ap.add_argument("--no-extras", action="store_true", help="skip serialized/latency/copy measurements")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batched measurement")
@@ -515,8 +521,9 @@ def main():
 
     # kernel shape: measured on this device for this workload (results do not depend on it)
     if args.tuning:
-        gh, gv, f, cc = (int(v) for v in args.tuning.split(","))
-        choice = (gh, gv, bool(f), bool(cc))
+        vals = [int(v) for v in args.tuning.split(",")] + [0]
+        gh, gv, f, cc, fp = vals[:5]
+        choice = (gh, gv, bool(f), bool(cc), bool(fp))
         tuned = {"candidates": None}
     else:
         probe = make_ctx()
@@ -599,12 +606,14 @@ def main():
         del csrc, cdst
 
     # the aggregation kernel reads the cost volume (u8) and writes one L_r
-    # plane (u8: Cmax + P2 = 148 < 256) per direction
+    # plane (u8: Cmax + P2 = 148 < 256) per direction it runs: all of them,
+    # or all but the last with the final pass
     Dp = 64 if D <= 64 else (128 if D <= 128 else 256)
+    final_pass = bool(tuning[4]) and not tuning[2]
     if tuning[2]:  # fused: census words of both views in, L_r out
         agg_bytes = P * W * H * (Dp + 2 * 8)
     else:  # cost volume in, L_r out
-        agg_bytes = P * W * H * Dp * (1 + 1)
+        agg_bytes = (P - 1 if final_pass else P) * W * H * Dp * (1 + 1)
     agg_ms = stage_ms["aggregate"] / max(ncalls, 1)
     achieved = agg_bytes / (agg_ms * 1e-3) / 1e9
     roof = {"kernel": "aggregate_kernel", "bound": "hbm", "achieved": round(achieved, 1),
@@ -613,6 +622,14 @@ def main():
     if "copy_gbs" in extras:
         roof["measured_copy_gbs"] = extras["copy_gbs"]
         roof["frac_of_measured_copy"] = round(achieved / extras["copy_gbs"], 4)
+    # the winner-take-all stage: the WTA kernel (P planes in, two maps out),
+    # or the final pass (cost volume and P - 1 planes in, two maps out)
+    wta_ms = stage_ms["wta"] / max(ncalls, 1)
+    wta_bytes = P * W * H * Dp + 4 * W * H  # P planes, or the cost volume and P - 1 planes
+    wta_gbs = wta_bytes / (wta_ms * 1e-3) / 1e9
+    wta_stage = {"kernel": "final_pass_kernel" if final_pass else "wta_kernel", "alg_bytes_per_launch": wta_bytes,
+                 "mean_launch_ms": round(wta_ms, 5), "achieved": round(wta_gbs, 1), "unit": "GB/s",
+                 "frac": round(wta_gbs / HBM_PEAK_GBS, 4)}
 
     # the whole path from the first census launch to the end of the WTA
     # (median and LR excluded), event-timed like the stages it spans
@@ -643,11 +660,12 @@ def main():
                    "median": cfg["median"], "lr_check": cfg["lr"], "scene": cfg["scene"],
                    "seed": cfg["seed"], "frames_in_flight": F,
                    "lanes_h": tuning[0], "lanes_v": tuning[1], "fused_cost": tuning[2],
-                   "fused_census_cost": tuning[3],
+                   "fused_census_cost": tuning[3], "final_pass": final_pass,
                    "autotune_ms_per_frame": tuned["candidates"]},
         "gcells_per_s": round(W * H * D * P * fps / 1e9, 2),
         "stage_ms": {k: round(v / max(ncalls, 1), 5) for k, v in stage_ms.items()},
         "roofline": roof,
+        "wta_stage": wta_stage,
         "pipeline": pipe,
     }
     if extras:

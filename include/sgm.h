@@ -123,9 +123,13 @@ int sgm_compute(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right, uint16_
  *   cost kernel writes the u8 cost volume C[H][W][Dp] that the aggregation
  *   reads.  Bit SGM_TUNE_FUSED_CENSUS_COST (9x7 windows): that cost volume
  *   comes from one census + cost launch instead of a census launch and a cost
- *   launch.  Default 0.
+ *   launch.  Bit SGM_TUNE_FINAL_PASS: the last path direction (right-to-left;
+ *   left-to-right with 2 paths) runs fused with the sum over directions and
+ *   the winner-take-all (Sec. 3.3), so its L_r is never stored; used where
+ *   the planes are u8, the cost volume is stored and neither SGM_LR_FULL
+ *   nor SGM_ADAPTIVE_P2 is set, otherwise ignored.  Default 0.
  * sgm_get_tuning reports the shape in effect. */
-enum { SGM_TUNE_FUSED_AGG = 1, SGM_TUNE_FUSED_CENSUS_COST = 2 };
+enum { SGM_TUNE_FUSED_AGG = 1, SGM_TUNE_FUSED_CENSUS_COST = 2, SGM_TUNE_FINAL_PASS = 4 };
 int sgm_set_tuning(sgm_ctx *ctx, int lanes_h, int lanes_v, int fused);
 int sgm_get_tuning(sgm_ctx *ctx, int *lanes_h, int *lanes_v, int *fused);
 

@@ -162,6 +162,7 @@ int sgm_set_options(sgm_ctx* c, unsigned flags, int lr_threshold) {
     p.lanes_v = c->plan.lanes_v;
     p.fused = c->plan.fused;
     p.cc_fused = c->plan.cc_fused;
+    p.final_pass = c->plan.final_pass;
     // the full left-right check needs a second cost volume and L_r set
     sgm::Plan big = p;
     big.l16 = true;
@@ -202,9 +203,11 @@ int sgm_set_tuning(sgm_ctx* c, int lanes_h, int lanes_v, int fused) {
     if ((lanes_h == 0) != (lanes_v == 0)) return set_err(SGM_EINVAL, "set both lane counts or neither");
     c->plan.lanes_h = lanes_h;
     c->plan.lanes_v = lanes_v;
-    if (fused & ~(SGM_TUNE_FUSED_AGG | SGM_TUNE_FUSED_CENSUS_COST)) return set_err(SGM_EINVAL, "unknown tuning bits");
+    if (fused & ~(SGM_TUNE_FUSED_AGG | SGM_TUNE_FUSED_CENSUS_COST | SGM_TUNE_FINAL_PASS))
+        return set_err(SGM_EINVAL, "unknown tuning bits");
     c->plan.fused = (fused & SGM_TUNE_FUSED_AGG) != 0;
     c->plan.cc_fused = (fused & SGM_TUNE_FUSED_CENSUS_COST) != 0;
+    c->plan.final_pass = (fused & SGM_TUNE_FINAL_PASS) != 0;
     drop_graphs(c);
     return SGM_OK;
 }
@@ -215,7 +218,9 @@ int sgm_get_tuning(sgm_ctx* c, int* lanes_h, int* lanes_v, int* fused) {
     if (gh <= 0 || gv <= 0) sgm::default_lanes(c->plan, &gh, &gv);
     if (lanes_h) *lanes_h = gh;
     if (lanes_v) *lanes_v = gv;
-    if (fused) *fused = (c->plan.fused ? SGM_TUNE_FUSED_AGG : 0) | (c->plan.cc_fused ? SGM_TUNE_FUSED_CENSUS_COST : 0);
+    if (fused)
+        *fused = (c->plan.fused ? SGM_TUNE_FUSED_AGG : 0) | (c->plan.cc_fused ? SGM_TUNE_FUSED_CENSUS_COST : 0) |
+                 (c->plan.final_pass ? SGM_TUNE_FINAL_PASS : 0);
     return SGM_OK;
 }
 
@@ -352,10 +357,22 @@ int sgm_debug_phase_sums(sgm_ctx* c, const uint8_t* left, const uint8_t* right, 
     if (!c) return set_err(SGM_EINVAL, "null context");
     if (int rc = check_ptrs(left, right, s_out)) return rc;
     if (phase < 0 || phase > 1) return set_err(SGM_EINVAL, "phase must be 0 or 1");
+    // the sums of the schedule the context runs: with the final pass, phase
+    // 0 from the planes of the first launch and phase 1 as the final pass
+    // forms them (its raw maps go to the workspace)
+    sgm::Plan p = c->plan;
+    p.median = true;
+    const bool fp = sgm::final_pass_active(p);
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = sgm::launch_matching_cost(c->plan, c->ws, left, right, !sgm::fused_aggregation(c->plan), s);
-    if (e == hipSuccess) e = sgm::launch_aggregate(c->plan, c->ws, s, left, right);
-    if (e == hipSuccess) e = sgm::launch_sum_planes(c->plan, c->ws, s_out, s, phase == 0 ? sgm::last_direction(c->plan) : -1);
+    hipError_t e = sgm::launch_matching_cost(p, c->ws, left, right, !sgm::fused_aggregation(p), s);
+    if (e == hipSuccess) e = sgm::launch_aggregate(p, c->ws, s, left, right, fp);
+    if (e == hipSuccess) {
+        if (fp)
+            e = phase == 0 ? sgm::launch_sum_planes(p, c->ws, s_out, s, -1, p.n_paths - 1)
+                           : sgm::launch_final_pass(p, c->ws, nullptr, s, s_out);
+        else
+            e = sgm::launch_sum_planes(p, c->ws, s_out, s, phase == 0 ? sgm::last_direction(p) : -1);
+    }
     if (e != hipSuccess) return hip_err(e, "kernel launch");
     return SGM_OK;
 }
@@ -385,8 +402,7 @@ int sgm_debug_raw_disparity(sgm_ctx* c, const uint8_t* left, const uint8_t* righ
     p.median = false;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = sgm::launch_matching_cost(p, c->ws, left, right, !sgm::fused_aggregation(p), s);
-    if (e == hipSuccess) e = sgm::launch_aggregate(p, c->ws, s, left, right);
-    if (e == hipSuccess) e = sgm::launch_wta(p, c->ws, nullptr, s);
+    if (e == hipSuccess) e = sgm::launch_aggregate_wta(p, c->ws, left, right, nullptr, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dl_out, c->ws.dl, (size_t)p.W * p.H * 2, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dr_out, c->ws.dr, (size_t)p.W * p.H * 2, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_err(e, "kernel launch");

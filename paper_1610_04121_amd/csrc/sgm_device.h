@@ -731,6 +731,31 @@ __device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint
                                            0, AUX);
 }
 
+// A lane's CPL L values as bytes in natural disparity order (u8 planes):
+// pair k holds disparities k and k + CPL/2 (split layout), so the bytes are
+// gathered with v_perm.
+template <int CPL>
+__device__ inline typename Raw<CPL>::T pack_u8(const u16x2 (&l)[CPL / 2]) {
+    constexpr uint32_t kLoBytes = 0x06020400u;  // (a.b0, b.b0, a.b2, b.b2) of perm(b, a)
+    constexpr uint32_t kPairLo = 0x05040100u;   // (a.lo16, b.lo16)
+    constexpr uint32_t kPairHi = 0x07060302u;   // (a.hi16, b.hi16)
+    if constexpr (CPL == 2) {
+        return (uint16_t)__builtin_amdgcn_perm(0u, as1(l[0]), 0x0C0C0200u);
+    } else if constexpr (CPL == 4) {
+        return (uint32_t)__builtin_amdgcn_perm(as1(l[1]), as1(l[0]), kLoBytes);
+    } else if constexpr (CPL == 8) {
+        const uint32_t t01 = __builtin_amdgcn_perm(as1(l[1]), as1(l[0]), kLoBytes);
+        const uint32_t t23 = __builtin_amdgcn_perm(as1(l[3]), as1(l[2]), kLoBytes);
+        return make_uint2(__builtin_amdgcn_perm(t23, t01, kPairLo), __builtin_amdgcn_perm(t23, t01, kPairHi));
+    } else {
+        uint32_t t[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) t[i] = __builtin_amdgcn_perm(as1(l[2 * i + 1]), as1(l[2 * i]), kLoBytes);
+        return make_uint4(__builtin_amdgcn_perm(t[1], t[0], kPairLo), __builtin_amdgcn_perm(t[3], t[2], kPairLo),
+                          __builtin_amdgcn_perm(t[1], t[0], kPairHi), __builtin_amdgcn_perm(t[3], t[2], kPairHi));
+    }
+}
+
 // Packs a lane's L values in natural disparity order (u8 or u16) and stores
 // them at byte offset `ofs` of the L_r plane.  NT: non-temporal stores (the
 // frame's planes exceed the memory-side cache); otherwise device-scope (sc1)
@@ -740,28 +765,10 @@ __device__ inline void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t ofs, uint
 template <int CPL, typename LT, bool NT = false>
 __device__ inline void store_l(__amdgpu_buffer_rsrc_t r, uint32_t ofs, const u16x2 (&l)[CPL / 2]) {
     constexpr int A = NT ? 2 : 16;
-    constexpr uint32_t kLoBytes = 0x06020400u;  // (a.b0, b.b0, a.b2, b.b2) of perm(b, a)
     constexpr uint32_t kPairLo = 0x05040100u;   // (a.lo16, b.lo16)
     constexpr uint32_t kPairHi = 0x07060302u;   // (a.hi16, b.hi16)
     if constexpr (sizeof(LT) == 1) {
-        if constexpr (CPL == 2) {
-            buffer_store<A>(r, ofs, (uint16_t)__builtin_amdgcn_perm(0u, as1(l[0]), 0x0C0C0200u));
-        } else if constexpr (CPL == 4) {
-            buffer_store<A>(r, ofs, (uint32_t)__builtin_amdgcn_perm(as1(l[1]), as1(l[0]), kLoBytes));
-        } else if constexpr (CPL == 8) {
-            const uint32_t t01 = __builtin_amdgcn_perm(as1(l[1]), as1(l[0]), kLoBytes);
-            const uint32_t t23 = __builtin_amdgcn_perm(as1(l[3]), as1(l[2]), kLoBytes);
-            buffer_store<A>(r, ofs, make_uint2(__builtin_amdgcn_perm(t23, t01, kPairLo),
-                                            __builtin_amdgcn_perm(t23, t01, kPairHi)));
-        } else {
-            uint32_t t[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) t[i] = __builtin_amdgcn_perm(as1(l[2 * i + 1]), as1(l[2 * i]), kLoBytes);
-            buffer_store<A>(r, ofs, make_uint4(__builtin_amdgcn_perm(t[1], t[0], kPairLo),
-                                            __builtin_amdgcn_perm(t[3], t[2], kPairLo),
-                                            __builtin_amdgcn_perm(t[1], t[0], kPairHi),
-                                            __builtin_amdgcn_perm(t[3], t[2], kPairHi)));
-        }
+        buffer_store<A>(r, ofs, pack_u8<CPL>(l));
     } else {
         constexpr int NP = CPL / 2;
         if constexpr (CPL == 2) {
@@ -843,10 +850,18 @@ __device__ inline uint32_t pack_selector(int k, int d0, int D, uint32_t pad) {
 template <int CPL> struct Prefetch { static constexpr int N = CPL >= 16 ? 8 : 16; };
 template <int CPL> struct FusedPrefetch { static constexpr int N = CPL >= 16 ? 2 : 4; };
 
+// Where aggregate_wave puts each step's L values: by default the direction's
+// L_r plane in global memory.  A sink (the final pass's LDS ring) instead
+// receives put(step, L) for every step and chunk_done() after every Prefetch
+// steps and after the last step.
+struct PlaneSink {};
+
 // ADAPT: the P2 of each step adapts to the base image's intensity change
 // along the path (adaptive_p2); the intensities are prefetched with the costs.
-template <int G, int CPL, typename LT, int KIND, bool FUSED, bool ADAPT = false, bool NT = false>
-__device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int lane) {
+template <int G, int CPL, typename LT, int KIND, bool FUSED, bool ADAPT = false, bool NT = false,
+          typename SINK = PlaneSink>
+__device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int lane, SINK* sink = nullptr) {
+    constexpr bool kToPlane = std::is_same_v<SINK, PlaneSink>;
     static_assert(!(FUSED && ADAPT), "adaptive P2 uses the cost-volume variant");
     constexpr int NP = CPL / 2;
     constexpr int Dp = G * CPL;
@@ -945,7 +960,7 @@ __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int l
     // ADAPT: this step's P2 (looked up during the previous step; at a path
     // start L and mm are 0 and the P2 of that step does not matter)
     uint32_t p2cur = (uint32_t)a.P2;
-    auto step = [&](const RawT& raw, uint32_t iv, uint32_t inext) {
+    auto step = [&](const RawT& raw, uint32_t iv, uint32_t inext, int t) {
         if constexpr (FUSED) {
             if constexpr (KIND == kHoriz)
                 xmin_all = xc;
@@ -1025,7 +1040,10 @@ __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int l
             tm = vmin(t[0], t[0].yx);
         }
         mm = as2(group_min<G>(as1(tm)));
-        store_l<CPL, LT, NT>(rl, lane_ofs(bo, xc) * (uint32_t)sizeof(LT), L);
+        if constexpr (kToPlane)
+            store_l<CPL, LT, NT>(rl, lane_ofs(bo, xc) * (uint32_t)sizeof(LT), L);
+        else
+            sink->put(t, L);
         advance(bo, xc);
         if constexpr (ADAPT) p2cur = p2next;
     };
@@ -1075,13 +1093,16 @@ __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int l
             advance(ba, xa);
             ring[j] = load(ba, xa);
             if constexpr (ADAPT) iring[j] = load_i(ba, xa);
-            step(raw, iv, ADAPT ? iring[ADAPT ? (j + 1) % PF : 0] : 0u);
+            step(raw, iv, ADAPT ? iring[ADAPT ? (j + 1) % PF : 0] : 0u, k + j);
         }
+        if constexpr (!kToPlane) sink->chunk_done();
     }
 #pragma unroll
     for (int j = 0; j < PF; ++j)
         if (k + j < steps)
-            step(ring[j], ADAPT ? iring[ADAPT ? j : 0] : 0u, ADAPT ? iring[ADAPT ? (j + 1) % PF : 0] : 0u);
+            step(ring[j], ADAPT ? iring[ADAPT ? j : 0] : 0u, ADAPT ? iring[ADAPT ? (j + 1) % PF : 0] : 0u, k + j);
+    if constexpr (!kToPlane)
+        if (k < steps) sink->chunk_done();
 }
 
 // ---------------------------------------------------------------------------
@@ -1187,6 +1208,73 @@ __device__ inline uint32_t lanes_min(uint32_t v, int G) {
     return v;
 }
 
+// The winner-take-all of one lane's 16 disparities d0 .. d0+15 of pixel
+// (x, y), given their summed costs S (pairs as pair_disps<LT>): keys
+// (S << 8) | d with a 0xFF top byte for padded levels; the pixel's smallest
+// key over its G lanes (consecutive, aligned) is D_L (1/16-pixel vertex with
+// sub-pixel output); with `right`, every (x, d) offers its key to column
+// x - d of the row's right-view keys (LDS, atomic minimum; targets x - d < 0
+// land in a guard region in front of the row).  s_out (debug): S u16
+// [H][W][D].
+template <typename LT>
+__device__ inline void wta_cells(const WtaArgs& a, int y, int x, int g, int G, const uint32_t (&S)[8],
+                                 uint32_t* keyR, bool right, uint16_t* s_out = nullptr, bool valid = true) {
+    right = right && valid;
+    if (!valid) s_out = nullptr;
+    const int d0 = 16 * g;
+    uint32_t best = ~0u;
+    // right-view targets x - d0 - 15 .. x - d0 from one base address
+    uint32_t* tgt = keyR + (x - d0 - 15);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        int dlo, dhi;
+        pair_disps<LT>(k, dlo, dhi);
+        const uint32_t dpair = (uint32_t)(d0 + dlo) | ((uint32_t)(d0 + dhi) << 8);
+        // key = [d, S.lo16, 0] with a 0xFF top byte for padded levels
+        const uint32_t klo = __builtin_amdgcn_perm(S[k], dpair, d0 + dlo < a.D ? 0x0C050400u : 0x0D050400u);
+        const uint32_t khi = __builtin_amdgcn_perm(S[k], dpair, d0 + dhi < a.D ? 0x0C070601u : 0x0D070601u);
+        best = min(best, min(klo, khi));
+        if (right) {
+            if (d0 + dlo < a.D) atomicMin(tgt + (15 - dlo), klo);
+            if (d0 + dhi < a.D) atomicMin(tgt + (15 - dhi), khi);
+        }
+        if (s_out) {
+            uint16_t* o = s_out + ((size_t)y * a.W + x) * a.D;
+            if (d0 + dlo < a.D) o[d0 + dlo] = (uint16_t)(S[k] & 0xFFFFu);
+            if (d0 + dhi < a.D) o[d0 + dhi] = (uint16_t)(S[k] >> 16);
+        }
+    }
+    best = lanes_min(best, G);
+    const int dbest = (int)(best & 0xFF);
+    uint32_t outv = (uint32_t)dbest;
+    if (a.subpixel) {
+        // S(dbest - 1) and S(dbest + 1) from the lanes holding them; the
+        // vertex of the parabola through the three, rounded half up to
+        // 1/16: f = floor((16 (a - c) + den) / (2 den)), den = a + c - 2b
+        uint32_t va = ~0u, vc = ~0u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            int dlo, dhi;
+            pair_disps<LT>(k, dlo, dhi);
+            const uint32_t slo = S[k] & 0xFFFFu, shi = S[k] >> 16;
+            if (d0 + dlo == dbest - 1) va = slo;
+            if (d0 + dhi == dbest - 1) va = shi;
+            if (d0 + dlo == dbest + 1) vc = slo;
+            if (d0 + dhi == dbest + 1) vc = shi;
+        }
+        va = lanes_min(va, G);
+        vc = lanes_min(vc, G);
+        int f = 0;
+        if (dbest > 0 && dbest < a.D - 1) {
+            const int b = (int)((best >> 8) & 0xFFFFu);
+            const int den = (int)va + (int)vc - 2 * b;
+            if (den > 0) f = floor_div(16 * ((int)va - (int)vc) + den, 2 * den);
+        }
+        outv = (uint32_t)(16 * dbest + f);
+    }
+    if (g == 0 && valid) a.dl[(size_t)y * a.W + x] = (uint16_t)outv;
+}
+
 template <typename LT, int NPL, bool NT>
 __device__ inline void wta_row_impl(const WtaArgs& a, int y, uint32_t* keyR_smem) {
     uint32_t* keyR = keyR_smem + kWtaGuard;  // keyR[t], t in [-kWtaGuard, W)
@@ -1201,55 +1289,9 @@ __device__ inline void wta_row_impl(const WtaArgs& a, int y, uint32_t* keyR_smem
     const int gshift = G == 4 ? 2 : (G == 8 ? 3 : 4);
     for (int i = threadIdx.x; i < a.W * G; i += blockDim.x) {
         const int x = i >> gshift, g = i & (G - 1);
-        const int d0 = 16 * g;
         uint32_t S[8];
-        sum16<LT, NPL, NT>(planes + ((size_t)y * a.W + x) * a.Dp + d0, a.plane, S);
-        uint32_t best = ~0u;
-        // right-view targets x - d0 - 15 .. x - d0 from one base address
-        uint32_t* tgt = keyR + (x - d0 - 15);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            int dlo, dhi;
-            pair_disps<LT>(k, dlo, dhi);
-            const uint32_t dpair = (uint32_t)(d0 + dlo) | ((uint32_t)(d0 + dhi) << 8);
-            // key = [d, S.lo16, 0] with a 0xFF top byte for padded levels
-            const uint32_t klo = __builtin_amdgcn_perm(S[k], dpair, d0 + dlo < a.D ? 0x0C050400u : 0x0D050400u);
-            const uint32_t khi = __builtin_amdgcn_perm(S[k], dpair, d0 + dhi < a.D ? 0x0C070601u : 0x0D070601u);
-            best = min(best, min(klo, khi));
-            if (right) {
-                if (d0 + dlo < a.D) atomicMin(tgt + (15 - dlo), klo);
-                if (d0 + dhi < a.D) atomicMin(tgt + (15 - dhi), khi);
-            }
-        }
-        best = lanes_min(best, G);
-        const int dbest = (int)(best & 0xFF);
-        uint32_t outv = (uint32_t)dbest;
-        if (a.subpixel) {
-            // S(dbest - 1) and S(dbest + 1) from the lanes holding them; the
-            // vertex of the parabola through the three, rounded half up to
-            // 1/16: f = floor((16 (a - c) + den) / (2 den)), den = a + c - 2b
-            uint32_t va = ~0u, vc = ~0u;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                int dlo, dhi;
-                pair_disps<LT>(k, dlo, dhi);
-                const uint32_t slo = S[k] & 0xFFFFu, shi = S[k] >> 16;
-                if (d0 + dlo == dbest - 1) va = slo;
-                if (d0 + dhi == dbest - 1) va = shi;
-                if (d0 + dlo == dbest + 1) vc = slo;
-                if (d0 + dhi == dbest + 1) vc = shi;
-            }
-            va = lanes_min(va, G);
-            vc = lanes_min(vc, G);
-            int f = 0;
-            if (dbest > 0 && dbest < a.D - 1) {
-                const int b = (int)((best >> 8) & 0xFFFFu);
-                const int den = (int)va + (int)vc - 2 * b;
-                if (den > 0) f = floor_div(16 * ((int)va - (int)vc) + den, 2 * den);
-            }
-            outv = (uint32_t)(16 * dbest + f);
-        }
-        if (g == 0) a.dl[(size_t)y * a.W + x] = (uint16_t)outv;
+        sum16<LT, NPL, NT>(planes + ((size_t)y * a.W + x) * a.Dp + 16 * g, a.plane, S);
+        wta_cells<LT>(a, y, x, g, G, S, keyR, right);
     }
     if (right) {
         __syncthreads();
@@ -1270,6 +1312,212 @@ __device__ inline void wta_row(const WtaArgs& a, int y, uint32_t* keyR_smem) {
         wta_row_impl<LT, 4, NT>(a, y, keyR_smem);
     else
         wta_row_impl<LT, 8, NT>(a, y, keyR_smem);
+}
+
+// ---------------------------------------------------------------------------
+// Final pass: the last path direction fused with the sum over directions and
+// the winner-take-all (Sec. 3.3), so that direction's L_r plane is never
+// written to memory nor read back.  The fused direction is horizontal
+// (right-to-left; left-to-right in the 2-path set): the right-view keys need
+// whole rows, and a row is the slice of a horizontal direction.
+//
+// A block has 4 wavefronts, one per SIMD of its CU, in two roles:
+//   * 2 producer waves run the recurrence of Eq. 3 along their rows (G = 64
+//     lanes per row, 32 when Dp = 64, so a lane holds CPL = Dp / G = 2 or 4
+//     disparities) exactly as aggregate_wave does, but put each step's L
+//     values into an LDS ring of two chunks of K steps (K = the cost
+//     prefetch depth) instead of a plane, and wait at a block barrier after
+//     every chunk.  Each recurrence is a dependent chain issued at one
+//     instruction per cycle slot of its SIMD, so no other producer shares
+//     that SIMD;
+//   * 2 consumer waves take chunk c after the barrier that completes it,
+//     while the producers work on chunk c + 1.  A chunk has K * R * Dp / 16
+//     (pixel, run of 16 disparities) items, M per consumer lane: each adds
+//     the P - 1 planes stored by the aggregation launch and the chunk's L
+//     values, and runs wta_cells.  The stored planes do not depend on the
+//     producers, so a lane loads its items' plane bytes FinalAhead chunks
+//     before it needs them (registers), which keeps the memory latency off
+//     the per-chunk barrier interval.
+// All waves pass the same number of barriers (one after the right-view key
+// initialisation, one per chunk, one at the end), after which the block
+// writes the right view of its rows from the LDS keys.
+// ---------------------------------------------------------------------------
+struct FinalArgs {
+    SliceArgs agg;          // the fused direction: cost volume, rx = +-1, ry = 0
+    const uint8_t* planes;  // the other P - 1 directions' u8 planes, contiguous
+    size_t plane;           // bytes per plane (W * H * Dp)
+    WtaArgs wta;            // outputs D_L (dl) and D_R (dr, or nullptr), W, H, D, Dp
+    uint16_t* s_out;        // debug: S u16 [H][W][D], or nullptr
+};
+
+constexpr int kFinalThreads = 256;  // 2 producer + 2 consumer waves
+
+template <int Dp>
+struct FinalLayout {
+    static constexpr int G = Dp == 64 ? 32 : 64;  // lanes per row
+    static constexpr int CPL = Dp / G;             // disparities per lane: 2 or 4
+    static constexpr int K = Prefetch<CPL>::N;     // steps per chunk
+    static constexpr int NPROD = 2, NC = 2;        // producer and consumer waves
+    static constexpr int RW = 64 / G;              // rows per producer wave
+    static constexpr int R = NPROD * RW;           // rows per block
+    static constexpr int ITEMS = K * R * (Dp / 16);
+    static constexpr int M = ITEMS / (64 * NC);    // items per consumer lane and chunk
+    static constexpr int ring_bytes = 2 * K * R * Dp;
+    static_assert(M * 64 * NC == ITEMS, "whole items per consumer lane");
+};
+
+// Rows per final-pass block and its LDS bytes (ring, then the rows' right-
+// view keys).
+__host__ __device__ inline int final_rows(int Dp) { return Dp == 64 ? 4 : 2; }
+__host__ __device__ inline size_t final_smem_bytes(int Dp, int W, bool right) {
+    const int R = final_rows(Dp);
+    return (size_t)2 * 16 * R * Dp + (right ? (size_t)4 * R * (W + kWtaGuard) : 0);
+}
+
+// Chunks of plane loads a consumer lane keeps in flight, within about 64
+// registers: 4 * M * NPL registers per chunk.
+template <int M, int NPL>
+struct FinalAhead {
+    static constexpr int n = 16 / (M * NPL);
+    static constexpr int N = n < 1 ? 1 : (n > 3 ? 3 : n);
+};
+
+// A producer's sink: step t's L values of row slot `row` go to
+// ring[(t / K) % 2][t % K][row][Dp] as bytes in disparity order.
+template <int Dp>
+struct LdsRingSink {
+    uint8_t* ring;
+    int row, q;
+    __device__ void put(int t, const u16x2 (&l)[FinalLayout<Dp>::CPL / 2]) {
+        using L = FinalLayout<Dp>;
+        const int buf = (t / L::K) & 1, j = t % L::K;
+        auto* dst = reinterpret_cast<typename Raw<L::CPL>::T*>(ring + ((buf * L::K + j) * L::R + row) * Dp + q * L::CPL);
+        *dst = pack_u8<L::CPL>(l);
+    }
+    __device__ void chunk_done() { __syncthreads(); }
+};
+
+// Consumer item i of chunk c: pixel (x, y) and its run g, or invalid past
+// the row's end or the image's last row (the same for the pixel's Dp / 16
+// lanes).
+template <int Dp>
+struct FinalItem {
+    int j, row, g, x, y;
+    bool valid;
+    __device__ FinalItem(const FinalArgs& f, int y0, int c, int i) {
+        using L = FinalLayout<Dp>;
+        constexpr int Gp = Dp / 16;
+        g = i % Gp;
+        const int pix = i / Gp;
+        j = pix % L::K;
+        row = pix / L::K;
+        const int t = c * L::K + j;
+        y = y0 + row;
+        valid = t < f.wta.W && y < f.wta.H;
+        x = f.agg.rx < 0 ? f.wta.W - 1 - t : t;
+    }
+};
+
+// Plane bytes of an item: one range-checked buffer load per plane, with the
+// byte offset of an invalid item past the plane's end (the hardware returns
+// zeros), so no branch surrounds a load and the loads of later chunks stay
+// in flight while earlier ones are used.  NT: non-temporal (planes that
+// exceed the memory-side cache).
+template <int NPL, bool NT>
+__device__ inline void load_planes16(const __amdgpu_buffer_rsrc_t (&rp)[NPL], uint32_t ofs, uint4 (&q)[NPL]) {
+#pragma unroll
+    for (int p = 0; p < NPL; ++p) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rp[p], ofs, 0, NT ? 2 : 0);
+        q[p] = make_uint4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+template <int Dp>
+__device__ inline uint32_t final_item_offset(const FinalArgs& f, const FinalItem<Dp>& it) {
+    return it.valid ? (uint32_t)(((size_t)it.y * f.wta.W + it.x) * Dp + 16 * it.g) : 0xFFFFFFF0u;
+}
+
+// One item of a chunk: every lane runs it (invalid items only skip the
+// stores and key updates inside wta_cells).
+template <int Dp, int NPL>
+__device__ inline void final_item_finish(const FinalArgs& f, const FinalItem<Dp>& it, int buf, const uint8_t* ring,
+                                         uint32_t* keyR, const uint4 (&q)[NPL]) {
+    using L = FinalLayout<Dp>;
+    uint32_t S[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) S[k] = 0;
+    auto add = [&](const uint4& v) {
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            S[2 * k] = as1(as2(S[2 * k]) + as2(__builtin_amdgcn_perm(0u, w[k], 0x0C020C00u)));
+            S[2 * k + 1] = as1(as2(S[2 * k + 1]) + as2(__builtin_amdgcn_perm(0u, w[k], 0x0C030C01u)));
+        }
+    };
+#pragma unroll
+    for (int p = 0; p < NPL; ++p) add(q[p]);
+    add(*reinterpret_cast<const uint4*>(ring + ((buf * L::K + it.j) * L::R + it.row) * Dp + 16 * it.g));
+    const int W = f.wta.W;
+    wta_cells<uint8_t>(f.wta, it.y, it.x, it.g, Dp / 16, S, keyR + it.row * (W + kWtaGuard) + kWtaGuard,
+                       f.wta.dr != nullptr, f.s_out, it.valid);
+}
+
+template <int Dp, int NPL, bool NT>
+__device__ inline void final_pass_block(const FinalArgs& f, int blk, uint8_t* smem) {
+    using L = FinalLayout<Dp>;
+    const int W = f.wta.W, H = f.wta.H;
+    const int y0 = blk * L::R;
+    uint8_t* ring = smem;
+    uint32_t* keyR = reinterpret_cast<uint32_t*>(smem + L::ring_bytes);
+    const bool right = f.wta.dr != nullptr;
+    const int kpitch = W + kWtaGuard;
+    if (right)
+        for (int i = threadIdx.x; i < L::R * kpitch; i += blockDim.x) keyR[i] = ~0u;
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (wave < L::NPROD) {
+        // rows y0 + wave * RW .. (a row past the image repeats the last row;
+        // the consumers skip it)
+        LdsRingSink<Dp> sink{ring, wave * L::RW + lane / L::G, lane % L::G};
+        aggregate_wave<L::G, L::CPL, uint8_t, kHoriz, false, false, false, LdsRingSink<Dp>>(
+            f.agg, min(y0 + wave * L::RW, H - 1), lane, &sink);
+    } else {
+        const int ctid = (wave - L::NPROD) * 64 + lane;
+        const int nchunks = (W + L::K - 1) / L::K;
+        __amdgpu_buffer_rsrc_t rp[NPL];
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) rp[p] = buffer_rsrc(f.planes + f.plane * p, (uint32_t)f.plane);
+        constexpr int A = FinalAhead<L::M, NPL>::N;
+        // plane bytes of the lane's M items of chunks c .. c + A - 1, slot c % A
+        uint4 q[A][L::M][NPL];
+        auto item = [&](int c, int m) { return FinalItem<Dp>(f, y0, c, ctid + m * 64 * L::NC); };
+#pragma unroll
+        for (int s = 0; s < A; ++s)
+#pragma unroll
+            for (int m = 0; m < L::M; ++m) load_planes16<NPL, NT>(rp, final_item_offset<Dp>(f, item(s, m)), q[s][m]);
+        auto chunk = [&](int c, uint4 (&qs)[L::M][NPL]) {
+            __syncthreads();  // chunk c is in the ring
+#pragma unroll
+            for (int m = 0; m < L::M; ++m) final_item_finish<Dp, NPL>(f, item(c, m), c & 1, ring, keyR, qs[m]);
+#pragma unroll
+            for (int m = 0; m < L::M; ++m) load_planes16<NPL, NT>(rp, final_item_offset<Dp>(f, item(c + A, m)), qs[m]);
+        };
+        int c0 = 0;
+        for (; c0 + A <= nchunks; c0 += A) {
+#pragma unroll
+            for (int s = 0; s < A; ++s) chunk(c0 + s, q[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < A; ++s)
+            if (c0 + s < nchunks) chunk(c0 + s, q[s]);  // the same for every consumer wave
+    }
+    __syncthreads();
+    if (right) {
+        for (int row = 0; row < L::R && y0 + row < H; ++row)
+            for (int i = threadIdx.x; i < W; i += blockDim.x)
+                f.wta.dr[(size_t)(y0 + row) * W + i] = (uint16_t)(keyR[row * kpitch + kWtaGuard + i] & 0xFF);
+    }
 }
 
 // ---------------------------------------------------------------------------

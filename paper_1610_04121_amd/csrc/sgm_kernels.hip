@@ -118,6 +118,14 @@ __global__ __launch_bounds__(1024) void wta_pair_kernel(WtaArgs l, WtaArgs r) {
         wta_row<LT, NT>(r, y - l.H, wta_smem);
 }
 
+// The final pass (see final_pass_block): NPL = n_paths - 1 stored planes;
+// NT: non-temporal plane loads.
+template <int Dp, int NPL, bool NT>
+__global__ __launch_bounds__(kFinalThreads) void final_pass_kernel(FinalArgs f) {
+    extern __shared__ __align__(16) uint8_t fp_smem[];
+    final_pass_block<Dp, NPL, NT>(f, blockIdx.x, fp_smem);
+}
+
 __global__ __launch_bounds__(256) void post_kernel(PostArgs a) {
     extern __shared__ uint16_t post_smem[];
     post_row(a, blockIdx.x, post_smem);
@@ -283,19 +291,22 @@ hipError_t launch_cost(const Plan& p, const Workspace& ws, hipStream_t stream, b
 }
 
 static void fill_agg_args(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right, int SH,
-                          int SV, AggArgs& a) {
+                          int SV, AggArgs& a, bool skip_last) {
     a.base = SliceArgs{ws.cost, ws.census_l, ws.census_r, nullptr, (uint32_t)((size_t)p.W * p.H * p.Dp),
                        p.W, p.H, p.D, p.P1, p.P2, p.cmax, 0, 0};
     a.lbuf = ws.lbuf;
     // directions of the left-base SGM (planes 0 .. P-1) and, for the full
     // left-right check, of the right-base SGM (planes P .. 2P-1)
     const int nsgm = p.lr_full ? 2 : 1;
-    a.ndirs = nsgm * p.n_paths;
+    const int all = nsgm * p.n_paths;
+    const int last = skip_last ? last_direction(p) : -1;
+    a.ndirs = all - (skip_last ? 1 : 0);
     // longest slices first, so that they start first
     int order[kMaxLaunchDirs], n = 0;
     const bool horiz_first = p.W >= p.H;
     for (int pass = 0; pass < 2; ++pass)
-        for (int i = 0; i < a.ndirs; ++i) {
+        for (int i = 0; i < all; ++i) {
+            if (i == last) continue;
             const bool horiz = direction(p.n_paths, i % p.n_paths).ry == 0;
             if ((horiz == horiz_first) == (pass == 0)) order[n++] = i;
         }
@@ -305,7 +316,8 @@ static void fill_agg_args(const Plan& p, const Workspace& ws, const uint8_t* lef
         const int S = d.ry == 0 ? SH : SV;
         a.rx[k] = d.rx;
         a.ry[k] = d.ry;
-        a.plane_index[k] = order[k];
+        // without the last direction the stored planes close up
+        a.plane_index[k] = order[k] - (last >= 0 && order[k] > last ? 1 : 0);
         a.cost[k] = order[k] < p.n_paths ? ws.cost : ws.cost_r;
         a.img[k] = order[k] < p.n_paths ? left : right;
         a.start[k] = acc;
@@ -325,12 +337,13 @@ static void fill_agg_args(const Plan& p, const Workspace& ws, const uint8_t* lef
 // Images of the two SGMs (base left / base right) for the adaptive P2.
 struct Images {
     const uint8_t *left, *right;
+    bool skip_last;  // leave out the direction the final pass fuses
 };
 
 template <int GH, int GV, int Dp, typename LT, bool FUSED, bool ADAPT, bool NT>
 static hipError_t launch_agg_t(const Plan& p, const Workspace& ws, Images im, hipStream_t stream) {
     AggArgs a;
-    fill_agg_args(p, ws, im.left, im.right, 64 / GH, 64 / GV, a);
+    fill_agg_args(p, ws, im.left, im.right, 64 / GH, 64 / GV, a, im.skip_last);
     hipLaunchKernelGGL((aggregate_kernel<GH, GV, Dp, LT, FUSED, ADAPT, NT>), dim3((a.total + 3) / 4), dim3(256), 0,
                        stream, a);
     return hipGetLastError();
@@ -371,10 +384,10 @@ void default_lanes(const Plan& p, int* gh, int* gv) {
 bool fused_aggregation(const Plan& p) { return p.fused && !p.lr_full && !p.adaptive; }
 
 hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stream, const uint8_t* left,
-                            const uint8_t* right) {
+                            const uint8_t* right, bool skip_last) {
     int gh = p.lanes_h, gv = p.lanes_v;
     if (gh <= 0 || gv <= 0) default_lanes(p, &gh, &gv);
-    const Images im{left, right};
+    const Images im{left, right, skip_last};
     if (p.adaptive) {
         if (!left || (p.lr_full && !right)) return hipErrorInvalidValue;
         return p.l16 ? launch_agg_lt<uint16_t, false, true, false>(p, ws, im, gh, gv, stream)
@@ -390,6 +403,56 @@ hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stre
                      : launch_agg_lt<uint8_t, false, false, true>(p, ws, im, gh, gv, stream);
     return p.l16 ? launch_agg_lt<uint16_t, false, false, false>(p, ws, im, gh, gv, stream)
                  : launch_agg_lt<uint8_t, false, false, false>(p, ws, im, gh, gv, stream);
+}
+
+bool final_pass_active(const Plan& p) {
+    if (!p.final_pass || p.l16 || p.lr_full || p.adaptive || fused_aggregation(p)) return false;
+    return final_smem_bytes(p.Dp, p.W, p.lrcheck) <= 64 * 1024;
+}
+
+template <int Dp, int NPL>
+static hipError_t launch_final_t(const Plan& p, const FinalArgs& f, hipStream_t stream) {
+    using L = FinalLayout<Dp>;
+    const size_t smem = final_smem_bytes(Dp, p.W, p.lrcheck);
+    auto k = p.nt_store ? final_pass_kernel<Dp, NPL, true> : final_pass_kernel<Dp, NPL, false>;
+    hipLaunchKernelGGL(k, dim3((p.H + L::R - 1) / L::R), dim3(kFinalThreads), smem, stream, f);
+    return hipGetLastError();
+}
+
+template <int Dp>
+static hipError_t launch_final_d(const Plan& p, const FinalArgs& f, hipStream_t stream) {
+    switch (p.n_paths) {
+        case 2: return launch_final_t<Dp, 1>(p, f, stream);
+        case 4: return launch_final_t<Dp, 3>(p, f, stream);
+        default: return launch_final_t<Dp, 7>(p, f, stream);
+    }
+}
+
+hipError_t launch_final_pass(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream, uint16_t* s_out) {
+    if (!final_pass_active(p)) return hipErrorInvalidValue;
+    const Dir d = direction(p.n_paths, last_direction(p));
+    const bool post = p.median || p.lrcheck;
+    const size_t plane = (size_t)p.W * p.H * p.Dp;
+    FinalArgs f;
+    f.agg = SliceArgs{ws.cost, ws.census_l, ws.census_r, nullptr, (uint32_t)plane, p.W, p.H, p.D, p.P1, p.P2,
+                      p.cmax, d.rx, d.ry};
+    f.planes = static_cast<const uint8_t*>(ws.lbuf);
+    f.plane = plane;
+    f.wta = WtaArgs{nullptr, plane, post ? ws.dl : out, p.lrcheck ? ws.dr : nullptr, p.W, p.H, p.D, p.Dp,
+                    p.n_paths - 1, p.subpixel ? 1 : 0};
+    f.s_out = s_out;
+    if (p.Dp == 64) return launch_final_d<64>(p, f, stream);
+    if (p.Dp == 128) return launch_final_d<128>(p, f, stream);
+    return launch_final_d<256>(p, f, stream);
+}
+
+hipError_t launch_aggregate_wta(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right,
+                                uint16_t* out, hipStream_t stream, hipEvent_t mid_event) {
+    const bool fp = final_pass_active(p);
+    hipError_t e = launch_aggregate(p, ws, stream, left, right, fp);
+    if (e == hipSuccess && mid_event) e = hipEventRecord(mid_event, stream);
+    if (e == hipSuccess) e = fp ? launch_final_pass(p, ws, out, stream) : launch_wta(p, ws, out, stream);
+    return e;
 }
 
 hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream) {
@@ -431,9 +494,7 @@ hipError_t launch_pipeline(const Plan& p, const Workspace& ws, const uint8_t* le
     mark(0);
     if (e == hipSuccess) e = launch_matching_cost(p, ws, left, right, !fused_aggregation(p), stream);
     mark(1);
-    if (e == hipSuccess) e = launch_aggregate(p, ws, stream, left, right);
-    mark(2);
-    if (e == hipSuccess) e = launch_wta(p, ws, out, stream);
+    if (e == hipSuccess) e = launch_aggregate_wta(p, ws, left, right, out, stream, events ? events[2] : nullptr);
     mark(3);
     if (e == hipSuccess) e = launch_post(p, ws, out, stream);
     mark(4);
@@ -444,14 +505,16 @@ hipError_t launch_census_only(const Plan& p, const uint8_t* img, uint64_t* out, 
     return launch_census_pair(p, img, img, out, out, 1, stream);
 }
 
-hipError_t launch_sum_planes(const Plan& p, const Workspace& ws, uint16_t* s_out, hipStream_t stream, int skip) {
+hipError_t launch_sum_planes(const Plan& p, const Workspace& ws, uint16_t* s_out, hipStream_t stream, int skip,
+                             int nplanes) {
     const size_t plane = (size_t)p.W * p.H * p.Dp;
+    if (nplanes < 0) nplanes = p.n_paths;
     if (p.l16)
         hipLaunchKernelGGL(sum_planes_kernel<uint16_t>, dim3(1024), dim3(256), 0, stream, ws.lbuf, plane, s_out,
-                           p.W, p.H, p.D, p.Dp, p.n_paths, skip);
+                           p.W, p.H, p.D, p.Dp, nplanes, skip);
     else
         hipLaunchKernelGGL(sum_planes_kernel<uint8_t>, dim3(1024), dim3(256), 0, stream, ws.lbuf, plane, s_out,
-                           p.W, p.H, p.D, p.Dp, p.n_paths, skip);
+                           p.W, p.H, p.D, p.Dp, nplanes, skip);
     return hipGetLastError();
 }
 

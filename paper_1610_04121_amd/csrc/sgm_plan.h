@@ -30,6 +30,8 @@ struct Plan {
     bool fused = false;        // aggregation computes costs from census words
                                // instead of reading the cost volume
     bool cc_fused = false;     // cost volume from one census + cost launch (9x7)
+    bool final_pass = false;   // the last direction fused with the sum and the
+                               // winner-take-all (where final_pass_active)
     int lanes_h = 0, lanes_v = 0;  // lanes per aggregation slice, horizontal / other
                                    // directions (16, 32, 64; 0 = default)
 };
@@ -71,9 +73,24 @@ hipError_t launch_cost(const Plan& p, const Workspace& ws, hipStream_t stream, b
 hipError_t launch_matching_cost(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right,
                                 bool need_cost, hipStream_t stream);
 bool census_cost_fusable(const Plan& p);
-// left / right: the caller's images (the base images of the adaptive P2)
+// left / right: the caller's images (the base images of the adaptive P2).
+// skip_last: every direction but last_direction(p), whose L_r the final
+// pass computes; the other planes are then numbered 0 .. n_paths - 2.
 hipError_t launch_aggregate(const Plan& p, const Workspace& ws, hipStream_t stream, const uint8_t* left = nullptr,
-                            const uint8_t* right = nullptr);
+                            const uint8_t* right = nullptr, bool skip_last = false);
+// Whether the final pass replaces the last direction's aggregation and the
+// WTA launch: the tuning asks for it and the plan allows it (u8 planes, the
+// cost volume, no full check, no adaptive P2, its LDS fits).
+bool final_pass_active(const Plan& p);
+// The final pass: after launch_aggregate(..., skip_last = true); writes the
+// raw maps (or `out` when no post stage follows); s_out (debug): S u16
+// [H][W][D].
+hipError_t launch_final_pass(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream,
+                             uint16_t* s_out = nullptr);
+// Aggregation and winner-take-all the way the plan runs them (the final pass
+// or aggregation + WTA): raw maps, or `out` when no post stage follows.
+hipError_t launch_aggregate_wta(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right,
+                                uint16_t* out, hipStream_t stream, hipEvent_t mid_event = nullptr);
 // whether the aggregation computes costs from census words (the tuning asks
 // for it and no option needs the cost volume)
 bool fused_aggregation(const Plan& p);
@@ -97,9 +114,10 @@ hipError_t launch_pipeline(const Plan& p, const Workspace& ws, const uint8_t* le
 // Debug taps.
 hipError_t launch_census_only(const Plan& p, const uint8_t* img, uint64_t* out,
                               hipStream_t stream);
-// S = sum of the L_r planes, leaving out plane `skip` (-1: none).
+// S = sum of the first nplanes L_r planes (-1: n_paths), leaving out plane
+// `skip` (-1: none).
 hipError_t launch_sum_planes(const Plan& p, const Workspace& ws, uint16_t* s_out,
-                             hipStream_t stream, int skip = -1);
+                             hipStream_t stream, int skip = -1, int nplanes = -1);
 // Copies plane `plane` of L_r (or the cost volume when plane < 0) out as u16
 // [H][W][D].
 hipError_t launch_extract_plane(const Plan& p, const Workspace& ws, int plane, uint16_t* out,

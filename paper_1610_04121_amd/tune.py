@@ -21,15 +21,25 @@ def padded_disp(max_disp: int) -> int:
     return 64 if max_disp <= 64 else (128 if max_disp <= 128 else 256)
 
 
-def candidates(max_disp: int, census_9x7: bool = True):
-    """(lanes_h, lanes_v, fused, census_cost) shapes the kernels provide for
-    this range: the cost volume from separate census and cost launches or
-    (9x7 windows) from one, or no cost volume at all (fused)."""
+def candidates(max_disp: int, census_9x7: bool = True, final_pass: bool = False):
+    """(lanes_h, lanes_v, fused, census_cost, final_pass) shapes the kernels
+    provide for this range: the cost volume from separate census and cost
+    launches or (9x7 windows) from one, or no cost volume at all (fused).
+    With final_pass, the shapes with a stored cost volume are also offered
+    with the last direction fused with the sum and the winner-take-all; they
+    are left out by default, having measured slower on every workload (the
+    fused pass runs a whole row's recurrence after the other directions)."""
     pairs = [(16, 16), (32, 16), (32, 32)]
     if padded_disp(max_disp) >= 128:
         pairs += [(64, 16), (64, 32)]
     costs = [(False, False), (True, False)] + ([(False, True)] if census_9x7 else [])
-    return [(gh, gv, f, cc) for gh, gv in pairs for f, cc in costs]
+    out = []
+    for gh, gv in pairs:
+        for f, cc in costs:
+            out.append((gh, gv, f, cc, False))
+            if final_pass and not f:
+                out.append((gh, gv, f, cc, True))
+    return out
 
 
 def cache_path() -> str:
@@ -88,7 +98,7 @@ def autotune(ctx, left=None, right=None, reps: int = 20, rounds: int = 2, use_ca
     key = cache_key(ctx)
     if use_cache:
         hit = load_cache().get(key)
-        if hit and tuple(hit.get("choice", ())) in set(_candidates(ctx)):
+        if hit and tuple(hit.get("choice", ())) in set(_candidates(ctx)):  # (older entries lack a field)
             ctx.set_tuning(*hit["choice"])
             return dict(hit, cached=True)
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -114,7 +124,7 @@ def autotune(ctx, left=None, right=None, reps: int = 20, rounds: int = 2, use_ca
     best = min(times, key=times.get)
     ctx.set_tuning(*best)
     entry = {"choice": list(best), "ms_per_frame": round(times[best], 5),
-             "candidates": {f"{gh},{gv},{int(f)},{int(cc)}": round(t, 5) for (gh, gv, f, cc), t in times.items()}}
+             "candidates": {",".join(str(int(v)) for v in cand): round(t, 5) for cand, t in times.items()}}
     if use_cache:
         try:
             save_entry(key, entry)

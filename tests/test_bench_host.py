@@ -35,6 +35,21 @@ def test_pipeline_bytes_of_the_fused_variants():
     assert bench.pipeline_bytes(W, H, Dp, P, (32, 16, 0, 1)) == census_cost
 
 
+def test_pipeline_bytes_with_the_final_pass():
+    # the last direction's plane is neither written nor read: 2N fewer bytes
+    W, H, Dp = 8, 3, 128
+    px, N = W * H, W * H * Dp
+    for P in (2, 4, 8):
+        plain = bench.pipeline_bytes(W, H, Dp, P, (32, 16, 0, 0, 0))
+        fp = bench.pipeline_bytes(W, H, Dp, P, (32, 16, 0, 0, 1))
+        assert plain - fp == 2 * N
+        assert fp == (2 * px + 16 * px) + (16 * px + N) + 2 * (P - 1) * N + (N + (P - 1) * N + 4 * px)
+        assert bench.pipeline_bytes(W, H, Dp, P, (32, 16, 0, 1, 1)) == \
+            bench.pipeline_bytes(W, H, Dp, P, (32, 16, 0, 1, 0)) - 2 * N
+    # the final pass needs the stored cost volume: ignored with fused costs
+    assert bench.pipeline_bytes(W, H, Dp, 4, (32, 16, 1, 0, 1)) == bench.pipeline_bytes(W, H, Dp, 4, (32, 16, 1, 0))
+
+
 def _write_pmc(path, counter, rows):
     with open(path, "w", newline="") as f:
         w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])

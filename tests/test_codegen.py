@@ -44,8 +44,8 @@ def test_no_packed_fp32(device_asm):
     assert not re.search(r"v_pk_(add|mul|fma)_f32", device_asm)
 
 
-def test_aggregation_kernels_do_not_spill(device_asm):
-    names = re.findall(r"^(_Z\S*aggregate_(?:batch_)?kernel\S*):", device_asm, re.M)
+def test_aggregation_and_final_pass_kernels_do_not_spill(device_asm):
+    names = re.findall(r"^(_Z\S*(?:aggregate_(?:batch_)?|final_pass_)kernel\S*):", device_asm, re.M)
     assert names
     for n in names:
         meta = device_asm[device_asm.index(n + ":"):]

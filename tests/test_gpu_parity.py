@@ -147,15 +147,17 @@ def test_raw_disparity_parity(gpu, W, H, D, P):
     assert (dr == want.dr_raw).all()
 
 
-@pytest.mark.parametrize("fused,census_cost", [(True, False), (False, False), (False, True)])
+@pytest.mark.parametrize("fused,census_cost,final_pass", [(True, False, False), (False, False, False),
+                                                          (False, True, False), (False, False, True),
+                                                          (False, True, True)])
 @pytest.mark.parametrize("name", list(synth.WORKLOADS))
-def test_workload_full_size_bit_exact(gpu, name, fused, census_cost):
+def test_workload_full_size_bit_exact(gpu, name, fused, census_cost, final_pass):
     cfg = synth.WORKLOADS[name]
     pair = synth.workload_pair(name)
-    _say(f"workload {name} fused={fused} census_cost={census_cost}")
+    _say(f"workload {name} fused={fused} census_cost={census_cost} final_pass={final_pass}")
     s = SGM(cfg["w"], cfg["h"], cfg["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, cfg["n_paths"],
             median=cfg["median"], lrcheck=cfg["lr"])
-    s.set_tuning(0, 0, fused, census_cost)
+    s.set_tuning(0, 0, fused, census_cost, final_pass)
     got = _np(s.compute(_t(pair.left, gpu), _t(pair.right, gpu)))
     s.close()
     want = oracle.sgm(pair.left, pair.right, cfg["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT,
@@ -478,26 +480,31 @@ def test_paths_sweep_full_size_every_kernel_shape(gpu, P):
             median=cfg["median"], lrcheck=cfg["lr"])
     for gh, gv in [(16, 16), (32, 16), (32, 32), (64, 16), (64, 32)]:
         for census_cost in (False, True):
-            _say(f"path sweep P={P} lanes=({gh},{gv}) census_cost={census_cost}")
-            s.set_tuning(gh, gv, False, census_cost)
-            got = _np(s.compute(tl, tr))
-            bad = np.argwhere(got != want)
-            assert len(bad) == 0, (gh, gv, census_cost, f"{len(bad)} pixels differ, first {bad[:5].tolist()}")
+            for final_pass in (False, True):
+                _say(f"path sweep P={P} lanes=({gh},{gv}) census_cost={census_cost} final_pass={final_pass}")
+                s.set_tuning(gh, gv, False, census_cost, final_pass)
+                got = _np(s.compute(tl, tr))
+                bad = np.argwhere(got != want)
+                assert len(bad) == 0, (gh, gv, census_cost, final_pass,
+                                       f"{len(bad)} pixels differ, first {bad[:5].tolist()}")
     s.close()
 
 
+@pytest.mark.parametrize("final_pass,lanes_h", [(False, 0), (True, 32), (True, 64)])
 @pytest.mark.parametrize("W,H,D,P,csct", [
     (37, 23, 16, 4, False), (29, 31, 20, 8, True), (70, 9, 130, 2, False), (64, 40, 64, 8, False),
-    (1, 5, 7, 4, False), (5, 1, 256, 2, False),
+    (1, 5, 7, 4, False), (5, 1, 256, 2, False), (203, 3, 200, 8, False),
 ])
-def test_phase_sums_parity(gpu, W, H, D, P, csct):
+def test_phase_sums_parity(gpu, W, H, D, P, csct, final_pass, lanes_h):
     """sgm_debug_phase_sums: phase 0 sums every direction but the one the
     final pass fuses (right-to-left; left-to-right with 2 paths), phase 1
-    all of them."""
+    all of them; with the final pass on, phase 1 is the sum the fused kernel
+    forms from the stored planes and its own recurrence."""
     rng = np.random.default_rng(W * 5 + H * 3 + D)
     l, r = _rand_pair(rng, W, H)
-    _say(f"phase sums {W}x{H} D={D} P={P} csct={csct}")
+    _say(f"phase sums {W}x{H} D={D} P={P} csct={csct} final_pass={final_pass} lanes_h={lanes_h}")
     s = SGM(W, H, D, 7, 86, P, csct=csct)
+    s.set_tuning(lanes_h, 16 if lanes_h else 0, False, False, final_pass)
     tl, tr = _t(l, gpu), _t(r, gpu)
     cl, cr = oracle.census(l, csct=csct), oracle.census(r, csct=csct)
     mc = oracle.cost_volume(cl, cr, D, oracle.cmax_of(csct=csct))
@@ -509,4 +516,35 @@ def test_phase_sums_parity(gpu, W, H, D, P, csct):
         got = _np(s.debug_phase_sums(tl, tr, phase))
         bad = np.argwhere(got != want)
         assert len(bad) == 0, (phase, f"{len(bad)} cells differ, first {bad[:5].tolist()}")
+    s.close()
+
+
+@pytest.mark.parametrize("trial", range(24))
+def test_fuzz_pipeline_final_pass(gpu, trial):
+    """The final pass (last direction fused with the sum and the winner-take-
+    all) on fuzzed shapes and options, against the oracle, for both of its
+    lane widths; raw maps through the debug tap as well."""
+    rng = np.random.default_rng(19000 + trial)
+    W, H = int(rng.integers(1, 90)), int(rng.integers(1, 40))
+    D = int(rng.choice([1, 7, 16, 40, 64, 65, 100, 128, 130, 200, 256]))
+    P = int(rng.choice([2, 4, 8]))
+    med, lr, sub, csct = (bool(rng.integers(0, 2)) for _ in range(4))
+    thr = int(rng.integers(0, 3))
+    gh = int(rng.choice([32, 64]))
+    l, r = _rand_pair(rng, W, H)
+    if trial % 3 == 0:  # textured pairs with a shift, so that disparities vary
+        pr = synth.make_pair(W, H, D, "RS", seed=19000 + trial)
+        l, r = pr.left, pr.right
+    _say(f"final pass fuzz {trial}: {W}x{H} D={D} P={P} med={med} lr={lr} sub={sub} csct={csct} thr={thr} gh={gh}")
+    s = SGM(W, H, D, 7, 86, P, median=med, lrcheck=lr, csct=csct, lr_threshold=thr, subpixel=sub)
+    s.set_tuning(gh, 16, False, False, True)
+    tl, tr = _t(l, gpu), _t(r, gpu)
+    got = _np(s.compute(tl, tr))
+    want = oracle.sgm(l, r, D, 7, 86, P, median=med, lr=lr, csct=csct, lr_thr=thr, subpixel=sub)
+    bad = np.argwhere(got != want.out)
+    assert len(bad) == 0, f"{len(bad)} pixels differ, first {bad[:5].tolist()}"
+    dl, dr = s.debug_raw_disparity(tl, tr)
+    want_raw = oracle.sgm(l, r, D, 7, 86, P, lr=True, csct=csct, subpixel=sub)
+    assert (_np(dl) == want_raw.dl_raw).all()
+    assert (_np(dr) == want_raw.dr_raw).all()
     s.close()
