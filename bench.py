@@ -73,32 +73,45 @@ def summarize_counters(fetch_csv: str, write_csv: str, copy_mib: int, tuning) ->
     """Per-dispatch HBM bytes of every kernel from two rocprofv3 --pmc runs
     (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
     same counter reads for the device copy of copy_mib MiB that the profiled
-    run made (--copy-calibration-mb)."""
+    run made (--copy-calibration-mb): the copy dispatches with the largest
+    readings (other copies, such as image uploads, are smaller).  When the run
+    also made the read-only reduction of --read-calibration-mb, its FETCH_SIZE
+    scale is reported as a cross-check of the read scale."""
     import csv
     from collections import defaultdict
 
-    def means(path, counter):
+    def rows(path, counter):
         acc = defaultdict(list)
         for r in csv.DictReader(open(path)):
             if r["Counter_Name"] == counter:
                 acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
-        return {k: sum(v) / len(v) for k, v in acc.items()}
+        return acc
 
-    fetch, write = means(fetch_csv, "FETCH_SIZE"), means(write_csv, "WRITE_SIZE")
+    def calib(acc, pattern):
+        vals = [v for k, vs in acc.items() if pattern in k for v in vs]
+        top = max(vals)
+        big = [v for v in vals if v >= 0.99 * top]
+        return sum(big) / len(big)
+
+    fr, wr = rows(fetch_csv, "FETCH_SIZE"), rows(write_csv, "WRITE_SIZE")
+    fetch = {k: sum(v) / len(v) for k, v in fr.items()}
+    write = {k: sum(v) / len(v) for k, v in wr.items()}
     copy_kib = copy_mib * 1024.0
-    copy_name = next(k for k in fetch if "copyBuffer" in k)
-    f_fetch, f_write = copy_kib / fetch[copy_name], copy_kib / write[copy_name]
+    f_fetch, f_write = copy_kib / calib(fr, "copyBuffer"), copy_kib / calib(wr, "copyBuffer")
     kernels = {}
     for k in fetch:
-        if k == copy_name or k not in write:
+        if "copyBuffer" in k or "at::native" in k or k not in write:
             continue
-        rd, wr = fetch[k] * f_fetch * 1024, write[k] * f_write * 1024
-        kernels[k] = {"read_bytes": round(rd), "write_bytes": round(wr), "fetch_kib": round(fetch[k], 2),
+        rd, wrb = fetch[k] * f_fetch * 1024, write[k] * f_write * 1024
+        kernels[k] = {"read_bytes": round(rd), "write_bytes": round(wrb), "fetch_kib": round(fetch[k], 2),
                       "write_kib": round(write[k], 2)}
     agg = next(k for k in kernels if "aggregate_kernel<" in k)
-    return {"kernel": agg, "kernel_sha": _kernel_sha(), "tuning": [int(v) for v in tuning],
-            "fetch_scale": round(f_fetch, 4), "write_scale": round(f_write, 4),
-            "bytes_per_launch": kernels[agg]["read_bytes"] + kernels[agg]["write_bytes"], "kernels": kernels}
+    out = {"kernel": agg, "kernel_sha": _kernel_sha(), "tuning": [int(v) for v in tuning],
+           "fetch_scale": round(f_fetch, 4), "write_scale": round(f_write, 4),
+           "bytes_per_launch": kernels[agg]["read_bytes"] + kernels[agg]["write_bytes"], "kernels": kernels}
+    if any("reduce_kernel" in k for k in fr):
+        out["fetch_scale_read_only"] = round(copy_kib / calib(fr, "reduce_kernel"), 4)
+    return out
 
 
 def pipeline_bytes(W: int, H: int, Dp: int, P: int, tuning) -> int:
@@ -482,6 +495,9 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
+    ap.add_argument("--read-calibration-mb", type=int, default=0,
+                    help="also run a read-only reduction (torch.sum of int64 words) over this many MiB: a second "
+                         "known-size reference for the byte counters, with another access pattern than the copy")
     ap.add_argument("--counters-from", default="",
                     help="FETCH_CSV,WRITE_CSV: summarize rocprofv3 --pmc output (with --copy-calibration-mb "
                          "and --tuning as in the profiled run) as JSON and exit")
@@ -685,6 +701,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         line["copy_calibration_bytes"] = n
+    if args.read_calibration_mb:
+        n = args.read_calibration_mb << 20
+        src = torch.ones(n // 8, dtype=torch.int64, device=dev)
+        for _ in range(3):
+            total = int(src.sum().item())
+        assert total == n // 8
+        line["read_calibration_bytes"] = n
     if not args.no_batch:
         print("bench: 64-pair batch vs sequential launches", file=sys.stderr, flush=True)
         line["batched"] = bench_batch(dev, args.batch_steps)

@@ -63,17 +63,28 @@ def test_counter_summary_scales_by_the_copy(tmp_path):
     agg = "void sgm::aggregate_kernel<32, 16, 128, unsigned char, false, false>(sgm::AggArgs)"
     cost = "void sgm::cost_kernel<false>(sgm::CostArgs)"
     mib = 256
-    # FETCH_SIZE reads half of a copy's bytes, WRITE_SIZE all of them
+    # FETCH_SIZE reads half of a copy's bytes, WRITE_SIZE all of them; small
+    # copies (image uploads) in the same run do not enter the calibration
     _write_pmc(tmp_path / "f.csv", "FETCH_SIZE",
-               [(copy, mib * 512.0), (agg, 1000.0), (agg, 1002.0), (cost, 10.0)])
-    _write_pmc(tmp_path / "w.csv", "WRITE_SIZE", [(copy, mib * 1024.0), (agg, 3000.0), (cost, 20.0)])
+               [(copy, mib * 512.0), (copy, 1.5), (copy, mib * 512.0), (agg, 1000.0), (agg, 1002.0), (cost, 10.0)])
+    _write_pmc(tmp_path / "w.csv", "WRITE_SIZE",
+               [(copy, mib * 1024.0), (copy, 0.03), (agg, 3000.0), (cost, 20.0)])
     s = bench.summarize_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), mib, ["32", "16", "0", "0"])
     assert s["kernel"] == agg and s["tuning"] == [32, 16, 0, 0]
     assert s["fetch_scale"] == 2.0 and s["write_scale"] == 1.0
     assert s["bytes_per_launch"] == 1001.0 * 2 * 1024 + 3000.0 * 1024
     assert s["kernels"][cost]["read_bytes"] == 20 * 1024
     assert copy not in s["kernels"]
+    assert "fetch_scale_read_only" not in s
     json.dumps(s)
+    # with the read-only reduction of the same size: its scale is reported
+    red = "void at::native::reduce_kernel<512, 1>"
+    _write_pmc(tmp_path / "f2.csv", "FETCH_SIZE",
+               [(copy, mib * 512.0), (red, mib * 512.0 * 1.0005), (agg, 1000.0)])
+    _write_pmc(tmp_path / "w2.csv", "WRITE_SIZE", [(copy, mib * 1024.0), (red, 16.0), (agg, 3000.0)])
+    s2 = bench.summarize_counters(str(tmp_path / "f2.csv"), str(tmp_path / "w2.csv"), mib, ["32", "16", "0", "0"])
+    assert abs(s2["fetch_scale_read_only"] - 2.0) < 0.01
+    assert red not in s2["kernels"]
 
 
 @pytest.mark.parametrize("n", [0, 2, 8])
