@@ -196,7 +196,7 @@ def _oracle_frame(spec):
     """Seconds for one oracle frame of a pair spec (worker of oracle_timing)."""
     import oracle
     from paper_1610_04121_amd import synth
-    pr = synth.make_pair(spec["w"], spec["h"], spec["max_disp"], spec["scene"], seed=spec["seed"])
+    pr = synth.spec_pair(spec)
     t0 = time.perf_counter()
     oracle.sgm(pr.left, pr.right, spec["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, spec["n_paths"],
                median=spec.get("median", False), lr=spec.get("lr", False))
@@ -312,6 +312,7 @@ def bench_batch(dev, steps: int, warmup: int = 3, post: bool = False):
         cells += it["w"] * it["h"] * it["max_disp"] * it["n_paths"]
     b = Batch(synth.P1_DEFAULT, synth.P2_DEFAULT)
     st = torch.cuda.current_stream()
+    tuned = b.autotune(pairs, use_cache=False)
     for _ in range(warmup):
         b.compute(pairs, stream=st)
     torch.cuda.synchronize()
@@ -350,117 +351,207 @@ def bench_batch(dev, steps: int, warmup: int = 3, post: bool = False):
             "pairs_per_s": round(len(pairs) / t_batch, 1), "gcells_per_s": round(cells / t_batch / 1e9, 1),
             "sequential_ms": round(t_seq * 1e3, 4), "sequential_pairs_per_s": round(len(pairs) / t_seq, 1),
             "speedup_vs_sequential": round(t_seq / t_batch, 3), "workspace_bytes": footprint,
+            "tuning": {"lanes_h_lanes_v": tuned["choice"], "ms_per_batch_by_shape": tuned["candidates"]},
             "shapes": "64 pairs, sizes from {320x240, 640x480, 1242x375, 1280x720}, D from {64, 128}, "
                       "4 or 8 paths, " + ("median + LR check" if post else "no median/LR")}
 
 
-def bench_serve(dev, qps_levels, n_req: int, slots: int = 4, streams: int = 4, max_group: int = 8,
-                group_cells: int = 1 << 28, overlap_queue: int = 3, seed: int = 1610041214):
+def _serve_setup(dev, seed):
+    """The served mix's kinds, one device-resident pair per kind."""
+    import torch
+
+    from paper_1610_04121_amd import synth
+    specs = synth.serve_kinds(seed)
+    pool = []
+    for k in specs:
+        pr = synth.spec_pair(k)
+        pool.append((torch.from_numpy(pr.left).to(dev), torch.from_numpy(pr.right).to(dev)))
+    return specs, pool
+
+
+class _OutPool:
+    """Output buffers per kind: a request holds one from its submission until
+    its completion has been observed.  Taking from an empty pool first waits
+    for that kind's oldest outstanding request (never the case at the sizes
+    used: the pools hold more than the longest backlog)."""
+
+    def __init__(self, dev, specs, per_kind):
+        import torch
+        self.free = [[torch.empty((k["h"], k["w"]), dtype=torch.uint16, device=dev) for _ in range(per_kind)]
+                     for k in specs]
+
+    def take(self, k, wait_oldest):
+        if not self.free[k]:
+            wait_oldest(k)
+        return self.free[k].pop()
+
+    def give(self, k, t):
+        self.free[k].append(t)
+
+
+def _serve_level(srv, specs, pool, outs, qps, n_req, n_warm, rng):
+    """One open-loop level through the server: n_warm warm-up requests, then
+    n_req measured ones, Poisson arrivals at qps.  Returns latency stats of
+    the measured requests, served frames/s, rejections and the mean group
+    size, plus the arrival schedule (for the plain baseline)."""
+    import collections
+
+    import numpy as np
+
+    from paper_1610_04121_amd.sgm import FINAL, REQ_DONE, SGM_EBUSY, SGMError
+    total = n_warm + n_req
+    arrivals = np.cumsum(rng.exponential(1.0 / qps, total))
+    which = rng.integers(0, len(specs), total)
+    cells = np.array([k["w"] * k["h"] * k["max_disp"] * 8 for k in specs], dtype=np.float64)
+    outstanding = collections.deque()  # (index, kind, ticket, buffer) in submission order
+    lat, done_at, rejected = {}, {}, 0
+
+    def finish(entry, block):
+        i, k, t, buf = entry
+        st, l = srv.wait(t) if block else srv.poll(t)
+        if st not in FINAL:
+            return False
+        assert st == REQ_DONE, st
+        lat[i], done_at[i] = l, arrivals[i] + l
+        outs.give(k, buf)
+        return True
+
+    def wait_oldest(k):
+        for e in list(outstanding):
+            if e[1] == k:
+                finish(e, True)
+                outstanding.remove(e)
+                return
+
+    g0 = srv.stats()
+    t0 = time.perf_counter() + 0.005
+    for i in range(total):
+        if i == n_warm:
+            g0 = srv.stats()
+        target = t0 + arrivals[i]
+        while True:
+            # harvest completions while waiting for the next arrival
+            while outstanding and finish(outstanding[0], False):
+                outstanding.popleft()
+            now = time.perf_counter()
+            if now >= target:
+                break
+            if target - now > 2e-3:
+                time.sleep(min(target - now - 1e-3, 1e-3))
+        k = int(which[i])
+        buf = outs.take(k, wait_oldest)
+        left, right = pool[k]
+        req = dict(left=left, right=right, out=buf, max_disp=specs[k]["max_disp"], n_paths=8, median=True,
+                   lrcheck=True, lr_threshold=1)
+        try:
+            outstanding.append((i, k, srv.submit(req), buf))
+        except SGMError as e:
+            if e.code != SGM_EBUSY:
+                raise
+            rejected += i >= n_warm
+            outs.give(k, buf)
+    while outstanding:
+        finish(outstanding.popleft(), True)
+    g1 = srv.stats()
+    meas = [i for i in range(n_warm, total) if i in lat]
+    l = np.array([lat[i] for i in meas])
+    span = max(done_at[i] for i in meas) - arrivals[n_warm]
+    return {"p50_ms": round(float(np.percentile(l, 50)) * 1e3, 3), "p99_ms": round(float(np.percentile(l, 99)) * 1e3, 3),
+            "frames_per_s": round(len(meas) / span, 1),
+            "gcells_per_s": round(sum(cells[which[i]] for i in meas) / span / 1e9, 1),
+            "rejected": rejected, "requests": n_req, "warmup": n_warm,
+            "mean_group": round((g1["grouped_requests"] - g0["grouped_requests"]) / max(1, g1["groups"] - g0["groups"]),
+                                2)}, arrivals[n_warm:] - arrivals[n_warm], which[n_warm:]
+
+
+def _plain_level(ctxs, specs, pool, outs, arrivals, which, st):
+    """The same arrival times through plain per-request launches: one context
+    per kind, one stream, each request synchronised before the next starts."""
+    import numpy as np
+    cells = np.array([k["w"] * k["h"] * k["max_disp"] * 8 for k in specs], dtype=np.float64)
+    t0 = time.perf_counter() + 0.005
+    plat = []
+    for i in range(len(arrivals)):
+        target = t0 + arrivals[i]
+        while time.perf_counter() < target:
+            pass
+        k = int(which[i])
+        buf = outs.take(k, lambda _: None)
+        ctxs[k].compute(pool[k][0], pool[k][1], buf, stream=st)
+        st.synchronize()
+        outs.give(k, buf)
+        plat.append(time.perf_counter() - target)
+    span = (t0 + arrivals[-1] + plat[-1]) - t0
+    return {"p50_ms": round(float(np.percentile(plat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(plat, 99)) * 1e3, 3),
+            "frames_per_s": round(len(plat) / span, 1),
+            "gcells_per_s": round(float(cells[which].sum()) / span / 1e9, 1)}
+
+
+def bench_serve(dev, qps_levels, min_requests: int = 1000, per_qps_s: float = 10.0, warmup: int = 100,
+                slots: int = 4, streams: int = 4, overlap_queue: int = 3, group_trial_s: float = 3.0,
+                seed: int = 1610041214):
     """Poisson arrivals of 8-path median + LR requests of mixed sizes and
-    disparity ranges, served by the continuous-batching server and, on the
-    same arrival times, by plain per-request launches (one context per
-    shape, one stream, each request synchronised before the next starts)."""
+    disparity ranges (the road scene scaled to each range), served by the
+    continuous-batching server and, on the same arrival times, by plain
+    per-request launches.  Each level runs max(min_requests, per_qps_s * qps)
+    requests after `warmup` warm-up requests.  First, at the highest level
+    (past saturation), the server runs with and without grouping (groups of
+    up to 2, 4, 8 requests against groups of one) for group_trial_s seconds
+    of arrivals each; the sweep uses the policy with the highest throughput."""
     import numpy as np
     import torch
 
     from paper_1610_04121_amd import SGM, synth
-    from paper_1610_04121_amd.sgm import REQ_DONE, SGM_EBUSY, SGMError, Server
+    from paper_1610_04121_amd.sgm import Server
 
-    specs = synth.serve_kinds(seed)
-    kinds = [(k["w"], k["h"], k["max_disp"]) for k in specs]
-    pool = []
-    for k in specs:
-        pr = synth.make_pair(k["w"], k["h"], k["max_disp"], k["scene"], seed=k["seed"])
-        pool.append((torch.from_numpy(pr.left).to(dev), torch.from_numpy(pr.right).to(dev)))
+    specs, pool = _serve_setup(dev, seed)
     budget = 64 << 30
-    srv = Server(budget, slots=slots, streams=streams, max_group=max_group, max_group_cells=group_cells,
-                 overlap_queue=overlap_queue)
-    ctxs = [SGM(w, h, d, synth.P1_DEFAULT, synth.P2_DEFAULT, 8, median=True, lrcheck=True) for (w, h, d) in kinds]
-    st = torch.cuda.current_stream()
-    outs = {k: [torch.empty((h, w), dtype=torch.uint16, device=dev) for _ in range(n_req)]
-            for k, (w, h, _) in enumerate(kinds)}
-
-    def req(k, j):
-        w, h, d = kinds[k]
-        return dict(left=pool[k][0], right=pool[k][1], out=outs[k][j], max_disp=d, n_paths=8,
-                    median=True, lrcheck=True, lr_threshold=1)
-
-    # warm-up: every kind once through both paths
-    for k in range(len(kinds)):
-        srv.wait(srv.submit(req(k, 0)))
-        ctxs[k].compute(pool[k][0], pool[k][1], outs[k][0], stream=st)
-    torch.cuda.synchronize()
-
+    top = max(qps_levels)
+    outs = _OutPool(dev, specs, per_kind=1024)
     rng = np.random.default_rng(seed)
-    cells = np.array([w * h * d * 8 for (w, h, d) in kinds], dtype=np.float64)
+    # grouping: measured at saturation
+    trials = {}
+    for mg in (1, 2, 4, 8):
+        srv = Server(budget, slots=slots, streams=streams, max_group=mg, max_pending=1 << 16,
+                     max_group_cells=1 << 62, overlap_queue=overlap_queue)
+        res, _, _ = _serve_level(srv, specs, pool, outs, top, int(group_trial_s * top), warmup,
+                                 np.random.default_rng(seed + 1))
+        srv.close()
+        trials[str(mg)] = res
+        print(f"bench: serve grouping max_group={mg} at {top}/s: {res['frames_per_s']} frames/s, "
+              f"p99 {res['p99_ms']} ms, mean group {res['mean_group']}", file=sys.stderr, flush=True)
+    best = max(trials, key=lambda g: trials[g]["frames_per_s"])
+    max_group = int(best)
+    srv = Server(budget, slots=slots, streams=streams, max_group=max_group, max_pending=1 << 16,
+                 max_group_cells=1 << 62, overlap_queue=overlap_queue)
+    ctxs = [SGM(k["w"], k["h"], k["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, 8, median=True, lrcheck=True)
+            for k in specs]
+    st = torch.cuda.current_stream()
+    for k in range(len(specs)):  # warm the plain path's contexts
+        buf = outs.take(k, lambda _: None)
+        ctxs[k].compute(pool[k][0], pool[k][1], buf, stream=st)
+        outs.give(k, buf)
+    torch.cuda.synchronize()
     levels = []
     for qps in qps_levels:
-        arrivals = np.cumsum(rng.exponential(1.0 / qps, n_req))
-        which = rng.integers(0, len(kinds), n_req)
-
-        def pace(t0, i):
-            target = t0 + arrivals[i]
-            while True:
-                now = time.perf_counter()
-                if now >= target:
-                    return
-                if target - now > 2e-3:
-                    time.sleep(target - now - 1e-3)
-
-        # server
-        g0 = srv.stats()
-        t0 = time.perf_counter() + 0.005
-        tickets, rejected = [], 0
-        for i in range(n_req):
-            pace(t0, i)
-            try:
-                tickets.append((i, srv.submit(req(int(which[i]), i))))
-            except SGMError as e:
-                if e.code != SGM_EBUSY:
-                    raise
-                rejected += 1
-        lat, done_at = [], []
-        for i, t in tickets:
-            status, l = srv.wait(t)
-            assert status == REQ_DONE
-            lat.append(l)
-            done_at.append(arrivals[i] + l)
-        g1 = srv.stats()
-        span = max(done_at) - arrivals[0]
-        served_cells = sum(cells[which[i]] for i, _ in tickets)
-        server_res = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                      "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                      "frames_per_s": round(len(lat) / span, 1),
-                      "gcells_per_s": round(served_cells / span / 1e9, 1),
-                      "rejected": rejected,
-                      "mean_group": round((g1["grouped_requests"] - g0["grouped_requests"]) /
-                                          max(1, g1["groups"] - g0["groups"]), 2)}
-        # plain per-request launches on the same schedule
-        t0 = time.perf_counter() + 0.005
-        plat = []
-        for i in range(n_req):
-            pace(t0, i)
-            k = int(which[i])
-            ctxs[k].compute(pool[k][0], pool[k][1], outs[k][i], stream=st)
-            st.synchronize()
-            plat.append(time.perf_counter() - (t0 + arrivals[i]))
-        pspan = (t0 + arrivals[-1] + plat[-1]) - (t0 + arrivals[0])
-        plain_res = {"p50_ms": round(float(np.percentile(plat, 50)) * 1e3, 3),
-                     "p99_ms": round(float(np.percentile(plat, 99)) * 1e3, 3),
-                     "frames_per_s": round(n_req / pspan, 1),
-                     "gcells_per_s": round(float(cells[which].sum()) / pspan / 1e9, 1)}
-        print(f"bench: serve qps={qps} server p99={server_res['p99_ms']} ms plain p99={plain_res['p99_ms']} ms",
-              file=sys.stderr, flush=True)
+        n_req = max(min_requests, int(per_qps_s * qps))
+        server_res, arr, which = _serve_level(srv, specs, pool, outs, qps, n_req, warmup, rng)
+        plain_res = _plain_level(ctxs, specs, pool, outs, arr, which, st)
+        print(f"bench: serve qps={qps} ({n_req} requests) server p99={server_res['p99_ms']} ms "
+              f"plain p99={plain_res['p99_ms']} ms", file=sys.stderr, flush=True)
         levels.append({"offered_qps": qps, "requests": n_req, "server": server_res, "plain": plain_res})
     stats = srv.stats()
     srv.close()
     for c in ctxs:
         c.close()
     return {"levels": levels, "budget_bytes": budget, "slots": slots, "streams": streams, "max_group": max_group,
-            "max_group_cells": group_cells, "overlap_queue": overlap_queue,
-            "peak_bytes": stats["peak_bytes"],
+            "max_group_cells": None, "overlap_queue": overlap_queue, "peak_bytes": stats["peak_bytes"],
+            "grouping_at_saturation": {"offered_qps": top, "requests": int(group_trial_s * top), "by_max_group": trials,
+                                       "chosen_max_group": max_group},
             "mix": "Poisson arrivals; sizes from {640x480, 1242x375, 1280x720, 1920x1080}, D from {128, 256}, "
-                   "8 paths, median + LR check; latency = submission to observed completion"}
+                   "8 paths, median + LR check, road scene scaled to D; latency = submission to observed completion; "
+                   f"max(1000, 10 qps) requests per level after {warmup} warm-up"}
 
 
 def main():
@@ -484,12 +575,12 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batched measurement")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-requests measurement")
-    ap.add_argument("--serve-qps", default="50,200,500,1000,1500,2000")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-qps", default="50,500,1000,1500,2000")
+    ap.add_argument("--serve-min-requests", type=int, default=1000,
+                    help="requests per level: max(this, --serve-seconds * qps), after 100 warm-up")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-streams", type=int, default=4)
-    ap.add_argument("--serve-max-group", type=int, default=8)
-    ap.add_argument("--serve-group-cells", type=int, default=1 << 28)
     ap.add_argument("--serve-overlap-queue", type=int, default=3)
     ap.add_argument("--latency-samples", type=int, default=300)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -714,9 +805,9 @@ def main():
         line["batched_median_lr"] = bench_batch(dev, args.batch_steps, post=True)
     if not args.no_serve:
         print("bench: served requests", file=sys.stderr, flush=True)
-        line["served"] = bench_serve(dev, [float(q) for q in args.serve_qps.split(",")], args.serve_requests,
-                                     args.serve_slots, args.serve_streams, args.serve_max_group,
-                                     args.serve_group_cells, args.serve_overlap_queue)
+        line["served"] = bench_serve(dev, [float(q) for q in args.serve_qps.split(",")], args.serve_min_requests,
+                                     args.serve_seconds, slots=args.serve_slots, streams=args.serve_streams,
+                                     overlap_queue=args.serve_overlap_queue)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(pair, cfg)

@@ -170,9 +170,10 @@ int sgm_compute_noalloc(int width, int height, int max_disp, int P1, int P2, int
  * One item is one stereo pair with its own size (w x h), disparity range,
  * path count and options; the census window and P1, P2 belong to the batch
  * (or server).  Buffers follow the conventions above.  Item flags:
- * SGM_MEDIAN3, SGM_LRCHECK, SGM_SUBPIXEL, and the item's left-right
- * threshold as SGM_ITEM_LR_THRESHOLD(t), t in [0, 255]; without it the
- * threshold is 1 (as for sgm_set_options). */
+ * SGM_MEDIAN3, SGM_LRCHECK, SGM_SUBPIXEL, SGM_LR_FULL (with SGM_LRCHECK),
+ * SGM_ADAPTIVE_P2, and the item's left-right threshold as
+ * SGM_ITEM_LR_THRESHOLD(t), t in [0, 255]; without it the threshold is 1 (as
+ * for sgm_set_options). */
 typedef struct {
     int w, h, max_disp, n_paths;
     unsigned flags;
@@ -190,13 +191,21 @@ typedef struct sgm_batch sgm_batch;
 sgm_batch *sgm_batch_create(int P1, int P2, int census_w, int census_h);
 
 /* Enqueues all n items on `stream`: one census, one cost, one aggregation,
- * one sum + winner-take-all and one median + LR launch for the whole batch.
+ * one sum + winner-take-all and one median + LR launch for the whole batch
+ * (items with SGM_LR_FULL add their right-base costs, directions and rows to
+ * the same launches).
  * The aggregation is a persistent kernel whose wavefronts take (pair,
  * direction, slice group) work items, longest first, from a queue.  The
  * runner keeps a device workspace that grows to the largest batch seen;
  * growing it waits for the device to go idle first.  Items must not share
  * output buffers.  Results are identical to n separate sgm_compute calls. */
 int sgm_batch_compute(sgm_batch *b, const sgm_item *items, int n, sgm_stream_t stream);
+
+/* Kernel shape of the batched aggregation (results never depend on it):
+ * lanes per horizontal slice (16 or 32) and per other slice (16 or 32) for
+ * every pair; 0 keeps the per-pair default (32 horizontal lanes when the
+ * image is wider than tall, else 16; 16 for the other directions). */
+int sgm_batch_set_tuning(sgm_batch *b, int lanes_h, int lanes_v);
 
 /* Device bytes sgm_batch_compute needs for these items (0 if one is invalid). */
 size_t sgm_batch_footprint(sgm_batch *b, const sgm_item *items, int n);

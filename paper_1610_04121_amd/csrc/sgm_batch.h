@@ -15,6 +15,9 @@ namespace sgm {
 struct BatchParams {
     int P1, P2, cw, ch;
     bool csct;
+    // lanes per aggregation slice for every pair: horizontal (16 or 32) and
+    // other directions (16 or 32); 0 = the per-pair default
+    int lanes_h = 0, lanes_v = 0;
 };
 
 // Per-pair plans and workspace offsets inside one arena.

@@ -36,16 +36,18 @@ struct BatchItem {
     uint64_t* census_l;
     uint64_t* census_r;
     uint8_t* cost;
-    void* lbuf;
+    uint8_t* cost_r;  // right-base costs (lr_full), else nullptr
+    void* lbuf;       // L_r planes; with lr_full the right-base planes follow
     uint16_t* dl;
     uint16_t* dr;
-    int W, H, D, Dp, P, cmax, l16, median, lrcheck, thr, csct, gh, subpixel;
+    int W, H, D, Dp, P, cmax, l16, median, lrcheck, thr, csct, gh, gv, subpixel, lr_full, adaptive;
     int census_blk0, cost_blk0, wta_blk0, post_blk0;  // first block in each launch
 };
 
-// One aggregation work item: S = 64 / G slices of one direction of one pair.
+// One aggregation work item: S = 64 / G slices of one direction of one pair;
+// rb = 1 for a direction of the right-base SGM (full left-right check).
 struct WorkItem {
-    int item, plane, rx, ry, first, steps;
+    int item, plane, rx, ry, first, steps, rb;
 };
 
 // Index of the pair whose block range [blk0, next blk0) holds block b.
@@ -81,39 +83,80 @@ __global__ __launch_bounds__(256) void census_batch_kernel(const BatchItem* item
     }
 }
 
+// Blocks 0 .. nx * H - 1 of a pair make its cost volume; with the full
+// left-right check, the next nx * H make the right-base costs.
+template <bool RB>
+__device__ inline void cost_batch_block(const BatchItem& it, int bx, int y, uint64_t* smem) {
+    const CostArgs a = RB ? CostArgs{it.census_r, it.census_l, it.cost_r, it.W, it.H, it.D, it.Dp, it.cmax}
+                          : CostArgs{it.census_l, it.census_r, it.cost, it.W, it.H, it.D, it.Dp, it.cmax};
+    if (it.Dp == 64)
+        cost_block<RB, 64>(a, bx, y, smem);
+    else if (it.Dp == 128)
+        cost_block<RB, 128>(a, bx, y, smem);
+    else
+        cost_block<RB, 256>(a, bx, y, smem);
+}
+
 __global__ __launch_bounds__(kCostThreads) void cost_batch_kernel(const BatchItem* items, int n) {
     extern __shared__ __align__(16) uint64_t cost_smem[];
     const int b = blockIdx.x;
     const BatchItem& it = items[find_item<&BatchItem::cost_blk0>(items, n, b)];
-    const int local = b - it.cost_blk0;
+    int local = b - it.cost_blk0;
     const int nx = (it.W + kCostTX - 1) / kCostTX;
-    CostArgs a{it.census_l, it.census_r, it.cost, it.W, it.H, it.D, it.Dp, it.cmax};
-    if (it.Dp == 64)
-        cost_block<false, 64>(a, local % nx, local / nx, cost_smem);
-    else if (it.Dp == 128)
-        cost_block<false, 128>(a, local % nx, local / nx, cost_smem);
-    else
-        cost_block<false, 256>(a, local % nx, local / nx, cost_smem);
-}
-
-// NT: non-temporal L_r stores (the batch's planes exceed the memory-side cache)
-template <typename LT, int Dp, bool NT>
-__device__ inline void aggregate_item(const SliceArgs& s, int kind, int gh, int first, int lane) {
-    if (kind == kHoriz) {
-        if (gh == 32)
-            aggregate_wave<32, Dp / 32, LT, kHoriz, false, false, NT>(s, first, lane);
-        else
-            aggregate_wave<16, Dp / 16, LT, kHoriz, false, false, NT>(s, first, lane);
-    } else if (kind == kVert) {
-        aggregate_wave<16, Dp / 16, LT, kVert, false, false, NT>(s, first, lane);
+    if (local < nx * it.H) {
+        cost_batch_block<false>(it, local % nx, local / nx, cost_smem);
     } else {
-        aggregate_wave<16, Dp / 16, LT, kDiag, false, false, NT>(s, first, lane);
+        local -= nx * it.H;
+        cost_batch_block<true>(it, local % nx, local / nx, cost_smem);
     }
 }
 
-template <bool NT>
+// NT: non-temporal L_r stores (the batch's planes exceed the memory-side
+// cache); ADAPT: adaptive P2 (the block's penalty table is in s.p2lut).
+template <typename LT, int Dp, bool NT, bool ADAPT>
+__device__ __attribute__((always_inline)) inline void aggregate_item(const SliceArgs& s, int kind, int g, int first,
+                                                                     int lane) {
+    if (kind == kHoriz) {
+        if (g == 32)
+            aggregate_wave<32, Dp / 32, LT, kHoriz, false, ADAPT, NT>(s, first, lane);
+        else
+            aggregate_wave<16, Dp / 16, LT, kHoriz, false, ADAPT, NT>(s, first, lane);
+    } else if (kind == kVert) {
+        if (g == 32)
+            aggregate_wave<32, Dp / 32, LT, kVert, false, ADAPT, NT>(s, first, lane);
+        else
+            aggregate_wave<16, Dp / 16, LT, kVert, false, ADAPT, NT>(s, first, lane);
+    } else {
+        if (g == 32)
+            aggregate_wave<32, Dp / 32, LT, kDiag, false, ADAPT, NT>(s, first, lane);
+        else
+            aggregate_wave<16, Dp / 16, LT, kDiag, false, ADAPT, NT>(s, first, lane);
+    }
+}
+
+// g: the work item's lanes per slice (its pair's horizontal or other group
+// width, by the direction's kind)
+template <typename LT, bool NT, bool ADAPT>
+__device__ __attribute__((always_inline)) inline void aggregate_item_dp(const SliceArgs& s, int Dp, int kind, int g,
+                                                                        int first, int lane) {
+    if (Dp == 64)
+        aggregate_item<LT, 64, NT, ADAPT>(s, kind, g, first, lane);
+    else if (Dp == 128)
+        aggregate_item<LT, 128, NT, ADAPT>(s, kind, g, first, lane);
+    else
+        aggregate_item<LT, 256, NT, ADAPT>(s, kind, g, first, lane);
+}
+
+// ANY_ADAPT: some pair of the batch uses the adaptive P2 (a second
+// instantiation, so batches without one keep the smaller kernel).
+template <bool NT, bool ANY_ADAPT>
 __global__ __launch_bounds__(256) void aggregate_batch_kernel(const BatchItem* items, const WorkItem* work,
                                                               int nwork, unsigned* queue_counter, int P1, int P2) {
+    __shared__ uint16_t p2lut[ANY_ADAPT ? 256 : 1];
+    if constexpr (ANY_ADAPT) {  // P1, P2 belong to the batch: one table per block
+        fill_p2_lut(p2lut, P1, P2);
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63;
     for (;;) {
         unsigned idx = 0;
@@ -125,33 +168,52 @@ __global__ __launch_bounds__(256) void aggregate_batch_kernel(const BatchItem* i
         const uint32_t plane = (uint32_t)it.W * (uint32_t)it.H * (uint32_t)it.Dp;
         void* lplane = it.l16 ? (void*)(reinterpret_cast<uint16_t*>(it.lbuf) + (size_t)plane * w.plane)
                               : (void*)(reinterpret_cast<uint8_t*>(it.lbuf) + (size_t)plane * w.plane);
-        const SliceArgs s{it.cost, it.census_l, it.census_r, lplane, plane, it.W, it.H, it.D, P1, P2, it.cmax, w.rx,
-                          w.ry};
+        // a right-base direction reads the right-base costs; the adaptive P2
+        // follows its SGM's base image
+        SliceArgs s{w.rb ? it.cost_r : it.cost, it.census_l, it.census_r, lplane, plane, it.W, it.H, it.D, P1, P2,
+                    it.cmax, w.rx, w.ry};
+        s.img = w.rb ? it.right : it.left;
+        s.p2lut = ANY_ADAPT ? p2lut : nullptr;
         const int kind = w.ry == 0 ? kHoriz : (w.rx == 0 ? kVert : kDiag);
-        if (it.l16) {
-            if (it.Dp == 64) aggregate_item<uint16_t, 64, NT>(s, kind, it.gh, w.first, lane);
-            else if (it.Dp == 128) aggregate_item<uint16_t, 128, NT>(s, kind, it.gh, w.first, lane);
-            else aggregate_item<uint16_t, 256, NT>(s, kind, it.gh, w.first, lane);
+        const int g = kind == kHoriz ? it.gh : it.gv;
+        if (ANY_ADAPT && it.adaptive) {
+            if (it.l16)
+                aggregate_item_dp<uint16_t, NT, ANY_ADAPT>(s, it.Dp, kind, g, w.first, lane);
+            else
+                aggregate_item_dp<uint8_t, NT, ANY_ADAPT>(s, it.Dp, kind, g, w.first, lane);
         } else {
-            if (it.Dp == 64) aggregate_item<uint8_t, 64, NT>(s, kind, it.gh, w.first, lane);
-            else if (it.Dp == 128) aggregate_item<uint8_t, 128, NT>(s, kind, it.gh, w.first, lane);
-            else aggregate_item<uint8_t, 256, NT>(s, kind, it.gh, w.first, lane);
+            if (it.l16)
+                aggregate_item_dp<uint16_t, NT, false>(s, it.Dp, kind, g, w.first, lane);
+            else
+                aggregate_item_dp<uint8_t, NT, false>(s, it.Dp, kind, g, w.first, lane);
         }
     }
 }
 
+// Blocks 0 .. H - 1 of a pair are its rows; with the full left-right check
+// blocks H .. 2H - 1 are the rows of the right-base SGM, whose winners are
+// D_R.
 template <bool NT>
 __global__ __launch_bounds__(1024) void wta_batch_kernel(const BatchItem* items, int n) {
     extern __shared__ uint32_t wta_smem[];
     const int b = blockIdx.x;
     const BatchItem& it = items[find_item<&BatchItem::wta_blk0>(items, n, b)];
     const bool post = it.median || it.lrcheck;
-    WtaArgs a{it.lbuf, (size_t)it.W * it.H * it.Dp, post ? it.dl : it.out, it.lrcheck ? it.dr : nullptr,
+    const size_t plane = (size_t)it.W * it.H * it.Dp;
+    int y = b - it.wta_blk0;
+    WtaArgs a{it.lbuf, plane, post ? it.dl : it.out, (it.lrcheck && !it.lr_full) ? it.dr : nullptr,
               it.W, it.H, it.D, it.Dp, it.P, it.subpixel};
+    if (y >= it.H) {  // right-base rows: planes P .. 2P - 1, winners into D_R
+        y -= it.H;
+        a.lbuf = static_cast<const uint8_t*>(it.lbuf) + plane * it.P * (it.l16 ? 2 : 1);
+        a.dl = it.dr;
+        a.dr = nullptr;
+        a.subpixel = 0;
+    }
     if (it.l16)
-        wta_row<uint16_t, NT>(a, b - it.wta_blk0, wta_smem);
+        wta_row<uint16_t, NT>(a, y, wta_smem);
     else
-        wta_row<uint8_t, NT>(a, b - it.wta_blk0, wta_smem);
+        wta_row<uint8_t, NT>(a, y, wta_smem);
 }
 
 __global__ __launch_bounds__(256) void post_batch_kernel(const BatchItem* items, int n) {
@@ -192,9 +254,17 @@ bool batch_plan(const BatchParams& bp, const sgm_item* items, int n, BatchLayout
         p.median = (it.flags & SGM_MEDIAN3) != 0;
         p.lrcheck = (it.flags & SGM_LRCHECK) != 0;
         p.subpixel = (it.flags & SGM_SUBPIXEL) != 0;
+        p.lr_full = (it.flags & SGM_LR_FULL) != 0;
+        p.adaptive = (it.flags & SGM_ADAPTIVE_P2) != 0;
         p.lr_thr = item_lr_threshold(it.flags);
-        if (it.flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK | SGM_SUBPIXEL | SGM_ITEM_THRESHOLD_SET | 0x00FF0000u)) {
-            *why = "item flags may only hold SGM_MEDIAN3, SGM_LRCHECK, SGM_SUBPIXEL and SGM_ITEM_LR_THRESHOLD(t)";
+        if (it.flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK | SGM_SUBPIXEL | SGM_LR_FULL | SGM_ADAPTIVE_P2 |
+                                   SGM_ITEM_THRESHOLD_SET | 0x00FF0000u)) {
+            *why = "item flags may only hold SGM_MEDIAN3, SGM_LRCHECK, SGM_SUBPIXEL, SGM_LR_FULL, SGM_ADAPTIVE_P2 "
+                   "and SGM_ITEM_LR_THRESHOLD(t)";
+            return false;
+        }
+        if (p.lr_full && !p.lrcheck) {
+            *why = "SGM_LR_FULL needs SGM_LRCHECK";
             return false;
         }
         if (!plan_finish(p, why)) return false;
@@ -300,13 +370,16 @@ int batch_enqueue(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_b
     std::vector<BatchItem> desc(n);
     const bool generic = !(bp.cw == 9 && bp.ch == 7);
     size_t cost_smem = 0, wta_smem = 0, post_smem = 0;
+    bool any_adapt = false;
     for (int i = 0; i < n; ++i) {
         const Plan& p = plans[i];
         const Workspace ws = workspace_carve(p, ws_base[i]);
         int gh, gv;
         default_lanes(p, &gh, &gv);
-        gh = gh == 32 ? 32 : 16;  // the batch kernel has 32- and 16-lane horizontal groups
-        gv = 16;
+        // the batch kernel has 32- and 16-lane groups; the runner's tuning,
+        // when set, applies to every pair
+        gh = bp.lanes_h ? bp.lanes_h : (gh == 32 ? 32 : 16);
+        gv = bp.lanes_v ? bp.lanes_v : 16;
         BatchItem& d = desc[i];
         d.left = items[i].left;
         d.right = items[i].right;
@@ -314,6 +387,7 @@ int batch_enqueue(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_b
         d.census_l = ws.census_l;
         d.census_r = ws.census_r;
         d.cost = ws.cost;
+        d.cost_r = ws.cost_r;
         d.lbuf = ws.lbuf;
         d.dl = ws.dl;
         d.dr = ws.dr;
@@ -329,14 +403,19 @@ int batch_enqueue(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_b
         d.thr = p.lr_thr;
         d.csct = p.csct ? 1 : 0;
         d.gh = gh;
+        d.gv = gv;
         d.subpixel = p.subpixel ? 1 : 0;
+        d.lr_full = p.lr_full ? 1 : 0;
+        d.adaptive = p.adaptive ? 1 : 0;
+        any_adapt = any_adapt || p.adaptive;
+        const int nsgm = p.lr_full ? 2 : 1;
         d.census_blk0 = (int)census_blocks;
         census_blocks += generic ? (size_t)2 * ((p.W + 15) / 16) * ((p.H + 15) / 16)
                                  : (size_t)2 * ((p.W + kCenTX - 1) / kCenTX) * ((p.H + kCenTY - 1) / kCenTY);
         d.cost_blk0 = (int)cost_blocks;
-        cost_blocks += (size_t)((p.W + kCostTX - 1) / kCostTX) * p.H;
+        cost_blocks += (size_t)nsgm * ((p.W + kCostTX - 1) / kCostTX) * p.H;
         d.wta_blk0 = (int)wta_blocks;
-        wta_blocks += p.H;
+        wta_blocks += (size_t)nsgm * p.H;
         d.post_blk0 = (int)post_blocks;
         if (p.median || p.lrcheck) post_blocks += p.H;
         const int nright = kCostTX + p.D - 1;
@@ -345,12 +424,14 @@ int batch_enqueue(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_b
             wta_smem = std::max(wta_smem, 4 * (size_t)(p.W + kWtaGuard));
             post_smem = std::max(post_smem, 2 * (size_t)p.W);
         }
-        for (int r = 0; r < p.n_paths; ++r) {
-            const Dir dir = direction(p.n_paths, r);
-            const int S = 64 / (dir.ry == 0 ? gh : gv);
-            const int nsl = slice_count(p.W, p.H, dir), steps = slice_steps(p.W, p.H, dir);
-            for (int f = 0; f < nsl; f += S) work.push_back(WorkItem{i, r, dir.rx, dir.ry, f, steps});
-        }
+        for (int sg = 0; sg < nsgm; ++sg)
+            for (int r = 0; r < p.n_paths; ++r) {
+                const Dir dir = direction(p.n_paths, r);
+                const int S = 64 / (dir.ry == 0 ? gh : gv);
+                const int nsl = slice_count(p.W, p.H, dir), steps = slice_steps(p.W, p.H, dir);
+                for (int f = 0; f < nsl; f += S)
+                    work.push_back(WorkItem{i, sg * p.n_paths + r, dir.rx, dir.ry, f, steps, sg});
+            }
     }
     if (census_blocks > 0x7FFFFFFF || cost_blocks > 0x7FFFFFFF || work.size() > 0x7FFFFFFF)
         return berr(SGM_EINVAL, "batch too large");
@@ -376,11 +457,13 @@ int batch_enqueue(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_b
     // the planes and cost volumes of the whole batch against the memory-side
     // cache: the store policy of the single-pair path (Plan::nt_store)
     long long fbytes = 0;
-    for (const BatchItem& d : desc) fbytes += (long long)d.W * d.H * d.Dp * (d.P * (d.l16 ? 2 : 1) + 1);
+    for (const BatchItem& d : desc)
+        fbytes += (long long)d.W * d.H * d.Dp * (d.P * (d.l16 ? 2 : 1) + 1) * (d.lr_full ? 2 : 1);
     const bool nt = fbytes > kMallBytes;
-    hipLaunchKernelGGL(nt ? aggregate_batch_kernel<true> : aggregate_batch_kernel<false>,
-                       dim3((waves + 3) / 4), dim3(256), 0, s, st->d_items, st->d_work, nwork, st->counter, bp.P1,
-                       bp.P2);
+    auto agg = nt ? (any_adapt ? aggregate_batch_kernel<true, true> : aggregate_batch_kernel<true, false>)
+                  : (any_adapt ? aggregate_batch_kernel<false, true> : aggregate_batch_kernel<false, false>);
+    hipLaunchKernelGGL(agg, dim3((waves + 3) / 4), dim3(256), 0, s, st->d_items, st->d_work, nwork, st->counter,
+                       bp.P1, bp.P2);
     hipLaunchKernelGGL(nt ? wta_batch_kernel<true> : wta_batch_kernel<false>, dim3((unsigned)wta_blocks), dim3(1024),
                        wta_smem, s, st->d_items, n);
     if (post_blocks > 0) {
@@ -451,6 +534,15 @@ sgm_batch* sgm_batch_create(int P1, int P2, int census_w, int census_h) {
         return nullptr;
     }
     return b;
+}
+
+int sgm_batch_set_tuning(sgm_batch* b, int lanes_h, int lanes_v) {
+    if (!b) return api_err(SGM_EINVAL, "null batch");
+    auto ok = [](int g) { return g == 0 || g == 16 || g == 32; };
+    if (!ok(lanes_h) || !ok(lanes_v)) return api_err(SGM_EINVAL, "batch lanes must be 0, 16 or 32");
+    b->bp.lanes_h = lanes_h;
+    b->bp.lanes_v = lanes_v;
+    return SGM_OK;
 }
 
 size_t sgm_batch_footprint(sgm_batch* b, const sgm_item* items, int n) {

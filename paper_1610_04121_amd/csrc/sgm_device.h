@@ -1302,8 +1302,8 @@ __device__ inline void wta_row_impl(const WtaArgs& a, int y, uint32_t* keyR_smem
 
 // One row of the WTA; the plane count (2, 4 or 8) is a template constant of
 // the row's code, so the plane loads unroll.  NT: non-temporal plane loads,
-// for planes that exceed the memory-side cache (they were stored
-// non-temporally too).
+// for planes that exceed the memory-side cache and were stored
+// non-temporally.
 template <typename LT, bool NT = false>
 __device__ inline void wta_row(const WtaArgs& a, int y, uint32_t* keyR_smem) {
     if (a.nplanes == 2)

@@ -455,14 +455,20 @@ hipError_t launch_aggregate_wta(const Plan& p, const Workspace& ws, const uint8_
     return e;
 }
 
+// Whether the L_r planes were stored non-temporally, so the WTA streams them
+// the same way: the plain aggregation kernels follow p.nt_store; the
+// adaptive-P2 and census-computing ones always store them normally.
+static bool planes_nt(const Plan& p) { return p.nt_store && !p.adaptive && !fused_aggregation(p); }
+
 hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream) {
+    const bool nt = planes_nt(p);
     if (p.lr_full) {
         const size_t plane = (size_t)p.W * p.H * p.Dp;
         const void* rbuf = static_cast<const uint8_t*>(ws.lbuf) + plane * p.n_paths * (p.l16 ? 2 : 1);
         WtaArgs l{ws.lbuf, plane, ws.dl, nullptr, p.W, p.H, p.D, p.Dp, p.n_paths, p.subpixel ? 1 : 0};
         WtaArgs r{rbuf, plane, ws.dr, nullptr, p.W, p.H, p.D, p.Dp, p.n_paths};
-        auto k = p.l16 ? (p.nt_store ? wta_pair_kernel<uint16_t, true> : wta_pair_kernel<uint16_t, false>)
-                       : (p.nt_store ? wta_pair_kernel<uint8_t, true> : wta_pair_kernel<uint8_t, false>);
+        auto k = p.l16 ? (nt ? wta_pair_kernel<uint16_t, true> : wta_pair_kernel<uint16_t, false>)
+                       : (nt ? wta_pair_kernel<uint8_t, true> : wta_pair_kernel<uint8_t, false>);
         hipLaunchKernelGGL(k, dim3(2 * p.H), dim3(1024), 0, stream, l, r);
         return hipGetLastError();
     }
@@ -471,9 +477,9 @@ hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStre
               p.W, p.H, p.D, p.Dp, p.n_paths, p.subpixel ? 1 : 0};
     const size_t smem = p.lrcheck ? 4 * (size_t)(p.W + kWtaGuard) : 0;
     // the planes are read the way they were stored: non-temporally when they
-    // exceed the memory-side cache
-    auto k = p.l16 ? (p.nt_store ? wta_kernel<uint16_t, true> : wta_kernel<uint16_t, false>)
-                   : (p.nt_store ? wta_kernel<uint8_t, true> : wta_kernel<uint8_t, false>);
+    // exceed the memory-side cache and the aggregation stored them so
+    auto k = p.l16 ? (nt ? wta_kernel<uint16_t, true> : wta_kernel<uint16_t, false>)
+                   : (nt ? wta_kernel<uint8_t, true> : wta_kernel<uint8_t, false>);
     hipLaunchKernelGGL(k, dim3(p.H), dim3(1024), smem, stream, a);
     return hipGetLastError();
 }

@@ -26,7 +26,7 @@ EXPORTS = [
     "sgm_compute_batch",
     "sgm_server_create", "sgm_server_set_policy", "sgm_server_request_bytes", "sgm_server_submit",
     "sgm_server_poll", "sgm_server_wait", "sgm_server_cancel", "sgm_server_get_stats", "sgm_server_destroy",
-    "sgm_server_create_ex", "sgm_debug_phase_sums", "sgm_compute_noalloc",
+    "sgm_server_create_ex", "sgm_debug_phase_sums", "sgm_compute_noalloc", "sgm_batch_set_tuning",
 ]
 NOALLOC_MAX_BYTES = 256 << 20
 
@@ -110,6 +110,8 @@ def lib() -> ctypes.CDLL:
     L.sgm_batch_compute.restype = i
     L.sgm_batch_footprint.argtypes = [P, ctypes.POINTER(Item), i]
     L.sgm_batch_footprint.restype = ctypes.c_size_t
+    L.sgm_batch_set_tuning.argtypes = [P, i, i]
+    L.sgm_batch_set_tuning.restype = i
     L.sgm_batch_destroy.argtypes = [P]
     L.sgm_batch_destroy.restype = None
     L.sgm_compute_batch.argtypes = [ctypes.POINTER(Item), i, i, i, i, i, P]
@@ -384,6 +386,8 @@ class Batch:
         self._b = lib().sgm_batch_create(P1, P2, census_w, census_h)
         if not self._b:
             raise SGMError(SGM_EINVAL, last_error())
+        self.params = dict(P1=P1, P2=P2, census_w=census_w, census_h=census_h)
+        self.tuning = (0, 0)
 
     def compute(self, pairs, stream=None):
         arr = _items(pairs)
@@ -393,6 +397,18 @@ class Batch:
     def footprint(self, pairs) -> int:
         arr = _items(pairs)
         return lib().sgm_batch_footprint(self._b, arr, len(pairs))
+
+    def set_tuning(self, lanes_h=0, lanes_v=0):
+        """Lanes per horizontal / other aggregation slice for every pair (16
+        or 32; 0 = the per-pair default).  Never changes results."""
+        _check(lib().sgm_batch_set_tuning(self._b, lanes_h, lanes_v))
+        self.tuning = (lanes_h, lanes_v)
+
+    def autotune(self, pairs, **kw) -> dict:
+        """Times every batch kernel shape on these pairs and keeps the fastest
+        (see tune.autotune_batch)."""
+        from . import tune
+        return tune.autotune_batch(self, pairs, **kw)
 
     def close(self):
         if getattr(self, "_b", None):

@@ -260,8 +260,18 @@ SERVE_DISP = [128, 256]
 
 def serve_kinds(seed: int = 1610041214):
     """The (size, disparity range) combinations of the served request mix,
-    8 paths with median and LR check, one seeded pair each."""
+    8 paths with median and LR check, one seeded pair each: the road scene K
+    with its disparities scaled to the range (ground plane 0 .. 100 D / 128,
+    obstacles at [20, 120) D / 128)."""
     kinds = []
     for k, ((w, h), d) in enumerate((s, d) for s in SERVE_SIZES for d in SERVE_DISP):
-        kinds.append(dict(w=w, h=h, max_disp=d, n_paths=8, median=True, lr=True, scene="R", seed=seed * 100 + k))
+        kinds.append(dict(w=w, h=h, max_disp=d, n_paths=8, median=True, lr=True, scene="K", scale_to_d=True,
+                          seed=seed * 100 + k))
     return kinds
+
+
+def spec_pair(spec: dict) -> StereoPair:
+    """The pair a workload spec (w, h, max_disp, scene, seed and optional
+    scale_to_d) describes."""
+    return make_pair(spec["w"], spec["h"], spec["max_disp"], spec["scene"], seed=spec["seed"],
+                     scale_to_d=spec.get("scale_to_d", False))

@@ -131,3 +131,61 @@ def autotune(ctx, left=None, right=None, reps: int = 20, rounds: int = 2, use_ca
         except OSError:
             pass  # a read-only cache location only costs a re-tune later
     return dict(entry, cached=False)
+
+
+BATCH_CANDIDATES = [(0, 0), (16, 16), (32, 16), (16, 32), (32, 32)]
+
+
+def batch_key(batch, pairs) -> str:
+    """Cache key of a batch: its parameters and the multiset of its pairs'
+    shapes and options (the order of the pairs does not change the work)."""
+    import hashlib
+    p = batch.params
+    sig = sorted((tuple(q["left"].shape), q["max_disp"], q["n_paths"], bool(q.get("median")), bool(q.get("lrcheck")),
+                  bool(q.get("subpixel")), bool(q.get("lr_full")), bool(q.get("adaptive_p2"))) for q in pairs)
+    h = hashlib.sha256(repr(sig).encode()).hexdigest()[:16]
+    return f"batch:{len(pairs)}:{h}:P1={p['P1']}:P2={p['P2']}:census={p['census_w']}x{p['census_h']}"
+
+
+def autotune_batch(batch, pairs, reps: int = 3, rounds: int = 1, use_cache: bool = True) -> dict:
+    """Picks and applies the fastest batched-aggregation kernel shape (lanes
+    per horizontal / other slice for every pair, or the per-pair default) for
+    this set of pairs: times each shape on the pairs themselves (HIP events
+    on the current stream), checks that every shape gives the same
+    disparities for every pair, and caches the choice under batch_key()."""
+    import torch
+    key = batch_key(batch, pairs)
+    if use_cache:
+        hit = load_cache().get(key)
+        if hit and tuple(hit.get("choice", ())) in set(BATCH_CANDIDATES):
+            batch.set_tuning(*hit["choice"])
+            return dict(hit, cached=True)
+    stream = torch.cuda.current_stream()
+    ref, times = None, {}
+    for _ in range(rounds):
+        for cand in BATCH_CANDIDATES:
+            batch.set_tuning(*cand)
+            batch.compute(pairs, stream=stream)
+            stream.synchronize()
+            outs = [q["out"].clone() for q in pairs]
+            if ref is None:
+                ref = outs
+            elif not all(torch.equal(a, b) for a, b in zip(outs, ref)):
+                raise RuntimeError(f"batch kernel shape {cand} changed the disparities")
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                batch.compute(pairs, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            times[cand] = min(times.get(cand, float("inf")), e0.elapsed_time(e1) / reps)
+    best = min(times, key=times.get)
+    batch.set_tuning(*best)
+    entry = {"choice": list(best), "ms_per_batch": round(times[best], 4),
+             "candidates": {f"{gh},{gv}": round(t, 4) for (gh, gv), t in times.items()}}
+    if use_cache:
+        try:
+            save_entry(key, entry)
+        except OSError:
+            pass
+    return dict(entry, cached=False)

@@ -22,7 +22,7 @@ P1, P2 = 7, 86
 def _one(spec):
     import oracle
     from paper_1610_04121_amd import synth
-    pair = synth.make_pair(spec["w"], spec["h"], spec["max_disp"], spec["scene"], seed=spec["seed"])
+    pair = synth.spec_pair(spec)
     out = oracle.sgm(pair.left, pair.right, spec["max_disp"], P1, P2, spec["n_paths"],
                      median=spec.get("median", False), lr=spec.get("lr", False)).out
     return dict(spec, sha_left=pair.sha_left, sha_right=pair.sha_right,

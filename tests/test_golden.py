@@ -37,5 +37,10 @@ def test_digest_entries_match_the_workload_definitions():
         assert [(i["w"], i["h"], i["max_disp"], i["n_paths"], i["seed"]) for i in items] == \
             [(g["w"], g["h"], g["max_disp"], g["n_paths"], g["seed"]) for g in doc[key]]
     kinds = synth.serve_kinds()
-    assert [(k["w"], k["h"], k["max_disp"], k["seed"]) for k in kinds] == \
-        [(g["w"], g["h"], g["max_disp"], g["seed"]) for g in doc["serve_kinds"]]
+    assert [(k["w"], k["h"], k["max_disp"], k["seed"], k["scene"], k["scale_to_d"]) for k in kinds] == \
+        [(g["w"], g["h"], g["max_disp"], g["seed"], g["scene"], g["scale_to_d"]) for g in doc["serve_kinds"]]
+    # the smallest served kind reproduces on the CPU
+    k = min(kinds, key=lambda k: k["w"] * k["h"] * k["max_disp"])
+    g = next(g for g in doc["serve_kinds"] if (g["w"], g["h"], g["max_disp"]) == (k["w"], k["h"], k["max_disp"]))
+    pr = synth.spec_pair(k)
+    assert pr.sha_left == g["sha_left"]

@@ -199,3 +199,91 @@ def test_batch_item_thresholds(gpu):
                           median=p["median"], lr=p["lrcheck"], lr_thr=p["lr_threshold"]).out
         assert (p["out"].cpu().numpy() == want).all(), k
     b.close()
+
+
+def test_batch_full_check_and_adaptive_items(gpu):
+    """Items with the full left-right check (a second SGM with the right image
+    as base) and with the adaptive P2, beside plain ones, in one batch: each
+    against the oracle with the same options."""
+    import torch
+    specs = [(64, 48, 40, 4, True, True), (97, 31, 64, 8, False, True), (40, 70, 130, 2, True, True),
+             (33, 33, 200, 8, True, True), (50, 20, 16, 4, False, False), (120, 20, 70, 8, True, True)]
+    opts = [(True, False, False), (False, True, False), (True, True, True), (True, False, True),
+            (False, True, False), (False, False, False)]  # (lr_full, adaptive, subpixel)
+    pairs = _pairs(specs, gpu, 1700)
+    for p, (lf, ad, sub) in zip(pairs, opts):
+        p["lr_full"], p["adaptive_p2"], p["subpixel"] = lf and p["lrcheck"], ad, sub
+    _say("batch with full-check and adaptive-P2 items")
+    b = Batch(7, 86)
+    b.compute(pairs)
+    torch.cuda.synchronize()
+    for k, p in enumerate(pairs):
+        want = oracle.sgm(p["np_left"], p["np_right"], p["max_disp"], 7, 86, p["n_paths"], median=p["median"],
+                          lr=p["lrcheck"], lr_full=p["lr_full"], adaptive=p["adaptive_p2"], subpixel=p["subpixel"]).out
+        got = p["out"].cpu().numpy()
+        assert (got == want).all(), (k, specs[k], opts[k], int((got != want).sum()))
+    b.close()
+
+
+def test_batch_adaptive_items_u16_planes(gpu):
+    """Adaptive P2 with P1 above P2 (16-bit planes) in a batch."""
+    import torch
+    specs = [(45, 30, 40, 4, True, True), (30, 45, 70, 8, False, True)]
+    pairs = _pairs(specs, gpu, 1900)
+    for p in pairs:
+        p["adaptive_p2"] = True
+    _say("batch with adaptive P2 and P1 = 200 > P2 = 100")
+    b = Batch(200, 100)
+    b.compute(pairs)
+    torch.cuda.synchronize()
+    for p in pairs:
+        want = oracle.sgm(p["np_left"], p["np_right"], p["max_disp"], 200, 100, p["n_paths"], median=p["median"],
+                          lr=p["lrcheck"], adaptive=True).out
+        assert (p["out"].cpu().numpy() == want).all()
+    b.close()
+
+
+@pytest.mark.parametrize("lanes", [(16, 16), (32, 16), (16, 32), (32, 32)])
+def test_batch_kernel_shapes_match_oracle(gpu, lanes):
+    """Every lane shape the batch tuner can pick, on pairs of every padded
+    disparity range, path count and plane type: bit-exact with the oracle."""
+    import torch
+    specs = [(64, 48, 40, 4, True, True), (97, 31, 64, 8, False, True), (40, 70, 130, 2, True, False),
+             (33, 33, 200, 8, False, True), (120, 20, 16, 8, True, True), (50, 45, 100, 4, False, False)]
+    pairs = _pairs(specs, gpu, 2300)
+    pairs[3]["adaptive_p2"] = True
+    pairs[1]["lr_full"] = True
+    _say(f"batch with lanes {lanes}")
+    b = Batch(7, 86)
+    b.set_tuning(*lanes)
+    b.compute(pairs)
+    torch.cuda.synchronize()
+    for k, p in enumerate(pairs):
+        want = oracle.sgm(p["np_left"], p["np_right"], p["max_disp"], 7, 86, p["n_paths"], median=p["median"],
+                          lr=p["lrcheck"], adaptive=p.get("adaptive_p2", False), lr_full=p.get("lr_full", False)).out
+        assert (p["out"].cpu().numpy() == want).all(), (k, lanes)
+    b.close()
+
+
+def test_batch_autotune_picks_a_shape_and_caches(gpu, tmp_path, monkeypatch):
+    import torch
+    from paper_1610_04121_amd import tune
+    monkeypatch.setenv("SGM_TUNE_CACHE", str(tmp_path / "tune.json"))
+    specs = [(160, 90, 64, 4, True, True), (90, 160, 128, 8, False, True), (200, 60, 100, 2, True, False)]
+    pairs = _pairs(specs, gpu, 2500)
+    b = Batch(7, 86)
+    _say("batch autotune")
+    res = b.autotune(pairs)
+    assert not res["cached"] and tuple(res["choice"]) in set(tune.BATCH_CANDIDATES)
+    assert len(res["candidates"]) == len(tune.BATCH_CANDIDATES)
+    b.compute(pairs)
+    torch.cuda.synchronize()
+    for p in pairs:
+        want = oracle.sgm(p["np_left"], p["np_right"], p["max_disp"], 7, 86, p["n_paths"], median=p["median"],
+                          lr=p["lrcheck"]).out
+        assert (p["out"].cpu().numpy() == want).all()
+    b.close()
+    b2 = Batch(7, 86)
+    res2 = b2.autotune(list(reversed(pairs)))  # the same multiset of pairs
+    assert res2["cached"] and res2["choice"] == res["choice"] and b2.tuning == tuple(res["choice"])
+    b2.close()

@@ -34,7 +34,8 @@ def _alone(req):
     import torch
     h, w = req["left"].shape
     c = SGM(w, h, req["max_disp"], 7, 86, req["n_paths"], median=req["median"], lrcheck=req["lrcheck"],
-            subpixel=req.get("subpixel", False))
+            subpixel=req.get("subpixel", False), lr_full=req.get("lr_full", False),
+            adaptive_p2=req.get("adaptive_p2", False))
     out = c.compute(req["left"], req["right"])
     torch.cuda.synchronize()
     res = out.cpu().numpy()
@@ -199,7 +200,7 @@ def test_served_mix_full_size_against_oracle_digests(gpu, grouped):
     assert len(golden) == len(kinds)
     reqs = []
     for k, g in zip(kinds, golden):
-        pr = synth.make_pair(k["w"], k["h"], k["max_disp"], k["scene"], seed=k["seed"])
+        pr = synth.spec_pair(k)
         assert pr.sha_left == g["sha_left"] and pr.sha_right == g["sha_right"]
         reqs.append(dict(left=torch.from_numpy(pr.left).to(gpu), right=torch.from_numpy(pr.right).to(gpu),
                          max_disp=k["max_disp"], n_paths=8, median=True, lrcheck=True, lr_threshold=1,
@@ -217,3 +218,29 @@ def test_served_mix_full_size_against_oracle_digests(gpu, grouped):
     for r, g in zip(reqs, golden):
         got = r["out"].cpu().numpy()
         assert hashlib.sha256(got.tobytes()).hexdigest() == g["out_sha256"], (g["w"], g["h"], g["max_disp"])
+
+
+def test_served_full_check_and_adaptive_requests(gpu):
+    """Requests with the full left-right check and with the adaptive P2, in
+    groups and alone: each against the oracle with the same options."""
+    import torch
+    reqs = []
+    for k, (w, h, d, p) in enumerate([(96, 64, 48, 8), (160, 90, 100, 4), (64, 48, 32, 2), (97, 31, 64, 8),
+                                      (120, 40, 130, 4), (33, 65, 20, 8)]):
+        r = _req(gpu, w, h, d, p, True, True, 2100 + k)
+        r["lr_full"] = k % 2 == 0
+        r["adaptive_p2"] = k % 3 != 2
+        reqs.append(r)
+    _say("served full-check and adaptive-P2 requests")
+    srv = Server(4 << 30, slots=2, max_group=4, max_group_cells=1 << 40, overlap_queue=1)
+    ts = [srv.submit(r) for r in reqs]
+    for t in ts:
+        assert srv.wait(t, 60000)[0] == REQ_DONE
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(reqs)
+    torch.cuda.synchronize()
+    for k, r in enumerate(reqs):
+        want = oracle.sgm(r["np_left"], r["np_right"], r["max_disp"], 7, 86, r["n_paths"], median=True, lr=True,
+                          lr_full=r["lr_full"], adaptive=r["adaptive_p2"]).out
+        assert (r["out"].cpu().numpy() == want).all(), k
