@@ -569,7 +569,7 @@ def main():
     ap.add_argument("--oracle-timing", action="store_true",
                     help="also time the CPU oracle on every workload (single-pair latencies, the 64-pair "
                          "batch over all cores, the served mix); takes a few minutes")
-    ap.add_argument("--tuning", default="", help="fixed kernel shape 'lanes_h,lanes_v,fused,census_cost[,final_pass]' "
+    ap.add_argument("--tuning", default="", help="fixed kernel shape 'lanes_h,lanes_v,fused,census_cost[,final_pass[,post_in_wta]]' "
                                                    "instead of autotuning (for profiler runs)")
     ap.add_argument("--no-extras", action="store_true", help="skip serialized/latency/copy measurements")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batched measurement")
@@ -628,9 +628,9 @@ def main():
 
     # kernel shape: measured on this device for this workload (results do not depend on it)
     if args.tuning:
-        vals = [int(v) for v in args.tuning.split(",")] + [0]
-        gh, gv, f, cc, fp = vals[:5]
-        choice = (gh, gv, bool(f), bool(cc), bool(fp))
+        vals = [int(v) for v in args.tuning.split(",")] + [0, 0]
+        gh, gv, f, cc, fp, pw = vals[:6]
+        choice = (gh, gv, bool(f), bool(cc), bool(fp), bool(pw))
         tuned = {"candidates": None}
     else:
         probe = make_ctx()

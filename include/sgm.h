@@ -127,9 +127,13 @@ int sgm_compute(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right, uint16_
  *   left-to-right with 2 paths) runs fused with the sum over directions and
  *   the winner-take-all (Sec. 3.3), so its L_r is never stored; used where
  *   the planes are u8, the cost volume is stored and neither SGM_LR_FULL
- *   nor SGM_ADAPTIVE_P2 is set, otherwise ignored.  Default 0.
+ *   nor SGM_ADAPTIVE_P2 is set, otherwise ignored.  Bit
+ *   SGM_TUNE_POST_IN_WTA: the median (Sec. 2) and left-right check (Sec. 5) run
+ *   inside the winner-take-all launch (the block that completes the raw rows
+ *   around a row filters it) instead of a launch of their own; ignored with
+ *   the final pass or without a post stage.  Default 0.
  * sgm_get_tuning reports the shape in effect. */
-enum { SGM_TUNE_FUSED_AGG = 1, SGM_TUNE_FUSED_CENSUS_COST = 2, SGM_TUNE_FINAL_PASS = 4 };
+enum { SGM_TUNE_FUSED_AGG = 1, SGM_TUNE_FUSED_CENSUS_COST = 2, SGM_TUNE_FINAL_PASS = 4, SGM_TUNE_POST_IN_WTA = 8 };
 int sgm_set_tuning(sgm_ctx *ctx, int lanes_h, int lanes_v, int fused);
 int sgm_get_tuning(sgm_ctx *ctx, int *lanes_h, int *lanes_v, int *fused);
 

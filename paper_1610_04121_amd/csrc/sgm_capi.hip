@@ -163,6 +163,7 @@ int sgm_set_options(sgm_ctx* c, unsigned flags, int lr_threshold) {
     p.fused = c->plan.fused;
     p.cc_fused = c->plan.cc_fused;
     p.final_pass = c->plan.final_pass;
+    p.post_in_wta = c->plan.post_in_wta;
     // the full left-right check needs a second cost volume and L_r set
     sgm::Plan big = p;
     big.l16 = true;
@@ -203,11 +204,12 @@ int sgm_set_tuning(sgm_ctx* c, int lanes_h, int lanes_v, int fused) {
     if ((lanes_h == 0) != (lanes_v == 0)) return set_err(SGM_EINVAL, "set both lane counts or neither");
     c->plan.lanes_h = lanes_h;
     c->plan.lanes_v = lanes_v;
-    if (fused & ~(SGM_TUNE_FUSED_AGG | SGM_TUNE_FUSED_CENSUS_COST | SGM_TUNE_FINAL_PASS))
+    if (fused & ~(SGM_TUNE_FUSED_AGG | SGM_TUNE_FUSED_CENSUS_COST | SGM_TUNE_FINAL_PASS | SGM_TUNE_POST_IN_WTA))
         return set_err(SGM_EINVAL, "unknown tuning bits");
     c->plan.fused = (fused & SGM_TUNE_FUSED_AGG) != 0;
     c->plan.cc_fused = (fused & SGM_TUNE_FUSED_CENSUS_COST) != 0;
     c->plan.final_pass = (fused & SGM_TUNE_FINAL_PASS) != 0;
+    c->plan.post_in_wta = (fused & SGM_TUNE_POST_IN_WTA) != 0;
     drop_graphs(c);
     return SGM_OK;
 }
@@ -220,7 +222,7 @@ int sgm_get_tuning(sgm_ctx* c, int* lanes_h, int* lanes_v, int* fused) {
     if (lanes_v) *lanes_v = gv;
     if (fused)
         *fused = (c->plan.fused ? SGM_TUNE_FUSED_AGG : 0) | (c->plan.cc_fused ? SGM_TUNE_FUSED_CENSUS_COST : 0) |
-                 (c->plan.final_pass ? SGM_TUNE_FINAL_PASS : 0);
+                 (c->plan.final_pass ? SGM_TUNE_FINAL_PASS : 0) | (c->plan.post_in_wta ? SGM_TUNE_POST_IN_WTA : 0);
     return SGM_OK;
 }
 

@@ -48,7 +48,16 @@ struct CensusArgs {
     const uint8_t* img[2];
     uint64_t* out[2];
     int W, H, csct;
+    // block (0, 0, 0) clears zero[0 .. nzero) for the frame's later launches
+    // (the row counters of the post stage inside the WTA launch)
+    int* zero = nullptr;
+    int nzero = 0;
 };
+
+__device__ inline void census_clear(const CensusArgs& a, int bx, int by, int z) {
+    if (a.zero && (bx | by | z) == 0)
+        for (int i = threadIdx.x; i < a.nzero; i += blockDim.x) a.zero[i] = 0;
+}
 
 // Byte-parallel comparison: bit 7 of byte b of the result is [u_b >= v_b]
 // for unsigned bytes (the other bits are don't-care).  vlo = v & 0x7F7F7F7F.
@@ -148,6 +157,7 @@ __device__ inline void census_words4(const uint8_t* tile, int TW, int r0, int c0
 }
 
 __device__ inline void census97_block(const CensusArgs& a, int bx, int by, int z) {
+    census_clear(a, bx, by, z);
     constexpr int RY = 3;
     constexpr int TW = kCenTX + 8, TH = kCenTY + 2 * RY;
     __shared__ __align__(16) uint8_t tile[TH * TW];
@@ -191,6 +201,7 @@ __device__ inline void census97_block(const CensusArgs& a, int bx, int by, int z
 
 // Any other window: one thread per pixel, straight from global memory.
 __device__ inline void census_generic_block(const CensusArgs& a, int rx, int ry, int bx, int by, int z) {
+    census_clear(a, bx, by, z);
     const int x = bx * 16 + (threadIdx.x & 15);
     const int y = by * 16 + (threadIdx.x >> 4);
 
@@ -376,6 +387,8 @@ struct CensusCostArgs {
     const uint8_t* right;
     uint8_t* cost;
     int W, H, D, Dp, cmax, csct;
+    int* zero = nullptr;  // as CensusArgs::zero
+    int nzero = 0;
 };
 
 // Byte sizes of the LDS regions of census_cost_block.
@@ -401,6 +414,8 @@ __host__ __device__ inline CcLayout cc_layout(int D, int Dp) {
 }
 
 __device__ inline void census_cost_block(const CensusCostArgs& a, int bx, int y, uint8_t* smem) {
+    if (a.zero && (bx | y) == 0)
+        for (int i = threadIdx.x; i < a.nzero; i += blockDim.x) a.zero[i] = 0;
     constexpr int RY = 3;
     const int D = a.D, Dp = a.Dp;
     const CcLayout L = cc_layout(D, Dp);
@@ -1116,6 +1131,16 @@ __device__ inline void aggregate_wave(const SliceArgs& a, int first_slice, int l
 // words, and targets x - d < 0 land in a guard region in front of the row.
 // The column's winner is argmin_d S(x + d, d), ties to the smallest d.
 // ---------------------------------------------------------------------------
+// The post stage (3x3 median of both maps, then the left-right check) of
+// one pair, read by post_row.
+struct PostArgs {
+    const uint16_t* dl;
+    const uint16_t* dr;
+    uint16_t* out;
+    int W, H, median, lrcheck, thr;
+    int subpixel = 0;  // dl in 1/16 pixel: the check uses its rounding
+};
+
 struct WtaArgs {
     const void* lbuf;
     size_t plane;
@@ -1123,6 +1148,13 @@ struct WtaArgs {
     uint16_t* dr;  // right disparity or nullptr
     int W, H, D, Dp, nplanes;
     int subpixel = 0;  // dl in 1/16 pixel: parabola vertex through S(d-1), S(d), S(d+1)
+    // The post stage run inside the WTA launch (rowcnt != nullptr): per-row
+    // counters (zeroed by the census launch of the same frame), `contrib`
+    // blocks writing raw rows per image row (2 when one launch makes D_L and
+    // D_R with separate blocks), and the post stage's arguments.
+    int* rowcnt = nullptr;
+    int contrib = 1;
+    PostArgs post{};
 };
 
 // floor(num / den) for den > 0
@@ -1275,6 +1307,8 @@ __device__ inline void wta_cells(const WtaArgs& a, int y, int x, int g, int G, c
     if (g == 0 && valid) a.dl[(size_t)y * a.W + x] = (uint16_t)outv;
 }
 
+__device__ inline void wta_fold_post(const WtaArgs& a, int y, uint16_t* rview);
+
 template <typename LT, int NPL, bool NT>
 __device__ inline void wta_row_impl(const WtaArgs& a, int y, uint32_t* keyR_smem) {
     uint32_t* keyR = keyR_smem + kWtaGuard;  // keyR[t], t in [-kWtaGuard, W)
@@ -1298,6 +1332,7 @@ __device__ inline void wta_row_impl(const WtaArgs& a, int y, uint32_t* keyR_smem
         for (int i = threadIdx.x; i < a.W; i += blockDim.x)
             a.dr[(size_t)y * a.W + i] = (uint16_t)(keyR[i] & 0xFF);
     }
+    if (a.rowcnt) wta_fold_post(a, y, reinterpret_cast<uint16_t*>(keyR_smem));
 }
 
 // One row of the WTA; the plane count (2, 4 or 8) is a template constant of
@@ -1551,14 +1586,6 @@ __device__ inline uint32_t median9(const uint16_t* img, int W, int H, int x, int
     return med3(lo, mid, hi);
 }
 
-struct PostArgs {
-    const uint16_t* dl;
-    const uint16_t* dr;
-    uint16_t* out;
-    int W, H, median, lrcheck, thr;
-    int subpixel = 0;  // dl in 1/16 pixel: the check uses its rounding
-};
-
 // One row of the post stage.  Each thread takes 4 columns per pass so that
 // the neighbour loads of a pass are in flight together (a 640-wide row is
 // one pass of a 256-thread block); the median and check switches are
@@ -1631,6 +1658,46 @@ __device__ inline void post_row(const PostArgs& a, int y, uint16_t* rview) {
             post_row_impl<false, true>(a, y, rview);
         else
             post_row_impl<false, false>(a, y, rview);
+    }
+}
+
+// The post stage inside the WTA launch, without any wait: row r's median
+// and check need the raw maps of rows r - 1 .. r + 1, so a block that has
+// written its raw row y counts itself into rows y - 1 .. y + 1, and the
+// block whose count completes a row (the last of the blocks that write its
+// neighbourhood, in whatever order they ran) runs that row's post stage and
+// clears its counter.  Every wave waits for its raw-map stores to complete
+// (a block barrier alone does not wait for global stores), then one thread
+// releases them with a device-scope fence (a write-back of this XCD's L2,
+// so one per block, not one per wave) before the counting, and acquires the
+// other blocks' rows after it (they may have been written through another
+// L2).
+__device__ inline void wta_fold_post(const WtaArgs& a, int y, uint16_t* rview) {
+    __shared__ int todo[3];
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): expcnt and lgkmcnt left at their maxima
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // the write-back has completed
+        for (int k = 0; k < 3; ++k) {
+            const int r = y - 1 + k;
+            todo[k] = 0;
+            if (r < 0 || r >= a.H) continue;
+            const int need = a.contrib * ((r > 0) + 1 + (r < a.H - 1));
+            if (atomicAdd(&a.rowcnt[r], 1) + 1 == need) {
+                atomicExch(&a.rowcnt[r], 0);
+                todo[k] = 1;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // the invalidation has completed before the barrier
+    }
+    __syncthreads();
+    for (int k = 0; k < 3; ++k) {
+        if (todo[k]) {
+            post_row(a.post, y - 1 + k, rview);
+            __syncthreads();  // rview is reused by the next row
+        }
     }
 }
 

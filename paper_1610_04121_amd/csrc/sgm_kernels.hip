@@ -209,7 +209,7 @@ size_t workspace_bytes(const Plan& p) {
     const size_t cells = npx * p.Dp;
     const int nsgm = p.lr_full ? 2 : 1;
     return align256(cells) + align256(cells * nsgm * p.n_paths * (p.l16 ? 2 : 1)) + 2 * align256(npx * 2) +
-           2 * align256(8 * (npx + kCensusGuard)) + (p.lr_full ? align256(cells) : 0);
+           2 * align256(8 * (npx + kCensusGuard)) + align256(4 * (size_t)p.H) + (p.lr_full ? align256(cells) : 0);
 }
 
 Workspace workspace_carve(const Plan& p, void* base) {
@@ -229,13 +229,15 @@ Workspace workspace_carve(const Plan& p, void* base) {
     b += align256(8 * (npx + kCensusGuard));
     ws.census_r = reinterpret_cast<uint64_t*>(b) + kCensusGuard;
     b += align256(8 * (npx + kCensusGuard));
+    ws.rowcnt = reinterpret_cast<int*>(b);
+    b += align256(4 * (size_t)p.H);
     if (p.lr_full) ws.cost_r = b;
     return ws;
 }
 
 static hipError_t launch_census_pair(const Plan& p, const uint8_t* left, const uint8_t* right, uint64_t* cl,
-                                     uint64_t* cr, int nimg, hipStream_t stream) {
-    CensusArgs a{{left, right}, {cl, cr}, p.W, p.H, p.csct ? 1 : 0};
+                                     uint64_t* cr, int nimg, hipStream_t stream, int* zero = nullptr) {
+    CensusArgs a{{left, right}, {cl, cr}, p.W, p.H, p.csct ? 1 : 0, zero, zero ? p.H : 0};
     if (p.cw == 9 && p.ch == 7) {
         dim3 grid((p.W + kCenTX - 1) / kCenTX, (p.H + kCenTY - 1) / kCenTY, nimg);
         hipLaunchKernelGGL(census97_kernel, grid, dim3(256), 0, stream, a);
@@ -248,7 +250,7 @@ static hipError_t launch_census_pair(const Plan& p, const uint8_t* left, const u
 
 hipError_t launch_census(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right,
                          hipStream_t stream) {
-    return launch_census_pair(p, left, right, ws.census_l, ws.census_r, 2, stream);
+    return launch_census_pair(p, left, right, ws.census_l, ws.census_r, 2, stream, ws.rowcnt);
 }
 
 bool census_cost_fusable(const Plan& p) { return p.cc_fused && p.cw == 9 && p.ch == 7; }
@@ -265,7 +267,7 @@ hipError_t launch_matching_cost(const Plan& p, const Workspace& ws, const uint8_
     hipError_t e = hipSuccess;
     if (need_cost && fusable) {
         const CcLayout L = cc_layout(p.D, p.Dp);
-        CensusCostArgs a{left, right, ws.cost, p.W, p.H, p.D, p.Dp, p.cmax, p.csct ? 1 : 0};
+        CensusCostArgs a{left, right, ws.cost, p.W, p.H, p.D, p.Dp, p.cmax, p.csct ? 1 : 0, ws.rowcnt, p.H};
         hipLaunchKernelGGL(census_cost_kernel, dim3((p.W + kCcTX - 1) / kCcTX, p.H), dim3(256), L.bytes, stream, a);
         e = hipGetLastError();
     }
@@ -446,12 +448,14 @@ hipError_t launch_final_pass(const Plan& p, const Workspace& ws, uint16_t* out, 
     return launch_final_d<256>(p, f, stream);
 }
 
+bool post_folded(const Plan& p) { return p.post_in_wta && (p.median || p.lrcheck) && !final_pass_active(p); }
+
 hipError_t launch_aggregate_wta(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right,
-                                uint16_t* out, hipStream_t stream, hipEvent_t mid_event) {
+                                uint16_t* out, hipStream_t stream, hipEvent_t mid_event, bool post_in_wta) {
     const bool fp = final_pass_active(p);
     hipError_t e = launch_aggregate(p, ws, stream, left, right, fp);
     if (e == hipSuccess && mid_event) e = hipEventRecord(mid_event, stream);
-    if (e == hipSuccess) e = fp ? launch_final_pass(p, ws, out, stream) : launch_wta(p, ws, out, stream);
+    if (e == hipSuccess) e = fp ? launch_final_pass(p, ws, out, stream) : launch_wta(p, ws, out, stream, post_in_wta);
     return e;
 }
 
@@ -460,21 +464,41 @@ hipError_t launch_aggregate_wta(const Plan& p, const Workspace& ws, const uint8_
 // adaptive-P2 and census-computing ones always store them normally.
 static bool planes_nt(const Plan& p) { return p.nt_store && !p.adaptive && !fused_aggregation(p); }
 
-hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream) {
+static PostArgs post_args(const Plan& p, const Workspace& ws, uint16_t* out) {
+    return PostArgs{ws.dl, ws.dr, out, p.W, p.H, p.median ? 1 : 0, p.lrcheck ? 1 : 0, p.lr_thr, p.subpixel ? 1 : 0};
+}
+
+hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream, bool post_in_wta) {
     const bool nt = planes_nt(p);
+    const bool post = p.median || p.lrcheck;
+    const bool fold = post_in_wta && post;
+    if (fold && !ws.rowcnt) return hipErrorInvalidValue;
     if (p.lr_full) {
         const size_t plane = (size_t)p.W * p.H * p.Dp;
         const void* rbuf = static_cast<const uint8_t*>(ws.lbuf) + plane * p.n_paths * (p.l16 ? 2 : 1);
         WtaArgs l{ws.lbuf, plane, ws.dl, nullptr, p.W, p.H, p.D, p.Dp, p.n_paths, p.subpixel ? 1 : 0};
         WtaArgs r{rbuf, plane, ws.dr, nullptr, p.W, p.H, p.D, p.Dp, p.n_paths};
+        size_t smem = 0;
+        if (fold) {  // D_L and D_R rows come from separate blocks
+            for (WtaArgs* w : {&l, &r}) {
+                w->rowcnt = ws.rowcnt;
+                w->contrib = 2;
+                w->post = post_args(p, ws, out);
+            }
+            smem = 2 * (size_t)p.W;  // the post stage's D_R medians
+        }
         auto k = p.l16 ? (nt ? wta_pair_kernel<uint16_t, true> : wta_pair_kernel<uint16_t, false>)
                        : (nt ? wta_pair_kernel<uint8_t, true> : wta_pair_kernel<uint8_t, false>);
-        hipLaunchKernelGGL(k, dim3(2 * p.H), dim3(1024), 0, stream, l, r);
+        hipLaunchKernelGGL(k, dim3(2 * p.H), dim3(1024), smem, stream, l, r);
         return hipGetLastError();
     }
-    const bool post = p.median || p.lrcheck;
     WtaArgs a{ws.lbuf, (size_t)p.W * p.H * p.Dp, post ? ws.dl : out, p.lrcheck ? ws.dr : nullptr,
               p.W, p.H, p.D, p.Dp, p.n_paths, p.subpixel ? 1 : 0};
+    if (fold) {
+        a.rowcnt = ws.rowcnt;
+        a.post = post_args(p, ws, out);
+    }
+    // the right-view keys; with the post stage inside, its D_R medians reuse them
     const size_t smem = p.lrcheck ? 4 * (size_t)(p.W + kWtaGuard) : 0;
     // the planes are read the way they were stored: non-temporally when they
     // exceed the memory-side cache and the aggregation stored them so
@@ -486,7 +510,7 @@ hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStre
 
 hipError_t launch_post(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream) {
     if (!p.median && !p.lrcheck) return hipSuccess;  // the WTA wrote `out`
-    PostArgs a{ws.dl, ws.dr, out, p.W, p.H, p.median ? 1 : 0, p.lrcheck ? 1 : 0, p.lr_thr, p.subpixel ? 1 : 0};
+    const PostArgs a = post_args(p, ws, out);
     hipLaunchKernelGGL(post_kernel, dim3(p.H), dim3(256), p.lrcheck ? 2 * (size_t)p.W : 0, stream, a);
     return hipGetLastError();
 }
@@ -500,9 +524,11 @@ hipError_t launch_pipeline(const Plan& p, const Workspace& ws, const uint8_t* le
     mark(0);
     if (e == hipSuccess) e = launch_matching_cost(p, ws, left, right, !fused_aggregation(p), stream);
     mark(1);
-    if (e == hipSuccess) e = launch_aggregate_wta(p, ws, left, right, out, stream, events ? events[2] : nullptr);
+    const bool fold = post_folded(p);
+    if (e == hipSuccess)
+        e = launch_aggregate_wta(p, ws, left, right, out, stream, events ? events[2] : nullptr, fold);
     mark(3);
-    if (e == hipSuccess) e = launch_post(p, ws, out, stream);
+    if (e == hipSuccess && !fold) e = launch_post(p, ws, out, stream);
     mark(4);
     return e;
 }

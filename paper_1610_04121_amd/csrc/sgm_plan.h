@@ -32,6 +32,8 @@ struct Plan {
     bool cc_fused = false;     // cost volume from one census + cost launch (9x7)
     bool final_pass = false;   // the last direction fused with the sum and the
                                // winner-take-all (where final_pass_active)
+    bool post_in_wta = false;  // the post stage inside the WTA launch (not after
+                               // the final pass)
     int lanes_h = 0, lanes_v = 0;  // lanes per aggregation slice, horizontal / other
                                    // directions (16, 32, 64; 0 = default)
 };
@@ -46,6 +48,8 @@ struct Workspace {
     uint16_t* dr = nullptr;    // raw right disparity u16 [H][W]
     uint64_t* census_l = nullptr;  // census words of the base image u64 [H][W]
     uint64_t* census_r = nullptr;  // census words of the match image u64 [H][W]
+    int* rowcnt = nullptr;     // i32 [H]: row counters of the post stage inside
+                               // the WTA launch, cleared by the census launch
 };
 
 // Fills the derived fields of a plan; returns false if invalid (message set).
@@ -89,13 +93,20 @@ hipError_t launch_final_pass(const Plan& p, const Workspace& ws, uint16_t* out, 
                              uint16_t* s_out = nullptr);
 // Aggregation and winner-take-all the way the plan runs them (the final pass
 // or aggregation + WTA): raw maps, or `out` when no post stage follows.
+// post_in_wta: the post stage runs inside the WTA launch (where
+// post_folded(p)) and `out` gets the final map.
 hipError_t launch_aggregate_wta(const Plan& p, const Workspace& ws, const uint8_t* left, const uint8_t* right,
-                                uint16_t* out, hipStream_t stream, hipEvent_t mid_event = nullptr);
+                                uint16_t* out, hipStream_t stream, hipEvent_t mid_event = nullptr,
+                                bool post_in_wta = false);
+// Whether launch_pipeline runs the post stage inside the WTA launch: the
+// tuning asks for it, a post stage exists and the final pass is not used.
+bool post_folded(const Plan& p);
 // whether the aggregation computes costs from census words (the tuning asks
 // for it and no option needs the cost volume)
 bool fused_aggregation(const Plan& p);
 void default_lanes(const Plan& p, int* gh, int* gv);
-hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream);
+hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream,
+                      bool post_in_wta = false);
 hipError_t launch_post(const Plan& p, const Workspace& ws, uint16_t* out, hipStream_t stream);
 // The direction the final pass fuses with the sum and the winner-take-all
 // (Sec. 3.3): right-to-left (direction index 1), or left-to-right (index 0)

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_PKG, "libsgm.so")
 
 SGM_OK, SGM_EINVAL, SGM_ENOMEM, SGM_EHIP, SGM_EBUSY, SGM_ECANCELED = 0, -1, -2, -3, -4, -5
 MEDIAN3, LRCHECK, CENSUS_CSCT, GRAPH, LR_FULL, SUBPIXEL, ADAPTIVE_P2 = 1, 2, 4, 8, 16, 32, 64
-TUNE_FUSED_AGG, TUNE_FUSED_CENSUS_COST, TUNE_FINAL_PASS = 1, 2, 4
+TUNE_FUSED_AGG, TUNE_FUSED_CENSUS_COST, TUNE_FINAL_PASS, TUNE_POST_IN_WTA = 1, 2, 4, 8
 INVALID = 0xFFFF
 
 EXPORTS = [
@@ -257,23 +257,26 @@ class SGM:
         from . import tune
         return tune.autotune(self, left, right, **kw)
 
-    def set_tuning(self, lanes_h=0, lanes_v=0, fused=False, census_cost=False, final_pass=False):
+    def set_tuning(self, lanes_h=0, lanes_v=0, fused=False, census_cost=False, final_pass=False,
+                   post_in_wta=False):
         """Kernel shapes (never change results): lanes per horizontal /
         other aggregation slice (0, 0 = default); ``fused``: the aggregation
         computes costs from census words (no cost volume); ``census_cost``:
         one census + cost launch builds the cost volume (9x7 windows);
         ``final_pass``: the last direction runs fused with the sum and the
-        winner-take-all (SGM_TUNE_FINAL_PASS)."""
+        winner-take-all (SGM_TUNE_FINAL_PASS); ``post_in_wta``: the median
+        and left-right check run inside the winner-take-all launch
+        (SGM_TUNE_POST_IN_WTA)."""
         flags = (TUNE_FUSED_AGG if fused else 0) | (TUNE_FUSED_CENSUS_COST if census_cost else 0) | \
-            (TUNE_FINAL_PASS if final_pass else 0)
+            (TUNE_FINAL_PASS if final_pass else 0) | (TUNE_POST_IN_WTA if post_in_wta else 0)
         _check(lib().sgm_set_tuning(self._ctx, lanes_h, lanes_v, flags))
 
     def tuning(self):
-        """(lanes_h, lanes_v, fused, census_cost, final_pass) in effect."""
+        """(lanes_h, lanes_v, fused, census_cost, final_pass, post_in_wta) in effect."""
         gh, gv, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(lib().sgm_get_tuning(self._ctx, ctypes.byref(gh), ctypes.byref(gv), ctypes.byref(f)))
         return (gh.value, gv.value, bool(f.value & TUNE_FUSED_AGG), bool(f.value & TUNE_FUSED_CENSUS_COST),
-                bool(f.value & TUNE_FINAL_PASS))
+                bool(f.value & TUNE_FINAL_PASS), bool(f.value & TUNE_POST_IN_WTA))
 
     @property
     def shape(self):

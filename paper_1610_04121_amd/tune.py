@@ -21,8 +21,8 @@ def padded_disp(max_disp: int) -> int:
     return 64 if max_disp <= 64 else (128 if max_disp <= 128 else 256)
 
 
-def candidates(max_disp: int, census_9x7: bool = True, final_pass: bool = False):
-    """(lanes_h, lanes_v, fused, census_cost, final_pass) shapes the kernels
+def candidates(max_disp: int, census_9x7: bool = True, final_pass: bool = False, post_in_wta: bool = False):
+    """(lanes_h, lanes_v, fused, census_cost, final_pass, post_in_wta) shapes the kernels
     provide for this range: the cost volume from separate census and cost
     launches or (9x7 windows) from one, or no cost volume at all (fused).
     With final_pass, the shapes with a stored cost volume are also offered
@@ -36,9 +36,9 @@ def candidates(max_disp: int, census_9x7: bool = True, final_pass: bool = False)
     out = []
     for gh, gv in pairs:
         for f, cc in costs:
-            out.append((gh, gv, f, cc, False))
+            out.append((gh, gv, f, cc, False, post_in_wta))
             if final_pass and not f:
-                out.append((gh, gv, f, cc, True))
+                out.append((gh, gv, f, cc, True, post_in_wta))
     return out
 
 

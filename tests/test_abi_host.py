@@ -140,17 +140,21 @@ def test_create_without_gpu_fails_cleanly(lib):
 def test_tuner_candidates_and_cache(tmp_path, monkeypatch):
     from paper_1610_04121_amd import tune
     c64 = tune.candidates(64)
-    assert all(gh in (16, 32) and gv in (16, 32) for gh, gv, _, _, _ in c64)
+    assert all(len(c) == 6 for c in c64)
+    assert all(gh in (16, 32) and gv in (16, 32) for gh, gv, *_ in c64)
     assert len(c64) == 9 and len(tune.candidates(65)) == 15 and len(tune.candidates(256)) == 15
     assert len(tune.candidates(128, census_9x7=False)) == 10
-    assert not any(f and cc for _, _, f, cc, _ in tune.candidates(128))
-    assert not any(fp for *_, fp in tune.candidates(128))
+    assert not any(f and cc for _, _, f, cc, *_ in tune.candidates(128))
+    assert not any(fp for *_, fp, _ in tune.candidates(128))
     # with the final pass offered: stored cost (with and without it), one
     # census + cost launch (with and without), fused costs (never with it)
     cf = tune.candidates(128, final_pass=True)
     assert len(cf) == 25 and len(tune.candidates(64, final_pass=True)) == 15
-    assert not any(f and fp for _, _, f, _, fp in cf)
+    assert not any(f and fp for _, _, f, _, fp, _ in cf)
     assert len(set(cf)) == len(cf)
+    # the post stage's placement is one fixed choice for every shape
+    assert {c[5] for c in tune.candidates(128)} == {False}
+    assert {c[5] for c in tune.candidates(128, post_in_wta=True)} == {True}
     monkeypatch.setenv("SGM_TUNE_CACHE", str(tmp_path / "t.json"))
     assert tune.load_cache() == {}
     tune.save_entry("a", {"choice": [32, 16, False]})

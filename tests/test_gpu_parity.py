@@ -147,17 +147,19 @@ def test_raw_disparity_parity(gpu, W, H, D, P):
     assert (dr == want.dr_raw).all()
 
 
-@pytest.mark.parametrize("fused,census_cost,final_pass", [(True, False, False), (False, False, False),
-                                                          (False, True, False), (False, False, True),
-                                                          (False, True, True)])
+@pytest.mark.parametrize("fused,census_cost,final_pass,post_in_wta", [
+    (True, False, False, False), (False, False, False, False), (False, True, False, False),
+    (False, False, True, False), (False, True, True, False), (False, True, False, True),
+    (True, False, False, True)])
 @pytest.mark.parametrize("name", list(synth.WORKLOADS))
-def test_workload_full_size_bit_exact(gpu, name, fused, census_cost, final_pass):
+def test_workload_full_size_bit_exact(gpu, name, fused, census_cost, final_pass, post_in_wta):
     cfg = synth.WORKLOADS[name]
     pair = synth.workload_pair(name)
-    _say(f"workload {name} fused={fused} census_cost={census_cost} final_pass={final_pass}")
+    _say(f"workload {name} fused={fused} census_cost={census_cost} final_pass={final_pass} "
+         f"post_in_wta={post_in_wta}")
     s = SGM(cfg["w"], cfg["h"], cfg["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, cfg["n_paths"],
             median=cfg["median"], lrcheck=cfg["lr"])
-    s.set_tuning(0, 0, fused, census_cost, final_pass)
+    s.set_tuning(0, 0, fused, census_cost, final_pass, post_in_wta)
     got = _np(s.compute(_t(pair.left, gpu), _t(pair.right, gpu)))
     s.close()
     want = oracle.sgm(pair.left, pair.right, cfg["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT,
@@ -547,4 +549,44 @@ def test_fuzz_pipeline_final_pass(gpu, trial):
     want_raw = oracle.sgm(l, r, D, 7, 86, P, lr=True, csct=csct, subpixel=sub)
     assert (_np(dl) == want_raw.dl_raw).all()
     assert (_np(dr) == want_raw.dr_raw).all()
+    s.close()
+
+
+@pytest.mark.parametrize("trial", range(24))
+def test_fuzz_post_in_wta(gpu, trial):
+    """The median and left-right check inside the winner-take-all launch (the
+    block completing a row's neighbourhood filters it) on fuzzed shapes and
+    options, including the full check's two-SGM launch, against the oracle;
+    every frame is computed twice so that the row counters left by one frame
+    are shown to be clear for the next."""
+    rng = np.random.default_rng(23000 + trial)
+    W, H = int(rng.integers(1, 120)), int(rng.integers(1, 50))
+    if trial < 3:
+        H = trial + 1  # one to three rows: rows with fewer neighbours
+    D = int(rng.choice([1, 7, 16, 40, 64, 65, 100, 128, 130, 200, 256]))
+    P = int(rng.choice([2, 4, 8]))
+    med, lr, sub, csct = (bool(rng.integers(0, 2)) for _ in range(4))
+    if not (med or lr):
+        med = True
+    full = lr and bool(rng.integers(0, 2))
+    adapt = bool(rng.integers(0, 2))
+    thr = int(rng.integers(0, 3))
+    tuning = TUNINGS[trial % len(TUNINGS)]
+    l, r = _rand_pair(rng, W, H)
+    if trial % 3 == 0:
+        pr = synth.make_pair(W, H, D, "RS", seed=23000 + trial)
+        l, r = pr.left, pr.right
+    _say(f"post-in-wta fuzz {trial}: {W}x{H} D={D} P={P} med={med} lr={lr} full={full} sub={sub} csct={csct} "
+         f"adapt={adapt} thr={thr} tuning={tuning}")
+    s = SGM(W, H, D, 7, 86, P, median=med, lrcheck=lr, csct=csct, lr_threshold=thr, subpixel=sub,
+            lr_full=full, adaptive_p2=adapt)
+    s.set_tuning(*tuning, False, True)
+    assert s.tuning()[5]
+    tl, tr = _t(l, gpu), _t(r, gpu)
+    want = oracle.sgm(l, r, D, 7, 86, P, median=med, lr=lr, csct=csct, lr_thr=thr, subpixel=sub, lr_full=full,
+                      adaptive=adapt).out
+    for rep in range(2):
+        got = _np(s.compute(tl, tr))
+        bad = np.argwhere(got != want)
+        assert len(bad) == 0, (rep, f"{len(bad)} pixels differ, first {bad[:5].tolist()}")
     s.close()
