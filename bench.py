@@ -114,6 +114,51 @@ def summarize_counters(fetch_csv: str, write_csv: str, copy_mib: int, tuning) ->
     return out
 
 
+def summarize_trace(csv_path: str, skip_frac: float = 0.2, frames_range=None) -> dict:
+    """Frame spans and gaps from a rocprofv3 --kernel-trace CSV of a run of
+    whole frames on one stream: a frame starts at each census launch; its
+    span runs from the first kernel's start to the last kernel's end, and
+    the gap before each kernel is its start minus the previous kernel's end.
+    frames_range (first, end) selects frames by launch order; then the first
+    skip_frac of them (warm-up) is left out; medians in us."""
+    import csv
+    rows = []
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if r.get("Kind", "KERNEL_DISPATCH") != "KERNEL_DISPATCH":
+                continue
+            name = r["Kernel_Name"]
+            short = name.replace("(anonymous namespace)::", "").split("(")[0].split("<")[0].split("::")[-1]
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short))
+    rows.sort()
+    frames, cur = [], []
+    for r in rows:
+        if r[2].startswith("census") and cur:
+            frames.append(cur)
+            cur = []
+        if r[2].startswith("census") or cur:
+            cur.append(r)
+    if cur:
+        frames.append(cur)
+    if frames_range:
+        frames = frames[frames_range[0]:frames_range[1]]
+    frames = frames[int(len(frames) * skip_frac):]
+    if not frames:
+        return {"frames": 0}
+    med = lambda v: round(float(sorted(v)[len(v) // 2]) / 1e3, 3)
+    spans = [f[-1][1] - f[0][0] for f in frames]
+    busy = [sum(e - s for s, e, _ in f) for f in frames]
+    gaps = {}
+    for f in frames:
+        for a, b in zip(f, f[1:]):
+            gaps.setdefault(f"{a[2]} -> {b[2]}", []).append(b[0] - a[1])
+    between = [b[0][0] - a[-1][1] for a, b in zip(frames, frames[1:])]
+    return {"frames": len(frames), "kernels_per_frame": len(frames[0]),
+            "span_us": med(spans), "kernel_time_us": med(busy), "idle_in_frame_us": med([s - b for s, b in zip(spans, busy)]),
+            "gap_us": {k: med(v) for k, v in gaps.items()},
+            "gap_between_frames_us": med(between) if between else None}
+
+
 def pipeline_bytes(W: int, H: int, Dp: int, P: int, tuning) -> int:
     """Algorithmic bytes of census, cost, aggregation and WTA for one frame
     (each byte read or written once per kernel that needs it): images in,
@@ -303,24 +348,36 @@ def bench_batch(dev, steps: int, warmup: int = 3, post: bool = False):
     from paper_1610_04121_amd.sgm import Batch
 
     items = synth.batch_items(64)
-    pairs, cells = [], 0
+    pairs, cells, alg_bytes = [], 0, 0
     for it in items:
         pr = synth.make_pair(it["w"], it["h"], it["max_disp"], it["scene"], seed=it["seed"])
         pairs.append(dict(left=torch.from_numpy(pr.left).to(dev), right=torch.from_numpy(pr.right).to(dev),
                           max_disp=it["max_disp"], n_paths=it["n_paths"], median=post, lrcheck=post,
                           out=torch.empty((it["h"], it["w"]), dtype=torch.uint16, device=dev)))
         cells += it["w"] * it["h"] * it["max_disp"] * it["n_paths"]
+        Dp = 64 if it["max_disp"] <= 64 else (128 if it["max_disp"] <= 128 else 256)
+        # the batch runs separate census and cost launches; the post stage
+        # reads both raw maps' 3x3 neighbourhoods and writes the output
+        alg_bytes += pipeline_bytes(it["w"], it["h"], Dp, it["n_paths"], (0, 0, False, False, False))
+        if post:
+            alg_bytes += 6 * it["w"] * it["h"]
     b = Batch(synth.P1_DEFAULT, synth.P2_DEFAULT)
     st = torch.cuda.current_stream()
     tuned = b.autotune(pairs, use_cache=False)
-    for _ in range(warmup):
-        b.compute(pairs, stream=st)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        b.compute(pairs, stream=st)
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / steps
+
+    def time_batch():
+        for _ in range(warmup):
+            b.compute(pairs, stream=st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.compute(pairs, stream=st)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    t_batch = time_batch()
+    b.set_graph(True)  # the same launches replayed from a captured graph
+    t_graph = time_batch()
     footprint = b.footprint(pairs)
     b.close()
 
@@ -347,10 +404,17 @@ def bench_batch(dev, steps: int, warmup: int = 3, post: bool = False):
     t_seq = (time.perf_counter() - t0) / steps
     for c in ctxs.values():
         c.close()
+    gbs = alg_bytes / t_batch / 1e9
     return {"pairs": len(pairs), "batches": steps, "ms_per_batch": round(t_batch * 1e3, 4),
             "pairs_per_s": round(len(pairs) / t_batch, 1), "gcells_per_s": round(cells / t_batch / 1e9, 1),
+            "graph_ms_per_batch": round(t_graph * 1e3, 4),
             "sequential_ms": round(t_seq * 1e3, 4), "sequential_pairs_per_s": round(len(pairs) / t_seq, 1),
             "speedup_vs_sequential": round(t_seq / t_batch, 3), "workspace_bytes": footprint,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(gbs / 8000.0, 4), "alg_bytes_per_batch": alg_bytes,
+                         "basis": "algorithmic bytes of census, cost, aggregation, sum + WTA"
+                                  + (" and median + LR" if post else "")
+                                  + " of all pairs, over the batch's wall time (direct launches)"},
             "tuning": {"lanes_h_lanes_v": tuned["choice"], "ms_per_batch_by_shape": tuned["candidates"]},
             "shapes": "64 pairs, sizes from {320x240, 640x480, 1242x375, 1280x720}, D from {64, 128}, "
                       "4 or 8 paths, " + ("median + LR check" if post else "no median/LR")}
@@ -563,7 +627,7 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD,
                     help="single-pair workload of synth.WORKLOADS to time (profiler runs of the other "
                          "workloads; the default is the headline workload)")
-    ap.add_argument("--profile-every", type=int, default=8,
+    ap.add_argument("--profile-every", type=int, default=32,
                     help="record stage events on every n-th frame of each context")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-timing", action="store_true",
@@ -592,7 +656,17 @@ def main():
     ap.add_argument("--counters-from", default="",
                     help="FETCH_CSV,WRITE_CSV: summarize rocprofv3 --pmc output (with --copy-calibration-mb "
                          "and --tuning as in the profiled run) as JSON and exit")
+    ap.add_argument("--graph", action="store_true",
+                    help="time the frames as graph replays (SGM_GRAPH; no stage events in the timed region)")
+    ap.add_argument("--trace-from", default="",
+                    help="KERNEL_TRACE_CSV: summarize a rocprofv3 --kernel-trace run of whole frames (frame span, "
+                         "kernel time, gaps between kernels) as JSON and exit")
+    ap.add_argument("--trace-frames", default="", help="FIRST:END frames (launch order) for --trace-from")
     args = ap.parse_args()
+    if args.trace_from:
+        rng = tuple(int(v) for v in args.trace_frames.split(":")) if args.trace_frames else None
+        print(json.dumps(summarize_trace(args.trace_from, frames_range=rng), indent=1))
+        return
     if args.counters_from:
         fcsv, wcsv = args.counters_from.split(",")
         print(json.dumps(summarize_counters(fcsv, wcsv, args.copy_calibration_mb, args.tuning.split(",")), indent=1))
@@ -638,7 +712,7 @@ def main():
         probe.close()
         choice = tuple(tuned["choice"])
     print(f"bench: autotuned kernel shape {choice}", file=sys.stderr, flush=True)
-    ctxs = [make_ctx(tuning=choice) for _ in range(F)]
+    ctxs = [make_ctx(graph=args.graph, tuning=choice) for _ in range(F)]
     streams = [torch.cuda.Stream() for _ in range(F)]
     outs = [torch.empty((H, W), dtype=torch.uint16, device=dev) for _ in range(F)]
     print(f"bench: {workload} inflight={F} warmup={args.warmup} steps={args.steps}",
@@ -652,7 +726,8 @@ def main():
     run(args.warmup)
     torch.cuda.synchronize()
     for c in ctxs:
-        c.profile(True, every=args.profile_every)
+        if not args.graph:  # (stage events would turn replays into direct launches)
+            c.profile(True, every=args.profile_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run(args.steps)
@@ -668,6 +743,17 @@ def main():
     elapsed = t1 - t0
     fps = args.steps / elapsed
     tuning = ctxs[0].tuning()
+    if args.graph:
+        # the stage events need direct launches: an untimed pass of the same
+        # frames on a direct-launch context gives the per-kernel times
+        pc = make_ctx(tuning=choice)
+        pc.profile(True, every=1)
+        for _ in range(min(args.steps, 400)):
+            pc.compute(left, right, outs[0], stream=streams[0])
+        torch.cuda.synchronize()
+        ncalls, stage_ms = pc.profile_read()
+        pc.profile(False)
+        pc.close()
 
     extras = {}
     if not args.no_extras:
@@ -765,7 +851,7 @@ def main():
         "config": {"workload": workload, "width": W, "height": H, "max_disp": D, "n_paths": P,
                    "census": "9x7 full", "P1": synth.P1_DEFAULT, "P2": synth.P2_DEFAULT,
                    "median": cfg["median"], "lr_check": cfg["lr"], "scene": cfg["scene"],
-                   "seed": cfg["seed"], "frames_in_flight": F,
+                   "seed": cfg["seed"], "frames_in_flight": F, "graph_replay": bool(args.graph),
                    "lanes_h": tuning[0], "lanes_v": tuning[1], "fused_cost": tuning[2],
                    "fused_census_cost": tuning[3], "final_pass": final_pass,
                    "autotune_ms_per_frame": tuned["candidates"]},

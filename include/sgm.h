@@ -211,6 +211,21 @@ int sgm_batch_compute(sgm_batch *b, const sgm_item *items, int n, sgm_stream_t s
  * image is wider than tall, else 16; 16 for the other directions). */
 int sgm_batch_set_tuning(sgm_batch *b, int lanes_h, int lanes_v);
 
+/* Graph replay for batches (enable 1; 0, the default, launches directly).
+ * With it on, sgm_batch_compute captures the batch's launches into a
+ * hipGraph the first time it sees a batch signature (the runner's kernel
+ * shape and every item's w, h, max_disp, n_paths and flags, in order) and
+ * replays that graph for later batches with the same signature, whatever
+ * their buffers: the graph's kernels read the items' pointers from a
+ * descriptor table that belongs to the graph, copied again on `stream`
+ * ahead of the replay when it changed.  Up to 8 graphs are kept, most
+ * recently used first; capturing a new one waits for `stream`, and dropping
+ * one (or turning graphs off) waits for the device.  Results are identical
+ * to direct launches.  Calls on different streams must not overlap (a
+ * replay and the next descriptor copy of the same graph are ordered by the
+ * stream only). */
+int sgm_batch_set_graph(sgm_batch *b, int enable);
+
 /* Device bytes sgm_batch_compute needs for these items (0 if one is invalid). */
 size_t sgm_batch_footprint(sgm_batch *b, const sgm_item *items, int n);
 

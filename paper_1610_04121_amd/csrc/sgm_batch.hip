@@ -361,13 +361,25 @@ int grow_staging(BatchStaging* b, size_t nitems, size_t nwork) {
 
 }  // namespace
 
-int batch_enqueue(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_base, const sgm_item* items, int n,
-                  BatchStaging* st, hipStream_t s) {
-    if (n <= 0) return SGM_OK;
-    // work items: every direction's slices of every pair, S per wavefront
+// Everything one batch's launches take, built on the host: the descriptor
+// and work tables and the launch shapes.
+struct BatchLaunch {
+    std::vector<BatchItem> desc;
     std::vector<WorkItem> work;
     size_t census_blocks = 0, cost_blocks = 0, wta_blocks = 0, post_blocks = 0;
-    std::vector<BatchItem> desc(n);
+    size_t cost_smem = 0, wta_smem = 0, post_smem = 0;
+    bool generic = false, any_adapt = false, nt = false;
+    int waves = 0;
+};
+
+int batch_build(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_base, const sgm_item* items, int n,
+                BatchLaunch& B) {
+    // work items: every direction's slices of every pair, S per wavefront
+    std::vector<WorkItem>& work = B.work;
+    size_t census_blocks = 0, cost_blocks = 0, wta_blocks = 0, post_blocks = 0;
+    std::vector<BatchItem>& desc = B.desc;
+    desc.assign(n, BatchItem{});
+    work.clear();
     const bool generic = !(bp.cw == 9 && bp.ch == 7);
     size_t cost_smem = 0, wta_smem = 0, post_smem = 0;
     bool any_adapt = false;
@@ -438,45 +450,98 @@ int batch_enqueue(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_b
     // longest slices first (largest-processing-time-first order)
     std::stable_sort(work.begin(), work.end(), [](const WorkItem& a, const WorkItem& c) { return a.steps > c.steps; });
 
-    if (int rc = grow_staging(st, desc.size(), work.size())) return rc;
-    memcpy(st->h_items, desc.data(), desc.size() * sizeof(BatchItem));
-    memcpy(st->h_work, work.data(), work.size() * sizeof(WorkItem));
-    hipError_t e = hipMemcpyAsync(st->d_items, st->h_items, desc.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(st->d_work, st->h_work, work.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipEventRecord(st->staged, s);
-    if (e != hipSuccess) return bhip(e, "descriptor copy");
-    st->staged_pending = true;
-
-    hipLaunchKernelGGL(census_batch_kernel, dim3((unsigned)census_blocks), dim3(256), 0, s, st->d_items, n,
-                       generic ? 1 : 0, (bp.cw - 1) / 2, (bp.ch - 1) / 2, st->counter);
-    hipLaunchKernelGGL(cost_batch_kernel, dim3((unsigned)cost_blocks), dim3(kCostThreads), cost_smem, s, st->d_items, n);
     // persistent grid: at most two wavefronts per SIMD (256 CUs x 4 SIMDs)
-    const int nwork = (int)work.size();
-    const int waves = std::min(nwork, 2048);
+    B.waves = std::min((int)work.size(), 2048);
     // the planes and cost volumes of the whole batch against the memory-side
     // cache: the store policy of the single-pair path (Plan::nt_store)
     long long fbytes = 0;
     for (const BatchItem& d : desc)
         fbytes += (long long)d.W * d.H * d.Dp * (d.P * (d.l16 ? 2 : 1) + 1) * (d.lr_full ? 2 : 1);
-    const bool nt = fbytes > kMallBytes;
-    auto agg = nt ? (any_adapt ? aggregate_batch_kernel<true, true> : aggregate_batch_kernel<true, false>)
-                  : (any_adapt ? aggregate_batch_kernel<false, true> : aggregate_batch_kernel<false, false>);
-    hipLaunchKernelGGL(agg, dim3((waves + 3) / 4), dim3(256), 0, s, st->d_items, st->d_work, nwork, st->counter,
-                       bp.P1, bp.P2);
-    hipLaunchKernelGGL(nt ? wta_batch_kernel<true> : wta_batch_kernel<false>, dim3((unsigned)wta_blocks), dim3(1024),
-                       wta_smem, s, st->d_items, n);
-    if (post_blocks > 0) {
+    B.nt = fbytes > kMallBytes;
+    B.generic = generic;
+    B.any_adapt = any_adapt;
+    B.census_blocks = census_blocks;
+    B.cost_blocks = cost_blocks;
+    B.wta_blocks = wta_blocks;
+    B.post_blocks = post_blocks;
+    B.cost_smem = cost_smem;
+    B.wta_smem = wta_smem;
+    B.post_smem = post_smem;
+    return SGM_OK;
+}
+
+hipError_t batch_launch(const BatchParams& bp, const BatchLaunch& B, const BatchItem* d_items, const WorkItem* d_work,
+                        unsigned* counter, hipStream_t s) {
+    const int n = (int)B.desc.size();
+    hipLaunchKernelGGL(census_batch_kernel, dim3((unsigned)B.census_blocks), dim3(256), 0, s, d_items, n,
+                       B.generic ? 1 : 0, (bp.cw - 1) / 2, (bp.ch - 1) / 2, counter);
+    hipLaunchKernelGGL(cost_batch_kernel, dim3((unsigned)B.cost_blocks), dim3(kCostThreads), B.cost_smem, s, d_items,
+                       n);
+    const int nwork = (int)B.work.size();
+    auto agg = B.nt ? (B.any_adapt ? aggregate_batch_kernel<true, true> : aggregate_batch_kernel<true, false>)
+                    : (B.any_adapt ? aggregate_batch_kernel<false, true> : aggregate_batch_kernel<false, false>);
+    hipLaunchKernelGGL(agg, dim3((B.waves + 3) / 4), dim3(256), 0, s, d_items, d_work, nwork, counter, bp.P1, bp.P2);
+    hipLaunchKernelGGL(B.nt ? wta_batch_kernel<true> : wta_batch_kernel<false>, dim3((unsigned)B.wta_blocks),
+                       dim3(1024), B.wta_smem, s, d_items, n);
+    if (B.post_blocks > 0) {
         // pairs without a post stage own empty block ranges; the search for
         // the last pair whose range starts at or before a block skips them
-        hipLaunchKernelGGL(post_batch_kernel, dim3((unsigned)post_blocks), dim3(256), post_smem, s, st->d_items, n);
+        hipLaunchKernelGGL(post_batch_kernel, dim3((unsigned)B.post_blocks), dim3(256), B.post_smem, s, d_items, n);
     }
-    e = hipGetLastError();
+    return hipGetLastError();
+}
+
+int batch_enqueue(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_base, const sgm_item* items, int n,
+                  BatchStaging* st, hipStream_t s) {
+    if (n <= 0) return SGM_OK;
+    BatchLaunch B;
+    if (int rc = batch_build(bp, plans, ws_base, items, n, B)) return rc;
+    if (int rc = grow_staging(st, B.desc.size(), B.work.size())) return rc;
+    memcpy(st->h_items, B.desc.data(), B.desc.size() * sizeof(BatchItem));
+    memcpy(st->h_work, B.work.data(), B.work.size() * sizeof(WorkItem));
+    hipError_t e =
+        hipMemcpyAsync(st->d_items, st->h_items, B.desc.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(st->d_work, st->h_work, B.work.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(st->staged, s);
+    if (e != hipSuccess) return bhip(e, "descriptor copy");
+    st->staged_pending = true;
+    e = batch_launch(bp, B, st->d_items, st->d_work, st->counter, s);
     if (e != hipSuccess) return bhip(e, "batch kernel launch");
     return SGM_OK;
 }
 
 }  // namespace sgm
+
+// A batch's launch sequence captured in a graph (sgm_batch_set_graph): the
+// kernels read descriptor and work tables and a queue counter that belong to
+// the graph.  The work table depends only on the items' shapes and options
+// (the signature); the descriptors also hold the caller's and the arena's
+// pointers, so they are copied again, ahead of the replay on the same stream,
+// whenever they differ from the last copy.
+struct BatchGraph {
+    std::vector<long long> sig;
+    sgm::BatchItem* d_items = nullptr;
+    sgm::WorkItem* d_work = nullptr;
+    unsigned* counter = nullptr;
+    sgm::BatchItem* h_items = nullptr;  // pinned source of the descriptor copies
+    hipEvent_t copied = nullptr;        // the last copy out of h_items
+    bool copy_pending = false;
+    std::vector<sgm::BatchItem> last;   // descriptors in d_items
+    hipGraphExec_t exec = nullptr;
+};
+
+static void graph_free(BatchGraph* g) {
+    if (!g) return;
+    if (g->copy_pending) (void)hipEventSynchronize(g->copied);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->d_items) (void)hipFree(g->d_items);
+    if (g->d_work) (void)hipFree(g->d_work);
+    if (g->counter) (void)hipFree(g->counter);
+    if (g->h_items) (void)hipHostFree(g->h_items);
+    if (g->copied) (void)hipEventDestroy(g->copied);
+    delete g;
+}
 
 struct sgm_batch {
     sgm::BatchParams bp;
@@ -484,7 +549,17 @@ struct sgm_batch {
     void* arena = nullptr;
     size_t arena_bytes = 0;
     sgm::BatchStaging* st = nullptr;
+    bool use_graph = false;
+    std::vector<BatchGraph*> graphs;  // most recently used first
+    hipStream_t capture_stream = nullptr;
 };
+
+static constexpr size_t kMaxBatchGraphs = 8;
+
+static void drop_batch_graphs(sgm_batch* b) {
+    for (BatchGraph* g : b->graphs) graph_free(g);
+    b->graphs.clear();
+}
 
 namespace {
 
@@ -495,6 +570,113 @@ int api_err(int code, const std::string& m) {
 
 int api_hip(hipError_t e, const char* what) {
     return api_err(SGM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// What a captured graph depends on besides pointers: the runner's kernel
+// shape and every item's size, range, path count and options.
+std::vector<long long> batch_signature(const sgm::BatchParams& bp, const sgm_item* items, int n) {
+    std::vector<long long> sig{n, bp.lanes_h, bp.lanes_v};
+    sig.reserve(3 + 5 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const sgm_item& it = items[i];
+        sig.insert(sig.end(), {it.w, it.h, it.max_disp, it.n_paths, (long long)it.flags});
+    }
+    return sig;
+}
+
+// Builds a graph entry for this batch: its tables, the work table's copy
+// (on `s`, so that it precedes the first replay) and the captured launches.
+int graph_create(sgm_batch* b, const sgm::BatchLaunch& B, std::vector<long long> sig, hipStream_t s,
+                 BatchGraph** out) {
+    using namespace sgm;
+    BatchGraph* g = new (std::nothrow) BatchGraph;
+    if (!g) return api_err(SGM_ENOMEM, "host allocation failed");
+    g->sig = std::move(sig);
+    const size_t nd = B.desc.size(), nw = B.work.size();
+    if (hipMalloc((void**)&g->d_items, nd * sizeof(BatchItem)) != hipSuccess ||
+        hipMalloc((void**)&g->d_work, nw * sizeof(WorkItem)) != hipSuccess ||
+        hipMalloc((void**)&g->counter, 256) != hipSuccess ||
+        hipHostMalloc((void**)&g->h_items, std::max(nd * sizeof(BatchItem), nw * sizeof(WorkItem)),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&g->copied, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        graph_free(g);
+        return api_err(SGM_ENOMEM, "batch graph allocation failed");
+    }
+    // the work table once, through the pinned buffer, waiting for the copy
+    // before the buffer holds descriptors
+    memcpy(g->h_items, B.work.data(), nw * sizeof(WorkItem));
+    hipError_t e = hipMemcpyAsync(g->d_work, g->h_items, nw * sizeof(WorkItem), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && !b->capture_stream) e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        graph_free(g);
+        return api_hip(e, "batch graph set-up");
+    }
+    e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        graph_free(g);
+        return api_hip(e, "hipStreamBeginCapture");
+    }
+    hipError_t le = batch_launch(b->bp, B, g->d_items, g->d_work, g->counter, b->capture_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(b->capture_stream, &graph);
+    if (le == hipSuccess && e == hipSuccess) e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        graph_free(g);
+        return api_hip(le != hipSuccess ? le : e, "batch graph capture");
+    }
+    *out = g;
+    return SGM_OK;
+}
+
+// sgm_batch_compute with graphs on: finds (or captures) the graph of this
+// batch's signature, copies the descriptors if they changed, replays it.
+int batch_replay(sgm_batch* b, const sgm::BatchLayout& L, uint8_t* const* bases, const sgm_item* items, int n,
+                 hipStream_t s) {
+    using namespace sgm;
+    BatchLaunch B;
+    if (int rc = batch_build(b->bp, L.plans.data(), bases, items, n, B)) return rc;
+    std::vector<long long> sig = batch_signature(b->bp, items, n);
+    size_t i = 0;
+    while (i < b->graphs.size() && b->graphs[i]->sig != sig) ++i;
+    if (i == b->graphs.size()) {
+        BatchGraph* g = nullptr;
+        if (int rc = graph_create(b, B, std::move(sig), s, &g)) return rc;
+        if (b->graphs.size() == kMaxBatchGraphs) {
+            // its last replay and copy were enqueued on a stream the caller
+            // may still run: wait for the device before freeing its tables
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) {
+                graph_free(g);
+                return api_hip(e, "hipDeviceSynchronize");
+            }
+            graph_free(b->graphs.back());
+            b->graphs.pop_back();
+        }
+        b->graphs.insert(b->graphs.begin(), g);
+    } else if (i > 0) {
+        std::swap(b->graphs[i], b->graphs[0]);
+    }
+    BatchGraph* g = b->graphs[0];
+    const size_t bytes = B.desc.size() * sizeof(BatchItem);
+    if (g->last.size() != B.desc.size() || memcmp(g->last.data(), B.desc.data(), bytes) != 0) {
+        if (g->copy_pending) {
+            hipError_t e = hipEventSynchronize(g->copied);
+            if (e != hipSuccess) return api_hip(e, "hipEventSynchronize");
+            g->copy_pending = false;
+        }
+        memcpy(g->h_items, B.desc.data(), bytes);
+        hipError_t e = hipMemcpyAsync(g->d_items, g->h_items, bytes, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipEventRecord(g->copied, s);
+        if (e != hipSuccess) return api_hip(e, "descriptor copy");
+        g->copy_pending = true;
+        g->last = B.desc;
+    }
+    hipError_t e = hipGraphLaunch(g->exec, s);
+    if (e != hipSuccess) return api_hip(e, "hipGraphLaunch");
+    return SGM_OK;
 }
 
 }  // namespace
@@ -545,6 +727,18 @@ int sgm_batch_set_tuning(sgm_batch* b, int lanes_h, int lanes_v) {
     return SGM_OK;
 }
 
+int sgm_batch_set_graph(sgm_batch* b, int enable) {
+    if (!b) return api_err(SGM_EINVAL, "null batch");
+    if (enable != 0 && enable != 1) return api_err(SGM_EINVAL, "enable must be 0 or 1");
+    b->use_graph = enable != 0;
+    if (!b->use_graph) {
+        hipError_t e = hipDeviceSynchronize();  // replays may still read the graphs' tables
+        if (e != hipSuccess) return api_hip(e, "hipDeviceSynchronize");
+        drop_batch_graphs(b);
+    }
+    return SGM_OK;
+}
+
 size_t sgm_batch_footprint(sgm_batch* b, const sgm_item* items, int n) {
     if (!b) return 0;
     sgm::BatchLayout L;
@@ -584,13 +778,16 @@ int sgm_batch_compute(sgm_batch* b, const sgm_item* items, int n, sgm_stream_t s
     }
     std::vector<uint8_t*> bases(n);
     for (int i = 0; i < n; ++i) bases[i] = static_cast<uint8_t*>(b->arena) + L.offsets[i];
-    return batch_enqueue(b->bp, L.plans.data(), bases.data(), items, n, b->st, s);
+    if (!b->use_graph) return batch_enqueue(b->bp, L.plans.data(), bases.data(), items, n, b->st, s);
+    return batch_replay(b, L, bases.data(), items, n, s);
 }
 
 void sgm_batch_destroy(sgm_batch* b) {
     if (!b) return;
     (void)hipSetDevice(b->device);
     (void)hipDeviceSynchronize();
+    drop_batch_graphs(b);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     if (b->arena) (void)hipFree(b->arena);
     sgm::staging_destroy(b->st);
     delete b;

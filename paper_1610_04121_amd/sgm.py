@@ -27,6 +27,7 @@ EXPORTS = [
     "sgm_server_create", "sgm_server_set_policy", "sgm_server_request_bytes", "sgm_server_submit",
     "sgm_server_poll", "sgm_server_wait", "sgm_server_cancel", "sgm_server_get_stats", "sgm_server_destroy",
     "sgm_server_create_ex", "sgm_debug_phase_sums", "sgm_compute_noalloc", "sgm_batch_set_tuning",
+    "sgm_batch_set_graph",
 ]
 NOALLOC_MAX_BYTES = 256 << 20
 
@@ -112,6 +113,8 @@ def lib() -> ctypes.CDLL:
     L.sgm_batch_footprint.restype = ctypes.c_size_t
     L.sgm_batch_set_tuning.argtypes = [P, i, i]
     L.sgm_batch_set_tuning.restype = i
+    L.sgm_batch_set_graph.argtypes = [P, i]
+    L.sgm_batch_set_graph.restype = i
     L.sgm_batch_destroy.argtypes = [P]
     L.sgm_batch_destroy.restype = None
     L.sgm_compute_batch.argtypes = [ctypes.POINTER(Item), i, i, i, i, i, P]
@@ -385,12 +388,20 @@ def _items(pairs):
 class Batch:
     """Runs many pairs of different shapes with one launch per stage."""
 
-    def __init__(self, P1=7, P2=86, census_w=9, census_h=7):
+    def __init__(self, P1=7, P2=86, census_w=9, census_h=7, graph=False):
         self._b = lib().sgm_batch_create(P1, P2, census_w, census_h)
         if not self._b:
             raise SGMError(SGM_EINVAL, last_error())
         self.params = dict(P1=P1, P2=P2, census_w=census_w, census_h=census_h)
         self.tuning = (0, 0)
+        self.graph = False
+        if graph:
+            self.set_graph(True)
+
+    def set_graph(self, enable: bool):
+        """Replay a captured hipGraph per batch signature (sgm_batch_set_graph)."""
+        _check(lib().sgm_batch_set_graph(self._b, 1 if enable else 0))
+        self.graph = bool(enable)
 
     def compute(self, pairs, stream=None):
         arr = _items(pairs)

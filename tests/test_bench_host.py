@@ -131,3 +131,26 @@ def test_bench_rejects_an_unknown_workload():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 2
     assert "unknown workload" in r.stderr
+
+
+def test_trace_summary_frames_and_gaps(tmp_path):
+    """Frames start at each census launch; spans, kernel time and the gaps
+    before each kernel and between frames come from the timestamps."""
+    hdr = '"Kind","Kernel_Name","Start_Timestamp","End_Timestamp"\n'
+    rows, t = [], 0
+    for f in range(10):
+        for name, dur, gap in (("sgm::(anonymous namespace)::census97_kernel(sgm::dev::CensusArgs)", 5000, 0),
+                               ("void sgm::(anonymous namespace)::cost_kernel<false, 128>(sgm::dev::CostArgs)", 10000, 1000),
+                               ("void sgm::(anonymous namespace)::wta_kernel<unsigned char, false>(sgm::dev::WtaArgs)",
+                                20000, 2000)):
+            t += gap
+            rows.append(f'"KERNEL_DISPATCH","{name}",{t},{t + dur}\n')
+            t += dur
+        t += 8000  # between frames
+    p = tmp_path / "t_kernel_trace.csv"
+    p.write_text(hdr + "".join(rows))
+    s = bench.summarize_trace(str(p), skip_frac=0.0)
+    assert s["frames"] == 10 and s["kernels_per_frame"] == 3
+    assert s["span_us"] == 38.0 and s["kernel_time_us"] == 35.0 and s["idle_in_frame_us"] == 3.0
+    assert s["gap_us"] == {"census97_kernel -> cost_kernel": 1.0, "cost_kernel -> wta_kernel": 2.0}
+    assert s["gap_between_frames_us"] == 8.0

@@ -287,3 +287,104 @@ def test_batch_autotune_picks_a_shape_and_caches(gpu, tmp_path, monkeypatch):
     res2 = b2.autotune(list(reversed(pairs)))  # the same multiset of pairs
     assert res2["cached"] and res2["choice"] == res["choice"] and b2.tuning == tuple(res["choice"])
     b2.close()
+
+
+def test_batch_graph_replays_match_direct_launches(gpu):
+    """Graph replay of a mixed batch (plain, full-check, adaptive, sub-pixel
+    and post-filtered items): every replay, with eager work on the stream
+    between replays, new output buffers, new inputs, a second signature
+    captured in between and a larger arena, equals the direct launches."""
+    import torch
+    specs = [(64, 48, 40, 4, True, True), (97, 31, 64, 8, False, True), (40, 70, 130, 2, True, True),
+             (33, 33, 200, 8, True, False), (50, 20, 16, 4, False, False)]
+    opts = [(True, False, False), (False, True, False), (True, True, True), (False, False, True),
+            (False, False, False)]  # (lr_full, adaptive, subpixel)
+
+    def make(seed0):
+        pairs = _pairs(specs, gpu, seed0)
+        for p, (lf, ad, sub) in zip(pairs, opts):
+            p["lr_full"], p["adaptive_p2"], p["subpixel"] = lf and p["lrcheck"], ad, sub
+        return pairs
+
+    def direct(pairs):
+        b = Batch(7, 86)
+        want = [torch.empty_like(p["out"]) for p in pairs]
+        b.compute([dict(p, out=w) for p, w in zip(pairs, want)])
+        torch.cuda.synchronize()
+        b.close()
+        return [w.cpu().numpy() for w in want]
+
+    pairs = make(2300)
+    want = direct(pairs)
+    g = Batch(7, 86, graph=True)
+    scratch = torch.zeros(1 << 20, dtype=torch.float32, device=gpu)
+    for rep in range(4):
+        _say(f"batch graph replay {rep}")
+        for p in pairs:
+            p["out"].fill_(0xABC)  # so that a replay that writes nothing fails
+        g.compute(pairs)
+        scratch.mul_(0.5).add_(1.0)  # eager work on the same stream between replays
+        torch.cuda.synchronize()
+        for k, p in enumerate(pairs):
+            got = p["out"].cpu().numpy()
+            assert (got == want[k]).all(), (rep, k, int((got != want[k]).sum()))
+        if rep == 1:  # new output buffers: the descriptors are copied again
+            for p in pairs:
+                p["out"] = torch.empty_like(p["out"])
+    # a second signature, then new inputs under the first one again
+    sub = pairs[1:3]
+    want_sub = direct(sub)
+    _say("batch graph: second signature")
+    g.compute(sub)
+    torch.cuda.synchronize()
+    for k, p in enumerate(sub):
+        assert (p["out"].cpu().numpy() == want_sub[k]).all(), ("sub", k)
+    pairs2 = make(2400)
+    want2 = direct(pairs2)
+    for rep in range(2):
+        _say(f"batch graph: new inputs, replay {rep}")
+        g.compute(pairs2)
+        torch.cuda.synchronize()
+        for k, p in enumerate(pairs2):
+            assert (p["out"].cpu().numpy() == want2[k]).all(), ("new inputs", rep, k)
+    # a larger batch grows the arena; the first signature replays on the new one
+    big = make(2500) + _pairs([(160, 120, 64, 8, True, True)], gpu, 2600)
+    want_big = direct(big)
+    _say("batch graph: larger batch")
+    g.compute(big)
+    torch.cuda.synchronize()
+    for k, p in enumerate(big):
+        assert (p["out"].cpu().numpy() == want_big[k]).all(), ("big", k)
+    g.compute(pairs2)
+    torch.cuda.synchronize()
+    for k, p in enumerate(pairs2):
+        assert (p["out"].cpu().numpy() == want2[k]).all(), ("after growth", k)
+    g.set_graph(False)
+    g.compute(pairs)
+    torch.cuda.synchronize()
+    for k, p in enumerate(pairs):
+        assert (p["out"].cpu().numpy() == want[k]).all(), ("direct again", k)
+    g.close()
+
+
+@pytest.mark.parametrize("key,post", [("batch64", False), ("batch64_median_lr", True)])
+def test_batch_graph_workload_matches_oracle_digests(gpu, key, post):
+    """The 64-pair workload batch (without and with median + LR) through
+    graph replay, three replays, against the oracle's digests."""
+    import torch
+    items = synth.batch_items(64)
+    specs = [(it["w"], it["h"], it["max_disp"], it["n_paths"], post, post) for it in items]
+    pairs = _pairs(specs, gpu, 0, [(it["scene"], it["seed"]) for it in items])
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_hashes.json")))[key]
+    assert len(golden) == len(pairs)
+    g = Batch(7, 86, graph=True)
+    for rep in range(3):
+        _say(f"64-pair batch ({key}) graph replay {rep}")
+        for p in pairs:
+            p["out"].fill_(0xABC)
+        g.compute(pairs)
+        torch.cuda.synchronize()
+        for k, (p, gd) in enumerate(zip(pairs, golden)):
+            assert hashlib.sha256(p["np_left"].tobytes()).hexdigest() == gd["sha_left"], k
+            assert hashlib.sha256(p["out"].cpu().numpy().tobytes()).hexdigest() == gd["out_sha256"], (rep, k)
+    g.close()
