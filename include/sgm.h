@@ -141,7 +141,10 @@ int sgm_get_tuning(sgm_ctx *ctx, int *lanes_h, int *lanes_v, int *fused);
  * NULL is accepted. */
 void sgm_destroy(sgm_ctx *ctx);
 
-/* Message of the last failed call on this thread ("" if none). */
+/* Message of the last failed call on this thread ("" if none).  With the
+ * environment variable SGM_LOG=1 every such message is also printed on
+ * stderr when it is set; SGM_LOG=2 adds resource events (workspace growth,
+ * graph captures). */
 const char *sgm_last_error(void);
 
 /* Device bytes a context of this shape needs (workspace only; the caller's
@@ -210,6 +213,12 @@ int sgm_batch_compute(sgm_batch *b, const sgm_item *items, int n, sgm_stream_t s
  * every pair; 0 keeps the per-pair default (32 horizontal lanes when the
  * image is wider than tall, else 16; 16 for the other directions). */
 int sgm_batch_set_tuning(sgm_batch *b, int lanes_h, int lanes_v);
+
+/* Workgroups (4 wavefronts each) of the persistent aggregation grid: 0, the
+ * default, fills the device (512); 1 has one CU take the work items four at
+ * a time, a check that no result depends on their order or concurrency
+ * (results never depend on it). */
+int sgm_batch_set_grid(sgm_batch *b, int max_workgroups);
 
 /* Graph replay for batches (enable 1; 0, the default, launches directly).
  * With it on, sgm_batch_compute captures the batch's launches into a
@@ -339,6 +348,14 @@ void sgm_server_destroy(sgm_server *s);
  * number of recorded calls into *ncalls, and clears them. */
 int sgm_profile_enable(sgm_ctx *ctx, int every_n);
 int sgm_profile_read(sgm_ctx *ctx, double *stage_ms, int *ncalls);
+
+/* Allocation-failure hook, for tests of failure handling (process-wide,
+ * any thread): the next `after` device or pinned host allocations the
+ * library makes succeed and the `count` after them fail as if the memory
+ * were exhausted, so the call that needed them returns SGM_ENOMEM (a
+ * server request fails with SGM_REQ_FAILED) and no kernel is launched for
+ * it.  sgm_debug_fail_alloc(0, 0) turns it off. */
+void sgm_debug_fail_alloc(int after, int count);
 
 /* ---- debug taps: intermediates for stage-by-stage parity tests ---- */
 

@@ -18,6 +18,11 @@ struct BatchParams {
     // lanes per aggregation slice for every pair: horizontal (16 or 32) and
     // other directions (16 or 32); 0 = the per-pair default
     int lanes_h = 0, lanes_v = 0;
+    // workgroups of the persistent aggregation grid (4 wavefronts each); 0 =
+    // as many as fill the device (512), 1 takes the queue one item per
+    // wavefront at a time on one CU (a check that no result depends on the
+    // order or concurrency of the work items)
+    int max_workgroups = 0;
 };
 
 // Per-pair plans and workspace offsets inside one arena.

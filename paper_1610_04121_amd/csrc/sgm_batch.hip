@@ -291,7 +291,7 @@ struct BatchStaging {
 BatchStaging* staging_create() {
     BatchStaging* st = new (std::nothrow) BatchStaging;
     if (!st) return nullptr;
-    if (hipMalloc((void**)&st->counter, 256) != hipSuccess ||
+    if (sgm::dev_malloc((void**)&st->counter, 256) != hipSuccess ||
         hipEventCreateWithFlags(&st->staged, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         staging_destroy(st);
@@ -335,8 +335,8 @@ int grow_staging(BatchStaging* b, size_t nitems, size_t nwork) {
         b->h_items = nullptr;
         b->d_items = nullptr;
         b->items_cap = 0;
-        if (hipHostMalloc((void**)&b->h_items, cap * sizeof(BatchItem), hipHostMallocDefault) != hipSuccess ||
-            hipMalloc((void**)&b->d_items, cap * sizeof(BatchItem)) != hipSuccess) {
+        if (sgm::pinned_malloc((void**)&b->h_items, cap * sizeof(BatchItem)) != hipSuccess ||
+            sgm::dev_malloc((void**)&b->d_items, cap * sizeof(BatchItem)) != hipSuccess) {
             (void)hipGetLastError();
             return berr(SGM_ENOMEM, "batch descriptor allocation failed");
         }
@@ -349,8 +349,8 @@ int grow_staging(BatchStaging* b, size_t nitems, size_t nwork) {
         b->h_work = nullptr;
         b->d_work = nullptr;
         b->work_cap = 0;
-        if (hipHostMalloc((void**)&b->h_work, cap * sizeof(WorkItem), hipHostMallocDefault) != hipSuccess ||
-            hipMalloc((void**)&b->d_work, cap * sizeof(WorkItem)) != hipSuccess) {
+        if (sgm::pinned_malloc((void**)&b->h_work, cap * sizeof(WorkItem)) != hipSuccess ||
+            sgm::dev_malloc((void**)&b->d_work, cap * sizeof(WorkItem)) != hipSuccess) {
             (void)hipGetLastError();
             return berr(SGM_ENOMEM, "batch work-queue allocation failed");
         }
@@ -451,7 +451,7 @@ int batch_build(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_bas
     std::stable_sort(work.begin(), work.end(), [](const WorkItem& a, const WorkItem& c) { return a.steps > c.steps; });
 
     // persistent grid: at most two wavefronts per SIMD (256 CUs x 4 SIMDs)
-    B.waves = std::min((int)work.size(), 2048);
+    B.waves = std::min((int)work.size(), bp.max_workgroups > 0 ? 4 * std::min(bp.max_workgroups, 512) : 2048);
     // the planes and cost volumes of the whole batch against the memory-side
     // cache: the store policy of the single-pair path (Plan::nt_store)
     long long fbytes = 0;
@@ -575,8 +575,8 @@ int api_hip(hipError_t e, const char* what) {
 // What a captured graph depends on besides pointers: the runner's kernel
 // shape and every item's size, range, path count and options.
 std::vector<long long> batch_signature(const sgm::BatchParams& bp, const sgm_item* items, int n) {
-    std::vector<long long> sig{n, bp.lanes_h, bp.lanes_v};
-    sig.reserve(3 + 5 * (size_t)n);
+    std::vector<long long> sig{n, bp.lanes_h, bp.lanes_v, bp.max_workgroups};
+    sig.reserve(4 + 5 * (size_t)n);
     for (int i = 0; i < n; ++i) {
         const sgm_item& it = items[i];
         sig.insert(sig.end(), {it.w, it.h, it.max_disp, it.n_paths, (long long)it.flags});
@@ -593,11 +593,11 @@ int graph_create(sgm_batch* b, const sgm::BatchLaunch& B, std::vector<long long>
     if (!g) return api_err(SGM_ENOMEM, "host allocation failed");
     g->sig = std::move(sig);
     const size_t nd = B.desc.size(), nw = B.work.size();
-    if (hipMalloc((void**)&g->d_items, nd * sizeof(BatchItem)) != hipSuccess ||
-        hipMalloc((void**)&g->d_work, nw * sizeof(WorkItem)) != hipSuccess ||
-        hipMalloc((void**)&g->counter, 256) != hipSuccess ||
-        hipHostMalloc((void**)&g->h_items, std::max(nd * sizeof(BatchItem), nw * sizeof(WorkItem)),
-                      hipHostMallocDefault) != hipSuccess ||
+    if (sgm::dev_malloc((void**)&g->d_items, nd * sizeof(BatchItem)) != hipSuccess ||
+        sgm::dev_malloc((void**)&g->d_work, nw * sizeof(WorkItem)) != hipSuccess ||
+        sgm::dev_malloc((void**)&g->counter, 256) != hipSuccess ||
+        sgm::pinned_malloc((void**)&g->h_items, std::max(nd * sizeof(BatchItem), nw * sizeof(WorkItem))) !=
+            hipSuccess ||
         hipEventCreateWithFlags(&g->copied, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         graph_free(g);
@@ -628,6 +628,7 @@ int graph_create(sgm_batch* b, const sgm::BatchLaunch& B, std::vector<long long>
         return api_hip(le != hipSuccess ? le : e, "batch graph capture");
     }
     *out = g;
+    sgm::log_event("batch graph captured: " + std::to_string(nd) + " items, " + std::to_string(nw) + " work items");
     return SGM_OK;
 }
 
@@ -727,6 +728,13 @@ int sgm_batch_set_tuning(sgm_batch* b, int lanes_h, int lanes_v) {
     return SGM_OK;
 }
 
+int sgm_batch_set_grid(sgm_batch* b, int max_workgroups) {
+    if (!b) return api_err(SGM_EINVAL, "null batch");
+    if (max_workgroups < 0) return api_err(SGM_EINVAL, "max_workgroups must be >= 0");
+    b->bp.max_workgroups = max_workgroups;
+    return SGM_OK;
+}
+
 int sgm_batch_set_graph(sgm_batch* b, int enable) {
     if (!b) return api_err(SGM_EINVAL, "null batch");
     if (enable != 0 && enable != 1) return api_err(SGM_EINVAL, "enable must be 0 or 1");
@@ -769,12 +777,13 @@ int sgm_batch_compute(sgm_batch* b, const sgm_item* items, int n, sgm_stream_t s
         if (b->arena) (void)hipFree(b->arena);
         b->arena = nullptr;
         b->arena_bytes = 0;
-        e = hipMalloc(&b->arena, L.total);
+        e = sgm::dev_malloc(&b->arena, L.total);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return api_err(SGM_ENOMEM, std::string("batch workspace allocation failed: ") + hipGetErrorString(e));
         }
         b->arena_bytes = L.total;
+        sgm::log_event("batch workspace grown to " + std::to_string(L.total) + " bytes");
     }
     std::vector<uint8_t*> bases(n);
     for (int i = 0; i < n; ++i) bases[i] = static_cast<uint8_t*>(b->arena) + L.offsets[i];

@@ -1,7 +1,9 @@
 // C ABI of the SGM library (declared in include/sgm.h).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <array>
 #include <new>
@@ -14,16 +16,63 @@
 
 namespace {
 thread_local std::string g_err;
+
+// SGM_LOG: 0 (default) quiet, 1 every error message on stderr as it is set,
+// 2 also resource events (workspace growth, graph captures).
+int log_level() {
+    static const int level = [] {
+        const char* v = std::getenv("SGM_LOG");
+        return v ? std::atoi(v) : 0;
+    }();
+    return level;
+}
+
+// allocation-failure hook: the next g_alloc_pass allocations succeed, the
+// g_alloc_fail after them fail
+std::atomic<long long> g_alloc_pass{0}, g_alloc_fail{0};
+
+bool alloc_hook_fails() {
+    long long f = g_alloc_fail.load();
+    if (f <= 0) return false;
+    for (long long p = g_alloc_pass.load(); p > 0;)
+        if (g_alloc_pass.compare_exchange_weak(p, p - 1)) return false;
+    for (; f > 0;)
+        if (g_alloc_fail.compare_exchange_weak(f, f - 1)) return true;
+    return false;
+}
 }  // namespace
 
 namespace sgm {
-void set_last_error(const std::string& msg) { g_err = msg; }
+void set_last_error(const std::string& msg) {
+    g_err = msg;
+    if (log_level() >= 1 && !msg.empty()) std::fprintf(stderr, "sgm: error: %s\n", msg.c_str());
+}
+
+void log_event(const std::string& msg) {
+    if (log_level() >= 2) std::fprintf(stderr, "sgm: %s\n", msg.c_str());
+}
+
+hipError_t dev_malloc_bytes(void** p, size_t bytes) {
+    if (alloc_hook_fails()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+hipError_t pinned_malloc_bytes(void** p, size_t bytes) {
+    if (alloc_hook_fails()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
 }  // namespace sgm
 
 namespace {
 
 int set_err(int code, const std::string& msg) {
-    g_err = msg;
+    sgm::set_last_error(msg);
     return code;
 }
 
@@ -105,6 +154,12 @@ extern "C" {
 
 const char* sgm_last_error(void) { return g_err.c_str(); }
 
+void sgm_debug_fail_alloc(int after, int count) {
+    g_alloc_fail.store(0);
+    g_alloc_pass.store(after > 0 ? after : 0);
+    g_alloc_fail.store(count > 0 ? count : 0);
+}
+
 int sgm_validate(int width, int height, int max_disp, int P1, int P2, int n_paths, int census_w,
                  int census_h, unsigned flags) {
     sgm::Plan p;
@@ -142,7 +197,7 @@ sgm_ctx* sgm_create(int width, int height, int max_disp, int P1, int P2, int n_p
     sgm::Plan big = p;
     big.l16 = true;
     c->mem_bytes = sgm::workspace_bytes(big);
-    e = hipMalloc(&c->mem, c->mem_bytes);
+    e = sgm::dev_malloc(&c->mem, c->mem_bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         set_err(SGM_ENOMEM, std::string("hipMalloc of workspace failed: ") + hipGetErrorString(e));
@@ -172,7 +227,7 @@ int sgm_set_options(sgm_ctx* c, unsigned flags, int lr_threshold) {
         hipError_t e = hipDeviceSynchronize();  // the old workspace may still be in use
         if (e != hipSuccess) return hip_err(e, "hipDeviceSynchronize");
         void* mem = nullptr;
-        e = hipMalloc(&mem, need);
+        e = sgm::dev_malloc(&mem, need);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return set_err(SGM_ENOMEM, std::string("hipMalloc of workspace failed: ") + hipGetErrorString(e));
@@ -180,6 +235,7 @@ int sgm_set_options(sgm_ctx* c, unsigned flags, int lr_threshold) {
         (void)hipFree(c->mem);
         c->mem = mem;
         c->mem_bytes = need;
+        sgm::log_event("context workspace grown to " + std::to_string(need) + " bytes");
     }
     c->plan = p;
     c->ws = sgm::workspace_carve(p, c->mem);
@@ -307,6 +363,7 @@ int sgm_compute(sgm_ctx* c, const uint8_t* left, const uint8_t* right, uint16_t*
                 c->graphs.pop_back();
             }
             c->graphs.insert(c->graphs.begin(), {left, right, disp_out, exec});
+            sgm::log_event("pipeline graph captured (" + std::to_string(c->graphs.size()) + " cached)");
             i = 0;
         } else if (i > 0) {
             std::swap(c->graphs[i], c->graphs[0]);

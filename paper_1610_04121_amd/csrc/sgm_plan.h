@@ -60,6 +60,21 @@ bool plan_from_options(Plan& p, int w, int h, int d, int P1, int P2, int n_paths
                        int thr);
 // Message returned by sgm_last_error on this thread.
 void set_last_error(const std::string& msg);
+// Resource events (workspace growth, graph captures) on stderr when SGM_LOG >= 2.
+void log_event(const std::string& msg);
+// Every device and pinned host allocation of the library goes through these:
+// hipMalloc / hipHostMalloc, unless the allocation-failure hook
+// (sgm_debug_fail_alloc) says this one fails (hipErrorOutOfMemory).
+hipError_t dev_malloc_bytes(void** p, size_t bytes);
+hipError_t pinned_malloc_bytes(void** p, size_t bytes);
+template <typename T>
+inline hipError_t dev_malloc(T** p, size_t bytes) {
+    return dev_malloc_bytes(reinterpret_cast<void**>(p), bytes);
+}
+template <typename T>
+inline hipError_t pinned_malloc(T** p, size_t bytes) {
+    return pinned_malloc_bytes(reinterpret_cast<void**>(p), bytes);
+}
 size_t workspace_bytes(const Plan& p);
 // Carves a workspace out of one device allocation of workspace_bytes(p).
 Workspace workspace_carve(const Plan& p, void* base);

@@ -321,7 +321,7 @@ sgm_server* sgm_server_create_ex(size_t hbm_budget_bytes, int max_slots, int n_s
     s->device = dev;
     s->bp = sgm::BatchParams{P1, P2, census_w, census_h, false};
     s->budget = hbm_budget_bytes & ~(size_t)255;
-    e = hipMalloc(&s->arena, s->budget);
+    e = sgm::dev_malloc(&s->arena, s->budget);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         serr(SGM_ENOMEM, std::string("server workspace allocation failed: ") + hipGetErrorString(e));

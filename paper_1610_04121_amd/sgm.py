@@ -27,7 +27,7 @@ EXPORTS = [
     "sgm_server_create", "sgm_server_set_policy", "sgm_server_request_bytes", "sgm_server_submit",
     "sgm_server_poll", "sgm_server_wait", "sgm_server_cancel", "sgm_server_get_stats", "sgm_server_destroy",
     "sgm_server_create_ex", "sgm_debug_phase_sums", "sgm_compute_noalloc", "sgm_batch_set_tuning",
-    "sgm_batch_set_graph",
+    "sgm_batch_set_graph", "sgm_debug_fail_alloc", "sgm_batch_set_grid",
 ]
 NOALLOC_MAX_BYTES = 256 << 20
 
@@ -115,6 +115,10 @@ def lib() -> ctypes.CDLL:
     L.sgm_batch_set_tuning.restype = i
     L.sgm_batch_set_graph.argtypes = [P, i]
     L.sgm_batch_set_graph.restype = i
+    L.sgm_debug_fail_alloc.argtypes = [i, i]
+    L.sgm_debug_fail_alloc.restype = None
+    L.sgm_batch_set_grid.argtypes = [P, i]
+    L.sgm_batch_set_grid.restype = i
     L.sgm_batch_destroy.argtypes = [P]
     L.sgm_batch_destroy.restype = None
     L.sgm_compute_batch.argtypes = [ctypes.POINTER(Item), i, i, i, i, i, P]
@@ -398,6 +402,11 @@ class Batch:
         if graph:
             self.set_graph(True)
 
+    def set_grid(self, max_workgroups: int):
+        """Workgroups of the persistent aggregation grid (sgm_batch_set_grid;
+        0 = fill the device, 1 = one CU takes the queue)."""
+        _check(lib().sgm_batch_set_grid(self._b, max_workgroups))
+
     def set_graph(self, enable: bool):
         """Replay a captured hipGraph per batch signature (sgm_batch_set_graph)."""
         _check(lib().sgm_batch_set_graph(self._b, 1 if enable else 0))
@@ -505,3 +514,9 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def debug_fail_alloc(after: int, count: int):
+    """Allocation-failure hook (sgm_debug_fail_alloc): the next ``after``
+    library allocations succeed and the ``count`` after them fail."""
+    lib().sgm_debug_fail_alloc(after, count)

@@ -388,3 +388,32 @@ def test_batch_graph_workload_matches_oracle_digests(gpu, key, post):
             assert hashlib.sha256(p["np_left"].tobytes()).hexdigest() == gd["sha_left"], k
             assert hashlib.sha256(p["out"].cpu().numpy().tobytes()).hexdigest() == gd["out_sha256"], (rep, k)
     g.close()
+
+
+def test_batch_one_workgroup_grid_matches(gpu):
+    """The persistent aggregation grid cut to one workgroup (one CU takes the
+    whole queue) gives the same results as the full grid: no result depends
+    on the order or concurrency of the work items."""
+    import torch
+    specs = [(64, 48, 40, 4, True, True), (97, 31, 64, 8, False, True), (40, 70, 130, 2, True, True),
+             (33, 33, 200, 8, True, False)]
+    opts = [(True, False), (False, True), (True, True), (False, False)]  # (lr_full, adaptive)
+    pairs = _pairs(specs, gpu, 2700)
+    for p, (lf, ad) in zip(pairs, opts):
+        p["lr_full"], p["adaptive_p2"] = lf and p["lrcheck"], ad
+    b = Batch(7, 86)
+    b.compute(pairs)
+    torch.cuda.synchronize()
+    full = [p["out"].cpu().numpy() for p in pairs]
+    _say("batch with a one-workgroup aggregation grid")
+    b.set_grid(1)
+    for p in pairs:
+        p["out"].fill_(0xABC)
+    b.compute(pairs)
+    torch.cuda.synchronize()
+    for k, p in enumerate(pairs):
+        assert (p["out"].cpu().numpy() == full[k]).all(), k
+        want = oracle.sgm(p["np_left"], p["np_right"], p["max_disp"], 7, 86, p["n_paths"], median=p["median"],
+                          lr=p["lrcheck"], lr_full=p["lr_full"], adaptive=p["adaptive_p2"]).out
+        assert (full[k] == want).all(), k
+    b.close()
