@@ -466,7 +466,7 @@ def _serve_level(srv, specs, pool, outs, qps, n_req, n_warm, rng):
     total = n_warm + n_req
     arrivals = np.cumsum(rng.exponential(1.0 / qps, total))
     which = rng.integers(0, len(specs), total)
-    cells = np.array([k["w"] * k["h"] * k["max_disp"] * 8 for k in specs], dtype=np.float64)
+    cells = np.array([k["w"] * k["h"] * k["max_disp"] * k["n_paths"] for k in specs], dtype=np.float64)
     outstanding = collections.deque()  # (index, kind, ticket, buffer) in submission order
     lat, done_at, rejected = {}, {}, 0
 
@@ -505,8 +505,8 @@ def _serve_level(srv, specs, pool, outs, qps, n_req, n_warm, rng):
         k = int(which[i])
         buf = outs.take(k, wait_oldest)
         left, right = pool[k]
-        req = dict(left=left, right=right, out=buf, max_disp=specs[k]["max_disp"], n_paths=8, median=True,
-                   lrcheck=True, lr_threshold=1)
+        req = dict(left=left, right=right, out=buf, max_disp=specs[k]["max_disp"], n_paths=specs[k]["n_paths"],
+                   median=True, lrcheck=True, lr_threshold=1)
         try:
             outstanding.append((i, k, srv.submit(req), buf))
         except SGMError as e:
@@ -532,7 +532,7 @@ def _plain_level(ctxs, specs, pool, outs, arrivals, which, st):
     """The same arrival times through plain per-request launches: one context
     per kind, one stream, each request synchronised before the next starts."""
     import numpy as np
-    cells = np.array([k["w"] * k["h"] * k["max_disp"] * 8 for k in specs], dtype=np.float64)
+    cells = np.array([k["w"] * k["h"] * k["max_disp"] * k["n_paths"] for k in specs], dtype=np.float64)
     t0 = time.perf_counter() + 0.005
     plat = []
     for i in range(len(arrivals)):
@@ -550,6 +550,45 @@ def _plain_level(ctxs, specs, pool, outs, arrivals, which, st):
             "p99_ms": round(float(np.percentile(plat, 99)) * 1e3, 3),
             "frames_per_s": round(len(plat) / span, 1),
             "gcells_per_s": round(float(cells[which].sum()) / span / 1e9, 1)}
+
+
+def bench_serve_small(dev, qps: float = 80000.0, seconds: float = 1.5, warmup: int = 100, slots: int = 4,
+                      streams: int = 4, overlap_queue: int = 3, seed: int = 1610041215):
+    """Grouping where it can pay: Poisson arrivals of small requests (4 paths,
+    median + LR, 160x120 to 320x240, D 32 or 64, the road scene scaled to
+    D), offered past what ungrouped serving sustains, with groups of up to
+    1, 8 and 32 requests (no cell limit) and with the server's default
+    policy; frames/s and latency per policy."""
+    import numpy as np
+    import torch
+
+    from paper_1610_04121_amd import synth
+    from paper_1610_04121_amd.sgm import Server
+    specs = []
+    for k, ((w, h), d) in enumerate((s_, d_) for s_ in ((320, 240), (256, 192), (160, 120)) for d_ in (32, 64)):
+        specs.append(dict(w=w, h=h, max_disp=d, n_paths=4, scene="K", scale_to_d=True, seed=seed * 100 + k))
+    pool = []
+    for k in specs:
+        pr = synth.spec_pair(k)
+        pool.append((torch.from_numpy(pr.left).to(dev), torch.from_numpy(pr.right).to(dev)))
+    outs = _OutPool(dev, specs, per_kind=4096)
+    trials = {}
+    for name in ("1", "8", "32", "default"):
+        if name == "default":
+            srv = Server(16 << 30, slots=slots, streams=streams, max_pending=1 << 16, overlap_queue=overlap_queue)
+        else:
+            srv = Server(16 << 30, slots=slots, streams=streams, max_group=int(name), max_pending=1 << 16,
+                         max_group_cells=1 << 62, overlap_queue=overlap_queue)
+        res, _, _ = _serve_level(srv, specs, pool, outs, qps, int(seconds * qps), warmup,
+                                 np.random.default_rng(seed + 1))
+        srv.close()
+        trials[name] = res
+        print(f"bench: small-request serve max_group={name} at {qps}/s: {res['frames_per_s']} frames/s, "
+              f"p99 {res['p99_ms']} ms, mean group {res['mean_group']}", file=sys.stderr, flush=True)
+    return {"offered_qps": qps, "requests": int(seconds * qps), "by_max_group": trials,
+            "default_policy": {"max_group": 32, "max_group_cells": 1 << 28},
+            "mix": "Poisson arrivals; sizes from {320x240, 256x192, 160x120}, D from {32, 64}, 4 paths, median + "
+                   "LR check, road scene scaled to D", "slots": slots, "streams": streams}
 
 
 def bench_serve(dev, qps_levels, min_requests: int = 1000, per_qps_s: float = 10.0, warmup: int = 100,
@@ -894,6 +933,8 @@ def main():
         line["served"] = bench_serve(dev, [float(q) for q in args.serve_qps.split(",")], args.serve_min_requests,
                                      args.serve_seconds, slots=args.serve_slots, streams=args.serve_streams,
                                      overlap_queue=args.serve_overlap_queue)
+        line["served_small_grouping"] = bench_serve_small(dev, slots=args.serve_slots, streams=args.serve_streams,
+                                                          overlap_queue=args.serve_overlap_queue)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(pair, cfg)

@@ -301,10 +301,11 @@ sgm_server *sgm_server_create_ex(size_t hbm_budget_bytes, int max_slots, int n_s
                                  int census_w, int census_h);
 
 /* Group limits, queue length and overlap.  A group takes at most max_group
- * requests (default 8, at most 256) and, unless it holds a single request,
+ * requests (default 32, at most 256) and, unless it holds a single request,
  * at most max_group_cells cells in total (W * H * max_disp * n_paths summed
  * over its requests; default 2^28): requests that fill the device alone run
- * alone.  The queue accepts at most max_pending requests (default 4096).
+ * alone (grouping them measured slower), small ones run in groups (faster
+ * once the requests' launches outpace the device).  The queue accepts at most max_pending requests (default 4096).
  * While a group runs, a second one starts beside it only when at least
  * overlap_queue requests are queued (default 3; 1 = whenever a slot is
  * free): at light load a request waits for the running one rather than

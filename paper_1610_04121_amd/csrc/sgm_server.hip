@@ -122,7 +122,7 @@ struct sgm_server {
     std::deque<Request*> pending;
     std::unordered_map<uint64_t, Request*> live;  // every ticket not yet retired
     uint64_t next_ticket = 1;
-    int max_group = 8;
+    int max_group = 32;
     size_t max_pending = 4096;
     uint64_t max_group_cells = uint64_t(1) << 28;
     // while a group runs, another one starts beside it only if at least this

@@ -452,7 +452,7 @@ class Server:
     referenced here until the request reaches a final state."""
 
     def __init__(self, hbm_budget_bytes: int, slots: int = 4, streams: int | None = None, P1=7, P2=86,
-                 census_w=9, census_h=7, max_group: int = 8, max_pending: int = 4096,
+                 census_w=9, census_h=7, max_group: int = 32, max_pending: int = 4096,
                  max_group_cells: int = 1 << 28, overlap_queue: int = 3):
         """streams defaults to one per slot (groups run concurrently)."""
         if streams is None:
@@ -464,7 +464,7 @@ class Server:
         self._held = {}
         self.set_policy(max_group, max_pending, max_group_cells, overlap_queue)
 
-    def set_policy(self, max_group: int = 8, max_pending: int = 4096, max_group_cells: int = 1 << 28,
+    def set_policy(self, max_group: int = 32, max_pending: int = 4096, max_group_cells: int = 1 << 28,
                    overlap_queue: int = 3):
         _check(lib().sgm_server_set_policy(self._s, max_group, max_pending, max_group_cells, overlap_queue))
 
