@@ -1309,7 +1309,7 @@ __device__ inline void wta_cells(const WtaArgs& a, int y, int x, int g, int G, c
 
 __device__ inline void wta_fold_post(const WtaArgs& a, int y, uint16_t* rview);
 
-template <typename LT, int NPL, bool NT>
+template <typename LT, int NPL, bool NT, bool FOLD>
 __device__ inline void wta_row_impl(const WtaArgs& a, int y, uint32_t* keyR_smem) {
     uint32_t* keyR = keyR_smem + kWtaGuard;  // keyR[t], t in [-kWtaGuard, W)
     const bool right = a.dr != nullptr;
@@ -1332,21 +1332,23 @@ __device__ inline void wta_row_impl(const WtaArgs& a, int y, uint32_t* keyR_smem
         for (int i = threadIdx.x; i < a.W; i += blockDim.x)
             a.dr[(size_t)y * a.W + i] = (uint16_t)(keyR[i] & 0xFF);
     }
-    if (a.rowcnt) wta_fold_post(a, y, reinterpret_cast<uint16_t*>(keyR_smem));
+    if constexpr (FOLD) wta_fold_post(a, y, reinterpret_cast<uint16_t*>(keyR_smem));
 }
 
 // One row of the WTA; the plane count (2, 4 or 8) is a template constant of
 // the row's code, so the plane loads unroll.  NT: non-temporal plane loads,
 // for planes that exceed the memory-side cache and were stored
-// non-temporally.
-template <typename LT, bool NT = false>
+// non-temporally.  FOLD: the post stage runs inside the launch (a.rowcnt
+// set; wta_fold_post), a separate instantiation so that the plain kernel
+// keeps its registers.
+template <typename LT, bool NT = false, bool FOLD = false>
 __device__ inline void wta_row(const WtaArgs& a, int y, uint32_t* keyR_smem) {
     if (a.nplanes == 2)
-        wta_row_impl<LT, 2, NT>(a, y, keyR_smem);
+        wta_row_impl<LT, 2, NT, FOLD>(a, y, keyR_smem);
     else if (a.nplanes == 4)
-        wta_row_impl<LT, 4, NT>(a, y, keyR_smem);
+        wta_row_impl<LT, 4, NT, FOLD>(a, y, keyR_smem);
     else
-        wta_row_impl<LT, 8, NT>(a, y, keyR_smem);
+        wta_row_impl<LT, 8, NT, FOLD>(a, y, keyR_smem);
 }
 
 // ---------------------------------------------------------------------------

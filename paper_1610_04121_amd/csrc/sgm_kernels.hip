@@ -99,23 +99,23 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggArgs a) {
     }
 }
 
-template <typename LT, bool NT>
+template <typename LT, bool NT, bool FOLD>
 __global__ __launch_bounds__(1024) void wta_kernel(WtaArgs a) {
     extern __shared__ uint32_t wta_smem[];
-    wta_row<LT, NT>(a, blockIdx.x, wta_smem);
+    wta_row<LT, NT, FOLD>(a, blockIdx.x, wta_smem);
 }
 
 // Winner-take-all of two SGMs in one launch (full left-right check): rows
 // 0 .. H-1 of the left-base sums give D_L, blocks H .. 2H-1 the rows of the
 // right-base sums, D_R.
-template <typename LT, bool NT>
+template <typename LT, bool NT, bool FOLD>
 __global__ __launch_bounds__(1024) void wta_pair_kernel(WtaArgs l, WtaArgs r) {
     extern __shared__ uint32_t wta_smem[];
     const int y = blockIdx.x;
     if (y < l.H)
-        wta_row<LT, NT>(l, y, wta_smem);
+        wta_row<LT, NT, FOLD>(l, y, wta_smem);
     else
-        wta_row<LT, NT>(r, y - l.H, wta_smem);
+        wta_row<LT, NT, FOLD>(r, y - l.H, wta_smem);
 }
 
 // The final pass (see final_pass_block): NPL = n_paths - 1 stored planes;
@@ -487,8 +487,10 @@ hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStre
             }
             smem = 2 * (size_t)p.W;  // the post stage's D_R medians
         }
-        auto k = p.l16 ? (nt ? wta_pair_kernel<uint16_t, true> : wta_pair_kernel<uint16_t, false>)
-                       : (nt ? wta_pair_kernel<uint8_t, true> : wta_pair_kernel<uint8_t, false>);
+        auto k = fold ? (p.l16 ? (nt ? wta_pair_kernel<uint16_t, true, true> : wta_pair_kernel<uint16_t, false, true>)
+                               : (nt ? wta_pair_kernel<uint8_t, true, true> : wta_pair_kernel<uint8_t, false, true>))
+                      : (p.l16 ? (nt ? wta_pair_kernel<uint16_t, true, false> : wta_pair_kernel<uint16_t, false, false>)
+                               : (nt ? wta_pair_kernel<uint8_t, true, false> : wta_pair_kernel<uint8_t, false, false>));
         hipLaunchKernelGGL(k, dim3(2 * p.H), dim3(1024), smem, stream, l, r);
         return hipGetLastError();
     }
@@ -502,8 +504,10 @@ hipError_t launch_wta(const Plan& p, const Workspace& ws, uint16_t* out, hipStre
     const size_t smem = p.lrcheck ? 4 * (size_t)(p.W + kWtaGuard) : 0;
     // the planes are read the way they were stored: non-temporally when they
     // exceed the memory-side cache and the aggregation stored them so
-    auto k = p.l16 ? (nt ? wta_kernel<uint16_t, true> : wta_kernel<uint16_t, false>)
-                   : (nt ? wta_kernel<uint8_t, true> : wta_kernel<uint8_t, false>);
+    auto k = fold ? (p.l16 ? (nt ? wta_kernel<uint16_t, true, true> : wta_kernel<uint16_t, false, true>)
+                           : (nt ? wta_kernel<uint8_t, true, true> : wta_kernel<uint8_t, false, true>))
+                  : (p.l16 ? (nt ? wta_kernel<uint16_t, true, false> : wta_kernel<uint16_t, false, false>)
+                           : (nt ? wta_kernel<uint8_t, true, false> : wta_kernel<uint8_t, false, false>));
     hipLaunchKernelGGL(k, dim3(p.H), dim3(1024), smem, stream, a);
     return hipGetLastError();
 }

@@ -40,6 +40,7 @@ int oracle_direction(int n_paths, int index, int *rx, int *ry);
 /* oracle flag bits (oracle/sgm_oracle.c) */
 #define ORC_MEDIAN 1u
 #define ORC_LRCHECK 2u
+#define ORC_LRFULL 8u
 
 /* a blurred-noise pair shifted by `s` pixels, from a 32-bit LCG */
 static void make_pair(uint8_t *l, uint8_t *r, int W, int H, int s, uint32_t seed)
@@ -64,7 +65,8 @@ static void make_pair(uint8_t *l, uint8_t *r, int W, int H, int s, uint32_t seed
 
 static unsigned oracle_flags(unsigned flags)
 {
-    return ((flags & SGM_MEDIAN3) ? ORC_MEDIAN : 0u) | ((flags & SGM_LRCHECK) ? ORC_LRCHECK : 0u);
+    return ((flags & SGM_MEDIAN3) ? ORC_MEDIAN : 0u) | ((flags & SGM_LRCHECK) ? ORC_LRCHECK : 0u) |
+           ((flags & SGM_LR_FULL) ? ORC_LRFULL : 0u);
 }
 
 /* One pair on the device: images in, output buffer, host copies. */
@@ -207,6 +209,37 @@ static int run_batch(hipStream_t st)
     return bad != 0;
 }
 
+/* A batch runner replaying a captured graph, twice, the second time into
+ * freshly cleared outputs. */
+static int run_batch_graph(hipStream_t st)
+{
+    pair_t p[2];
+    if (pair_setup(&p[0], 70, 44, 40, 4, SGM_MEDIAN3 | SGM_LRCHECK, 31u)) return 1;
+    if (pair_setup(&p[1], 45, 60, 64, 8, SGM_LRCHECK | SGM_LR_FULL, 32u)) return 1;
+    sgm_item items[2];
+    for (int k = 0; k < 2; k++) {
+        sgm_item it = {p[k].W, p[k].H, p[k].D, p[k].paths, p[k].flags, p[k].dl, p[k].dr, p[k].dout};
+        items[k] = it;
+    }
+    sgm_batch *b = sgm_batch_create(7, 86, 9, 7);
+    CHECK(b != NULL, "sgm_batch_create");
+    CHECK(sgm_batch_set_graph(b, 2) == SGM_EINVAL, "graph flag out of range");
+    CHECK(sgm_batch_set_graph(b, 1) == SGM_OK, "sgm_batch_set_graph");
+    long bad = 0;
+    for (int rep = 0; rep < 2; rep++) {
+        for (int k = 0; k < 2; k++)
+            CHECK(hipMemsetAsync(p[k].dout, 0xAB, (size_t)p[k].W * p[k].H * 2, st) == hipSuccess, "clear");
+        CHECK(sgm_batch_compute(b, items, 2, (sgm_stream_t)st) == SGM_OK, "sgm_batch_compute (graph)");
+        for (int k = 0; k < 2; k++) {
+            long d = pair_diff(&p[k], "sgm_batch_compute (graph)");
+            bad += d < 0 ? 1 : d;
+        }
+    }
+    sgm_batch_destroy(b);
+    for (int k = 0; k < 2; k++) pair_free(&p[k]);
+    return bad != 0;
+}
+
 /* A server with two slots: two requests, waited for by polling. */
 static int run_server(void)
 {
@@ -257,6 +290,13 @@ int main(void)
     sgm_destroy(NULL);
     CHECK(sgm_server_create(1 << 20, 0, 7, 86, 9, 7) == NULL, "server with no slot");
     sgm_server_destroy(NULL);
+    /* a forced allocation failure: no context, a message, then recovery */
+    sgm_debug_fail_alloc(0, 1);
+    CHECK(sgm_create(32, 16, 8, 7, 86, 4, 9, 7) == NULL && strlen(sgm_last_error()) > 0, "forced failure");
+    sgm_debug_fail_alloc(0, 0);
+    c = sgm_create(32, 16, 8, 7, 86, 4, 9, 7);
+    CHECK(c != NULL, "create after the forced failure");
+    sgm_destroy(c);
 
     int fails = 0;
     fails += run_single(160, 90, 48, 4, 0, st);
@@ -264,6 +304,7 @@ int main(void)
     fails += run_single(97, 31, 20, 2, SGM_LRCHECK, st);
     fails += run_taps(st);
     fails += run_batch(st);
+    fails += run_batch_graph(st);
     fails += run_server();
     CHECK(hipStreamDestroy(st) == hipSuccess, "hipStreamDestroy");
     if (fails) {
