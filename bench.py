@@ -327,7 +327,7 @@ def bench_variant(left, right, cfg, tuning, steps: int, warmup: int = 50, **opts
     for _ in range(warmup):
         c.compute(left, right, o, stream=st)
     torch.cuda.synchronize()
-    c.profile(True, every=8)
+    c.profile(True, every=32)
     t0 = time.perf_counter()
     for _ in range(steps):
         c.compute(left, right, o, stream=st)
@@ -809,20 +809,43 @@ def main():
                 c.compute(left, right, outs[0], stream=st0)
             torch.cuda.synchronize()
             extras[mode] = round((args.steps // 2) / (time.perf_counter() - ta), 2)
+            # single frames between two events, each waited for (the events
+            # themselves leave the device idle a few microseconds)
+            lat = []
+            for _ in range(args.latency_samples):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(st0)
+                c.compute(left, right, outs[0], stream=st0)
+                e1.record(st0)
+                e1.synchronize()
+                lat.append(e0.elapsed_time(e1))
+            lat = np.array(lat)
+            extras["latency_ms" if mode == "graph" else "latency_ms_eager"] = {
+                "p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
+                "mode": ("graph replay" if mode == "graph" else "direct launches") + ", one frame in flight",
+                "samples": len(lat)}
             if mode == "graph":
-                lat = []
-                for _ in range(args.latency_samples):
-                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    e0.record(st0)
-                    c.compute(left, right, outs[0], stream=st0)
-                    e1.record(st0)
-                    e1.synchronize()
-                    lat.append(e0.elapsed_time(e1))
-                lat = np.array(lat)
-                extras["latency_ms"] = {"p50": round(float(np.percentile(lat, 50)), 4),
-                                        "p99": round(float(np.percentile(lat, 99)), 4),
-                                        "mode": "graph replay, one frame in flight"}
                 c.close()
+        # the packed-u16 VALU rate the aggregation is compared with: the probe
+        # issues 16 VALU instructions per wave per round (4 waves per block)
+        from paper_1610_04121_amd.sgm import valu_probe
+        pb, pit = 8192, 2048
+        sink = torch.zeros(pb * 256, dtype=torch.int32, device=dev)
+        for _ in range(2):
+            valu_probe(pb, pit, sink)
+        pe0, pe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        pe0.record()
+        for _ in range(5):
+            valu_probe(pb, pit, sink)
+        pe1.record()
+        pe1.synchronize()
+        inst_s = 5 * pb * 4 * pit * 16 / (pe0.elapsed_time(pe1) * 1e-3)
+        nominal = 1024 * 2.4e9 / 4  # one wave64 instruction per SIMD per 4 cycles at 2.4 GHz
+        extras["valu_probe"] = {"wave_instr_per_s": round(inst_s / 1e9, 1), "unit": "G wave64 VALU instr/s",
+                                "nominal_peak": round(nominal / 1e9, 1), "frac_of_nominal": round(inst_s / nominal, 4),
+                                "packed_u16_tops": round(inst_s * 64 * 2 / 1e12, 1),
+                                "kernel": "valu_probe_kernel: 8 independent v_pk_add_u16 + v_pk_min_u16 pairs per round"}
+        del sink
         # achievable HBM bandwidth: a timed device-to-device copy of 512 MiB
         nb = 512 << 20
         csrc = torch.empty(nb, dtype=torch.uint8, device=dev)
@@ -902,7 +925,9 @@ def main():
     }
     if extras:
         line["serialized_fps"] = {"eager": extras["eager"], "graph": extras["graph"]}
+        line["valu_probe"] = extras["valu_probe"]
         line["latency_ms"] = extras["latency_ms"]
+        line["latency_ms_eager"] = extras["latency_ms_eager"]
         line["paths_sweep"] = bench_paths(left, right, cfg, max(200, args.steps // 4))
         line["lr_full"] = bench_variant(left, right, cfg, choice, max(200, args.steps // 4), lr_full=True)
         line["subpixel"] = bench_variant(left, right, cfg, choice, max(200, args.steps // 4), subpixel=True)

@@ -468,6 +468,14 @@ int sgm_debug_raw_disparity(sgm_ctx* c, const uint8_t* left, const uint8_t* righ
     return SGM_OK;
 }
 
+int sgm_debug_valu_probe(int blocks, int iters, uint32_t* sink, sgm_stream_t stream) {
+    if (blocks < 1 || blocks > (1 << 20) || iters < 1) return set_err(SGM_EINVAL, "blocks in [1, 2^20], iters >= 1");
+    if (!sink) return set_err(SGM_EINVAL, "null buffer pointer");
+    hipError_t e = sgm::launch_valu_probe(blocks, iters, sink, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_err(e, "kernel launch");
+    return SGM_OK;
+}
+
 int sgm_path_walk(int width, int height, int rx, int ry, int slice, int max_steps, int* xs, int* ys,
                   uint8_t* restart) {
     if (width < 1 || height < 1 || rx < -1 || rx > 1 || ry < -1 || ry > 1 || (rx == 0 && ry == 0))

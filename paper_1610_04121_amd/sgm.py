@@ -27,7 +27,7 @@ EXPORTS = [
     "sgm_server_create", "sgm_server_set_policy", "sgm_server_request_bytes", "sgm_server_submit",
     "sgm_server_poll", "sgm_server_wait", "sgm_server_cancel", "sgm_server_get_stats", "sgm_server_destroy",
     "sgm_server_create_ex", "sgm_debug_phase_sums", "sgm_compute_noalloc", "sgm_batch_set_tuning",
-    "sgm_batch_set_graph", "sgm_debug_fail_alloc", "sgm_batch_set_grid",
+    "sgm_batch_set_graph", "sgm_debug_fail_alloc", "sgm_batch_set_grid", "sgm_debug_valu_probe",
 ]
 NOALLOC_MAX_BYTES = 256 << 20
 
@@ -119,6 +119,8 @@ def lib() -> ctypes.CDLL:
     L.sgm_debug_fail_alloc.restype = None
     L.sgm_batch_set_grid.argtypes = [P, i]
     L.sgm_batch_set_grid.restype = i
+    L.sgm_debug_valu_probe.argtypes = [i, i, P, P]
+    L.sgm_debug_valu_probe.restype = i
     L.sgm_batch_destroy.argtypes = [P]
     L.sgm_batch_destroy.restype = None
     L.sgm_compute_batch.argtypes = [ctypes.POINTER(Item), i, i, i, i, i, P]
@@ -520,3 +522,10 @@ def debug_fail_alloc(after: int, count: int):
     """Allocation-failure hook (sgm_debug_fail_alloc): the next ``after``
     library allocations succeed and the ``count`` after them fail."""
     lib().sgm_debug_fail_alloc(after, count)
+
+
+def valu_probe(blocks: int, iters: int, sink, stream=None):
+    """Enqueues the packed-u16 VALU throughput probe (sgm_debug_valu_probe):
+    16 VALU instructions per wave per round, 4 waves per block; ``sink`` is
+    a device uint32 tensor of blocks * 256 elements."""
+    _check(lib().sgm_debug_valu_probe(blocks, iters, _ptr(sink, "torch.int32", (blocks * 256,)), _stream(stream)))

@@ -201,3 +201,12 @@ def test_noalloc_rejects_oversized_and_invalid_calls_before_the_gpu():
                                  None) == sgm.SGM_EINVAL
     assert L.sgm_compute_noalloc(64, 48, 32, 7, 86, 4, 9, 7, 0, 1, buf, buf, buf, None) == sgm.SGM_EINVAL
     assert sgm.NOALLOC_MAX_BYTES == 256 << 20
+
+
+def test_valu_probe_validates_before_launching(lib):
+    from paper_1610_04121_amd import sgm
+    assert lib.sgm_debug_valu_probe(0, 16, None, None) == sgm.SGM_EINVAL
+    assert "blocks" in sgm.last_error()
+    assert lib.sgm_debug_valu_probe(4, 0, None, None) == sgm.SGM_EINVAL
+    assert lib.sgm_debug_valu_probe(4, 16, None, None) == sgm.SGM_EINVAL
+    assert "null" in sgm.last_error()
