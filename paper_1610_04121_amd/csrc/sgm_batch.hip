@@ -657,8 +657,8 @@ int batch_replay(sgm_batch* b, const sgm::BatchLayout& L, uint8_t* const* bases,
             b->graphs.pop_back();
         }
         b->graphs.insert(b->graphs.begin(), g);
-    } else if (i > 0) {
-        std::swap(b->graphs[i], b->graphs[0]);
+    } else if (i > 0) {  // to the front, keeping the others in order
+        std::rotate(b->graphs.begin(), b->graphs.begin() + i, b->graphs.begin() + i + 1);
     }
     BatchGraph* g = b->graphs[0];
     const size_t bytes = B.desc.size() * sizeof(BatchItem);

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <array>
 #include <new>
 #include <string>
@@ -365,8 +366,8 @@ int sgm_compute(sgm_ctx* c, const uint8_t* left, const uint8_t* right, uint16_t*
             c->graphs.insert(c->graphs.begin(), {left, right, disp_out, exec});
             sgm::log_event("pipeline graph captured (" + std::to_string(c->graphs.size()) + " cached)");
             i = 0;
-        } else if (i > 0) {
-            std::swap(c->graphs[i], c->graphs[0]);
+        } else if (i > 0) {  // to the front, keeping the others in order
+            std::rotate(c->graphs.begin(), c->graphs.begin() + i, c->graphs.begin() + i + 1);
             i = 0;
         }
         hipError_t e = hipGraphLaunch(c->graphs[i].exec, (hipStream_t)stream);
