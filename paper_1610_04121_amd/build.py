@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsgm.so")
-SOURCES = ["sgm_kernels.hip", "sgm_batch.hip", "sgm_server.hip", "sgm_capi.hip", "sgm_static.hip"]
+SOURCES = ["sgm_kernels.hip", "sgm_batch.hip", "sgm_server.hip", "sgm_capi.hip", "sgm_static.hip", "sgm_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

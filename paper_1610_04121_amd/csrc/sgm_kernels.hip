@@ -537,36 +537,6 @@ hipError_t launch_pipeline(const Plan& p, const Workspace& ws, const uint8_t* le
     return e;
 }
 
-// Packed-u16 VALU throughput probe (a measurement of the ALU peak the
-// aggregation's instruction counts are compared with): every lane runs
-// `iters` rounds of 8 independent (v_pk_add_u16, v_pk_min_u16) pairs, so a
-// wave issues 16 VALU instructions per round with no dependent pair closer
-// than 8 instructions.  The result only reaches memory in the (never taken)
-// case that it equals a constant, so the stores cost nothing but keep the
-// work.
-typedef unsigned short valu_u16x2 __attribute__((ext_vector_type(2)));
-
-__global__ __launch_bounds__(256) void valu_probe_kernel(int iters, uint32_t* sink) {
-    valu_u16x2 a[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-        a[j] = valu_u16x2{(unsigned short)(threadIdx.x + j), (unsigned short)(blockIdx.x + 3 * j)};
-    const valu_u16x2 inc = {1, 3}, cap = {0x7FF0, 0x7FE0};
-    for (int i = 0; i < iters; ++i) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) a[j] = __builtin_elementwise_min(a[j] + inc, cap);
-    }
-    uint32_t r = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) r ^= (uint32_t)a[j].x | ((uint32_t)a[j].y << 16);
-    if (r == 0x9E3779B9u) sink[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = r;
-}
-
-hipError_t launch_valu_probe(int blocks, int iters, uint32_t* sink, hipStream_t stream) {
-    hipLaunchKernelGGL(valu_probe_kernel, dim3(blocks), dim3(256), 0, stream, iters, sink);
-    return hipGetLastError();
-}
-
 hipError_t launch_census_only(const Plan& p, const uint8_t* img, uint64_t* out, hipStream_t stream) {
     return launch_census_pair(p, img, img, out, out, 1, stream);
 }
