@@ -417,3 +417,51 @@ def test_batch_one_workgroup_grid_matches(gpu):
                           lr=p["lrcheck"], lr_full=p["lr_full"], adaptive=p["adaptive_p2"]).out
         assert (full[k] == want).all(), k
     b.close()
+
+
+@pytest.mark.parametrize("trial", range(12))
+def test_fuzz_batches(gpu, trial):
+    """Random batches: 1 to 10 items of random sizes (down to 1x1), ranges,
+    path counts and options (median, check with its threshold, full check,
+    sub-pixel output, adaptive P2), a random kernel shape, direct launches,
+    graph replay (twice) or the one-workgroup grid; every item against the
+    oracle."""
+    import torch
+    rng = np.random.default_rng(31000 + trial)
+    n = int(rng.integers(1, 11))
+    pairs, wants = [], []
+    for k in range(n):
+        w, h = int(rng.integers(1, 121)), int(rng.integers(1, 61))
+        d = int(rng.choice([1, 5, 16, 33, 64, 65, 100, 128, 129, 200, 256]))
+        p = int(rng.choice([2, 4, 8]))
+        med, lr, sub, adapt = (bool(rng.integers(0, 2)) for _ in range(4))
+        full = lr and bool(rng.integers(0, 2))
+        thr = int(rng.integers(0, 4))
+        if k % 3 == 0:
+            pr = synth.make_pair(w, h, d, "RS", seed=31000 + 100 * trial + k)
+            l_, r_ = pr.left, pr.right
+        else:
+            l_ = rng.integers(0, 256, (h, w), dtype=np.uint8)
+            r_ = rng.integers(0, 256, (h, w), dtype=np.uint8)
+        pairs.append(dict(left=_t(l_, gpu), right=_t(r_, gpu), max_disp=d, n_paths=p, median=med, lrcheck=lr,
+                          lr_threshold=thr, lr_full=full, subpixel=sub, adaptive_p2=adapt,
+                          out=torch.full((h, w), 0xABC, dtype=torch.uint16, device=gpu)))
+        wants.append(oracle.sgm(l_, r_, d, 7, 86, p, median=med, lr=lr, lr_thr=thr, lr_full=full, subpixel=sub,
+                                adaptive=adapt).out)
+    lanes = [(0, 0), (16, 16), (32, 16), (16, 32), (32, 32)][trial % 5]
+    mode = ["direct", "graph", "grid1"][trial % 3]
+    _say(f"batch fuzz {trial}: {n} items, lanes={lanes}, mode={mode}")
+    b = Batch(7, 86, graph=(mode == "graph"))
+    b.set_tuning(*lanes)
+    if mode == "grid1":
+        b.set_grid(1)
+    for rep in range(2 if mode == "graph" else 1):
+        for p in pairs:
+            p["out"].fill_(0xABC)
+        b.compute(pairs)
+        torch.cuda.synchronize()
+        for k, (p, want) in enumerate(zip(pairs, wants)):
+            got = p["out"].cpu().numpy()
+            assert (got == want).all(), (rep, k, p["left"].shape, p["max_disp"], p["n_paths"],
+                                         int((got != want).sum()))
+    b.close()
