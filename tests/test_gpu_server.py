@@ -244,3 +244,52 @@ def test_served_full_check_and_adaptive_requests(gpu):
         want = oracle.sgm(r["np_left"], r["np_right"], r["max_disp"], 7, 86, r["n_paths"], median=True, lr=True,
                           lr_full=r["lr_full"], adaptive=r["adaptive_p2"]).out
         assert (r["out"].cpu().numpy() == want).all(), k
+
+
+@pytest.mark.parametrize("trial", range(4))
+def test_fuzz_served_requests(gpu, trial):
+    """Random small requests (sizes down to 1x1, any range, paths and
+    options) from two submitting threads under a random group policy and
+    slot / stream count; every result against the oracle."""
+    import torch
+    rng = np.random.default_rng(41000 + trial)
+    reqs = []
+    for k in range(24):
+        w, h = int(rng.integers(1, 100)), int(rng.integers(1, 50))
+        d = int(rng.choice([1, 8, 16, 40, 64, 65, 128, 200, 256]))
+        p = int(rng.choice([2, 4, 8]))
+        med, lr = bool(rng.integers(0, 2)), bool(rng.integers(0, 2))
+        r = _req(gpu, w, h, d, p, med, lr, 41000 + 100 * trial + k)
+        r["lr_full"] = lr and bool(rng.integers(0, 2))
+        r["adaptive_p2"] = bool(rng.integers(0, 2))
+        r["subpixel"] = bool(rng.integers(0, 2))
+        r["lr_threshold"] = int(rng.integers(0, 3))
+        reqs.append(r)
+    slots = int(rng.choice([1, 2, 4]))
+    streams = int(rng.integers(1, slots + 1))
+    max_group = int(rng.choice([1, 4, 32]))
+    overlap = int(rng.choice([1, 3]))
+    _say(f"served fuzz {trial}: slots={slots} streams={streams} max_group={max_group} overlap={overlap}")
+    srv = Server(2 << 30, slots=slots, streams=streams, max_group=max_group, max_group_cells=1 << 40,
+                 overlap_queue=overlap)
+    tickets = [None] * len(reqs)
+
+    def submit(idx):
+        for i in idx:
+            tickets[i] = srv.submit(reqs[i])
+
+    th = [threading.Thread(target=submit, args=(range(j, len(reqs), 2),)) for j in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for i, t in enumerate(tickets):
+        assert srv.wait(t, 60000)[0] == REQ_DONE, i
+    srv.close()
+    torch.cuda.synchronize()
+    for i, r in enumerate(reqs):
+        want = oracle.sgm(r["np_left"], r["np_right"], r["max_disp"], 7, 86, r["n_paths"], median=r["median"],
+                          lr=r["lrcheck"], lr_thr=r["lr_threshold"], lr_full=r["lr_full"],
+                          adaptive=r["adaptive_p2"], subpixel=r["subpixel"]).out
+        got = r["out"].cpu().numpy()
+        assert (got == want).all(), (i, r["left"].shape, r["max_disp"], int((got != want).sum()))
