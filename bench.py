@@ -845,6 +845,19 @@ def main():
                                 "nominal_peak": round(nominal / 1e9, 1), "frac_of_nominal": round(inst_s / nominal, 4),
                                 "packed_u16_tops": round(inst_s * 64 * 2 / 1e12, 1),
                                 "kernel": "valu_probe_kernel: 8 independent v_pk_add_u16 + v_pk_min_u16 pairs per round"}
+        # dependent chains, one wave per SIMD (256 blocks of 4 waves): clock
+        # cycles per link at the 2.4 GHz peak clock
+        lat = {}
+        for mode, name in ((1, "pk_add_then_pk_min"), (2, "dpp_row_mirror_min_then_add"),
+                           (3, "permlane16_swap_min_add")):
+            lit = 4096
+            valu_probe(256, 64, sink[:256 * 256], mode=mode)
+            pe0.record()
+            valu_probe(256, lit, sink[:256 * 256], mode=mode)
+            pe1.record()
+            pe1.synchronize()
+            lat[name] = round(pe0.elapsed_time(pe1) * 1e-3 * 2.4e9 / (lit * 8), 2)
+        extras["valu_probe"]["dependent_link_cycles"] = lat
         del sink
         # achievable HBM bandwidth: a timed device-to-device copy of 512 MiB
         nb = 512 << 20

@@ -394,14 +394,19 @@ int sgm_debug_stage(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right, int
 int sgm_debug_raw_disparity(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right,
                             uint16_t *dl_out, uint16_t *dr_out, sgm_stream_t stream);
 
-/* Measurement helper: the packed 16-bit VALU throughput the aggregation's
- * arithmetic (Eq. 3 on u16 pairs) is compared with.  Enqueues `blocks`
- * blocks of 256 threads, each lane running `iters` rounds of 8 independent
- * packed add + packed min pairs (16 VALU instructions per wave per round);
- * time it with events on `stream`.  sink: device u32 [blocks * 256], written
- * only in a case that does not occur (it keeps the work).  SGM_EINVAL for
- * blocks outside [1, 2^20], iters < 1 or a null sink. */
-int sgm_debug_valu_probe(int blocks, int iters, uint32_t *sink, sgm_stream_t stream);
+/* Measurement helper: VALU rates the aggregation's arithmetic (Eq. 3 on u16
+ * pairs, its DPP and permlane group minimum) is compared with.  Enqueues
+ * `blocks` blocks of 256 threads; time them with events on `stream`.
+ *   mode 0: throughput - each lane runs `iters` rounds of 8 independent
+ *           packed add + packed min pairs (16 VALU instructions per wave per
+ *           round);
+ *   mode 1..3: latency - one dependent chain per lane, 8 links per round:
+ *           1 packed add then packed min, 2 a minimum with a DPP row_mirror
+ *           operand then an add, 3 a permlane16 swap, a minimum and an add.
+ * sink: device u32 [blocks * 256], written only in a case that does not
+ * occur (it keeps the work).  SGM_EINVAL for a mode outside 0 .. 3, blocks
+ * outside [1, 2^20], iters < 1 or a null sink. */
+int sgm_debug_valu_probe(int mode, int blocks, int iters, uint32_t *sink, sgm_stream_t stream);
 
 /* Host-only: the pixels a GPU aggregation slice visits.  Direction
  * (rx, ry) in {-1,0,1}^2 \ {(0,0)}; slice in [0, number of slices) where

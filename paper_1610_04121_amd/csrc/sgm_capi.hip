@@ -469,10 +469,12 @@ int sgm_debug_raw_disparity(sgm_ctx* c, const uint8_t* left, const uint8_t* righ
     return SGM_OK;
 }
 
-int sgm_debug_valu_probe(int blocks, int iters, uint32_t* sink, sgm_stream_t stream) {
+int sgm_debug_valu_probe(int mode, int blocks, int iters, uint32_t* sink, sgm_stream_t stream) {
+    if (mode < 0 || mode > 3) return set_err(SGM_EINVAL, "mode must be 0 .. 3");
     if (blocks < 1 || blocks > (1 << 20) || iters < 1) return set_err(SGM_EINVAL, "blocks in [1, 2^20], iters >= 1");
     if (!sink) return set_err(SGM_EINVAL, "null buffer pointer");
-    hipError_t e = sgm::launch_valu_probe(blocks, iters, sink, (hipStream_t)stream);
+    hipError_t e = mode == 0 ? sgm::launch_valu_probe(blocks, iters, sink, (hipStream_t)stream)
+                             : sgm::launch_valu_latency_probe(mode, blocks, iters, sink, (hipStream_t)stream);
     if (e != hipSuccess) return hip_err(e, "kernel launch");
     return SGM_OK;
 }

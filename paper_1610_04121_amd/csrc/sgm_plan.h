@@ -141,6 +141,10 @@ hipError_t launch_pipeline(const Plan& p, const Workspace& ws, const uint8_t* le
 // The packed-u16 VALU throughput probe: blocks x 256 threads, 16 VALU
 // instructions per wave per round; sink holds blocks * 256 u32.
 hipError_t launch_valu_probe(int blocks, int iters, uint32_t* sink, hipStream_t stream);
+// Dependent-chain latency probes (mode 1: packed u16 add + min, 2: min via
+// DPP row_mirror + add, 3: permlane16 swap + min + add), one chain per lane,
+// 8 links per round.
+hipError_t launch_valu_latency_probe(int mode, int blocks, int iters, uint32_t* sink, hipStream_t stream);
 hipError_t launch_census_only(const Plan& p, const uint8_t* img, uint64_t* out,
                               hipStream_t stream);
 // S = sum of the first nplanes L_r planes (-1: n_paths), leaving out plane

@@ -119,7 +119,7 @@ def lib() -> ctypes.CDLL:
     L.sgm_debug_fail_alloc.restype = None
     L.sgm_batch_set_grid.argtypes = [P, i]
     L.sgm_batch_set_grid.restype = i
-    L.sgm_debug_valu_probe.argtypes = [i, i, P, P]
+    L.sgm_debug_valu_probe.argtypes = [i, i, i, P, P]
     L.sgm_debug_valu_probe.restype = i
     L.sgm_batch_destroy.argtypes = [P]
     L.sgm_batch_destroy.restype = None
@@ -524,8 +524,10 @@ def debug_fail_alloc(after: int, count: int):
     lib().sgm_debug_fail_alloc(after, count)
 
 
-def valu_probe(blocks: int, iters: int, sink, stream=None):
-    """Enqueues the packed-u16 VALU throughput probe (sgm_debug_valu_probe):
-    16 VALU instructions per wave per round, 4 waves per block; ``sink`` is
-    a device uint32 tensor of blocks * 256 elements."""
-    _check(lib().sgm_debug_valu_probe(blocks, iters, _ptr(sink, "torch.int32", (blocks * 256,)), _stream(stream)))
+def valu_probe(blocks: int, iters: int, sink, stream=None, mode: int = 0):
+    """Enqueues a VALU probe (sgm_debug_valu_probe): mode 0, throughput (16
+    VALU instructions per wave per round); modes 1-3, dependent chains of 8
+    links per round.  4 waves per block; ``sink`` is a device int32 tensor
+    of blocks * 256 elements."""
+    _check(lib().sgm_debug_valu_probe(mode, blocks, iters, _ptr(sink, "torch.int32", (blocks * 256,)),
+                                      _stream(stream)))

@@ -205,8 +205,10 @@ def test_noalloc_rejects_oversized_and_invalid_calls_before_the_gpu():
 
 def test_valu_probe_validates_before_launching(lib):
     from paper_1610_04121_amd import sgm
-    assert lib.sgm_debug_valu_probe(0, 16, None, None) == sgm.SGM_EINVAL
+    assert lib.sgm_debug_valu_probe(0, 0, 16, None, None) == sgm.SGM_EINVAL
     assert "blocks" in sgm.last_error()
-    assert lib.sgm_debug_valu_probe(4, 0, None, None) == sgm.SGM_EINVAL
-    assert lib.sgm_debug_valu_probe(4, 16, None, None) == sgm.SGM_EINVAL
+    assert lib.sgm_debug_valu_probe(0, 4, 0, None, None) == sgm.SGM_EINVAL
+    assert lib.sgm_debug_valu_probe(4, 4, 16, None, None) == sgm.SGM_EINVAL
+    assert "mode" in sgm.last_error()
+    assert lib.sgm_debug_valu_probe(1, 4, 16, None, None) == sgm.SGM_EINVAL
     assert "null" in sgm.last_error()
