@@ -64,7 +64,12 @@ def _traffic(tuning):
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != _kernel_sha() or list(t.get("tuning", [])) != [int(v) for v in tuning]:
+    # the recorded shape (lanes_h, lanes_v, fused, census_cost) must match,
+    # and every later tuning switch (final pass, post stage inside the WTA)
+    # must be off, as in the counted runs
+    ref = [int(v) for v in t.get("tuning", [])]
+    cur = [int(v) for v in tuning]
+    if t.get("kernel_sha") != _kernel_sha() or not ref or cur[:len(ref)] != ref or any(cur[len(ref):]):
         return None
     return t.get("bytes_per_launch")
 

@@ -118,6 +118,12 @@ def test_committed_traffic_summary_is_used_only_for_the_kernels_it_measured():
     other = list(summary["tuning"])
     other[0] = 16 if other[0] != 16 else 32
     assert bench._traffic(tuple(other)) is None
+    # the context reports a longer tuning tuple (final pass, post stage inside
+    # the WTA): those switches off is the counted shape, either on is not
+    if summary["kernel_sha"] == bench._kernel_sha():
+        assert bench._traffic(tuple(summary["tuning"]) + (False, False)) == summary["bytes_per_launch"]
+    assert bench._traffic(tuple(summary["tuning"]) + (True, False)) is None
+    assert bench._traffic(tuple(summary["tuning"]) + (False, True)) is None
     # every L_r byte written once; reads at most the algorithmic ones (L2 hits
     # may serve part of a slice's second read), so no wasted re-reads
     agg = summary["kernels"][summary["kernel"]]
