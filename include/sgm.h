@@ -282,6 +282,8 @@ typedef struct {
                                   grouped_requests / groups) */
     uint64_t pending, running; /* current queue length, requests in flight */
     size_t bytes_in_use, peak_bytes, budget_bytes;
+    uint64_t timed_out;        /* requests failed by the watchdog (also in failed) */
+    uint64_t draining_groups;  /* stuck groups the device has not completed yet */
 } sgm_server_stats;
 
 /* Creates a server on the current HIP device.  hbm_budget_bytes: workspace
@@ -312,6 +314,16 @@ sgm_server *sgm_server_create_ex(size_t hbm_budget_bytes, int max_slots, int n_s
  * sharing the device with it. */
 int sgm_server_set_policy(sgm_server *s, int max_group, int max_pending, uint64_t max_group_cells,
                           int overlap_queue);
+
+/* Watchdog on completion events: a group still running timeout_ms after
+ * its launch is declared stuck, and its requests end as SGM_REQ_FAILED at
+ * once (counted in stats.timed_out), so that their callers stop waiting.
+ * The device work cannot be taken back: the group's workspace and slot stay
+ * reserved until its completion event fires (stats.draining_groups counts
+ * such groups), and until then the device may still read the requests'
+ * images and write their outputs, so a caller must not reuse those buffers
+ * before draining_groups is back to 0.  0 (the default) turns it off. */
+int sgm_server_set_watchdog(sgm_server *s, int timeout_ms);
 
 /* Workspace bytes a request takes from the budget (0 if invalid). */
 size_t sgm_server_request_bytes(sgm_server *s, const sgm_item *req);

@@ -102,7 +102,14 @@ struct Slot {
     hipStream_t stream = nullptr;  // shared with the other slots of its stream
     hipEvent_t done = nullptr;
     sgm::BatchStaging* st = nullptr;
-    std::vector<Request*> group;  // empty = free
+    std::vector<Request*> group;  // empty and not draining = free
+    Clock::time_point t_launch;
+    // a group the watchdog declared stuck: its requests have failed and left
+    // the slot, whose workspace blocks (offset, bytes) stay reserved until
+    // the device completes the group
+    bool draining = false;
+    std::vector<std::pair<size_t, size_t>> held;
+    bool busy() const { return !group.empty() || draining; }
 };
 
 }  // namespace
@@ -129,6 +136,9 @@ struct sgm_server {
     // many requests are queued: at light load a request then waits for the
     // running one instead of sharing the device with it
     int overlap_queue = 3;
+    // a group still running this long after its launch is declared stuck
+    // (0: never)
+    int watchdog_ms = 0;
     bool stop = false;
     std::atomic<uint64_t> wake{0};  // bumped by every submission and by shutdown
     sgm_server_stats stats{};
@@ -161,6 +171,37 @@ void retire_group(sgm_server* s, Slot& slot, bool ok, Clock::time_point now) {
     slot.group.clear();
 }
 
+// The watchdog: fails the requests of a group that has run longer than the
+// limit (their callers stop waiting), keeps its workspace blocks and its
+// slot until the device completes it.  Called with the lock held.
+void declare_stuck(sgm_server* s, Slot& slot, Clock::time_point now) {
+    for (Request* r : slot.group) {
+        slot.held.emplace_back(r->offset, r->bytes);
+        r->status = SGM_REQ_FAILED;
+        r->latency_s = std::chrono::duration<double>(now - r->t_submit).count();
+        s->stats.failed++;
+        s->stats.timed_out++;
+        s->stats.running--;
+    }
+    slot.group.clear();
+    slot.draining = true;
+    s->stats.draining_groups++;
+}
+
+// A stuck group has completed: its workspace blocks and slot are free again.
+void drained(sgm_server* s, Slot& slot) {
+    for (const auto& b : slot.held) s->alloc.release(b.first, b.second);
+    slot.held.clear();
+    slot.draining = false;
+    s->stats.draining_groups--;
+    s->stats.bytes_in_use = s->alloc.used();
+}
+
+bool overdue(const sgm_server* s, const Slot& slot, Clock::time_point now) {
+    return s->watchdog_ms > 0 && !slot.group.empty() &&
+           now - slot.t_launch > std::chrono::milliseconds(s->watchdog_ms);
+}
+
 void scheduler(sgm_server* s) {
     (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
@@ -171,13 +212,21 @@ void scheduler(sgm_server* s) {
         // 1. completions
         bool any_busy = false, finished = false;
         for (Slot& slot : s->slots) {
-            if (slot.group.empty()) continue;
+            if (!slot.busy()) continue;
             const hipError_t q = hipEventQuery(slot.done);
             if (q == hipErrorNotReady) {
                 any_busy = true;
+                const Clock::time_point now = Clock::now();
+                if (overdue(s, slot, now)) {
+                    declare_stuck(s, slot, now);
+                    finished = true;
+                }
                 continue;
             }
-            retire_group(s, slot, q == hipSuccess, Clock::now());
+            if (slot.draining)
+                drained(s, slot);
+            else
+                retire_group(s, slot, q == hipSuccess, Clock::now());
             finished = true;
         }
         if (finished) s->cv_done.notify_all();
@@ -185,7 +234,7 @@ void scheduler(sgm_server* s) {
         // 2. admission: fill free slots from the head of the queue
         for (Slot& slot : s->slots) {
             if (s->pending.empty()) break;
-            if (!slot.group.empty()) continue;
+            if (slot.busy()) continue;
             if (any_busy && (int)s->pending.size() < s->overlap_queue) break;
             uint64_t cells = 0;
             while (!s->pending.empty() && (int)slot.group.size() < s->max_group) {
@@ -226,6 +275,7 @@ void scheduler(sgm_server* s) {
                                         slot.stream);
             }
             if (rc == SGM_OK && hipEventRecord(slot.done, slot.stream) != hipSuccess) rc = SGM_EHIP;
+            slot.t_launch = Clock::now();
             lk.lock();
             if (rc != SGM_OK) {
                 retire_group(s, slot, false, Clock::now());
@@ -248,8 +298,10 @@ void scheduler(sgm_server* s) {
             const uint64_t seen = s->wake.load();
             lk.unlock();
             for (bool ready = false; !ready && s->wake.load() == seen;) {
+                const Clock::time_point now = Clock::now();
                 for (Slot& slot : s->slots)
-                    if (!slot.group.empty() && hipEventQuery(slot.done) != hipErrorNotReady) ready = true;
+                    if (slot.busy() && (hipEventQuery(slot.done) != hipErrorNotReady || overdue(s, slot, now)))
+                        ready = true;
                 if (!ready) std::this_thread::yield();
             }
             lk.lock();
@@ -463,6 +515,17 @@ int sgm_server_cancel(sgm_server* s, uint64_t ticket) {
     s->stats.canceled++;
     s->stats.pending = s->pending.size();
     s->cv_done.notify_all();
+    return SGM_OK;
+}
+
+int sgm_server_set_watchdog(sgm_server* s, int timeout_ms) {
+    if (!s) return serr(SGM_EINVAL, "null server");
+    if (timeout_ms < 0) return serr(SGM_EINVAL, "timeout_ms must be >= 0");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->watchdog_ms = timeout_ms;
+    }
+    s->wake.fetch_add(1);  // the scheduler re-reads the limit
     return SGM_OK;
 }
 

@@ -28,6 +28,7 @@ EXPORTS = [
     "sgm_server_poll", "sgm_server_wait", "sgm_server_cancel", "sgm_server_get_stats", "sgm_server_destroy",
     "sgm_server_create_ex", "sgm_debug_phase_sums", "sgm_compute_noalloc", "sgm_batch_set_tuning",
     "sgm_batch_set_graph", "sgm_debug_fail_alloc", "sgm_batch_set_grid", "sgm_debug_valu_probe",
+    "sgm_server_set_watchdog",
 ]
 NOALLOC_MAX_BYTES = 256 << 20
 
@@ -39,7 +40,8 @@ class ServerStats(ctypes.Structure):
     """Mirror of sgm_server_stats."""
     _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "rejected", "canceled", "failed",
                                               "groups", "grouped_requests", "pending", "running")] + \
-               [(n, ctypes.c_size_t) for n in ("bytes_in_use", "peak_bytes", "budget_bytes")]
+               [(n, ctypes.c_size_t) for n in ("bytes_in_use", "peak_bytes", "budget_bytes")] + \
+               [(n, ctypes.c_uint64) for n in ("timed_out", "draining_groups")]
 
 
 class Item(ctypes.Structure):
@@ -145,6 +147,8 @@ def lib() -> ctypes.CDLL:
     L.sgm_server_cancel.restype = i
     L.sgm_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
     L.sgm_server_get_stats.restype = i
+    L.sgm_server_set_watchdog.argtypes = [P, i]
+    L.sgm_server_set_watchdog.restype = i
     L.sgm_server_destroy.argtypes = [P]
     L.sgm_server_destroy.restype = None
     L.sgm_set_tuning.argtypes = [P, i, i, i]
@@ -499,6 +503,11 @@ class Server:
 
     def cancel(self, ticket):
         _check(lib().sgm_server_cancel(self._s, ticket))
+
+    def set_watchdog(self, timeout_ms: int):
+        """Fail the requests of a group still running timeout_ms after its
+        launch (sgm_server_set_watchdog; 0 = off)."""
+        _check(lib().sgm_server_set_watchdog(self._s, timeout_ms))
 
     def stats(self) -> dict:
         st = ServerStats()

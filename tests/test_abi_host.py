@@ -212,3 +212,16 @@ def test_valu_probe_validates_before_launching(lib):
     assert "mode" in sgm.last_error()
     assert lib.sgm_debug_valu_probe(1, 4, 16, None, None) == sgm.SGM_EINVAL
     assert "null" in sgm.last_error()
+
+
+def test_server_stats_mirror_matches_the_header():
+    # sgm_server_stats: 9 uint64 counters, 3 size_t byte counts, 2 uint64 watchdog counters
+    import ctypes
+
+    from paper_1610_04121_amd.sgm import ServerStats
+    assert ctypes.sizeof(ServerStats) == 14 * 8
+    names = [n for n, _ in ServerStats._fields_]
+    assert names[-2:] == ["timed_out", "draining_groups"]
+    hdr = open(os.path.join(ROOT, "include", "sgm.h")).read()
+    body = hdr[hdr.index("uint64_t submitted, completed"):hdr.index("} sgm_server_stats;")]
+    assert "timed_out" in body and body.index("budget_bytes") < body.index("timed_out") < body.index("draining_groups")

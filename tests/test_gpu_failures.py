@@ -152,3 +152,43 @@ def test_server_group_allocation_failure_is_isolated(gpu, hook):
             alone = c.compute(r["left"], r["right"]).cpu().numpy()
             c.close()
             assert (got == alone).all(), i
+
+
+def test_server_watchdog_fails_a_stuck_group_and_drains_it(gpu):
+    """A 1 ms watchdog declares a group of a few ms stuck: its request fails
+    at once, its workspace stays reserved until the device completes the
+    group (which still writes the exact result), and with the watchdog off
+    the next request completes normally."""
+    import time
+
+    import torch
+    pr = _pair(1920, 1080, 256, 90)
+    big = dict(left=_t(pr.left, gpu), right=_t(pr.right, gpu), max_disp=256, n_paths=8,
+               out=torch.zeros((1080, 1920), dtype=torch.uint16, device=gpu))
+    srv = Server(16 << 30, slots=1, max_group=1)
+    srv.set_watchdog(1)
+    _say("server watchdog: a 1920x1080, D=256, 8-path request under a 1 ms limit")
+    t = srv.submit(big)
+    st, _ = srv.wait(t, 60000)
+    assert st == REQ_FAILED
+    stats = srv.stats()
+    assert stats["timed_out"] == 1 and stats["failed"] == 1
+    deadline = time.time() + 20
+    while srv.stats()["draining_groups"] and time.time() < deadline:
+        time.sleep(0.001)
+    stats = srv.stats()
+    assert stats["draining_groups"] == 0 and stats["bytes_in_use"] == 0, stats
+    torch.cuda.synchronize()
+    c = SGM(1920, 1080, 256, 7, 86, 8)
+    alone = c.compute(big["left"], big["right"]).cpu().numpy()
+    c.close()
+    assert (big["out"].cpu().numpy() == alone).all()  # the device finished the stuck group
+    srv.set_watchdog(0)
+    pr2 = _pair(97, 31, 64, 91)
+    small = dict(left=_t(pr2.left, gpu), right=_t(pr2.right, gpu), max_disp=64, n_paths=4, median=True,
+                 lrcheck=True, out=torch.zeros((31, 97), dtype=torch.uint16, device=gpu))
+    t2 = srv.submit(small)
+    assert srv.wait(t2, 60000)[0] == REQ_DONE
+    srv.close()
+    want = oracle.sgm(pr2.left, pr2.right, 64, 7, 86, 4, median=True, lr=True).out
+    assert (small["out"].cpu().numpy() == want).all()
