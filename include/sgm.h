@@ -99,6 +99,9 @@ int sgm_validate(int width, int height, int max_disp, int P1, int P2, int n_path
  * P1, P2 are the penalties of Eq. 3 for disparity changes of one and of more
  * than one level.  The path set is: 2 = left-to-right and top-to-bottom
  * (Sec. 4); 4 = the four axial directions; 8 = axial plus diagonal.
+ * The environment variable SGM_TUNE="lanes_h,lanes_v,bits" sets the initial
+ * kernel shape of every new context (the arguments of sgm_set_tuning; a
+ * malformed or rejected value is ignored, and reported when SGM_LOG >= 2).
  * Returns NULL on error (SGM_EINVAL / SGM_ENOMEM / SGM_EHIP). */
 sgm_ctx *sgm_create(int width, int height, int max_disp, int P1, int P2, int n_paths,
                     int census_w, int census_h);
@@ -116,8 +119,9 @@ int sgm_compute(sgm_ctx *ctx, const uint8_t *left, const uint8_t *right, uint16_
 
 /* Kernel shapes (results never depend on them):
  *   lanes_h - lanes per horizontal aggregation slice (16, 32 or 64), lanes_v
- *   - lanes per vertical / diagonal slice (16 or 32); 0 and 0 select the
- *   built-in default.
+ *   - lanes per vertical / diagonal slice (16 or 32), with lanes_h >= lanes_v
+ *   (the shapes 16/16, 32/16, 32/32, 64/16 and 64/32; 64 acts as 32 when the
+ *   padded range is 64 levels); 0 and 0 select the built-in default.
  *   fused   - bit SGM_TUNE_FUSED_AGG: the aggregation computes the matching
  *   costs from census words itself (no cost volume in memory); otherwise a
  *   cost kernel writes the u8 cost volume C[H][W][Dp] that the aggregation

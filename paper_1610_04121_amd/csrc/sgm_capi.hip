@@ -206,6 +206,20 @@ sgm_ctx* sgm_create(int width, int height, int max_disp, int P1, int P2, int n_p
         return nullptr;
     }
     c->ws = sgm::workspace_carve(p, c->mem);
+    // SGM_TUNE="lanes_h,lanes_v,bits": the initial kernel shape of every new
+    // context (as sgm_set_tuning); a malformed or rejected value leaves the
+    // default and is reported through SGM_LOG
+    if (const char* env = std::getenv("SGM_TUNE")) {
+        int gh = 0, gv = 0, bits = 0;
+        char tail = 0;
+        if (std::sscanf(env, "%d,%d,%d%c", &gh, &gv, &bits, &tail) != 3 ||
+            sgm_set_tuning(c, gh, gv, bits) != SGM_OK) {
+            c->plan.lanes_h = c->plan.lanes_v = 0;
+            c->plan.fused = c->plan.cc_fused = c->plan.final_pass = c->plan.post_in_wta = false;
+            sgm::log_event(std::string("SGM_TUNE ignored: ") + env);
+            g_err.clear();
+        }
+    }
     return c;
 }
 
@@ -259,6 +273,8 @@ int sgm_set_tuning(sgm_ctx* c, int lanes_h, int lanes_v, int fused) {
     if (!ok(lanes_h) || !ok(lanes_v)) return set_err(SGM_EINVAL, "lanes must be 0, 16, 32 or 64");
     if (lanes_v == 64) return set_err(SGM_EINVAL, "lanes_v must be 0, 16 or 32");
     if ((lanes_h == 0) != (lanes_v == 0)) return set_err(SGM_EINVAL, "set both lane counts or neither");
+    if (lanes_h < lanes_v)
+        return set_err(SGM_EINVAL, "lanes_h must be at least lanes_v (shapes 16/16, 32/16, 32/32, 64/16, 64/32)");
     c->plan.lanes_h = lanes_h;
     c->plan.lanes_v = lanes_v;
     if (fused & ~(SGM_TUNE_FUSED_AGG | SGM_TUNE_FUSED_CENSUS_COST | SGM_TUNE_FINAL_PASS | SGM_TUNE_POST_IN_WTA))

@@ -32,3 +32,27 @@ def test_autotune_picks_candidate_and_caches(gpu, tmp_path, monkeypatch):
     assert res2["cached"] and res2["choice"] == res["choice"]
     assert s2.tuning() == tuple(res["choice"])
     s2.close()
+
+
+def test_sgm_tune_environment_sets_the_initial_shape(gpu, monkeypatch):
+    import torch
+
+    import oracle
+    from paper_1610_04121_amd import SGM, synth
+    pr = synth.make_pair(96, 40, 48, "RS", seed=5150)
+    l = torch.from_numpy(pr.left).to(gpu)
+    r = torch.from_numpy(pr.right).to(gpu)
+    want = oracle.sgm(pr.left, pr.right, 48, 7, 86, 4, median=True, lr=True).out
+    monkeypatch.setenv("SGM_TUNE", "32,32,2")  # one census + cost launch
+    s = SGM(96, 40, 48, 7, 86, 4, median=True, lrcheck=True)
+    assert s.tuning() == (32, 32, False, True, False, False)
+    assert (s.compute(l, r).cpu().numpy() == want).all()
+    s.close()
+    # rejected lanes, a shape that does not exist, too few fields, unknown bit, junk
+    for bad in ("16,24,0", "16,32,0", "32,16", "32,16,64", "x"):
+        monkeypatch.setenv("SGM_TUNE", bad)
+        s = SGM(96, 40, 48, 7, 86, 4, median=True, lrcheck=True)
+        default = s.tuning()
+        assert default[2:] == (False, False, False, False), (bad, default)
+        assert (s.compute(l, r).cpu().numpy() == want).all()
+        s.close()
