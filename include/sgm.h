@@ -182,7 +182,7 @@ int sgm_compute_noalloc(int width, int height, int max_disp, int P1, int P2, int
  * path count and options; the census window and P1, P2 belong to the batch
  * (or server).  Buffers follow the conventions above.  Item flags:
  * SGM_MEDIAN3, SGM_LRCHECK, SGM_SUBPIXEL, SGM_LR_FULL (with SGM_LRCHECK),
- * SGM_ADAPTIVE_P2, and the item's left-right threshold as
+ * SGM_ADAPTIVE_P2, SGM_CENSUS_CSCT, and the item's left-right threshold as
  * SGM_ITEM_LR_THRESHOLD(t), t in [0, 255]; without it the threshold is 1 (as
  * for sgm_set_options). */
 typedef struct {

@@ -250,7 +250,7 @@ bool batch_plan(const BatchParams& bp, const sgm_item* items, int n, BatchLayout
         p.n_paths = it.n_paths;
         p.cw = bp.cw;
         p.ch = bp.ch;
-        p.csct = bp.csct;
+        p.csct = bp.csct || (it.flags & SGM_CENSUS_CSCT) != 0;
         p.median = (it.flags & SGM_MEDIAN3) != 0;
         p.lrcheck = (it.flags & SGM_LRCHECK) != 0;
         p.subpixel = (it.flags & SGM_SUBPIXEL) != 0;
@@ -258,9 +258,9 @@ bool batch_plan(const BatchParams& bp, const sgm_item* items, int n, BatchLayout
         p.adaptive = (it.flags & SGM_ADAPTIVE_P2) != 0;
         p.lr_thr = item_lr_threshold(it.flags);
         if (it.flags & ~(unsigned)(SGM_MEDIAN3 | SGM_LRCHECK | SGM_SUBPIXEL | SGM_LR_FULL | SGM_ADAPTIVE_P2 |
-                                   SGM_ITEM_THRESHOLD_SET | 0x00FF0000u)) {
-            *why = "item flags may only hold SGM_MEDIAN3, SGM_LRCHECK, SGM_SUBPIXEL, SGM_LR_FULL, SGM_ADAPTIVE_P2 "
-                   "and SGM_ITEM_LR_THRESHOLD(t)";
+                                   SGM_CENSUS_CSCT | SGM_ITEM_THRESHOLD_SET | 0x00FF0000u)) {
+            *why = "item flags may only hold SGM_MEDIAN3, SGM_LRCHECK, SGM_SUBPIXEL, SGM_LR_FULL, SGM_ADAPTIVE_P2, "
+                   "SGM_CENSUS_CSCT and SGM_ITEM_LR_THRESHOLD(t)";
             return false;
         }
         if (p.lr_full && !p.lrcheck) {

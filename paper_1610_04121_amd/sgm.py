@@ -380,13 +380,13 @@ class SGM:
 
 def _items(pairs):
     """pairs: dicts with left, right, out (device tensors), max_disp, n_paths and
-    optional median, lrcheck, subpixel, lr_full, adaptive_p2, lr_threshold."""
+    optional median, lrcheck, subpixel, lr_full, adaptive_p2, csct, lr_threshold."""
     arr = (Item * len(pairs))()
     for k, p in enumerate(pairs):
         h, w = p["left"].shape
         flags = (MEDIAN3 if p.get("median") else 0) | (LRCHECK if p.get("lrcheck") else 0) | \
             (SUBPIXEL if p.get("subpixel") else 0) | (LR_FULL if p.get("lr_full") else 0) | \
-            (ADAPTIVE_P2 if p.get("adaptive_p2") else 0)
+            (ADAPTIVE_P2 if p.get("adaptive_p2") else 0) | (CENSUS_CSCT if p.get("csct") else 0)
         if p.get("lr_threshold", 1) != 1:
             flags |= item_lr_threshold(p["lr_threshold"])
         arr[k] = Item(w, h, p["max_disp"], p["n_paths"], flags,

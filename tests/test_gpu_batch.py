@@ -423,7 +423,7 @@ def test_batch_one_workgroup_grid_matches(gpu):
 def test_fuzz_batches(gpu, trial):
     """Random batches: 1 to 10 items of random sizes (down to 1x1), ranges,
     path counts and options (median, check with its threshold, full check,
-    sub-pixel output, adaptive P2), a random kernel shape, direct launches,
+    sub-pixel output, adaptive P2, CSCT census), a random kernel shape, direct launches,
     graph replay (twice) or the one-workgroup grid; every item against the
     oracle."""
     import torch
@@ -434,7 +434,7 @@ def test_fuzz_batches(gpu, trial):
         w, h = int(rng.integers(1, 121)), int(rng.integers(1, 61))
         d = int(rng.choice([1, 5, 16, 33, 64, 65, 100, 128, 129, 200, 256]))
         p = int(rng.choice([2, 4, 8]))
-        med, lr, sub, adapt = (bool(rng.integers(0, 2)) for _ in range(4))
+        med, lr, sub, adapt, csct = (bool(rng.integers(0, 2)) for _ in range(5))
         full = lr and bool(rng.integers(0, 2))
         thr = int(rng.integers(0, 4))
         if k % 3 == 0:
@@ -444,10 +444,10 @@ def test_fuzz_batches(gpu, trial):
             l_ = rng.integers(0, 256, (h, w), dtype=np.uint8)
             r_ = rng.integers(0, 256, (h, w), dtype=np.uint8)
         pairs.append(dict(left=_t(l_, gpu), right=_t(r_, gpu), max_disp=d, n_paths=p, median=med, lrcheck=lr,
-                          lr_threshold=thr, lr_full=full, subpixel=sub, adaptive_p2=adapt,
+                          lr_threshold=thr, lr_full=full, subpixel=sub, adaptive_p2=adapt, csct=csct,
                           out=torch.full((h, w), 0xABC, dtype=torch.uint16, device=gpu)))
         wants.append(oracle.sgm(l_, r_, d, 7, 86, p, median=med, lr=lr, lr_thr=thr, lr_full=full, subpixel=sub,
-                                adaptive=adapt).out)
+                                adaptive=adapt, csct=csct).out)
     lanes = [(0, 0), (16, 16), (32, 16), (16, 32), (32, 32)][trial % 5]
     mode = ["direct", "graph", "grid1"][trial % 3]
     _say(f"batch fuzz {trial}: {n} items, lanes={lanes}, mode={mode}")

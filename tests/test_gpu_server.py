@@ -264,6 +264,7 @@ def test_fuzz_served_requests(gpu, trial):
         r["adaptive_p2"] = bool(rng.integers(0, 2))
         r["subpixel"] = bool(rng.integers(0, 2))
         r["lr_threshold"] = int(rng.integers(0, 3))
+        r["csct"] = bool(rng.integers(0, 2))
         reqs.append(r)
     slots = int(rng.choice([1, 2, 4]))
     streams = int(rng.integers(1, slots + 1))
@@ -290,6 +291,6 @@ def test_fuzz_served_requests(gpu, trial):
     for i, r in enumerate(reqs):
         want = oracle.sgm(r["np_left"], r["np_right"], r["max_disp"], 7, 86, r["n_paths"], median=r["median"],
                           lr=r["lrcheck"], lr_thr=r["lr_threshold"], lr_full=r["lr_full"],
-                          adaptive=r["adaptive_p2"], subpixel=r["subpixel"]).out
+                          adaptive=r["adaptive_p2"], subpixel=r["subpixel"], csct=r["csct"]).out
         got = r["out"].cpu().numpy()
         assert (got == want).all(), (i, r["left"].shape, r["max_disp"], int((got != want).sum()))
