@@ -280,6 +280,39 @@ def test_lr_check_hand_example():
     assert oracle.lr_check(dl2, np.zeros_like(dl2), 1)[0, 0] == 0xFFFF
 
 
+def test_lr_check_threshold_is_monotone_and_saturates():
+    # a larger threshold never invalidates a pixel a smaller one kept; thr =
+    # 0 keeps exactly the pixels whose two disparities agree; a threshold at
+    # least the range keeps every pixel whose match x - d lies in the image
+    W, H, D = 37, 9, 12
+    dl = RNG.integers(0, D, (H, W)).astype(np.uint16)
+    dr = RNG.integers(0, D, (H, W)).astype(np.uint16)
+    outs = [oracle.lr_check(dl, dr, t) for t in range(D + 1)]
+    for lo, hi in zip(outs, outs[1:]):
+        assert ((lo == 0xFFFF) | (hi == lo)).all()  # kept at thr -> kept, unchanged, at thr + 1
+        assert ((lo != 0xFFFF) <= (hi != 0xFFFF)).all()
+    xs = np.arange(W)[None, :].repeat(H, 0)
+    inside = xs - dl.astype(int) >= 0
+    assert ((outs[D] != 0xFFFF) == inside).all()
+    agree = np.zeros_like(inside)
+    for y in range(H):
+        for x in range(W):
+            agree[y, x] = inside[y, x] and dr[y, x - dl[y, x]] == dl[y, x]
+    assert ((outs[0] != 0xFFFF) == agree).all()
+    kept = outs[1] != 0xFFFF
+    assert (outs[1][kept] == dl[kept]).all()  # a kept pixel keeps its left disparity
+
+
+def test_median_commutes_with_increasing_maps():
+    # the median of 9 is an order statistic: a strictly increasing map of the
+    # values commutes with it (a sum or mean would not)
+    a = RNG.integers(0, 200, (13, 17)).astype(np.uint16)
+    f = lambda v: (v.astype(np.int64) ** 2 + 3 * v + 1).astype(np.uint16)  # increasing on [0, 199]
+    assert (oracle.median3(f(a)) == f(oracle.median3(a))).all()
+    c = np.full((5, 6), 77, dtype=np.uint16)
+    assert (oracle.median3(c) == c).all()
+
+
 # --------------------------------------------------------------------------
 # Whole pipeline
 # --------------------------------------------------------------------------
