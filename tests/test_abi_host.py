@@ -225,3 +225,16 @@ def test_server_stats_mirror_matches_the_header():
     hdr = open(os.path.join(ROOT, "include", "sgm.h")).read()
     body = hdr[hdr.index("uint64_t submitted, completed"):hdr.index("} sgm_server_stats;")]
     assert "timed_out" in body and body.index("budget_bytes") < body.index("timed_out") < body.index("draining_groups")
+
+
+@pytest.mark.skipif(gpu_available(), reason="checks the behaviour on a host without a GPU")
+def test_creation_fails_cleanly_without_a_device(lib):
+    # valid parameters but no device: NULL and a HIP message, no crash
+    assert not lib.sgm_create(64, 48, 16, 7, 86, 4, 9, 7)
+    assert "hip" in sgm.last_error().lower()
+    assert not lib.sgm_batch_create(7, 86, 9, 7)
+    assert "hip" in sgm.last_error().lower()
+    assert not lib.sgm_server_create(1 << 20, 1, 7, 86, 9, 7)
+    assert "hip" in sgm.last_error().lower()
+    with pytest.raises(sgm.SGMError):
+        sgm.SGM(64, 48, 16)
