@@ -914,6 +914,13 @@ def main():
             "frac": round(pipe_gbs / HBM_PEAK_GBS, 4)}
     if "copy_gbs" in extras:
         pipe["frac_of_measured_copy"] = round(pipe_gbs / extras["copy_gbs"], 4)
+    # the same span against the byte count of the schedule with u16 partial
+    # sums and costs recomputed in every pass (images in, (4P - 4) sweeps of
+    # W * H * D u16 partial-sum bytes, the two raw maps out), the usual
+    # yardstick for "fraction of the HBM roofline" of this path
+    u16_bytes = 2 * W * H + (4 * P - 4) * W * H * D + 2 * W * H * (2 if cfg["lr"] else 1)
+    pipe["alg_bytes_u16_partial_sum_schedule"] = u16_bytes
+    pipe["frac_u16_partial_sum_schedule"] = round(u16_bytes / (pipe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
     line = {
         "metric": METRIC,
