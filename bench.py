@@ -425,6 +425,55 @@ def bench_batch(dev, steps: int, warmup: int = 3, post: bool = False):
                       "4 or 8 paths, " + ("median + LR check" if post else "no median/LR")}
 
 
+def bench_batch_small(dev, steps: int = 400, warmup: int = 20, seed: int = 1610041216):
+    """A launch-bound batch: 8 small pairs (160x120 to 320x240, D 32 or 64,
+    4 paths, median + LR), by direct launches, by graph replay and as 8
+    plain single-pair launches on one stream."""
+    import numpy as np
+    import torch
+
+    from paper_1610_04121_amd import SGM, synth
+    from paper_1610_04121_amd.sgm import Batch
+    rng = np.random.default_rng(seed)
+    pairs = []
+    for k in range(8):
+        (w, h), d = [(160, 120), (256, 192), (320, 240)][k % 3], int(rng.choice([32, 64]))
+        pr = synth.make_pair(w, h, d, "K", seed=seed * 10 + k, scale_to_d=True)
+        pairs.append(dict(left=torch.from_numpy(pr.left).to(dev), right=torch.from_numpy(pr.right).to(dev),
+                          max_disp=d, n_paths=4, median=True, lrcheck=True,
+                          out=torch.empty((h, w), dtype=torch.uint16, device=dev)))
+    st = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
+
+    b = Batch(synth.P1_DEFAULT, synth.P2_DEFAULT)
+    t_direct = timed(lambda: b.compute(pairs, stream=st))
+    b.set_graph(True)
+    t_graph = timed(lambda: b.compute(pairs, stream=st))
+    b.close()
+    ctxs = [SGM(p["left"].shape[1], p["left"].shape[0], p["max_disp"], synth.P1_DEFAULT, synth.P2_DEFAULT, 4,
+                median=True, lrcheck=True) for p in pairs]
+
+    def seq():
+        for c, p in zip(ctxs, pairs):
+            c.compute(p["left"], p["right"], p["out"], stream=st)
+
+    t_seq = timed(seq)
+    for c in ctxs:
+        c.close()
+    return {"pairs": len(pairs), "ms_per_batch": round(t_direct, 4), "graph_ms_per_batch": round(t_graph, 4),
+            "sequential_ms": round(t_seq, 4), "graph_speedup_vs_direct": round(t_direct / t_graph, 3),
+            "shapes": "8 pairs of 160x120, 256x192 or 320x240, D 32 or 64, 4 paths, median + LR"}
+
+
 def _serve_setup(dev, seed):
     """The served mix's kinds, one device-resident pair per kind."""
     import torch
@@ -978,6 +1027,7 @@ def main():
         print("bench: 64-pair batch vs sequential launches", file=sys.stderr, flush=True)
         line["batched"] = bench_batch(dev, args.batch_steps)
         line["batched_median_lr"] = bench_batch(dev, args.batch_steps, post=True)
+        line["batched_small"] = bench_batch_small(dev)
     if not args.no_serve:
         print("bench: served requests", file=sys.stderr, flush=True)
         line["served"] = bench_serve(dev, [float(q) for q in args.serve_qps.split(",")], args.serve_min_requests,
