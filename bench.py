@@ -420,7 +420,7 @@ def bench_batch(dev, steps: int, warmup: int = 3, post: bool = False):
                          "basis": "algorithmic bytes of census, cost, aggregation, sum + WTA"
                                   + (" and median + LR" if post else "")
                                   + " of all pairs, over the batch's wall time (direct launches)"},
-            "tuning": {"lanes_h_lanes_v": tuned["choice"], "ms_per_batch_by_shape": tuned["candidates"]},
+            "tuning": {"lanes_h_lanes_v_grid": tuned["choice"], "ms_per_batch_by_shape": tuned["candidates"]},
             "shapes": "64 pairs, sizes from {320x240, 640x480, 1242x375, 1280x720}, D from {64, 128}, "
                       "4 or 8 paths, " + ("median + LR check" if post else "no median/LR")}
 

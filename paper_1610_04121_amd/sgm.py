@@ -404,6 +404,7 @@ class Batch:
             raise SGMError(SGM_EINVAL, last_error())
         self.params = dict(P1=P1, P2=P2, census_w=census_w, census_h=census_h)
         self.tuning = (0, 0)
+        self.grid = 0
         self.graph = False
         if graph:
             self.set_graph(True)
@@ -412,6 +413,7 @@ class Batch:
         """Workgroups of the persistent aggregation grid (sgm_batch_set_grid;
         0 = fill the device, 1 = one CU takes the queue)."""
         _check(lib().sgm_batch_set_grid(self._b, max_workgroups))
+        self.grid = max_workgroups
 
     def set_graph(self, enable: bool):
         """Replay a captured hipGraph per batch signature (sgm_batch_set_graph)."""
@@ -434,8 +436,8 @@ class Batch:
         self.tuning = (lanes_h, lanes_v)
 
     def autotune(self, pairs, **kw) -> dict:
-        """Times every batch kernel shape on these pairs and keeps the fastest
-        (see tune.autotune_batch)."""
+        """Times every batch kernel shape and grid size on these pairs and
+        keeps the fastest (see tune.autotune_batch)."""
         from . import tune
         return tune.autotune_batch(self, pairs, **kw)
 

@@ -133,7 +133,16 @@ def autotune(ctx, left=None, right=None, reps: int = 20, rounds: int = 2, use_ca
     return dict(entry, cached=False)
 
 
-BATCH_CANDIDATES = [(0, 0), (16, 16), (32, 16), (16, 32), (32, 32)]
+# (lanes per horizontal slice, lanes per other slice, aggregation workgroups).
+# Workgroups 0 lets the persistent grid hold up to two wavefronts per SIMD,
+# which hides the latency of one slice's min-plus chain behind another's
+# when the queue is long; 256 keeps one wavefront per SIMD (one workgroup per
+# CU), which wins when a few long slices set the launch time and would
+# otherwise share a SIMD with other slices (two 640x240 pairs at D = 128:
+# 97 -> 72 us for the aggregation).
+BATCH_LANES = [(0, 0), (16, 16), (32, 16), (16, 32), (32, 32)]
+BATCH_GRIDS = [0, 256]
+BATCH_CANDIDATES = [(gh, gv, g) for g in BATCH_GRIDS for (gh, gv) in BATCH_LANES]
 
 
 def batch_key(batch, pairs) -> str:
@@ -142,29 +151,37 @@ def batch_key(batch, pairs) -> str:
     import hashlib
     p = batch.params
     sig = sorted((tuple(q["left"].shape), q["max_disp"], q["n_paths"], bool(q.get("median")), bool(q.get("lrcheck")),
-                  bool(q.get("subpixel")), bool(q.get("lr_full")), bool(q.get("adaptive_p2"))) for q in pairs)
+                  bool(q.get("subpixel")), bool(q.get("lr_full")), bool(q.get("adaptive_p2")), bool(q.get("csct")),
+                  int(q.get("lr_threshold", 1))) for q in pairs)
     h = hashlib.sha256(repr(sig).encode()).hexdigest()[:16]
     return f"batch:{len(pairs)}:{h}:P1={p['P1']}:P2={p['P2']}:census={p['census_w']}x{p['census_h']}"
 
 
+def _apply_batch(batch, cand):
+    gh, gv, grid = cand
+    batch.set_tuning(gh, gv)
+    batch.set_grid(grid)
+
+
 def autotune_batch(batch, pairs, reps: int = 3, rounds: int = 1, use_cache: bool = True) -> dict:
     """Picks and applies the fastest batched-aggregation kernel shape (lanes
-    per horizontal / other slice for every pair, or the per-pair default) for
-    this set of pairs: times each shape on the pairs themselves (HIP events
-    on the current stream), checks that every shape gives the same
-    disparities for every pair, and caches the choice under batch_key()."""
+    per horizontal / other slice for every pair, or the per-pair default, and
+    the persistent grid's workgroup count) for this set of pairs: times each
+    shape on the pairs themselves (HIP events on the current stream), checks
+    that every shape gives the same disparities for every pair, and caches
+    the choice under batch_key()."""
     import torch
     key = batch_key(batch, pairs)
     if use_cache:
         hit = load_cache().get(key)
         if hit and tuple(hit.get("choice", ())) in set(BATCH_CANDIDATES):
-            batch.set_tuning(*hit["choice"])
+            _apply_batch(batch, tuple(hit["choice"]))
             return dict(hit, cached=True)
     stream = torch.cuda.current_stream()
     ref, times = None, {}
     for _ in range(rounds):
         for cand in BATCH_CANDIDATES:
-            batch.set_tuning(*cand)
+            _apply_batch(batch, cand)
             batch.compute(pairs, stream=stream)
             stream.synchronize()
             outs = [q["out"].clone() for q in pairs]
@@ -180,9 +197,9 @@ def autotune_batch(batch, pairs, reps: int = 3, rounds: int = 1, use_cache: bool
             e1.synchronize()
             times[cand] = min(times.get(cand, float("inf")), e0.elapsed_time(e1) / reps)
     best = min(times, key=times.get)
-    batch.set_tuning(*best)
+    _apply_batch(batch, best)
     entry = {"choice": list(best), "ms_per_batch": round(times[best], 4),
-             "candidates": {f"{gh},{gv}": round(t, 4) for (gh, gv), t in times.items()}}
+             "candidates": {",".join(map(str, c)): round(t, 4) for c, t in times.items()}}
     if use_cache:
         try:
             save_entry(key, entry)

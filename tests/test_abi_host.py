@@ -165,6 +165,27 @@ def test_tuner_candidates_and_cache(tmp_path, monkeypatch):
     assert tune.load_cache() == {}
 
 
+def test_batch_tuner_candidates_and_key():
+    import types
+    import numpy as np
+    from paper_1610_04121_amd import tune
+    c = tune.BATCH_CANDIDATES
+    assert len(set(c)) == len(c) == len(tune.BATCH_LANES) * len(tune.BATCH_GRIDS)
+    # every lane shape is offered with the device-filling grid and with one
+    # workgroup per CU
+    assert {g for *_, g in c} == {0, 256}
+    assert {(gh, gv) for gh, gv, _ in c} == set(tune.BATCH_LANES)
+    b = types.SimpleNamespace(params=dict(P1=7, P2=86, census_w=9, census_h=7))
+    img = np.zeros((48, 64), np.uint8)
+    base = [dict(left=img, max_disp=32, n_paths=4), dict(left=np.zeros((20, 30), np.uint8), max_disp=64, n_paths=8)]
+    k = tune.batch_key(b, base)
+    assert tune.batch_key(b, list(reversed(base))) == k  # a multiset of pairs
+    # every per-pair option that changes the work changes the key
+    for opt, val in [("median", True), ("lrcheck", True), ("subpixel", True), ("lr_full", True),
+                     ("adaptive_p2", True), ("csct", True), ("lr_threshold", 3)]:
+        assert tune.batch_key(b, [dict(base[0], **{opt: val}), base[1]]) != k, opt
+
+
 def test_full_lr_flag_rules(lib):
     from paper_1610_04121_amd import sgm
     ok = lib.sgm_validate(64, 48, 32, 7, 86, 4, 9, 7, sgm.LRCHECK | sgm.LR_FULL)
