@@ -3,15 +3,18 @@
 //
 // Census, cost, WTA and post launches flatten every pair's blocks into one
 // grid; a block finds its pair by binary search over the pairs' first-block
-// offsets.  The aggregation is a persistent kernel: its wavefronts take work
-// items (pair, direction, group of slices) from a queue in device memory,
-// longest slices first, through a vector atomic counter that the census
-// launch resets (no memset, so the launches can also be graph-captured).
-// Items are independent within the aggregation, so no wavefront ever waits
-// for another and every wavefront leaves the loop when the queue is empty.
+// offsets.  The aggregation is a persistent kernel: its workgroups take
+// quads of work items (pair, direction, group of slices; one item per
+// wavefront) from a queue in device memory, longest slices first, through a
+// vector atomic counter that the census launch resets (no memset, so the
+// launches can also be graph-captured).  Items are independent within the
+// aggregation: the wavefronts of a workgroup meet at a barrier between
+// quads, no workgroup ever waits for another, and every workgroup leaves the
+// loop when the queue is empty.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <new>
 #include <string>
@@ -45,10 +48,18 @@ struct BatchItem {
 };
 
 // One aggregation work item: S = 64 / G slices of one direction of one pair;
-// rb = 1 for a direction of the right-base SGM (full left-right check).
+// rb = 1 for a direction of the right-base SGM (full left-right check);
+// item = -1 marks an empty place of a quad.
 struct WorkItem {
     int item, plane, rx, ry, first, steps, rb;
 };
+
+// Work items go out four at a time, one per wavefront of a workgroup (a
+// quad).  Opposite axis-aligned directions over the same two slice groups
+// share a quad (A, A, B, B), so both walks over a slice's costs run on one
+// CU and its L2 and the second read can hit there, as in the single-pair
+// aggregation launch.
+constexpr int kQuad = 4;
 
 // Index of the pair whose block range [blk0, next blk0) holds block b.
 template <int BatchItem::*FIRST>
@@ -148,22 +159,28 @@ __device__ __attribute__((always_inline)) inline void aggregate_item_dp(const Sl
 }
 
 // ANY_ADAPT: some pair of the batch uses the adaptive P2 (a second
-// instantiation, so batches without one keep the smaller kernel).
+// instantiation, so batches without one keep the smaller kernel).  A
+// workgroup takes one quad of work items at a time, wavefront k its item k;
+// the quad's items have the same length, so its wavefronts finish together.
 template <bool NT, bool ANY_ADAPT>
 __global__ __launch_bounds__(256) void aggregate_batch_kernel(const BatchItem* items, const WorkItem* work,
-                                                              int nwork, unsigned* queue_counter, int P1, int P2) {
+                                                              int nquads, unsigned* queue_counter, int P1, int P2) {
     __shared__ uint16_t p2lut[ANY_ADAPT ? 256 : 1];
-    if constexpr (ANY_ADAPT) {  // P1, P2 belong to the batch: one table per block
+    __shared__ unsigned quad;
+    if constexpr (ANY_ADAPT)  // P1, P2 belong to the batch: one table per block
         fill_p2_lut(p2lut, P1, P2);
-        __syncthreads();
-    }
     const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     for (;;) {
-        unsigned idx = 0;
-        if (lane == 0) idx = atomicAdd(queue_counter, 1u);
-        idx = __builtin_amdgcn_readfirstlane(idx);
-        if (idx >= (unsigned)nwork) break;
-        const WorkItem w = work[idx];
+        // the barrier also ends every wavefront's read of the previous quad
+        // index (and, on the first pass, the penalty table's fill)
+        __syncthreads();
+        if (threadIdx.x == 0) quad = atomicAdd(queue_counter, 1u);
+        __syncthreads();
+        const unsigned q = __builtin_amdgcn_readfirstlane(quad);
+        if (q >= (unsigned)nquads) break;
+        const WorkItem w = work[(size_t)q * kQuad + wave];
+        if (w.item < 0) continue;
         const BatchItem& it = items[w.item];
         const uint32_t plane = (uint32_t)it.W * (uint32_t)it.H * (uint32_t)it.Dp;
         void* lplane = it.l16 ? (void*)(reinterpret_cast<uint16_t*>(it.lbuf) + (size_t)plane * w.plane)
@@ -369,13 +386,16 @@ struct BatchLaunch {
     size_t census_blocks = 0, cost_blocks = 0, wta_blocks = 0, post_blocks = 0;
     size_t cost_smem = 0, wta_smem = 0, post_smem = 0;
     bool generic = false, any_adapt = false, nt = false;
-    int waves = 0;
+    int blocks = 0;  // persistent aggregation workgroups
 };
 
 int batch_build(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_base, const sgm_item* items, int n,
                 BatchLaunch& B) {
-    // work items: every direction's slices of every pair, S per wavefront
+    // work items: every direction's slices of every pair, S per wavefront,
+    // in quads (kQuad items, one workgroup each)
     std::vector<WorkItem>& work = B.work;
+    std::vector<std::array<WorkItem, kQuad>> quads;
+    std::vector<WorkItem> singles;  // items without an opposite partner
     size_t census_blocks = 0, cost_blocks = 0, wta_blocks = 0, post_blocks = 0;
     std::vector<BatchItem>& desc = B.desc;
     desc.assign(n, BatchItem{});
@@ -441,17 +461,49 @@ int batch_build(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_bas
                 const Dir dir = direction(p.n_paths, r);
                 const int S = 64 / (dir.ry == 0 ? gh : gv);
                 const int nsl = slice_count(p.W, p.H, dir), steps = slice_steps(p.W, p.H, dir);
-                for (int f = 0; f < nsl; f += S)
-                    work.push_back(WorkItem{i, sg * p.n_paths + r, dir.rx, dir.ry, f, steps, sg});
+                auto unit = [&](int rr, const Dir& dd, int f) {
+                    return WorkItem{i, sg * p.n_paths + rr, dd.rx, dd.ry, f, steps, sg};
+                };
+                // with 4 or 8 paths, directions 0/1 (+-x) and 2/3 (+-y) are
+                // opposite pairs of equal slice counts
+                if (p.n_paths >= 4 && r < 4) {
+                    if (r & 1) continue;  // handled with its partner
+                    const Dir opp = direction(p.n_paths, r + 1);
+                    int f = 0;
+                    for (; f + S < nsl; f += 2 * S)
+                        quads.push_back({unit(r, dir, f), unit(r, dir, f + S), unit(r + 1, opp, f),
+                                         unit(r + 1, opp, f + S)});
+                    if (f < nsl) {  // an odd slice-group count: the last one of each
+                        singles.push_back(unit(r, dir, f));
+                        singles.push_back(unit(r + 1, opp, f));
+                    }
+                    continue;
+                }
+                for (int f = 0; f < nsl; f += S) singles.push_back(unit(r, dir, f));
             }
     }
-    if (census_blocks > 0x7FFFFFFF || cost_blocks > 0x7FFFFFFF || work.size() > 0x7FFFFFFF)
+    // the unpaired items, longest first, fill quads of their own
+    std::stable_sort(singles.begin(), singles.end(),
+                     [](const WorkItem& a, const WorkItem& c) { return a.steps > c.steps; });
+    for (size_t k = 0; k < singles.size(); k += kQuad) {
+        std::array<WorkItem, kQuad> qd;
+        for (int j = 0; j < kQuad; ++j)
+            qd[j] = k + j < singles.size() ? singles[k + j] : WorkItem{-1, 0, 0, 0, 0, 0, 0};
+        quads.push_back(qd);
+    }
+    if (census_blocks > 0x7FFFFFFF || cost_blocks > 0x7FFFFFFF || quads.size() > 0x1FFFFFFF)
         return berr(SGM_EINVAL, "batch too large");
-    // longest slices first (largest-processing-time-first order)
-    std::stable_sort(work.begin(), work.end(), [](const WorkItem& a, const WorkItem& c) { return a.steps > c.steps; });
+    // longest slices first (largest-processing-time-first order); a quad's
+    // first item is one of its longest
+    std::stable_sort(quads.begin(), quads.end(),
+                     [](const std::array<WorkItem, kQuad>& a, const std::array<WorkItem, kQuad>& c) {
+                         return a[0].steps > c[0].steps;
+                     });
+    work.clear();
+    for (const auto& qd : quads) work.insert(work.end(), qd.begin(), qd.end());
 
     // persistent grid: at most two wavefronts per SIMD (256 CUs x 4 SIMDs)
-    B.waves = std::min((int)work.size(), bp.max_workgroups > 0 ? 4 * std::min(bp.max_workgroups, 512) : 2048);
+    B.blocks = std::min((int)quads.size(), bp.max_workgroups > 0 ? std::min(bp.max_workgroups, 512) : 512);
     // the planes and cost volumes of the whole batch against the memory-side
     // cache: the store policy of the single-pair path (Plan::nt_store)
     long long fbytes = 0;
@@ -477,10 +529,11 @@ hipError_t batch_launch(const BatchParams& bp, const BatchLaunch& B, const Batch
                        B.generic ? 1 : 0, (bp.cw - 1) / 2, (bp.ch - 1) / 2, counter);
     hipLaunchKernelGGL(cost_batch_kernel, dim3((unsigned)B.cost_blocks), dim3(kCostThreads), B.cost_smem, s, d_items,
                        n);
-    const int nwork = (int)B.work.size();
+    const int nquads = (int)(B.work.size() / kQuad);
     auto agg = B.nt ? (B.any_adapt ? aggregate_batch_kernel<true, true> : aggregate_batch_kernel<true, false>)
                     : (B.any_adapt ? aggregate_batch_kernel<false, true> : aggregate_batch_kernel<false, false>);
-    hipLaunchKernelGGL(agg, dim3((B.waves + 3) / 4), dim3(256), 0, s, d_items, d_work, nwork, counter, bp.P1, bp.P2);
+    hipLaunchKernelGGL(agg, dim3((unsigned)B.blocks), dim3(256), 0, s, d_items, d_work, nquads, counter, bp.P1,
+                       bp.P2);
     hipLaunchKernelGGL(B.nt ? wta_batch_kernel<true> : wta_batch_kernel<false>, dim3((unsigned)B.wta_blocks),
                        dim3(1024), B.wta_smem, s, d_items, n);
     if (B.post_blocks > 0) {

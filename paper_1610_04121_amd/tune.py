@@ -139,7 +139,7 @@ def autotune(ctx, left=None, right=None, reps: int = 20, rounds: int = 2, use_ca
 # when the queue is long; 256 keeps one wavefront per SIMD (one workgroup per
 # CU), which wins when a few long slices set the launch time and would
 # otherwise share a SIMD with other slices (two 640x240 pairs at D = 128:
-# 97 -> 72 us for the aggregation).
+# 64 -> 59 us for the aggregation).
 BATCH_LANES = [(0, 0), (16, 16), (32, 16), (16, 32), (32, 32)]
 BATCH_GRIDS = [0, 256]
 BATCH_CANDIDATES = [(gh, gv, g) for g in BATCH_GRIDS for (gh, gv) in BATCH_LANES]
