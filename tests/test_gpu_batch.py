@@ -54,6 +54,39 @@ def test_heterogeneous_batch_matches_oracle(gpu):
     b.close()
 
 
+@pytest.mark.parametrize("grid", [0, 256, 1])
+def test_quads_with_odd_and_even_slice_group_counts(gpu, grid):
+    """The aggregation queue hands out quads: opposite axis-aligned directions
+    over two slice groups, the rest (diagonals, the 2-path set, the last
+    group of an odd count) packed four at a time with empty places.  Items
+    whose +-x and +-y group counts are odd, even and one, at 2, 4 and 8
+    paths, with and without the full check (a second SGM's planes), for each
+    grid size, against the oracle."""
+    import torch
+    # lanes 32 / 16: a horizontal group is 2 rows, a vertical one 4 columns
+    specs = [(9, 5, 16, 4), (8, 4, 16, 4), (12, 6, 20, 8), (1, 1, 4, 4), (13, 7, 33, 2), (9, 6, 8, 8),
+             (16, 3, 40, 4), (5, 10, 16, 8)]
+    pairs, wants = [], []
+    for k, (w, h, d, p) in enumerate(specs):
+        pr = synth.make_pair(w, h, d, "RS", seed=52000 + k)
+        full = k % 3 == 1
+        pairs.append(dict(left=_t(pr.left, gpu), right=_t(pr.right, gpu), max_disp=d, n_paths=p, median=k % 2 == 0,
+                          lrcheck=full or k % 4 == 0, lr_full=full,
+                          out=torch.full((h, w), 0xABC, dtype=torch.uint16, device=gpu)))
+        wants.append(oracle.sgm(pr.left, pr.right, d, 7, 86, p, median=k % 2 == 0, lr=full or k % 4 == 0,
+                                lr_full=full).out)
+    _say(f"batch quads, grid {grid}")
+    b = Batch(7, 86)
+    b.set_tuning(32, 16)
+    b.set_grid(grid)
+    b.compute(pairs)
+    torch.cuda.synchronize()
+    for k, (p, want) in enumerate(zip(pairs, wants)):
+        got = p["out"].cpu().numpy()
+        assert (got == want).all(), (k, specs[k], int((got != want).sum()))
+    b.close()
+
+
 def test_batch_u16_planes_and_generic_census(gpu):
     import torch
     specs = [(45, 30, 40, 4, True, True), (30, 45, 70, 8, False, True)]
