@@ -452,13 +452,13 @@ def test_batch_one_workgroup_grid_matches(gpu):
     b.close()
 
 
-@pytest.mark.parametrize("trial", range(12))
+@pytest.mark.parametrize("trial", range(16))
 def test_fuzz_batches(gpu, trial):
     """Random batches: 1 to 10 items of random sizes (down to 1x1), ranges,
     path counts and options (median, check with its threshold, full check,
     sub-pixel output, adaptive P2, CSCT census), a random kernel shape, direct launches,
-    graph replay (twice) or the one-workgroup grid; every item against the
-    oracle."""
+    graph replay (twice, with the default grid or one workgroup per CU) or the
+    one-workgroup grid; every item against the oracle."""
     import torch
     rng = np.random.default_rng(31000 + trial)
     n = int(rng.integers(1, 11))
@@ -482,13 +482,15 @@ def test_fuzz_batches(gpu, trial):
         wants.append(oracle.sgm(l_, r_, d, 7, 86, p, median=med, lr=lr, lr_thr=thr, lr_full=full, subpixel=sub,
                                 adaptive=adapt, csct=csct).out)
     lanes = [(0, 0), (16, 16), (32, 16), (16, 32), (32, 32)][trial % 5]
-    mode = ["direct", "graph", "grid1"][trial % 3]
+    mode = ["direct", "graph", "grid1", "graph_grid256"][trial % 4]
     _say(f"batch fuzz {trial}: {n} items, lanes={lanes}, mode={mode}")
-    b = Batch(7, 86, graph=(mode == "graph"))
+    b = Batch(7, 86, graph=mode.startswith("graph"))
     b.set_tuning(*lanes)
     if mode == "grid1":
         b.set_grid(1)
-    for rep in range(2 if mode == "graph" else 1):
+    if mode == "graph_grid256":
+        b.set_grid(256)
+    for rep in range(2 if mode.startswith("graph") else 1):
         for p in pairs:
             p["out"].fill_(0xABC)
         b.compute(pairs)
