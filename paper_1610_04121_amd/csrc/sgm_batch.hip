@@ -55,10 +55,11 @@ struct WorkItem {
 };
 
 // Work items go out four at a time, one per wavefront of a workgroup (a
-// quad).  Opposite axis-aligned directions over the same two slice groups
-// share a quad (A, A, B, B), so both walks over a slice's costs run on one
-// CU and its L2 and the second read can hit there, as in the single-pair
-// aggregation launch.
+// quad).  Opposite directions over the same pixels share a quad (A, A, B,
+// B): the axis-aligned ones over the same two slice groups, the diagonals
+// over the groups that cover (most of) the same pixels.  Both walks over a
+// pixel's costs then run on one CU and its L2, and the second read can hit
+// there, as in the single-pair aggregation launch.
 constexpr int kQuad = 4;
 
 // Index of the pair whose block range [blk0, next blk0) holds block b.
@@ -464,19 +465,39 @@ int batch_build(const BatchParams& bp, const Plan* plans, uint8_t* const* ws_bas
                 auto unit = [&](int rr, const Dir& dd, int f) {
                     return WorkItem{i, sg * p.n_paths + rr, dd.rx, dd.ry, f, steps, sg};
                 };
-                // with 4 or 8 paths, directions 0/1 (+-x) and 2/3 (+-y) are
-                // opposite pairs of equal slice counts
-                if (p.n_paths >= 4 && r < 4) {
-                    if (r & 1) continue;  // handled with its partner
-                    const Dir opp = direction(p.n_paths, r + 1);
-                    int f = 0;
-                    for (; f + S < nsl; f += 2 * S)
-                        quads.push_back({unit(r, dir, f), unit(r, dir, f + S), unit(r + 1, opp, f),
-                                         unit(r + 1, opp, f + S)});
-                    if (f < nsl) {  // an odd slice-group count: the last one of each
-                        singles.push_back(unit(r, dir, f));
-                        singles.push_back(unit(r + 1, opp, f));
+                // Quads of directions ra and rb (opposite, equal slice counts
+                // and lengths): rb's groups in the order of key_b (the first
+                // slice of ra over the same pixels) meet ra's groups in
+                // order, two and two; an odd count leaves one of each
+                auto pair_up = [&](int ra, int rb, auto key_b) {
+                    const Dir da = direction(p.n_paths, ra), db = direction(p.n_paths, rb);
+                    std::vector<int> fb;
+                    for (int f = 0; f < nsl; f += S) fb.push_back(f);
+                    std::stable_sort(fb.begin(), fb.end(), [&](int u, int v) { return key_b(u) < key_b(v); });
+                    size_t g = 0;
+                    for (; g + 1 < fb.size(); g += 2)
+                        quads.push_back({unit(ra, da, (int)g * S), unit(ra, da, (int)(g + 1) * S), unit(rb, db, fb[g]),
+                                         unit(rb, db, fb[g + 1])});
+                    if (g < fb.size()) {
+                        singles.push_back(unit(ra, da, (int)g * S));
+                        singles.push_back(unit(rb, db, fb[g]));
                     }
+                };
+                // with 4 or 8 paths, directions 0/1 (+-x) and 2/3 (+-y) are
+                // opposite pairs over the same slices
+                if (p.n_paths >= 4 && r < 4) {
+                    if ((r & 1) == 0) pair_up(r, r + 1, [](int f) { return f; });
+                    continue;
+                }
+                // with 8 paths, 4 (1, 1) / 7 (-1, -1) and 5 (-1, 1) / 6 (1, -1)
+                // are opposite diagonals.  Under the wrap schedule the slice
+                // from column c of the top row covers x = c +- y (mod W);
+                // the opposite one from column c' of the bottom row covers
+                // x = c' -+ (H - 1 - y), the same pixels when c' = c +- (H - 1)
+                if (p.n_paths == 8) {
+                    const int W = p.W, k = (p.H - 1) % p.W;
+                    if (r == 4) pair_up(4, 7, [=](int f) { return (f - k + W) % W; });
+                    if (r == 5) pair_up(5, 6, [=](int f) { return (f + k) % W; });
                     continue;
                 }
                 for (int f = 0; f < nsl; f += S) singles.push_back(unit(r, dir, f));
